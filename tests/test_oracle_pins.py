@@ -1,0 +1,387 @@
+"""Pins for the CPU oracle: facts fixed by the paper and by mathematics, not by the oracle itself.
+
+Each test names what pins which part:
+* hand-worked golden cells (tests/golden/*.txt, derivations inside)    -> recursion, axis choice, cut, ties, Step 7
+* weight/momentum/energy conservation                                  -> merge (centroid and pair)
+* energy never gained by the centroid (Jensen)                         -> Step 7 energy statement
+* CV bound on every merged subset, recomputed with numpy               -> Steps 2-3
+* single-subset limit against numpy.average                            -> Step 1 centroid
+* zero tolerance on a lattice = numpy.unique duplicate classes         -> Steps 3-6 termination and cuts
+* 1-D data = weighted-mean bisection of a sorted list (exact Fractions)-> Steps 4-6
+* two cold counter-moving beams split into exactly the two beams       -> zero-mean momentum CV
+* looser tolerance gives a coarsening of the finer partition           -> structure of the recursion
+* FIXED-mode invariances (permutation, powers of two)                  -> fixed-point frames
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_00636_amd import workloads as W
+from tests.helpers import (FIELDS, conserved_totals, energy, load_golden, partition_sets,
+                           subsets_of)
+
+GOLDEN_FILES = ["px_bisection_6.txt", "corners_tie_4.txt", "px_ladder_8.txt"]
+MODES = [oracle.FIXED, oracle.PAPER]
+
+
+def _run_arr(arr, cell_off, **kw):
+    return oracle.run([arr[:, i] for i in range(7)], cell_off, **kw)
+
+
+@pytest.mark.parametrize("fname", GOLDEN_FILES)
+@pytest.mark.parametrize("decide", MODES)
+def test_golden_cells(fname, decide):
+    arr, prm, merge, subsets, merged = load_golden(fname)
+    mm = oracle.CENTROID if merge == "centroid" else oracle.PAIR
+    r = _run_arr(arr, np.array([0, arr.shape[0]]), merge_mode=mm, decide=decide, **prm)
+    got = subsets_of(r.perm, r.subset_id, np.array([0, arr.shape[0]]), 0)
+    assert [list(map(int, s)) for s in got] == subsets
+    out = np.stack([r.out[f] for f in ("w", "x", "y", "z", "px", "py", "pz")], axis=1)
+    # FIXED mode merges the FP32-rounded inputs
+    tol = 1e-6 if decide == oracle.FIXED else 1e-12
+    np.testing.assert_allclose(out, merged, rtol=tol, atol=tol)
+
+
+def _momentum_cloud(n_cells=20, n=300, seed=1):
+    """Cells whose momenta have clearly nonzero means in every component, so that merging happens."""
+    r = np.random.Generator(np.random.Philox(seed))
+    cells = []
+    for c in range(n_cells):
+        k = n + int(r.integers(-50, 50))
+        x = r.random(k); y = r.random(k); z = r.random(k)
+        px = 1.0 + 0.1 * r.standard_normal(k)
+        py = 0.5 + 0.05 * r.standard_normal(k)
+        pz = -0.3 + 0.05 * r.standard_normal(k)
+        w = 0.5 + r.random(k)
+        cells.append(np.stack([x, y, z, px, py, pz, w], axis=1))
+    return W.from_cells(cells, params=dict(tol_x=0.3, tol_p=0.08, n_min_cell=0, min_subset=4,
+                                           cell_len=(1, 1, 1), mass=1.0))
+
+
+@pytest.mark.parametrize("decide", MODES)
+@pytest.mark.parametrize("merge", [oracle.PAIR, oracle.CENTROID])
+def test_conservation(decide, merge):
+    wl = _momentum_cloud()
+    if decide == oracle.FIXED:
+        wl = wl.astype(np.float32)
+    r = oracle.run_workload(wl, decide=decide, merge_mode=merge)
+    assert r.stats["n_merged"].sum() > 100            # the case really merges
+    assert r.out_total < wl.n
+    tin = conserved_totals(wl.arrays(), 1.0)
+    tout = conserved_totals([r.out[f] for f in FIELDS], 1.0)
+    scale = np.array([tin[0], *([np.sum(wl.w * np.abs(p)) for p in (wl.px, wl.py, wl.pz)]), tin[4]])
+    err = np.abs(tout - tin) / scale
+    assert err[:4].max() < 1e-14
+    if merge == oracle.PAIR:
+        assert err[4] < 1e-14
+    else:
+        assert tout[4] <= tin[4] * (1 + 1e-15)       # the centroid loses energy (Jensen)
+        assert tout[4] < tin[4]
+
+
+def test_pair_geometry():
+    """Each pair: equal half weights, same position, P +- delta with delta orthogonal to P, and both
+    members carry the subset's mean energy."""
+    wl = _momentum_cloud(n_cells=5)
+    r = oracle.run_workload(wl, decide=oracle.PAPER, merge_mode=oracle.PAIR)
+    off = r.out_off
+    for c in range(wl.n_cells):
+        subs = subsets_of(r.perm, r.subset_id, wl.cell_off, c)
+        o = int(off[c])
+        for s in subs:
+            s = np.array(s)
+            if len(s) < 4:
+                o += len(s)
+                continue
+            w = wl.w[s]; Wt = w.sum()
+            P = np.array([np.average(getattr(wl, f)[s], weights=w) for f in ("px", "py", "pz")])
+            ebar = np.average(energy(wl.px[s], wl.py[s], wl.pz[s], 1.0), weights=w)
+            a = np.array([r.out[f][o] for f in ("px", "py", "pz")])
+            b = np.array([r.out[f][o + 1] for f in ("px", "py", "pz")])
+            assert r.out["w"][o] == pytest.approx(Wt / 2, rel=1e-15)
+            assert r.out["w"][o + 1] == pytest.approx(Wt / 2, rel=1e-15)
+            np.testing.assert_allclose((a + b) / 2, P, rtol=1e-13, atol=1e-15)
+            d = (a - b) / 2
+            assert abs(np.dot(d, P)) <= 1e-12 * np.linalg.norm(P) * max(np.linalg.norm(d), 1e-300)
+            for v in (a, b):
+                assert energy(*v, 1.0) == pytest.approx(ebar, rel=1e-14)
+            o += 2
+
+
+@pytest.mark.parametrize("decide", MODES)
+def test_cv_bound_on_merged_subsets(decide):
+    """Every merged subset satisfies Delta_X <= T_X and Delta_P <= T_P, recomputed with numpy.
+    FIXED mode may exceed the real-valued bound only by its quantisation (equal weights here)."""
+    r0 = np.random.Generator(np.random.Philox(7))
+    wl = _momentum_cloud(n_cells=10, seed=3)
+    wl.w[:] = 1.0
+    if decide == oracle.FIXED:
+        wl = wl.astype(np.float32)
+    prm = wl.params
+    r = oracle.run_workload(wl, decide=decide)
+    q = [np.asarray(getattr(wl, f), np.float64) for f in FIELDS]
+    n_checked = 0
+    for c in range(wl.n_cells):
+        for s in subsets_of(r.perm, r.subset_id, wl.cell_off, c):
+            s = np.array(s)
+            if len(s) < prm["min_subset"]:
+                continue
+            w = q[6][s]
+            for l in range(6):
+                mu = np.average(q[l][s], weights=w)
+                sig = np.sqrt(np.average((q[l][s] - mu) ** 2, weights=w))
+                if l < 3:
+                    cv, T = sig / 1.0, prm["tol_x"]
+                    slack = 2.0 ** -15 + 2.0 ** -24
+                else:
+                    cv, T = (sig / abs(mu) if mu != 0 else (0 if sig == 0 else np.inf)), prm["tol_p"]
+                    pmax = np.abs(q[l][wl.cell_off[c]:wl.cell_off[c + 1]]).max()
+                    slack = 2.0 ** -21 * pmax / abs(mu) * (1 + T) + 2.0 ** -24
+                if decide == oracle.PAPER:
+                    slack = 1e-12 * T
+                assert cv <= T + slack, (c, l, cv, T)
+            n_checked += 1
+    assert n_checked > 50
+    del r0
+
+
+@pytest.mark.parametrize("decide", MODES)
+@pytest.mark.parametrize("merge", [oracle.PAIR, oracle.CENTROID])
+def test_huge_tolerance_is_weighted_average(decide, merge):
+    """No CV reaches the tolerance: each cell is one subset whose centroid is numpy.average."""
+    wl = _momentum_cloud(n_cells=6, seed=5)
+    if decide == oracle.FIXED:
+        wl = wl.astype(np.float32)
+    r = oracle.run_workload(wl, decide=decide, merge_mode=merge, tol_x=100.0, tol_p=100.0)
+    assert np.all(r.n_subsets == 1)
+    k = 2 if merge == oracle.PAIR else 1
+    assert r.out_total == k * wl.n_cells
+    for c in range(wl.n_cells):
+        s = slice(wl.cell_off[c], wl.cell_off[c + 1])
+        w = np.asarray(wl.w[s], np.float64)
+        o = slice(k * c, k * c + k)
+        assert r.out["w"][o].sum() == pytest.approx(w.sum(), rel=1e-15)
+        for f in ("x", "y", "z", "px", "py", "pz"):
+            want = np.average(np.asarray(getattr(wl, f)[s], np.float64), weights=w)
+            got = np.average(r.out[f][o], weights=r.out["w"][o])
+            assert got == pytest.approx(want, rel=1e-13, abs=1e-15)
+
+
+def _lattice_cells(seed, n_cells=12, n=64):
+    r = np.random.Generator(np.random.Philox(seed))
+    cells = []
+    for c in range(n_cells):
+        k = n + int(r.integers(-20, 20))
+        base = r.integers(0, 3, size=(k, 6)).astype(np.float64)
+        # few distinct values so duplicates are common
+        base[:, :3] = base[:, :3] * 1000.0          # positions on an exact grid (L = 65536)
+        base[:, 3:] = base[:, 3:] - 1.0             # momenta in {-1, 0, 1}
+        w = r.integers(1, 4, size=(k, 1)).astype(np.float64)
+        cells.append(np.concatenate([base, w], axis=1))
+    return W.from_cells(cells, params=dict(tol_x=0.0, tol_p=0.0, n_min_cell=0, min_subset=1,
+                                           cell_len=(65536.0,) * 3, mass=1.0))
+
+
+@pytest.mark.parametrize("decide", MODES)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_zero_tolerance_gives_duplicate_classes(decide, seed):
+    """With T = 0 a subset is finished only when all its CVs vanish, i.e. its members coincide in all
+    six coordinates; no cut ever separates identical particles.  So the final subsets are exactly the
+    classes of numpy.unique over the (x, p) rows."""
+    wl = _lattice_cells(seed)
+    r = oracle.run_workload(wl, decide=decide, merge_mode=oracle.CENTROID)
+    for c in range(wl.n_cells):
+        lo, hi = wl.cell_off[c], wl.cell_off[c + 1]
+        rows = np.stack([getattr(wl, f)[lo:hi] for f in FIELDS[:6]], axis=1)
+        _, inv = np.unique(rows, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        want = sorted(tuple(sorted(np.nonzero(inv == u)[0] + lo)) for u in range(inv.max() + 1))
+        assert partition_sets(r.perm, r.subset_id, wl.cell_off, c) == want
+
+
+def _bisect_1d(vals, wts, idx, T, min_subset):
+    """Textbook 1-D weighted-mean bisection on exact rationals (Steps 2-6 with one varying axis)."""
+    if len(idx) < min_subset:
+        return [sorted(idx)]
+    Wt = sum(wts[i] for i in idx)
+    mu = sum(wts[i] * vals[i] for i in idx) / Wt
+    var = sum(wts[i] * (vals[i] - mu) ** 2 for i in idx) / Wt
+    if mu == 0:
+        done = var == 0
+    else:
+        done = var <= T * T * mu * mu
+    if done:
+        return [sorted(idx)]
+    left = [i for i in idx if vals[i] <= mu]
+    right = [i for i in idx if vals[i] > mu]
+    return _bisect_1d(vals, wts, left, T, min_subset) + _bisect_1d(vals, wts, right, T, min_subset)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_one_dimensional_bisection(seed):
+    """Only px varies: the partition is the recursive weighted-mean bisection of a list.  The expected
+    result is computed with exact Fractions on the same binary values.  Lattice values make FIXED-mode
+    codes exact, so both decision modes must give it."""
+    r = np.random.Generator(np.random.Philox(100 + seed))
+    n = int(r.integers(5, 200))
+    px = r.integers(1, 64, size=n).astype(np.float64)        # exact in every representation
+    w = r.integers(1, 5, size=n).astype(np.float64)
+    arr = np.zeros((n, 7))
+    arr[:, :3] = 0.5
+    arr[:, 3] = px
+    arr[:, 6] = w
+    T = float([0.05, 0.1, 0.2, 0.3, 0.02, 0.15][seed])
+    vals = [Fraction(v) for v in px]
+    wts = [Fraction(v) for v in w]
+    # FIXED mode compares with T rounded to a multiple of 2^-24; PAPER with T itself.
+    Tq = Fraction(round(T * 2 ** 24), 2 ** 24)
+    for decide in MODES:
+        Tm = Fraction(T) if decide == oracle.PAPER else Tq
+        want = sorted(tuple(s) for s in _bisect_1d(vals, wts, list(range(n)), Tm, 2))
+        rr = _run_arr(arr, np.array([0, n]), tol_x=0.5, tol_p=float(Tm),
+                      min_subset=2, merge_mode=oracle.CENTROID, decide=decide)
+        got = partition_sets(rr.perm, rr.subset_id, np.array([0, n]), 0)
+        if decide == oracle.PAPER and got != want:
+            assert rr.stats["min_margin"][0] < 1e-9     # only a certified near-tie may differ
+        else:
+            assert got == want
+
+
+@pytest.mark.parametrize("decide", MODES)
+def test_two_cold_beams_split_once(decide):
+    """Two beams with p = +-0.2 x (no spread), same position: the root's mean px is exactly 0, so its
+    px CV is infinite and the first cut separates the beams; each beam then has zero spread."""
+    n = 40
+    arr = np.zeros((n, 7))
+    arr[:, :3] = 0.5
+    fwd = np.arange(n) % 3 == 0
+    k = int(fwd.sum())
+    arr[:, 3] = np.where(fwd, 0.25, -0.25)
+    arr[:, 6] = np.where(fwd, float(n - k), float(k))   # total momentum of the two beams cancels exactly
+    r = _run_arr(arr, np.array([0, n]), tol_x=0.1, tol_p=0.01, min_subset=2,
+                 merge_mode=oracle.CENTROID, decide=decide)
+    assert r.n_subsets[0] == 2
+    sets = partition_sets(r.perm, r.subset_id, np.array([0, n]), 0)
+    assert sets == sorted([tuple(np.nonzero(arr[:, 3] < 0)[0]), tuple(np.nonzero(arr[:, 3] > 0)[0])])
+    assert sorted(r.out["px"]) == [-0.25, 0.25]
+
+
+@pytest.mark.parametrize("decide", MODES)
+def test_looser_tolerance_coarsens(decide):
+    """The axis and cut of a subset do not depend on T; T only decides where the recursion stops.
+    So the partition at a looser tolerance is a coarsening of the one at a tighter tolerance, and each
+    coarse subset is a run of consecutive fine subsets in depth-first order."""
+    wl = _momentum_cloud(n_cells=8, seed=11)
+    if decide == oracle.FIXED:
+        wl = wl.astype(np.float32)
+    fine = oracle.run_workload(wl, decide=decide, tol_x=0.15, tol_p=0.04)
+    coarse = oracle.run_workload(wl, decide=decide, tol_x=0.4, tol_p=0.12)
+    assert coarse.n_subsets.sum() < fine.n_subsets.sum()
+    for c in range(wl.n_cells):
+        fs = [tuple(s) for s in subsets_of(fine.perm, fine.subset_id, wl.cell_off, c)]
+        cs = [tuple(s) for s in subsets_of(coarse.perm, coarse.subset_id, wl.cell_off, c)]
+        i = 0
+        for s in cs:
+            acc = []
+            while len(acc) < len(s):
+                acc.extend(fs[i]); i += 1
+            assert sorted(acc) == sorted(s)
+        assert i == len(fs)
+
+
+def test_fixed_mode_invariances():
+    """FIXED decisions use per-cell frames: scaling all momenta or all weights of a cell by a power of
+    two, or permuting its particles, leaves the partition (as sets) unchanged."""
+    wl = _momentum_cloud(n_cells=6, seed=13).astype(np.float32)
+    ref = oracle.run_workload(wl)
+    for kind in ("p", "w", "perm"):
+        w2 = wl.astype(np.float32)
+        mapping = np.arange(wl.n)
+        if kind == "p":
+            for f in ("px", "py", "pz"):
+                setattr(w2, f, getattr(w2, f) * np.float32(2.0 ** 7))
+        elif kind == "w":
+            w2.w = w2.w * np.float32(2.0 ** -5)
+        else:
+            r = np.random.Generator(np.random.Philox(2))
+            for c in range(wl.n_cells):
+                lo, hi = wl.cell_off[c], wl.cell_off[c + 1]
+                mapping[lo:hi] = lo + r.permutation(hi - lo)
+            for f in FIELDS:
+                setattr(w2, f, getattr(wl, f)[mapping])
+        got = oracle.run_workload(w2)
+        for c in range(wl.n_cells):
+            a = partition_sets(ref.perm, ref.subset_id, wl.cell_off, c)
+            b = [tuple(sorted(int(mapping[i]) for i in s))
+                 for s in partition_sets(got.perm, got.subset_id, wl.cell_off, c)]
+            assert sorted(b) == a, kind
+
+
+@pytest.mark.parametrize("decide", MODES)
+def test_structure(decide):
+    """Partition covers each cell once; passthrough particles are copied bit-for-bit; merged positions
+    lie inside their subset's bounding box; untouched cells (N <= N_min) are the identity."""
+    wl = W.two_stream_grid(nx=6, ny=5, mean=60, seed=4)
+    if decide == oracle.FIXED:
+        wl = wl.astype(np.float32)
+    r = oracle.run_workload(wl, decide=decide, n_min_cell=55, tol_x=0.3, tol_p=0.3)
+    q = {f: np.asarray(getattr(wl, f), np.float64) for f in FIELDS}
+    for c in range(wl.n_cells):
+        lo, hi = wl.cell_off[c], wl.cell_off[c + 1]
+        assert sorted(r.perm[lo:hi]) == list(range(lo, hi))
+        o = int(r.out_off[c])
+        if hi - lo <= 55:
+            assert r.n_subsets[c] == 0 and np.all(r.subset_id[lo:hi] == -1)
+            assert list(r.perm[lo:hi]) == list(range(lo, hi))
+            for f in FIELDS:
+                np.testing.assert_array_equal(r.out[f][o:o + hi - lo], q[f][lo:hi])
+            continue
+        for s in subsets_of(r.perm, r.subset_id, wl.cell_off, c):
+            s = np.array(s)
+            if len(s) < 4:
+                for f in FIELDS:
+                    np.testing.assert_array_equal(r.out[f][o:o + len(s)], q[f][s])
+                o += len(s)
+            else:
+                for f in ("x", "y", "z"):
+                    v = r.out[f][o:o + 2]
+                    assert np.all(v >= q[f][s].min() - 1e-12) and np.all(v <= q[f][s].max() + 1e-12)
+                o += 2
+        assert o == r.out_off[c + 1]
+
+
+def test_fixed_and_paper_agree_on_typical_data():
+    """On random data away from ties the two decision modes give the same partition (measured)."""
+    wl = _momentum_cloud(n_cells=10, seed=21).astype(np.float32)
+    wl.w[:] = 1.0
+    a = oracle.run_workload(wl, decide=oracle.FIXED)
+    b = oracle.run_workload(wl, decide=oracle.PAPER)
+    same = sum(partition_sets(a.perm, a.subset_id, wl.cell_off, c) ==
+               partition_sets(b.perm, b.subset_id, wl.cell_off, c) for c in range(wl.n_cells))
+    assert same >= 8
+
+
+def test_rejects_bad_arguments():
+    arr = np.ones((4, 7))
+    with pytest.raises(ValueError):
+        _run_arr(arr, np.array([0, 4]), tol_x=-1, tol_p=0.1)
+    with pytest.raises(ValueError):
+        _run_arr(arr, np.array([0, 4]), tol_x=0.1, tol_p=0.1, min_subset=1, merge_mode=oracle.PAIR)
+    with pytest.raises(ValueError):
+        _run_arr(arr, np.array([0, 4]), tol_x=200.0, tol_p=0.1, decide=oracle.FIXED)
+    with pytest.raises(ValueError):
+        _run_arr(arr, np.array([0, 4]), tol_x=0.1, tol_p=0.1, cell_len=(0, 1, 1))
+
+
+def test_bad_values_leave_cell_untouched():
+    good = np.random.Generator(np.random.Philox(0)).random((20, 7)) + 0.5
+    arr = good.copy(); arr[3, 6] = -1.0
+    arr2 = good.copy(); arr2[5, 4] = np.nan
+    both = np.concatenate([arr, arr2, good])
+    r = _run_arr(both, np.array([0, 20, 40, 60]), tol_x=0.1, tol_p=0.1, min_subset=2, decide=oracle.PAPER)
+    assert r.stats["flags"][0] & oracle.FLAG_BAD_VALUE
+    assert r.stats["flags"][1] & oracle.FLAG_BAD_VALUE
+    assert r.stats["flags"][2] == 0
+    assert np.all(r.subset_id[:40] == -1)
