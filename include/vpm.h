@@ -1,0 +1,157 @@
+/*
+ * vpm.h -- C ABI of the Voronoi particle-merging library for AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Luu, Tueckmantel, Pukhov, "Voronoi Particle Merging Algorithm for PIC
+ * Codes", Sec. "Algorithm", Steps 1-7): for every simulation cell holding more than
+ * N_min macroparticles, split the cell's particles recursively in 6-D phase space
+ * (x, y, z, px, py, pz).  A subset is cut by the hyperplane through its weighted centroid
+ * perpendicular to the axis whose coefficient of variation is largest (Steps 4-5; the CV is
+ * sigma/L for positions and sigma/|P| for momenta, Eqs. cv_x and cv_p), until all six CVs of
+ * every subset are within the tolerances T_X and T_P (Step 3).  Each finished subset is then
+ * replaced by merged particles (Step 7): its centroid (weight and momentum conserved), or a
+ * pair of half-weight particles at the centroid whose momenta P +- delta also conserve the
+ * subset's total energy (the two-particle merge the paper proposes in its remarks).
+ *
+ * Conventions shared by every entry point
+ *  - Particles are a structure of arrays (vpm_soa) of 7 DEVICE arrays x,y,z,px,py,pz,w of one
+ *    element type (vpm_params.dtype), sorted by cell.  Momenta are in units of m_e c.
+ *  - cell_off is a DEVICE array of n_cells+1 int64 offsets: cell c owns particles
+ *    cell_off[c] .. cell_off[c+1]-1; cell_off[0] = 0 and cell_off[n_cells] = n_particles.
+ *  - All device buffers are owned by the caller.  Entry points enqueue work on `stream` and
+ *    return without synchronising; results are valid once the stream has completed.  They
+ *    never allocate: the context's workspace is allocated by vpm_reserve only.
+ *  - A context may be used by one host thread and one stream at a time.
+ *  - Host-checkable argument errors are returned immediately and nothing is enqueued.
+ *    Data-dependent problems found on the device (bad values, offsets that decrease,
+ *    cells above 65,536 particles) set sticky flags read by vpm_device_status; the
+ *    affected cells are passed through unchanged.
+ *
+ * Decision modes (vpm_params.decide)
+ *  VPM_DECIDE_FIXED  every split decision is an exact integer function of per-cell fixed-point
+ *                    codes (weights 2^-15 of the cell's largest weight, positions 2^-16 of
+ *                    the cell length, momenta 2^-22 of the cell's largest |p| per axis, all
+ *                    taken from the FP32 values), so partitions are bit-reproducible across
+ *                    launch shapes and runs.  Tolerances are used as round(T * 2^24) / 2^24 and
+ *                    must be < 128.  Requires dtype VPM_F32.
+ *  VPM_DECIDE_FP64   the paper's statistics evaluated literally in IEEE double, one workgroup
+ *                    per cell.  Requires dtype VPM_F64.
+ */
+#ifndef VPM_H
+#define VPM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VPM_OK = 0,
+    VPM_ERR_INVALID_ARG = -1,   /* null pointer, negative size, tolerance/length out of range */
+    VPM_ERR_UNSUPPORTED = -2,   /* a dtype/decide combination this build does not implement   */
+    VPM_ERR_CAPACITY = -3,      /* more particles or cells than vpm_reserve provided for       */
+    VPM_ERR_HIP = -4,           /* a HIP runtime call failed (message: vpm_last_error)         */
+    VPM_ERR_NO_DEVICE = -5      /* no usable GPU                                               */
+} vpm_status;
+
+typedef enum { VPM_F32 = 0, VPM_F64 = 1 } vpm_dtype;
+typedef enum { VPM_DECIDE_FIXED = 0, VPM_DECIDE_FP64 = 1 } vpm_decide;
+typedef enum { VPM_MERGE_PAIR = 0, VPM_MERGE_CENTROID = 1 } vpm_merge_mode;
+
+/* Sticky device flags (vpm_device_status). */
+#define VPM_FLAG_BAD_VALUE      0x1u  /* w <= 0, NaN or Inf in a cell: that cell passed through     */
+#define VPM_FLAG_OUT_OF_CELL    0x2u  /* a particle lay more than one cell length from the cell's
+                                         lowest coordinate; its position code was clamped (FIXED)  */
+#define VPM_FLAG_CELL_TOO_LARGE 0x4u  /* a cell above 65,536 particles: passed through            */
+#define VPM_FLAG_BAD_OFFSETS    0x8u  /* cell_off decreasing or not ending at n_particles          */
+
+typedef struct {
+    double  tol_x;        /* T_X >= 0: position tolerance (Step 3)                            */
+    double  tol_p;        /* T_P >= 0: momentum tolerance (Step 3)                            */
+    int32_t n_min_cell;   /* N_min >= 0: a cell is merged only if it holds more particles     */
+    int32_t min_subset;   /* >= 1 (>= 2 for PAIR): finished subsets smaller than this are not
+                             merged; their particles are copied unchanged                     */
+    double  cell_len[3];  /* L_x, L_y, L_z > 0: the cell side lengths in Delta_X = sigma/L     */
+    double  mass;         /* particle mass in m_e units (1 for e-/e+, 0 for photons): the
+                             energy of a particle is sqrt(mass^2 + |p|^2)                     */
+    int32_t merge_mode;   /* vpm_merge_mode */
+    int32_t decide;       /* vpm_decide */
+    int32_t dtype;        /* vpm_dtype of every particle array */
+    int32_t reserved;     /* must be 0 */
+} vpm_params;
+
+typedef struct { void *x, *y, *z, *px, *py, *pz, *w; } vpm_soa;   /* device pointers */
+
+typedef struct vpm_ctx vpm_ctx;
+
+/* Create a context on HIP device `device`.  Returns VPM_ERR_NO_DEVICE if there is none. */
+vpm_status vpm_create(vpm_ctx **ctx, int device);
+
+/* Free the context and its workspace.  Waits for work the context enqueued. */
+vpm_status vpm_destroy(vpm_ctx *ctx);
+
+/* Allocate the context's device workspace for up to max_particles particles and max_cells
+ * cells per call (about 40 bytes per particle plus 32 bytes per cell).  The only call that
+ * allocates device memory.  May be called again to grow; it synchronises the device. */
+vpm_status vpm_reserve(vpm_ctx *ctx, int64_t max_particles, int64_t max_cells);
+
+/* Host-only validation of a parameter block (no device needed). */
+vpm_status vpm_check_params(const vpm_params *p);
+
+/* The fused hot path: partition every cell (Steps 1-6) and replace its finished subsets
+ * (Step 7).  Output, per cell in cell order: the cell's final subsets in depth-first order
+ * (the lower side V1 of each cut before the upper side V2); a merged subset emits 1 particle
+ * (CENTROID) or 2 (PAIR, the +delta one first); a subset below min_subset emits its particles
+ * unchanged in input order; a cell with N <= N_min, or one flagged on the device, is copied
+ * unchanged.
+ *   out        7 device arrays of the same dtype with capacity >= n_particles
+ *   out_off    device int64[n_cells+1]: exclusive prefix of the per-cell output counts
+ *   out_total  device int64 scalar: out_off[n_cells]                                         */
+vpm_status vpm_run(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, int64_t n_cells,
+                   int64_t n_particles, const vpm_params *p, vpm_soa *out, int64_t *out_off,
+                   int64_t *out_total, hipStream_t stream);
+
+/* Partition only (Steps 1-6).
+ *   perm       device int32[n_particles]: for each slot of cell c's range, the global index of
+ *              the input particle in that slot; final subsets are contiguous and in depth-first
+ *              order, members in input order; identity for cells that are not processed
+ *   subset_id  device int32[n_particles]: cell-local ordinal of the final subset of each slot,
+ *              -1 for cells that are not processed
+ *   n_subsets  device int32[n_cells]: number of final subsets per cell (0 if not processed)    */
+vpm_status vpm_partition(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off,
+                         int64_t n_cells, int64_t n_particles, const vpm_params *p,
+                         int32_t *perm, int32_t *subset_id, int32_t *n_subsets,
+                         hipStream_t stream);
+
+/* Replacement only (Step 7), from a partition in vpm_partition's format: subsets of size
+ * >= min_subset are merged, smaller ones copied.  Output as vpm_run.  In FIXED mode the
+ * pair direction uses the cell's fixed-point codes, exactly as vpm_run does.                */
+vpm_status vpm_merge(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, int64_t n_cells,
+                     int64_t n_particles, const vpm_params *p, const int32_t *perm,
+                     const int32_t *subset_id, const int32_t *n_subsets, vpm_soa *out,
+                     int64_t *out_off, int64_t *out_total, hipStream_t stream);
+
+/* Read (and, if clear != 0, reset) the sticky device flags.  Synchronises the device. */
+vpm_status vpm_device_status(vpm_ctx *ctx, uint32_t *flags_out, int clear);
+
+/* Per-kernel timing of the context's launches, for benchmarking.  When enabled, every
+ * internal kernel launch is bracketed by HIP events on the caller's stream.  vpm_profile_read
+ * synchronises, and returns up to max_kernels entries: name, number of launches and total
+ * milliseconds since the last reset.  Returns the number of kernels in *n_out.              */
+vpm_status vpm_profile_enable(vpm_ctx *ctx, int enable);
+vpm_status vpm_profile_read(vpm_ctx *ctx, int max_kernels, char names[][48], int64_t *launches,
+                            double *total_ms, int *n_out, int reset);
+
+/* Text for a status code; message of the last HIP failure in this context (or ""). */
+const char *vpm_status_string(vpm_status st);
+const char *vpm_last_error(vpm_ctx *ctx);
+
+/* Library build identification (target architecture and version). */
+const char *vpm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VPM_H */

@@ -1,0 +1,230 @@
+// Common kernels: per-call reset, cell binning, output-offset scan, compaction copy, identity
+// partition for cells that are not processed.
+#include "vpm_device.hpp"
+#include "vpm_internal.h"
+
+namespace vpm {
+namespace {
+
+constexpr int SCAN_BLOCK = 1024;
+constexpr int SCAN_PER_THREAD = 4;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_PER_THREAD;
+
+__global__ void k_reset(int32_t* counters) {
+    // queue lengths [0, 8) and work counters [8, 16)
+    if (threadIdx.x < 16) counters[threadIdx.x] = 0;
+}
+
+// Classify every cell by size and append it to its queue (wave-aggregated atomics).
+__global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_cells, int64_t n_particles,
+                                             int32_t n_min_cell, int32_t* counters, int32_t* q_untouched,
+                                             int32_t* q_a, int32_t* q_b, int32_t* q_big, int64_t* out_count,
+                                             uint8_t* cell_mode, uint32_t* flags) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int cls = -1;
+    if (c < n_cells) {
+        const int64_t lo = cell_off[c], hi = cell_off[c + 1];
+        int64_t n = hi - lo;
+        uint32_t f = 0;
+        const bool range_ok = lo >= 0 && hi >= lo && hi <= n_particles;
+        if (!range_ok) { f |= FLAG_BAD_OFFSETS; n = 0; }     // never read outside the arrays
+        if (c == 0 && lo != 0) f |= FLAG_BAD_OFFSETS;
+        if (c == n_cells - 1 && hi != n_particles) f |= FLAG_BAD_OFFSETS;
+        if (n > NMAX_BIG) f |= FLAG_TOO_LARGE;
+        if (f) atomicOr(flags, f);
+        if (n == 0 || n <= n_min_cell || n > NMAX_BIG || !range_ok) {
+            cls = Q_UNTOUCHED;
+            out_count[c] = n;
+            cell_mode[c] = CELL_UNTOUCHED;
+        } else if (n <= NMAX_A) {
+            cls = Q_A;
+        } else if (n <= NMAX_B) {
+            cls = Q_B;
+        } else {
+            cls = Q_BIG;
+        }
+    }
+    int32_t* qs[Q_COUNT] = {q_untouched, q_a, q_b, q_big};
+#pragma unroll
+    for (int q = 0; q < Q_COUNT; ++q) {
+        const uint64_t m = __ballot(cls == q);
+        if (m == 0) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(&counters[q], __popcll(m));
+        base = __shfl(base, leader);
+        if (cls == q) qs[q][base + __popcll(m & lanes_below())] = (int32_t)c;
+    }
+}
+
+// Scan phase 1: per-tile totals of out_count.
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int64_t* cnt, int64_t n, int64_t* tiles) {
+    __shared__ int64_t red[SCAN_BLOCK / WAVE + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) if (base + k < n) s += cnt[base + k];
+    int64_t tot;
+    block_exclusive_scan<SCAN_BLOCK>(s, red, &tot);
+    if (threadIdx.x == 0) tiles[blockIdx.x] = tot;
+}
+
+// Scan phase 2: exclusive scan of the tile totals (single workgroup, loops over chunks).
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tile_totals(int64_t* tiles, int64_t ntiles, int64_t* out_total) {
+    __shared__ int64_t red[SCAN_BLOCK / WAVE + 1];
+    int64_t carry = 0;
+    for (int64_t b = 0; b < ntiles; b += SCAN_BLOCK) {
+        const int64_t i = b + threadIdx.x;
+        const int64_t v = i < ntiles ? tiles[i] : 0;
+        int64_t tot;
+        const int64_t pre = block_exclusive_scan<SCAN_BLOCK>(v, red, &tot);
+        if (i < ntiles) tiles[i] = carry + pre;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out_total = carry;
+}
+
+// Scan phase 3: write the exclusive prefix (out_off) and out_off[n].
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int64_t* cnt, int64_t n, const int64_t* tiles,
+                                                           int64_t* out_off, const int64_t* out_total) {
+    __shared__ int64_t red[SCAN_BLOCK / WAVE + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+    int64_t v[SCAN_PER_THREAD];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) { v[k] = base + k < n ? cnt[base + k] : 0; s += v[k]; }
+    int64_t tot;
+    int64_t pre = block_exclusive_scan<SCAN_BLOCK>(s, red, &tot) + tiles[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+        if (base + k < n) out_off[base + k] = pre;
+        pre += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out_off[n] = *out_total;
+}
+
+// Compaction: every output slot o finds its cell by binary search in out_off, then copies from the
+// cell's temporary output (processed cells) or from the input (untouched cells).
+template <typename T>
+struct Tables { const T* tmp[7]; const T* in[7]; T* out[7]; };
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter(const int64_t* cell_off, int64_t n_cells, const int64_t* out_off,
+                                                 const uint8_t* cell_mode, Tables<T> tb) {
+    const int64_t total = out_off[n_cells];
+    const int64_t per_block = (int64_t)blockDim.x * 4;
+    const int64_t o0 = (int64_t)blockIdx.x * per_block;
+    if (o0 >= total) return;
+    __shared__ int64_t s_lo, s_hi;
+    if (threadIdx.x == 0) {
+        // cells holding the block's first and last output slots
+        auto find = [&](int64_t o) {
+            int64_t lo = 0, hi = n_cells - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (out_off[mid] <= o) lo = mid; else hi = mid - 1;
+            }
+            return lo;
+        };
+        s_lo = find(o0);
+        s_hi = find(min(total, o0 + per_block) - 1);
+    }
+    __syncthreads();
+    const int64_t clo = s_lo, chi = s_hi;
+    for (int k = 0; k < 4; ++k) {
+        const int64_t o = o0 + (int64_t)k * blockDim.x + threadIdx.x;
+        if (o >= total) break;
+        int64_t lo = clo, hi = chi;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (out_off[mid] <= o) lo = mid; else hi = mid - 1;
+        }
+        const int64_t c = lo;
+        const int64_t src = cell_off[c] + (o - out_off[c]);
+        if (cell_mode[c] == CELL_UNTOUCHED) {
+#pragma unroll
+            for (int f = 0; f < 7; ++f) tb.out[f][o] = tb.in[f][src];
+        } else {
+#pragma unroll
+            for (int f = 0; f < 7; ++f) tb.out[f][o] = tb.tmp[f][src];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_identity(const int64_t* cell_off, int64_t n_particles, const int32_t* queue,
+                                                  const int32_t* counters, int qidx, int32_t* perm, int32_t* subset_id,
+                                                  int32_t* n_subsets) {
+    const int nq = counters[qidx];
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int c = queue[q];
+        int64_t lo = cell_off[c], hi = cell_off[c + 1];
+        if (lo < 0 || hi < lo || hi > n_particles) hi = lo;           // invalid range: write nothing
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) { perm[i] = (int32_t)i; subset_id[i] = -1; }
+        if (threadIdx.x == 0) n_subsets[c] = 0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off, int64_t n_cells,
+                      int64_t n_particles, int32_t n_min_cell) {
+    if (lc.pre) lc.pre(lc.prof, "reset", lc.stream);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, lc.stream, ws.counters);
+    if (lc.post) lc.post(lc.prof, "reset", lc.stream);
+    if (n_cells == 0) return hipGetLastError();
+    if (lc.pre) lc.pre(lc.prof, "bin", lc.stream);
+    const int64_t blocks = (n_cells + 255) / 256;
+    hipLaunchKernelGGL(k_bin, dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells, n_particles,
+                       n_min_cell, ws.counters, ws.queue[Q_UNTOUCHED], ws.queue[Q_A], ws.queue[Q_B],
+                       ws.queue[Q_BIG], ws.out_count, ws.cell_mode, ws.flags);
+    if (lc.post) lc.post(lc.prof, "bin", lc.stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_offsets(const Workspace& ws, const LaunchCfg& lc, int64_t n_cells, int64_t* out_off,
+                               int64_t* out_total) {
+    const int64_t ntiles = (n_cells + SCAN_TILE - 1) / SCAN_TILE;
+    if (lc.pre) lc.pre(lc.prof, "scan", lc.stream);
+    if (ntiles > 0)
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(SCAN_BLOCK), 0, lc.stream, ws.out_count,
+                           n_cells, ws.scan_blocks);
+    hipLaunchKernelGGL(k_scan_tile_totals, dim3(1), dim3(SCAN_BLOCK), 0, lc.stream, ws.scan_blocks, ntiles,
+                       out_total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)(ntiles > 0 ? ntiles : 1)), dim3(SCAN_BLOCK), 0, lc.stream,
+                       ws.out_count, n_cells, ws.scan_blocks, out_off, out_total);
+    if (lc.post) lc.post(lc.prof, "scan", lc.stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off, int64_t n_cells,
+                          int64_t n_particles, const int64_t* out_off, const void* const in[7], void* const out[7],
+                          int elem_size) {
+    if (n_cells == 0 || n_particles == 0) return hipSuccess;
+    const int64_t blocks = (n_particles + 1023) / 1024;     // out_total <= n_particles
+    if (lc.pre) lc.pre(lc.prof, "scatter", lc.stream);
+    if (elem_size == 4) {
+        Tables<float> tb;
+        for (int f = 0; f < 7; ++f) { tb.tmp[f] = (const float*)ws.tmp[f]; tb.in[f] = (const float*)in[f]; tb.out[f] = (float*)out[f]; }
+        hipLaunchKernelGGL(k_scatter<float>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells,
+                           out_off, ws.cell_mode, tb);
+    } else {
+        Tables<double> tb;
+        for (int f = 0; f < 7; ++f) { tb.tmp[f] = (const double*)ws.tmp[f]; tb.in[f] = (const double*)in[f]; tb.out[f] = (double*)out[f]; }
+        hipLaunchKernelGGL(k_scatter<double>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells,
+                           out_off, ws.cell_mode, tb);
+    }
+    if (lc.post) lc.post(lc.prof, "scatter", lc.stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off, int64_t n_particles,
+                           int32_t* perm, int32_t* subset_id, int32_t* n_subsets) {
+    if (lc.pre) lc.pre(lc.prof, "identity", lc.stream);
+    hipLaunchKernelGGL(k_identity, dim3(1024), dim3(256), 0, lc.stream, cell_off, n_particles, ws.queue[Q_UNTOUCHED],
+                       ws.counters, (int)Q_UNTOUCHED, perm, subset_id, n_subsets);
+    if (lc.post) lc.post(lc.prof, "identity", lc.stream);
+    return hipGetLastError();
+}
+
+}  // namespace vpm

@@ -1,0 +1,396 @@
+// Host side of the C ABI (include/vpm.h): argument validation, the context and its workspace,
+// and stream-ordered enqueue of the kernels.  Nothing here synchronises except vpm_reserve,
+// vpm_destroy, vpm_device_status and vpm_profile_read.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vpm_internal.h"
+
+using namespace vpm;
+
+namespace vpm {
+int64_t fixed_big_slab_bytes();
+}
+
+struct vpm_ctx {
+    int device = 0;
+    int cu_count = 0;
+    Workspace ws;
+    int grid_a = 0, grid_b = 0, grid_big = 0, grid_fp64 = 0;
+    std::string last_error;
+    // profiling
+    bool profiling = false;
+    struct Rec { int kernel; hipEvent_t a, b; };
+    std::vector<std::string> knames;
+    std::vector<int64_t> klaunch;
+    std::vector<double> kms;
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    int open_kernel = -1;
+    hipEvent_t open_event = nullptr;
+};
+
+namespace {
+
+vpm_status hip_fail(vpm_ctx* ctx, hipError_t e, const char* what) {
+    if (ctx) {
+        ctx->last_error = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return VPM_ERR_HIP;
+}
+
+hipEvent_t take_event(vpm_ctx* c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void prof_pre(void* p, const char* name, hipStream_t s) {
+    vpm_ctx* c = (vpm_ctx*)p;
+    int k = -1;
+    for (size_t i = 0; i < c->knames.size(); ++i)
+        if (c->knames[i] == name) k = (int)i;
+    if (k < 0) {
+        c->knames.push_back(name);
+        c->klaunch.push_back(0);
+        c->kms.push_back(0.0);
+        k = (int)c->knames.size() - 1;
+    }
+    hipEvent_t e = take_event(c);
+    if (e) hipEventRecord(e, s);
+    c->open_kernel = k;
+    c->open_event = e;
+}
+
+void prof_post(void* p, const char* name, hipStream_t s) {
+    (void)name;
+    vpm_ctx* c = (vpm_ctx*)p;
+    hipEvent_t e = take_event(c);
+    if (e && c->open_event) {
+        hipEventRecord(e, s);
+        c->pending.push_back({c->open_kernel, c->open_event, e});
+    }
+    c->open_event = nullptr;
+}
+
+LaunchCfg make_cfg(vpm_ctx* c, hipStream_t s) {
+    LaunchCfg lc;
+    lc.stream = s;
+    lc.grid_a = c->grid_a;
+    lc.grid_b = c->grid_b;
+    lc.grid_big = c->grid_big;
+    lc.grid_fp64 = c->grid_fp64;
+    lc.pre = c->profiling ? prof_pre : nullptr;
+    lc.post = c->profiling ? prof_post : nullptr;
+    lc.prof = c;
+    return lc;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+void free_ws(Workspace& ws) {
+    for (int f = 0; f < 7; ++f) if (ws.tmp[f]) hipFree(ws.tmp[f]);
+    if (ws.out_count) hipFree(ws.out_count);
+    if (ws.cell_mode) hipFree(ws.cell_mode);
+    for (int q = 0; q < Q_COUNT; ++q) if (ws.queue[q]) hipFree(ws.queue[q]);
+    if (ws.counters) hipFree(ws.counters);
+    if (ws.flags) hipFree(ws.flags);
+    if (ws.scan_blocks) hipFree(ws.scan_blocks);
+    if (ws.big) hipFree(ws.big);
+    if (ws.perm2) hipFree(ws.perm2);
+    if (ws.stack) hipFree(ws.stack);
+    ws = Workspace();
+}
+
+vpm_status check_soa(const vpm_soa* s) {
+    if (!s || !s->x || !s->y || !s->z || !s->px || !s->py || !s->pz || !s->w) return VPM_ERR_INVALID_ARG;
+    return VPM_OK;
+}
+
+vpm_status common_checks(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int64_t n_cells,
+                         int64_t n_particles, const vpm_params* p) {
+    if (!ctx || !cell_off || n_cells < 0 || n_particles < 0) return VPM_ERR_INVALID_ARG;
+    vpm_status st = vpm_check_params(p);
+    if (st != VPM_OK) return st;
+    if (check_soa(in) != VPM_OK) return VPM_ERR_INVALID_ARG;
+    if (!((p->decide == VPM_DECIDE_FIXED && p->dtype == VPM_F32) ||
+          (p->decide == VPM_DECIDE_FP64 && p->dtype == VPM_F64)))
+        return VPM_ERR_UNSUPPORTED;
+    if (n_particles > ctx->ws.cap_particles || n_cells > ctx->ws.cap_cells) return VPM_ERR_CAPACITY;
+    if (n_particles >= (int64_t)1 << 31) return VPM_ERR_CAPACITY;   // int32 permutation indices
+    return VPM_OK;
+}
+
+FixedParams fixed_params(const vpm_params* p) {
+    FixedParams f;
+    f.that_x = (uint64_t)llrint(p->tol_x * 16777216.0);
+    f.that_p = (uint64_t)llrint(p->tol_p * 16777216.0);
+    for (int a = 0; a < 3; ++a) f.s[a] = (float)(65536.0 / p->cell_len[a]);
+    f.min_subset = p->min_subset;
+    f.merge_mode = p->merge_mode;
+    f.mass = p->mass;
+    return f;
+}
+
+Fp64Params fp64_params(const vpm_params* p) {
+    Fp64Params f;
+    f.tol_x = p->tol_x;
+    f.tol_p = p->tol_p;
+    for (int a = 0; a < 3; ++a) f.L[a] = p->cell_len[a];
+    f.mass = p->mass;
+    f.min_subset = p->min_subset;
+    f.merge_mode = p->merge_mode;
+    f.n_min_cell = p->n_min_cell;
+    return f;
+}
+
+Soa32 soa32(const vpm_soa* s) {
+    return Soa32{(const float*)s->x, (const float*)s->y, (const float*)s->z, (const float*)s->px,
+                 (const float*)s->py, (const float*)s->pz, (const float*)s->w};
+}
+Soa64 soa64(const vpm_soa* s) {
+    return Soa64{(const double*)s->x, (const double*)s->y, (const double*)s->z, (const double*)s->px,
+                 (const double*)s->py, (const double*)s->pz, (const double*)s->w};
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vpm_version(void) { return "vpm 0.1 gfx950"; }
+
+const char* vpm_status_string(vpm_status st) {
+    switch (st) {
+        case VPM_OK: return "ok";
+        case VPM_ERR_INVALID_ARG: return "invalid argument";
+        case VPM_ERR_UNSUPPORTED: return "unsupported dtype/decision combination";
+        case VPM_ERR_CAPACITY: return "workspace capacity exceeded (call vpm_reserve)";
+        case VPM_ERR_HIP: return "HIP runtime error";
+        case VPM_ERR_NO_DEVICE: return "no GPU device";
+    }
+    return "unknown status";
+}
+
+const char* vpm_last_error(vpm_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+vpm_status vpm_check_params(const vpm_params* p) {
+    if (!p) return VPM_ERR_INVALID_ARG;
+    if (!(std::isfinite(p->tol_x) && p->tol_x >= 0.0) || !(std::isfinite(p->tol_p) && p->tol_p >= 0.0))
+        return VPM_ERR_INVALID_ARG;
+    if (p->decide != VPM_DECIDE_FIXED && p->decide != VPM_DECIDE_FP64) return VPM_ERR_INVALID_ARG;
+    if (p->decide == VPM_DECIDE_FIXED && (p->tol_x >= 128.0 || p->tol_p >= 128.0)) return VPM_ERR_INVALID_ARG;
+    if (p->n_min_cell < 0) return VPM_ERR_INVALID_ARG;
+    if (p->min_subset < 1 || p->min_subset > NMAX_BIG) return VPM_ERR_INVALID_ARG;
+    if (p->merge_mode != VPM_MERGE_PAIR && p->merge_mode != VPM_MERGE_CENTROID) return VPM_ERR_INVALID_ARG;
+    if (p->merge_mode == VPM_MERGE_PAIR && p->min_subset < 2) return VPM_ERR_INVALID_ARG;
+    for (int a = 0; a < 3; ++a) if (!finite_pos(p->cell_len[a])) return VPM_ERR_INVALID_ARG;
+    if (!(std::isfinite(p->mass) && p->mass >= 0.0)) return VPM_ERR_INVALID_ARG;
+    if (p->dtype != VPM_F32 && p->dtype != VPM_F64) return VPM_ERR_INVALID_ARG;
+    if (p->reserved != 0) return VPM_ERR_INVALID_ARG;
+    return VPM_OK;
+}
+
+vpm_status vpm_create(vpm_ctx** out, int device) {
+    if (!out) return VPM_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return VPM_ERR_NO_DEVICE;
+    if (device < 0 || device >= n) return VPM_ERR_INVALID_ARG;
+    vpm_ctx* c = new vpm_ctx();
+    c->device = device;
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) { delete c; return VPM_ERR_HIP; }
+    hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device);
+    if (c->cu_count <= 0) c->cu_count = 256;
+    int nb = 0;
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(0), 256, fixed_lds_bytes(NMAX_A));
+    c->grid_a = c->cu_count * (nb > 0 ? nb : 1);
+    nb = 0;
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(1), 256, fixed_lds_bytes(NMAX_B));
+    c->grid_b = c->cu_count * (nb > 0 ? nb : 1);
+    c->grid_big = c->cu_count;
+    c->grid_fp64 = c->cu_count * 16;
+    *out = c;
+    return VPM_OK;
+}
+
+vpm_status vpm_destroy(vpm_ctx* ctx) {
+    if (!ctx) return VPM_ERR_INVALID_ARG;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    free_ws(ctx->ws);
+    for (auto& r : ctx->pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+    for (auto e : ctx->pool) hipEventDestroy(e);
+    delete ctx;
+    return VPM_OK;
+}
+
+vpm_status vpm_reserve(vpm_ctx* ctx, int64_t max_particles, int64_t max_cells) {
+    if (!ctx || max_particles < 0 || max_cells < 0) return VPM_ERR_INVALID_ARG;
+    if (max_particles <= ctx->ws.cap_particles && max_cells <= ctx->ws.cap_cells && ctx->ws.counters)
+        return VPM_OK;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    const int64_t np = std::max<int64_t>(max_particles, ctx->ws.cap_particles) + 1;
+    const int64_t nc = std::max<int64_t>(max_cells, ctx->ws.cap_cells) + 1;
+    free_ws(ctx->ws);
+    Workspace& ws = ctx->ws;
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (e != hipSuccess) return;
+        e = hipMalloc(p, bytes ? bytes : 16);
+    };
+    for (int f = 0; f < 7; ++f) alloc(&ws.tmp[f], (size_t)np * 8);
+    alloc((void**)&ws.out_count, (size_t)nc * 8);
+    alloc((void**)&ws.cell_mode, (size_t)nc);
+    for (int q = 0; q < Q_COUNT; ++q) alloc((void**)&ws.queue[q], (size_t)nc * 4);
+    alloc((void**)&ws.counters, 4096);
+    alloc((void**)&ws.flags, 256);
+    alloc((void**)&ws.scan_blocks, (size_t)(nc / 4096 + 2) * 8);
+    ws.big_bytes = fixed_big_slab_bytes() * ctx->grid_big;
+    alloc((void**)&ws.big, (size_t)ws.big_bytes);
+    alloc((void**)&ws.perm2, (size_t)np * 2 * 4);
+    alloc((void**)&ws.stack, (size_t)np * 8);
+    if (e == hipSuccess) e = hipMemset(ws.counters, 0, 4096);
+    if (e == hipSuccess) e = hipMemset(ws.flags, 0, 256);
+    if (e != hipSuccess) {
+        free_ws(ws);
+        return hip_fail(ctx, e, "vpm_reserve");
+    }
+    ws.cap_particles = np - 1;
+    ws.cap_cells = nc - 1;
+    return VPM_OK;
+}
+
+vpm_status vpm_run(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int64_t n_cells,
+                   int64_t n_particles, const vpm_params* p, vpm_soa* out, int64_t* out_off,
+                   int64_t* out_total, hipStream_t stream) {
+    vpm_status st = common_checks(ctx, in, cell_off, n_cells, n_particles, p);
+    if (st != VPM_OK) return st;
+    if (check_soa(out) != VPM_OK || !out_off || !out_total) return VPM_ERR_INVALID_ARG;
+    hipSetDevice(ctx->device);
+    LaunchCfg lc = make_cfg(ctx, stream);
+    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell);
+    if (e != hipSuccess) return hip_fail(ctx, e, "bin");
+    if (p->decide == VPM_DECIDE_FIXED)
+        e = launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fixed_params(p), 0, nullptr, nullptr, nullptr);
+    else
+        e = launch_fp64_cells(ctx->ws, lc, soa64(in), cell_off, n_cells, fp64_params(p), 0, nullptr, nullptr, nullptr);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cells");
+    e = launch_scan_offsets(ctx->ws, lc, n_cells, out_off, out_total);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scan");
+    const void* ins[7] = {in->x, in->y, in->z, in->px, in->py, in->pz, in->w};
+    void* outs[7] = {out->x, out->y, out->z, out->px, out->py, out->pz, out->w};
+    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs,
+                       p->dtype == VPM_F32 ? 4 : 8);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scatter");
+    return VPM_OK;
+}
+
+vpm_status vpm_partition(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int64_t n_cells,
+                         int64_t n_particles, const vpm_params* p, int32_t* perm, int32_t* subset_id,
+                         int32_t* n_subsets, hipStream_t stream) {
+    vpm_status st = common_checks(ctx, in, cell_off, n_cells, n_particles, p);
+    if (st != VPM_OK) return st;
+    if (!perm || !subset_id || !n_subsets) return VPM_ERR_INVALID_ARG;
+    hipSetDevice(ctx->device);
+    LaunchCfg lc = make_cfg(ctx, stream);
+    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell);
+    if (e != hipSuccess) return hip_fail(ctx, e, "bin");
+    if (p->decide == VPM_DECIDE_FIXED)
+        e = launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fixed_params(p), 1, perm, subset_id, n_subsets);
+    else
+        e = launch_fp64_cells(ctx->ws, lc, soa64(in), cell_off, n_cells, fp64_params(p), 1, perm, subset_id,
+                              n_subsets);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cells");
+    e = launch_identity(ctx->ws, lc, cell_off, n_particles, perm, subset_id, n_subsets);
+    if (e != hipSuccess) return hip_fail(ctx, e, "identity");
+    return VPM_OK;
+}
+
+vpm_status vpm_merge(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int64_t n_cells,
+                     int64_t n_particles, const vpm_params* p, const int32_t* perm, const int32_t* subset_id,
+                     const int32_t* n_subsets, vpm_soa* out, int64_t* out_off, int64_t* out_total,
+                     hipStream_t stream) {
+    vpm_status st = common_checks(ctx, in, cell_off, n_cells, n_particles, p);
+    if (st != VPM_OK) return st;
+    if (!perm || !subset_id || !n_subsets || check_soa(out) != VPM_OK || !out_off || !out_total)
+        return VPM_ERR_INVALID_ARG;
+    hipSetDevice(ctx->device);
+    LaunchCfg lc = make_cfg(ctx, stream);
+    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell);
+    if (e != hipSuccess) return hip_fail(ctx, e, "bin");
+    if (p->decide == VPM_DECIDE_FIXED)
+        e = launch_fixed_merge(ctx->ws, lc, soa32(in), cell_off, n_cells, p->n_min_cell, fixed_params(p), perm,
+                               subset_id, n_subsets);
+    else
+        e = launch_fp64_merge(ctx->ws, lc, soa64(in), cell_off, n_cells, fp64_params(p), perm, subset_id,
+                              n_subsets);
+    if (e != hipSuccess) return hip_fail(ctx, e, "merge");
+    e = launch_scan_offsets(ctx->ws, lc, n_cells, out_off, out_total);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scan");
+    const void* ins[7] = {in->x, in->y, in->z, in->px, in->py, in->pz, in->w};
+    void* outs[7] = {out->x, out->y, out->z, out->px, out->py, out->pz, out->w};
+    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs,
+                       p->dtype == VPM_F32 ? 4 : 8);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scatter");
+    return VPM_OK;
+}
+
+vpm_status vpm_device_status(vpm_ctx* ctx, uint32_t* flags_out, int clear) {
+    if (!ctx || !flags_out) return VPM_ERR_INVALID_ARG;
+    if (!ctx->ws.flags) { *flags_out = 0; return VPM_OK; }
+    hipSetDevice(ctx->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(flags_out, ctx->ws.flags, 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && clear) e = hipMemset(ctx->ws.flags, 0, 4);
+    if (e != hipSuccess) return hip_fail(ctx, e, "vpm_device_status");
+    return VPM_OK;
+}
+
+vpm_status vpm_profile_enable(vpm_ctx* ctx, int enable) {
+    if (!ctx) return VPM_ERR_INVALID_ARG;
+    ctx->profiling = enable != 0;
+    return VPM_OK;
+}
+
+vpm_status vpm_profile_read(vpm_ctx* ctx, int max_kernels, char names[][48], int64_t* launches,
+                            double* total_ms, int* n_out, int reset) {
+    if (!ctx || !n_out || max_kernels < 0) return VPM_ERR_INVALID_ARG;
+    hipSetDevice(ctx->device);
+    for (auto& r : ctx->pending) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(ctx, e, "vpm_profile_read");
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.a, r.b);
+        ctx->kms[r.kernel] += ms;
+        ctx->klaunch[r.kernel] += 1;
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->pending.clear();
+    const int n = (int)ctx->knames.size();
+    *n_out = n;
+    for (int i = 0; i < n && i < max_kernels; ++i) {
+        if (names) { std::strncpy(names[i], ctx->knames[i].c_str(), 47); names[i][47] = 0; }
+        if (launches) launches[i] = ctx->klaunch[i];
+        if (total_ms) total_ms[i] = ctx->kms[i];
+    }
+    if (reset) {
+        for (auto& v : ctx->klaunch) v = 0;
+        for (auto& v : ctx->kms) v = 0.0;
+    }
+    return VPM_OK;
+}
+
+}  // extern "C"

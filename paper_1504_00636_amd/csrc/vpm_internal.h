@@ -1,0 +1,105 @@
+// Internal declarations shared by the host library and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vpm.h"
+
+namespace vpm {
+
+// Per-cell handling decided by the binning kernel.
+enum CellMode : uint8_t { CELL_PROCESSED = 0, CELL_UNTOUCHED = 1 };
+
+// Size bins of the fixed-point path.
+constexpr int NMAX_A = 1024;    // workgroup per cell, everything in LDS
+constexpr int NMAX_B = 4096;    // workgroup per cell, everything in LDS (one workgroup per CU)
+constexpr int NMAX_BIG = 65536; // workgroup per cell, working set in global scratch
+enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_BIG = 3, Q_COUNT = 4 };
+
+// Status bits (mirrors VPM_FLAG_* plus one internal bit).
+constexpr uint32_t FLAG_BAD_VALUE = VPM_FLAG_BAD_VALUE;
+constexpr uint32_t FLAG_OUT_OF_CELL = VPM_FLAG_OUT_OF_CELL;
+constexpr uint32_t FLAG_TOO_LARGE = VPM_FLAG_CELL_TOO_LARGE;
+constexpr uint32_t FLAG_BAD_OFFSETS = VPM_FLAG_BAD_OFFSETS;
+constexpr uint32_t FLAG_INTERNAL = 0x80000000u;  // a cut left one side empty (never expected)
+
+// Device workspace, allocated by vpm_reserve.
+struct Workspace {
+    int64_t cap_particles = 0, cap_cells = 0;
+    void* tmp[7] = {};              // temporary per-cell outputs at the cell's input offset (8 B/elt)
+    int64_t* out_count = nullptr;   // [cap_cells]
+    uint8_t* cell_mode = nullptr;   // [cap_cells]
+    int32_t* queue[Q_COUNT] = {};   // [cap_cells] each
+    int32_t* counters = nullptr;    // [64]: queue lengths, work counters
+    uint32_t* flags = nullptr;      // sticky status
+    int64_t* scan_blocks = nullptr; // block totals for the offset scan
+    // global-memory working set of the big-cell path, indexed by input position
+    uint8_t* big = nullptr;
+    int64_t big_bytes = 0;
+    // scratch for the FP64 path: two permutation buffers and a node stack per particle slot
+    int32_t* perm2 = nullptr;       // [2 * cap_particles]
+    int64_t* stack = nullptr;       // [cap_particles]
+};
+
+// Fixed-point decision parameters derived on the host from vpm_params.
+struct FixedParams {
+    uint64_t that_x, that_p;        // round(T * 2^24)
+    float s[3];                     // fl32(65536 / L_a)
+    int32_t min_subset;
+    int32_t merge_mode;
+    double mass;
+};
+
+struct LaunchCfg {
+    hipStream_t stream;
+    int grid_a, grid_b, grid_big, grid_fp64;   // persistent grid sizes
+    // profiling hooks (may be null)
+    void (*pre)(void* prof, const char* name, hipStream_t s);
+    void (*post)(void* prof, const char* name, hipStream_t s);
+    void* prof;
+};
+
+struct Soa32 { const float *x, *y, *z, *px, *py, *pz, *w; };
+struct Soa32Out { float *x, *y, *z, *px, *py, *pz, *w; };
+struct Soa64 { const double *x, *y, *z, *px, *py, *pz, *w; };
+struct Soa64Out { double *x, *y, *z, *px, *py, *pz, *w; };
+
+// ---- launchers (vpm_common.hip) ----
+hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,
+                      int64_t n_cells, int64_t n_particles, int32_t n_min_cell);
+hipError_t launch_scan_offsets(const Workspace& ws, const LaunchCfg& lc, int64_t n_cells,
+                               int64_t* out_off, int64_t* out_total);
+hipError_t launch_scatter(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,
+                          int64_t n_cells, int64_t n_particles, const int64_t* out_off,
+                          const void* const in[7], void* const out[7], int elem_size);
+hipError_t launch_identity(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,
+                           int64_t n_particles, int32_t* perm, int32_t* subset_id,
+                           int32_t* n_subsets);
+
+// ---- fixed-point path (vpm_fixed.hip) ----
+// mode 0: run (partition + merge into ws.tmp), mode 1: partition only
+hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
+                              const int64_t* cell_off, const FixedParams& fp, int mode,
+                              int32_t* perm, int32_t* subset_id, int32_t* n_subsets);
+hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
+                              const int64_t* cell_off, int64_t n_cells, int32_t n_min_cell,
+                              const FixedParams& fp, const int32_t* perm,
+                              const int32_t* subset_id, const int32_t* n_subsets);
+int fixed_lds_bytes(int nmax);
+const void* fixed_kernel_ptr(int which);   // for occupancy queries: 0 = A, 1 = B, 2 = big
+
+// ---- plain FP64 path (vpm_fp64.hip) ----
+struct Fp64Params {
+    double tol_x, tol_p, L[3], mass;
+    int32_t min_subset, merge_mode, n_min_cell;
+};
+hipError_t launch_fp64_cells(const Workspace& ws, const LaunchCfg& lc, const Soa64& in,
+                             const int64_t* cell_off, int64_t n_cells, const Fp64Params& fp,
+                             int mode, int32_t* perm, int32_t* subset_id, int32_t* n_subsets);
+hipError_t launch_fp64_merge(const Workspace& ws, const LaunchCfg& lc, const Soa64& in,
+                             const int64_t* cell_off, int64_t n_cells, const Fp64Params& fp,
+                             const int32_t* perm, const int32_t* subset_id,
+                             const int32_t* n_subsets);
+
+}  // namespace vpm

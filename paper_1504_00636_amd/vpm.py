@@ -1,0 +1,299 @@
+"""Python binding of libvpm.so (include/vpm.h): argument marshalling only.
+
+Every entry point keeps its C name (vpm_create, vpm_reserve, vpm_run, vpm_partition, vpm_merge,
+vpm_check_params, vpm_device_status, ...).  Tensors are passed as raw device pointers; the stream is
+torch's current HIP stream unless one is given.  All computation happens in the HIP library; if the
+library is missing this module raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvpm.so")
+
+VPM_OK, VPM_ERR_INVALID_ARG, VPM_ERR_UNSUPPORTED, VPM_ERR_CAPACITY, VPM_ERR_HIP, VPM_ERR_NO_DEVICE = \
+    0, -1, -2, -3, -4, -5
+VPM_F32, VPM_F64 = 0, 1
+VPM_DECIDE_FIXED, VPM_DECIDE_FP64 = 0, 1
+VPM_MERGE_PAIR, VPM_MERGE_CENTROID = 0, 1
+VPM_FLAG_BAD_VALUE, VPM_FLAG_OUT_OF_CELL, VPM_FLAG_CELL_TOO_LARGE, VPM_FLAG_BAD_OFFSETS = 1, 2, 4, 8
+
+EXPORTS = ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_partition",
+           "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read",
+           "vpm_status_string", "vpm_last_error", "vpm_version")
+
+
+class VpmParams(C.Structure):
+    _fields_ = [("tol_x", C.c_double), ("tol_p", C.c_double),
+                ("n_min_cell", C.c_int32), ("min_subset", C.c_int32),
+                ("cell_len", C.c_double * 3), ("mass", C.c_double),
+                ("merge_mode", C.c_int32), ("decide", C.c_int32),
+                ("dtype", C.c_int32), ("reserved", C.c_int32)]
+
+
+class VpmSoa(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in ("x", "y", "z", "px", "py", "pz", "w")]
+
+
+class VpmError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status}){' - ' + detail if detail else ''}")
+
+
+_lib = None
+
+
+def lib():
+    """Load libvpm.so (built by paper_1504_00636_amd.build.build()); raise if it is not there."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1504_00636_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    P = C.POINTER
+    L.vpm_create.argtypes = [P(vp), C.c_int]
+    L.vpm_destroy.argtypes = [vp]
+    L.vpm_reserve.argtypes = [vp, i64, i64]
+    L.vpm_check_params.argtypes = [P(VpmParams)]
+    L.vpm_run.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), P(VpmSoa), vp, vp, vp]
+    L.vpm_partition.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, vp]
+    L.vpm_merge.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, P(VpmSoa), vp, vp, vp, vp]
+    L.vpm_device_status.argtypes = [vp, P(C.c_uint32), C.c_int]
+    L.vpm_profile_enable.argtypes = [vp, C.c_int]
+    L.vpm_profile_read.argtypes = [vp, C.c_int, vp, P(C.c_int64), P(C.c_double), P(C.c_int), C.c_int]
+    L.vpm_status_string.argtypes = [C.c_int]
+    L.vpm_status_string.restype = C.c_char_p
+    L.vpm_last_error.argtypes = [vp]
+    L.vpm_last_error.restype = C.c_char_p
+    L.vpm_version.restype = C.c_char_p
+    for f in ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_partition",
+              "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read"):
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def status_string(st: int) -> str:
+    return lib().vpm_status_string(int(st)).decode()
+
+
+def vpm_version() -> str:
+    return lib().vpm_version().decode()
+
+
+def make_params(tol_x, tol_p, n_min_cell=0, min_subset=4, cell_len=(1.0, 1.0, 1.0), mass=1.0,
+                merge_mode=VPM_MERGE_PAIR, decide=VPM_DECIDE_FIXED, dtype=None) -> VpmParams:
+    p = VpmParams()
+    p.tol_x, p.tol_p = float(tol_x), float(tol_p)
+    p.n_min_cell, p.min_subset = int(n_min_cell), int(min_subset)
+    for a in range(3):
+        p.cell_len[a] = float(cell_len[a])
+    p.mass = float(mass)
+    p.merge_mode, p.decide = int(merge_mode), int(decide)
+    if dtype is None:
+        dtype = VPM_F32 if decide == VPM_DECIDE_FIXED else VPM_F64
+    p.dtype = int(dtype)
+    p.reserved = 0
+    return p
+
+
+def vpm_check_params(p: VpmParams) -> int:
+    """Host-only parameter validation; returns the status code."""
+    return int(lib().vpm_check_params(C.byref(p)))
+
+
+# ------------------------------------------------------------------------------------------
+# tensor marshalling
+# ------------------------------------------------------------------------------------------
+
+def _soa(arrs: Sequence, dtype, n_min: int, what: str) -> VpmSoa:
+    import torch
+    if len(arrs) != 7:
+        raise ValueError(f"{what}: need 7 arrays (x, y, z, px, py, pz, w)")
+    s = VpmSoa()
+    for f, t in zip(("x", "y", "z", "px", "py", "pz", "w"), arrs):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{what}.{f}: expected a device tensor")
+        if t.dtype != dtype or not t.is_contiguous() or t.numel() < n_min:
+            raise ValueError(f"{what}.{f}: expected contiguous {dtype} with >= {n_min} elements")
+        setattr(s, f, t.data_ptr())
+    return s
+
+
+def _dev(t, dtype, n: int, what: str) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous() \
+            or t.numel() < n:
+        raise ValueError(f"{what}: expected a contiguous device {dtype} tensor with >= {n} elements")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(getattr(stream, "cuda_stream", stream) or 0)
+
+
+def _torch_dtype(p: VpmParams):
+    import torch
+    return torch.float32 if p.dtype == VPM_F32 else torch.float64
+
+
+class Context:
+    """Owns a vpm_ctx (one device, one stream at a time) and its workspace."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        st = lib().vpm_create(C.byref(h), int(device))
+        if st != VPM_OK:
+            raise VpmError(st, "vpm_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vpm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str):
+        if st != VPM_OK:
+            detail = lib().vpm_last_error(self.h).decode() if st == VPM_ERR_HIP else ""
+            raise VpmError(st, what, detail)
+
+    def reserve(self, max_particles: int, max_cells: int):
+        self._check(lib().vpm_reserve(self.h, int(max_particles), int(max_cells)), "vpm_reserve")
+
+    def run(self, inp, cell_off, n_particles: int, p: VpmParams, out, out_off, out_total, stream=None):
+        import torch
+        n_cells = cell_off.numel() - 1
+        dt = _torch_dtype(p)
+        si = _soa(inp, dt, n_particles, "in")
+        so = _soa(out, dt, n_particles, "out")
+        st = lib().vpm_run(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"), n_cells,
+                           int(n_particles), C.byref(p), C.byref(so),
+                           _dev(out_off, torch.int64, n_cells + 1, "out_off"),
+                           _dev(out_total, torch.int64, 1, "out_total"), _stream(stream))
+        self._check(st, "vpm_run")
+
+    def partition(self, inp, cell_off, n_particles: int, p: VpmParams, perm, subset_id, n_subsets, stream=None):
+        import torch
+        n_cells = cell_off.numel() - 1
+        si = _soa(inp, _torch_dtype(p), n_particles, "in")
+        st = lib().vpm_partition(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"),
+                                 n_cells, int(n_particles), C.byref(p),
+                                 _dev(perm, torch.int32, n_particles, "perm"),
+                                 _dev(subset_id, torch.int32, n_particles, "subset_id"),
+                                 _dev(n_subsets, torch.int32, n_cells, "n_subsets"), _stream(stream))
+        self._check(st, "vpm_partition")
+
+    def merge(self, inp, cell_off, n_particles: int, p: VpmParams, perm, subset_id, n_subsets, out, out_off,
+              out_total, stream=None):
+        import torch
+        n_cells = cell_off.numel() - 1
+        dt = _torch_dtype(p)
+        si = _soa(inp, dt, n_particles, "in")
+        so = _soa(out, dt, n_particles, "out")
+        st = lib().vpm_merge(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"), n_cells,
+                             int(n_particles), C.byref(p), _dev(perm, torch.int32, n_particles, "perm"),
+                             _dev(subset_id, torch.int32, n_particles, "subset_id"),
+                             _dev(n_subsets, torch.int32, n_cells, "n_subsets"), C.byref(so),
+                             _dev(out_off, torch.int64, n_cells + 1, "out_off"),
+                             _dev(out_total, torch.int64, 1, "out_total"), _stream(stream))
+        self._check(st, "vpm_merge")
+
+    def device_status(self, clear: bool = False) -> int:
+        f = C.c_uint32(0)
+        self._check(lib().vpm_device_status(self.h, C.byref(f), int(clear)), "vpm_device_status")
+        return int(f.value)
+
+    def profile_enable(self, on: bool = True):
+        self._check(lib().vpm_profile_enable(self.h, int(on)), "vpm_profile_enable")
+
+    def profile_read(self, reset: bool = True):
+        """{kernel name: (launches, total ms)} since the last reset."""
+        nmax = 64
+        names = (C.c_char * 48 * nmax)()
+        launches = (C.c_int64 * nmax)()
+        ms = (C.c_double * nmax)()
+        n = C.c_int(0)
+        self._check(lib().vpm_profile_read(self.h, nmax, C.cast(names, C.c_void_p), launches, ms, C.byref(n),
+                                           int(reset)), "vpm_profile_read")
+        return {bytes(names[i]).split(b"\0")[0].decode(): (int(launches[i]), float(ms[i]))
+                for i in range(min(n.value, nmax))}
+
+
+# C-named module-level wrappers -----------------------------------------------------------
+
+def vpm_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def vpm_reserve(ctx: Context, max_particles: int, max_cells: int):
+    ctx.reserve(max_particles, max_cells)
+
+
+def vpm_run(ctx: Context, *a, **k):
+    ctx.run(*a, **k)
+
+
+def vpm_partition(ctx: Context, *a, **k):
+    ctx.partition(*a, **k)
+
+
+def vpm_merge(ctx: Context, *a, **k):
+    ctx.merge(*a, **k)
+
+
+def vpm_device_status(ctx: Context, clear: bool = False) -> int:
+    return ctx.device_status(clear)
+
+
+def vpm_destroy(ctx: Context):
+    ctx.close()
+
+
+# ------------------------------------------------------------------------------------------
+# convenience: a whole population in, merged population out
+# ------------------------------------------------------------------------------------------
+
+@dataclass
+class RunResult:
+    out: list             # 7 device tensors (first out_total entries valid)
+    out_off: object       # int64 device tensor [n_cells+1]
+    out_total: int
+
+
+def upload(wl, dtype=None, device="cuda"):
+    """Copy a workloads.Workload to the device: (list of 7 tensors, cell_off tensor)."""
+    import numpy as np
+    import torch
+    dt = dtype or (torch.float32 if wl.x.dtype == np.float32 else torch.float64)
+    arrs = [torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt) for a in wl.arrays()]
+    off = torch.from_numpy(np.ascontiguousarray(wl.cell_off)).to(device=device)
+    return arrs, off
+
+
+def run_population(ctx: Context, arrs, cell_off, p: VpmParams, stream=None) -> RunResult:
+    import torch
+    n = int(arrs[0].numel())
+    n_cells = cell_off.numel() - 1
+    out = [torch.empty_like(a) for a in arrs]
+    out_off = torch.empty(n_cells + 1, dtype=torch.int64, device=arrs[0].device)
+    out_total = torch.empty(1, dtype=torch.int64, device=arrs[0].device)
+    ctx.run(arrs, cell_off, n, p, out, out_off, out_total, stream)
+    tot = int(out_total.item())
+    return RunResult(out, out_off, tot)

@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point that include/vpm.h
+declares, validates parameters without a device, and reports a missing device cleanly."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1504_00636_amd import vpm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "vpm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vpm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = vpm.lib()
+    names = _declared()
+    assert "vpm_run" in names and "vpm_partition" in names and "vpm_merge" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(vpm.EXPORTS) == set(names)
+
+
+def test_version_string():
+    assert "gfx950" in vpm.vpm_version()
+
+
+def _p(**kw):
+    base = dict(tol_x=0.1, tol_p=0.05, n_min_cell=0, min_subset=4, cell_len=(1, 1, 1), mass=1.0)
+    base.update(kw)
+    return vpm.make_params(**base)
+
+
+def test_check_params_accepts_valid():
+    assert vpm.vpm_check_params(_p()) == vpm.VPM_OK
+    assert vpm.vpm_check_params(_p(decide=vpm.VPM_DECIDE_FP64)) == vpm.VPM_OK
+    assert vpm.vpm_check_params(_p(merge_mode=vpm.VPM_MERGE_CENTROID, min_subset=1)) == vpm.VPM_OK
+    assert vpm.vpm_check_params(_p(mass=0.0)) == vpm.VPM_OK
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tol_x=-0.1), dict(tol_p=float("nan")), dict(tol_x=128.0), dict(tol_p=1e9),
+    dict(n_min_cell=-1), dict(min_subset=0), dict(min_subset=1), dict(min_subset=70000),
+    dict(cell_len=(1, 0, 1)), dict(cell_len=(1, 1, float("inf"))), dict(mass=-1.0),
+    dict(merge_mode=7), dict(decide=3), dict(dtype=5),
+])
+def test_check_params_rejects(bad):
+    assert vpm.vpm_check_params(_p(**bad)) == vpm.VPM_ERR_INVALID_ARG
+
+
+def test_fp64_mode_allows_large_tolerance():
+    assert vpm.vpm_check_params(_p(decide=vpm.VPM_DECIDE_FP64, tol_x=1e6)) == vpm.VPM_OK
+
+
+def test_reserved_field_must_be_zero():
+    p = _p()
+    p.reserved = 1
+    assert vpm.vpm_check_params(p) == vpm.VPM_ERR_INVALID_ARG
+
+
+def test_null_params_rejected():
+    assert vpm.lib().vpm_check_params(None) == vpm.VPM_ERR_INVALID_ARG
+
+
+def test_status_strings():
+    for st in (0, -1, -2, -3, -4, -5):
+        assert vpm.status_string(st)
+
+
+def test_create_without_gpu_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert vpm.lib().vpm_create(C.byref(h), 0) == vpm.VPM_ERR_NO_DEVICE
+
+
+def test_entry_points_reject_null_context():
+    L = vpm.lib()
+    p = _p()
+    assert L.vpm_run(None, None, None, 0, 0, C.byref(p), None, None, None, None) == vpm.VPM_ERR_INVALID_ARG
+    assert L.vpm_partition(None, None, None, 0, 0, C.byref(p), None, None, None, None) == vpm.VPM_ERR_INVALID_ARG
+    assert L.vpm_reserve(None, 1, 1) == vpm.VPM_ERR_INVALID_ARG

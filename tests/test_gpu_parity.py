@@ -1,0 +1,247 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bar (fixed-point FP32 path): final-subset membership and order bit-exact, output counts exact,
+copied particles bit-identical, merged particles within 1e-6 (relative to W, L, the merged energy)
+plus one FP32 rounding of the stored value.  FP64 path: partitions equal except at certified
+near-ties, merged values within 1e-12.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_00636_amd import vpm, workloads as W
+from tests.gpu_common import (FIELDS, check_merged_values, check_partition_equal, gpu_partition, gpu_run,
+                              oracle_params)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MERGES = [vpm.VPM_MERGE_PAIR, vpm.VPM_MERGE_CENTROID]
+CLOUD = dict(tol_x=0.3, tol_p=0.08, n_min_cell=0, min_subset=4, cell_len=(1.0, 1.0, 1.0), mass=1.0)
+
+
+def cloud_cells(sizes, seed=0, spread=0.05, dtype=np.float32):
+    """Cells whose momenta have nonzero means, so that subsets merge."""
+    r = np.random.Generator(np.random.Philox(seed))
+    cells = []
+    for k in sizes:
+        px = 1.0 + 2 * spread * r.standard_normal(k)
+        py = 0.5 + spread * r.standard_normal(k)
+        pz = -0.3 + spread * r.standard_normal(k)
+        cells.append(np.stack([r.random(k), r.random(k), r.random(k), px, py, pz, 0.5 + r.random(k)], axis=1))
+    return W.from_cells(cells, params=dict(CLOUD), dtype=dtype)
+
+
+def full_check(wl, params, merge=vpm.VPM_MERGE_PAIR):
+    ref = oracle.run_workload(wl, decide=oracle.FIXED, merge_mode=merge, **oracle_params(params))
+    check_partition_equal(wl, params, ref=ref)
+    got, got_off, tot = gpu_run(wl, params, merge=merge)
+    assert tot == ref.out_total
+    check_merged_values(wl, params, merge, got, got_off, ref)
+    return ref
+
+
+def test_single_cell_two_beams():
+    wl = W.single_cell_two_beams().astype(np.float32)
+    full_check(wl, wl.params)
+
+
+@pytest.mark.parametrize("merge", MERGES)
+def test_merging_cloud(merge):
+    wl = cloud_cells([300, 257, 64, 1000, 5, 4, 3, 2, 1, 0, 700], seed=1)
+    params = dict(CLOUD, min_subset=4 if merge == vpm.VPM_MERGE_PAIR else 2)
+    ref = full_check(wl, params, merge)
+    assert ref.stats["n_merged"].sum() > 50
+
+
+@pytest.mark.parametrize("merge", MERGES)
+def test_size_bins_and_ragged_tails(merge):
+    """Sizes around every group-size and bin boundary (1024 / 4096 LDS bins, the global-memory bin)."""
+    sizes = [1, 2, 3, 4, 5, 7, 8, 9, 16, 17, 63, 64, 65, 255, 256, 257, 511, 512, 513,
+             1023, 1024, 1025, 2047, 4095, 4096, 4097, 9001]
+    wl = cloud_cells(sizes, seed=2, spread=0.08)
+    full_check(wl, dict(CLOUD, min_subset=3), merge)
+
+
+def test_untouched_and_empty_cells():
+    wl = cloud_cells([0, 5, 20, 0, 21, 22, 0], seed=3)
+    params = dict(CLOUD, n_min_cell=20)
+    ref = full_check(wl, params)
+    assert all(ref.n_subsets[c] == 0 for c in (0, 1, 2, 3, 6)) and ref.n_subsets[4] > 0
+    perm, sid, nsub = gpu_partition(wl, params)
+    lo, hi = wl.cell_off[2], wl.cell_off[3]
+    assert np.all(sid[lo:hi] == -1) and np.all(perm[lo:hi] == np.arange(lo, hi))
+
+
+def test_bad_values_flag_and_pass_through():
+    wl = cloud_cells([50, 50, 50, 50], seed=4)
+    wl.w[wl.cell_off[1] + 3] = -1.0
+    wl.py[wl.cell_off[2] + 7] = np.nan
+    c = __import__("tests.gpu_common", fromlist=["ctx"]).ctx()
+    c.device_status(clear=True)
+    got, got_off, tot = gpu_run(wl, CLOUD)
+    assert c.device_status(clear=True) & vpm.VPM_FLAG_BAD_VALUE
+    assert tot == int(got_off[-1])
+    # cells 1 and 2 are copied unchanged, in input order
+    for cc in (1, 2):
+        lo, hi = wl.cell_off[cc], wl.cell_off[cc + 1]
+        o = got_off[cc]
+        assert got_off[cc + 1] - o == hi - lo
+        for f in ("x", "w"):
+            np.testing.assert_array_equal(got[f][o:o + hi - lo], getattr(wl, f)[lo:hi].astype(np.float64))
+    # the healthy cells match the oracle
+    sub = wl.cells([0, 3])
+    ref = oracle.run_workload(sub, **oracle_params(CLOUD))
+    for k, cc in enumerate((0, 3)):
+        assert got_off[cc + 1] - got_off[cc] == ref.out_off[k + 1] - ref.out_off[k]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_zero_tolerance_lattice(seed):
+    """T = 0: subsets are the duplicate classes; exercises deep trees of tiny subsets and ties."""
+    r = np.random.Generator(np.random.Philox(seed))
+    cells = []
+    for k in (40, 300, 900, 2500):
+        base = r.integers(0, 3, size=(k, 6)).astype(np.float64)
+        base[:, :3] *= 1000.0
+        base[:, 3:] -= 1.0
+        w = r.integers(1, 4, size=(k, 1)).astype(np.float64)
+        cells.append(np.concatenate([base, w], axis=1))
+    params = dict(tol_x=0.0, tol_p=0.0, n_min_cell=0, min_subset=1, cell_len=(65536.0,) * 3, mass=1.0)
+    wl = W.from_cells(cells, params=params, dtype=np.float32)
+    full_check(wl, params, vpm.VPM_MERGE_CENTROID)
+
+
+def test_huge_tolerance_single_subset():
+    wl = cloud_cells([100, 3000, 5000, 1], seed=5)
+    params = dict(CLOUD, tol_x=100.0, tol_p=100.0)
+    ref = full_check(wl, params)
+    assert list(ref.n_subsets) == [1, 1, 1, 1]
+
+
+def test_identical_particles():
+    k = 777
+    cell = np.tile(np.array([[0.25, 0.5, 0.75, 1.0, 0.0, -2.0, 1.5]]), (k, 1))
+    wl = W.from_cells([cell, cell[:5]], params=dict(CLOUD, tol_x=0.0, tol_p=0.0), dtype=np.float32)
+    full_check(wl, dict(CLOUD, tol_x=0.0, tol_p=0.0))
+
+
+def test_max_cell_size_and_too_large():
+    """65,536 particles is the largest cell the library merges; one more is flagged and copied."""
+    wl = cloud_cells([65536, 65537, 10], seed=6)
+    c = __import__("tests.gpu_common", fromlist=["ctx"]).ctx()
+    c.device_status(clear=True)
+    perm, sid, nsub = gpu_partition(wl, CLOUD)
+    assert c.device_status(clear=True) & vpm.VPM_FLAG_CELL_TOO_LARGE
+    sub = wl.cells([0, 2])
+    ref = oracle.run_workload(sub, **oracle_params(CLOUD))
+    n0 = 65536
+    np.testing.assert_array_equal(perm[:n0], ref.perm[:n0])
+    np.testing.assert_array_equal(sid[:n0], ref.subset_id[:n0])
+    lo, hi = wl.cell_off[1], wl.cell_off[2]
+    assert np.all(sid[lo:hi] == -1) and nsub[1] == 0
+
+
+def test_repeatable_bit_identical():
+    wl = cloud_cells([800, 3000, 12000, 50], seed=7)
+    a, ao, _ = gpu_run(wl, CLOUD)
+    b, bo, _ = gpu_run(wl, CLOUD)
+    np.testing.assert_array_equal(ao, bo)
+    for f in FIELDS:
+        np.testing.assert_array_equal(a[f], b[f])
+
+
+def _sampled_check(wl, params, sample, merge=vpm.VPM_MERGE_PAIR):
+    """Run the whole population on the GPU (the benchmark's launch configuration) and compare the
+    sampled cells with the oracle run on those cells alone."""
+    perm, sid, nsub = gpu_partition(wl, params)
+    got, got_off, tot = gpu_run(wl, params, merge=merge)
+    sub = wl.cells(sample)
+    ref = oracle.run_workload(sub, merge_mode=merge, **oracle_params(params))
+    for k, c in enumerate(sample):
+        lo, hi = int(wl.cell_off[c]), int(wl.cell_off[c + 1])
+        slo = int(sub.cell_off[k])
+        assert nsub[c] == ref.n_subsets[k]
+        np.testing.assert_array_equal(perm[lo:hi] - lo, ref.perm[slo:slo + hi - lo] - slo)
+        np.testing.assert_array_equal(sid[lo:hi], ref.subset_id[slo:slo + hi - lo])
+        assert got_off[c + 1] - got_off[c] == ref.out_off[k + 1] - ref.out_off[k]
+    # merged values of the sampled cells
+    sel = np.concatenate([np.arange(got_off[c], got_off[c + 1]) for c in sample])
+    g = {f: got[f][sel] for f in FIELDS}
+    check_merged_values(sub, params, merge, g, ref.out_off, ref)
+    return got, got_off, tot
+
+
+def test_two_stream_full_size_sampled():
+    """256 x 256 cells, Poisson(512) per cell (33.5M particles), FP32, sampled cells vs the oracle."""
+    wl = W.two_stream_grid(seed=0).astype(np.float32)
+    r = np.random.Generator(np.random.Philox(11))
+    sample = np.sort(r.choice(wl.n_cells, 300, replace=False))
+    _sampled_check(wl, wl.params, sample)
+
+
+def test_two_stream_paper_tolerances_sampled():
+    """Same population with the paper's two-stream tolerances (T_X 0.8, T_P 0.15, N_min 200): merges."""
+    wl = W.two_stream_grid(nx=64, ny=64, seed=1).astype(np.float32)
+    params = dict(W.TWO_STREAM_PAPER_PARAMS)
+    sample = np.arange(0, wl.n_cells, 7)
+    _sampled_check(wl, params, sample)
+
+
+def test_shower_full_size_sampled():
+    """64^3 cells, lognormal occupancy up to 32,768, gamma^-2 momenta: every size bin, sampled."""
+    wl = W.shower_grid(seed=0)
+    cnt = np.diff(wl.cell_off)
+    r = np.random.Generator(np.random.Philox(12))
+    big = np.nonzero(cnt > 4096)[0]
+    mid = np.nonzero((cnt > 1024) & (cnt <= 4096))[0]
+    small = np.nonzero((cnt > 10) & (cnt <= 1024))[0]
+    tiny = np.nonzero(cnt <= 10)[0]
+    sample = np.sort(np.concatenate([r.choice(big, 6, replace=False), [int(np.argmax(cnt))],
+                                     r.choice(mid, 40, replace=False), r.choice(small, 200, replace=False),
+                                     r.choice(tiny, 20, replace=False)]))
+    sample = np.unique(sample)
+    _sampled_check(wl, wl.params, sample)
+
+
+def test_shower_with_merging_sampled():
+    """Shower-shaped cells with loose momentum tolerance so that subsets merge (lognormal weights,
+    gamma up to 1e4): exercises the fixed-point merge sums over a wide dynamic range."""
+    wl = W.shower_grid(nc=16, seed=3)
+    params = dict(wl.params, tol_p=100.0, tol_x=0.5)
+    sample = np.arange(0, wl.n_cells, 5)
+    for merge in MERGES:
+        _sampled_check(wl, params, sample, merge)
+
+
+# ---------------------------------------------------------------------------- FP64 path
+
+def _fp64_check(wl, params, merge=vpm.VPM_MERGE_PAIR):
+    ref = oracle.run_workload(wl, decide=oracle.PAPER, merge_mode=merge, **oracle_params(params))
+    perm, sid, nsub = gpu_partition(wl, params, decide=vpm.VPM_DECIDE_FP64)
+    bad = []
+    for c in range(wl.n_cells):
+        lo, hi = wl.cell_off[c], wl.cell_off[c + 1]
+        if not (np.array_equal(perm[lo:hi], ref.perm[lo:hi]) and np.array_equal(sid[lo:hi], ref.subset_id[lo:hi])):
+            bad.append(c)
+    for c in bad:
+        assert ref.stats["min_margin"][c] < 1e-9, f"cell {c} differs without a near-tie"
+    got, got_off, tot = gpu_run(wl, params, decide=vpm.VPM_DECIDE_FP64, merge=merge)
+    good = [c for c in range(wl.n_cells) if c not in bad]
+    sub = wl.cells(good)
+    rsub = oracle.run_workload(sub, decide=oracle.PAPER, merge_mode=merge, **oracle_params(params))
+    sel = np.concatenate([np.arange(got_off[c], got_off[c + 1]) for c in good]) if good else np.zeros(0, int)
+    check_merged_values(sub, params, merge, {f: got[f][sel] for f in FIELDS}, rsub.out_off, rsub, rel=1e-12)
+    return len(bad)
+
+
+@pytest.mark.parametrize("merge", MERGES)
+def test_fp64_path_cloud(merge):
+    wl = cloud_cells([300, 257, 64, 1000, 5, 4, 3, 2, 1, 0, 700, 5000], seed=8, dtype=np.float64)
+    params = dict(CLOUD, min_subset=4 if merge == vpm.VPM_MERGE_PAIR else 2)
+    assert _fp64_check(wl, params, merge) <= 1
+
+
+def test_fp64_path_two_stream():
+    wl = W.two_stream_grid(nx=32, ny=32, seed=2)
+    assert _fp64_check(wl, wl.params) <= 2
