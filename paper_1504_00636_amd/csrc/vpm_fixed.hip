@@ -45,7 +45,8 @@ struct Node { IdxT start, len; int32_t thr_axis; };   // thr_axis = (threshold <
 struct Frame {
     float lo[3], hi[3], pmax[3], wmax;
     int ew, ep[3], pzero[3];
-    int gw, gx[3], gd[3], ge;
+    int ext_e[3];        // frexp exponent of the cell's extent per position axis
+    int eb;              // frexp exponent of a bound on |eps_i - eps_pivot| over the cell
     int bad;
 };
 
@@ -447,7 +448,21 @@ VPM_DEV void split_node(Shared& S, const CellMem<IdxT>& M, const FixedArgs& A, N
     }
 }
 
+VPM_DEV int ceil_log2(int v) {
+    int b = 0;
+    while ((1 << b) < v) ++b;
+    return b;
+}
+
 // Merge one finished subset with a lane group (Step 7) and write its 1 or 2 particles.
+//
+// Two passes over the subset, all sums exact int64 on fixed grids (so the result does not depend
+// on the summation order):
+//   pass 1: W = sum w and sum w p on cell-wide grids  ->  a pivot momentum pt ~ P (FP32);
+//   pass 2: sum w (x - lo), sum w (p - pt), sum w (eps_i - eps(pt)) on grids scaled to this
+//           subset's own W, so subsets of light particles keep full precision.
+// eps_i - eps(pt) is formed as (|d|^2 + 2 pt.d) / (eps_i + eps(pt)), d = p - pt, which does not
+// cancel; the FP64 solve then forms r = mean(eps)^2 - m^2 - |P|^2 from these differences.
 template <typename IdxT>
 VPM_DEV void merge_leaf(const Shared& S, const CellMem<IdxT>& M, const FixedArgs& A, int64_t off,
                         int start, int len, int lid, int g) {
@@ -455,55 +470,64 @@ VPM_DEV void merge_leaf(const Shared& S, const CellMem<IdxT>& M, const FixedArgs
     const uint8_t inf = M.info[start];
     const IdxT* src = idx_buf(M, inf & INF_PARITY);
     const int jdir = (inf >> INF_JSHIFT) & 3;
-    const int64_t i0 = off + src[start];
-    const float q0 = A.in.px[i0], q1 = A.in.py[i0], q2 = A.in.pz[i0];
+    const int gb = 62 - ceil_log2(len);          // |term| < 2^gb keeps the sum below 2^62
+
+    // pass 1
+    const int gw = gb - F.ew;
+    const int g1x = gb - F.ew - F.ep[0], g1y = gb - F.ew - F.ep[1], g1z = gb - F.ew - F.ep[2];
+    int64_t sw = 0, s1x = 0, s1y = 0, s1z = 0;
+    for (int j = lid; j < len; j += g) {
+        const int64_t i = off + src[start + j];
+        const float w = A.in.w[i];
+        sw += fixq(w, 1.0f, gw);
+        s1x += fixq(w, A.in.px[i], g1x);
+        s1y += fixq(w, A.in.py[i], g1y);
+        s1z += fixq(w, A.in.pz[i], g1z);
+    }
+    sw = group_sum(sw, g);
+    s1x = group_sum(s1x, g); s1y = group_sum(s1y, g); s1z = group_sum(s1z, g);
+    const double W = ldexp((double)sw, -gw);
+    const float q0 = (float)(ldexp((double)s1x, -g1x) / W);
+    const float q1 = (float)(ldexp((double)s1y, -g1y) / W);
+    const float q2 = (float)(ldexp((double)s1z, -g1z) / W);
+
+    // pass 2
+    int eW = 0;
+    frexp(W, &eW);                                // W < 2^eW
+    const int gx0 = 61 - eW - F.ext_e[0], gx1 = 61 - eW - F.ext_e[1], gx2 = 61 - eW - F.ext_e[2];
+    const int gd0 = 61 - eW - F.ep[0] - 1, gd1 = 61 - eW - F.ep[1] - 1, gd2 = 61 - eW - F.ep[2] - 1;
+    const int ge = 61 - eW - F.eb;
     const float m = (float)A.P.mass;
     const float m2 = m * m;
     const float e0f = sqrtf(m2 + (q0 * q0 + q1 * q1 + q2 * q2));
-
-    int64_t sw = 0, sx0 = 0, sx1 = 0, sx2 = 0, sd0 = 0, sd1 = 0, sd2 = 0, se = 0;
+    int64_t sx0 = 0, sx1 = 0, sx2 = 0, sd0 = 0, sd1 = 0, sd2 = 0, se = 0;
     for (int j = lid; j < len; j += g) {
         const int64_t i = off + src[start + j];
         const float w = A.in.w[i];
         const float x = A.in.x[i] - F.lo[0], y = A.in.y[i] - F.lo[1], z = A.in.z[i] - F.lo[2];
         const float px = A.in.px[i], py = A.in.py[i], pz = A.in.pz[i];
         const float d0 = px - q0, d1 = py - q1, d2 = pz - q2;
-        const float eps = sqrtf(m2 + (px * px + py * py + pz * pz));
-        const float den = eps + e0f;
-        const float num = (d0 * d0 + d1 * d1 + d2 * d2) + 2.0f * (q0 * d0 + q1 * d1 + q2 * d2);
-        const float t = den > 0.0f ? num / den : 0.0f;
-        sw += fixq(w, 1.0f, F.gw);
-        sx0 += fixq(w, x, F.gx[0]); sx1 += fixq(w, y, F.gx[1]); sx2 += fixq(w, z, F.gx[2]);
-        sd0 += fixq(w, d0, F.gd[0]); sd1 += fixq(w, d1, F.gd[1]); sd2 += fixq(w, d2, F.gd[2]);
-        se += fixq(w, t, F.ge);
+        sx0 += fixq(w, x, gx0); sx1 += fixq(w, y, gx1); sx2 += fixq(w, z, gx2);
+        sd0 += fixq(w, d0, gd0); sd1 += fixq(w, d1, gd1); sd2 += fixq(w, d2, gd2);
+        if (A.P.merge_mode == VPM_MERGE_PAIR) {
+            const float eps = sqrtf(m2 + (px * px + py * py + pz * pz));
+            const float den = eps + e0f;
+            const float num = (d0 * d0 + d1 * d1 + d2 * d2) + 2.0f * (q0 * d0 + q1 * d1 + q2 * d2);
+            se += fixq(w, den > 0.0f ? num / den : 0.0f, ge);
+        }
     }
-    sw = group_sum(sw, g);
     sx0 = group_sum(sx0, g); sx1 = group_sum(sx1, g); sx2 = group_sum(sx2, g);
     sd0 = group_sum(sd0, g); sd1 = group_sum(sd1, g); sd2 = group_sum(sd2, g);
     se = group_sum(se, g);
     if (lid != 0) return;
 
-    const double W = ldexp((double)sw, -F.gw);
-    const double X[3] = {F.lo[0] + ldexp((double)sx0, -F.gx[0]) / W,
-                         F.lo[1] + ldexp((double)sx1, -F.gx[1]) / W,
-                         F.lo[2] + ldexp((double)sx2, -F.gx[2]) / W};
+    const double X[3] = {F.lo[0] + ldexp((double)sx0, -gx0) / W,
+                         F.lo[1] + ldexp((double)sx1, -gx1) / W,
+                         F.lo[2] + ldexp((double)sx2, -gx2) / W};
     const double pt[3] = {q0, q1, q2};
-    const double Pm[3] = {pt[0] + ldexp((double)sd0, -F.gd[0]) / W,
-                          pt[1] + ldexp((double)sd1, -F.gd[1]) / W,
-                          pt[2] + ldexp((double)sd2, -F.gd[2]) / W};
-    const double md = A.P.mass;
-    const double et = sqrt(md * md + (pt[0] * pt[0] + pt[1] * pt[1] + pt[2] * pt[2]));
-    const double P2 = Pm[0] * Pm[0] + Pm[1] * Pm[1] + Pm[2] * Pm[2];
-    const double e0 = sqrt(md * md + P2);
-    const double a1 = ldexp((double)se, -F.ge) / W;              // mean energy - e(first)
-    const double dn = et + e0;
-    const double a2 = dn > 0.0 ? ((pt[0] - Pm[0]) * (pt[0] + Pm[0]) + (pt[1] - Pm[1]) * (pt[1] + Pm[1]) +
-                                  (pt[2] - Pm[2]) * (pt[2] + Pm[2])) / dn
-                               : 0.0;                             // e(first) - e(P)
-    const double Aex = a1 + a2;                                   // mean energy - e(P)
-    double r = Aex * (Aex + 2.0 * e0);
-    if (!(r > 0.0)) r = 0.0;
-
+    const double Pm[3] = {pt[0] + ldexp((double)sd0, -gd0) / W,
+                          pt[1] + ldexp((double)sd1, -gd1) / W,
+                          pt[2] + ldexp((double)sd2, -gd2) / W};
     const int64_t o = off + M.emit[start];
     if (A.P.merge_mode == VPM_MERGE_CENTROID) {
         A.tmp.w[o] = (float)W;
@@ -511,6 +535,18 @@ VPM_DEV void merge_leaf(const Shared& S, const CellMem<IdxT>& M, const FixedArgs
         A.tmp.px[o] = (float)Pm[0]; A.tmp.py[o] = (float)Pm[1]; A.tmp.pz[o] = (float)Pm[2];
         return;
     }
+    const double md = A.P.mass;
+    const double et = sqrt(md * md + (pt[0] * pt[0] + pt[1] * pt[1] + pt[2] * pt[2]));
+    const double P2 = Pm[0] * Pm[0] + Pm[1] * Pm[1] + Pm[2] * Pm[2];
+    const double e0 = sqrt(md * md + P2);
+    const double a1 = ldexp((double)se, -ge) / W;               // mean energy - eps(pt)
+    const double dn = et + e0;
+    const double a2 = dn > 0.0 ? ((pt[0] - Pm[0]) * (pt[0] + Pm[0]) + (pt[1] - Pm[1]) * (pt[1] + Pm[1]) +
+                                  (pt[2] - Pm[2]) * (pt[2] + Pm[2])) / dn
+                               : 0.0;                             // eps(pt) - eps(P)
+    const double Aex = a1 + a2;                                   // mean energy - eps(P)
+    double r = Aex * (Aex + 2.0 * e0);
+    if (!(r > 0.0)) r = 0.0;
     const double pj = jdir == 0 ? Pm[0] : (jdir == 1 ? Pm[1] : Pm[2]);
     double u[3] = {jdir == 0 ? 1.0 : 0.0, jdir == 1 ? 1.0 : 0.0, jdir == 2 ? 1.0 : 0.0};
     if (P2 > 0.0) {
@@ -598,17 +634,13 @@ __global__ __launch_bounds__(BLOCK) void k_fixed_cells(FixedArgs A) {
                 for (int a = 0; a < 3; ++a) { F.lo[a] = -v[1 + a]; F.hi[a] = v[4 + a]; F.pmax[a] = v[7 + a]; }
                 F.bad = v[10] != 0.0f;
                 F.ew = frexp_exp(F.wmax);
-                int emax = -1000;
                 for (int a = 0; a < 3; ++a) {
                     F.pzero[a] = F.pmax[a] == 0.0f;
                     F.ep[a] = frexp_exp(F.pmax[a]);
-                    if (!F.pzero[a] && F.ep[a] > emax) emax = F.ep[a];
-                    F.gx[a] = 46 - F.ew - frexp_exp(F.hi[a] - F.lo[a]);
-                    F.gd[a] = 46 - F.ew - (F.ep[a] + 1);
+                    F.ext_e[a] = frexp_exp(F.hi[a] - F.lo[a]);
                 }
-                F.gw = 46 - F.ew;
-                const float B = 4.0f * ((float)A.P.mass + F.pmax[0] + F.pmax[1] + F.pmax[2]);
-                F.ge = 46 - F.ew - frexp_exp(B);
+                // |eps_i - eps_j| <= m + |p|_1 for any two particles of the cell; 4x margin
+                F.eb = frexp_exp(4.0f * ((float)A.P.mass + F.pmax[0] + F.pmax[1] + F.pmax[2]));
                 S.nnodes[0] = 0; S.nnodes[1] = 0;
             }
             __syncthreads();

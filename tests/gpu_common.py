@@ -50,8 +50,9 @@ def oracle_params(params: dict):
     return {k: params[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset", "cell_len", "mass")}
 
 
-def check_partition_equal(wl, params, decide_gpu=vpm.VPM_DECIDE_FIXED, decide_orc=oracle.FIXED, ref=None):
-    perm, sid, nsub = gpu_partition(wl, params, decide_gpu)
+def check_partition_equal(wl, params, decide_gpu=vpm.VPM_DECIDE_FIXED, decide_orc=oracle.FIXED, ref=None,
+                          merge=vpm.VPM_MERGE_PAIR):
+    perm, sid, nsub = gpu_partition(wl, params, decide_gpu, merge)
     if ref is None:
         ref = oracle.run_workload(wl, decide=decide_orc, **oracle_params(params))
     np.testing.assert_array_equal(nsub, ref.n_subsets)

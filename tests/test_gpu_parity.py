@@ -34,7 +34,7 @@ def cloud_cells(sizes, seed=0, spread=0.05, dtype=np.float32):
 
 def full_check(wl, params, merge=vpm.VPM_MERGE_PAIR):
     ref = oracle.run_workload(wl, decide=oracle.FIXED, merge_mode=merge, **oracle_params(params))
-    check_partition_equal(wl, params, ref=ref)
+    check_partition_equal(wl, params, ref=ref, merge=merge)
     got, got_off, tot = gpu_run(wl, params, merge=merge)
     assert tot == ref.out_total
     check_merged_values(wl, params, merge, got, got_off, ref)
@@ -154,7 +154,7 @@ def test_repeatable_bit_identical():
 def _sampled_check(wl, params, sample, merge=vpm.VPM_MERGE_PAIR):
     """Run the whole population on the GPU (the benchmark's launch configuration) and compare the
     sampled cells with the oracle run on those cells alone."""
-    perm, sid, nsub = gpu_partition(wl, params)
+    perm, sid, nsub = gpu_partition(wl, params, merge=merge)
     got, got_off, tot = gpu_run(wl, params, merge=merge)
     sub = wl.cells(sample)
     ref = oracle.run_workload(sub, merge_mode=merge, **oracle_params(params))
