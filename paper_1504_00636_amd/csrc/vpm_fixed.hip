@@ -1,35 +1,37 @@
 // Fixed-point Voronoi particle merging on gfx950 (the batched FP32 hot path).
 //
-// One workgroup owns one simulation cell at a time (persistent grid popping a size-binned
-// queue).  The cell's particles are turned into integer codes once (Sec. "Algorithm",
-// Step 1 collects the cell; the codes fix its frame):
+// One wavefront owns one simulation cell at a time (persistent grid; each wave pops cells from a
+// size-binned queue and works in its own LDS slice, or in a global slab for very large cells).
+// The cell's particles are turned into integer codes once (Sec. "Algorithm", Step 1 collects the
+// cell; the codes fix its frame):
 //     weight    omega = rint(w * 2^(15 - e_w))          e_w: frexp exponent of the cell's max w
 //     position  c     = min(rint((x - lo) * s), 65535) - 32768,  s = fl32(65536 / L), lo = cell min
 //     momentum  c     = rint(p * 2^(22 - e_a))          e_a: frexp exponent of the cell's max |p_a|
-// and every subset ("Voronoi cell") is described by exact integer moments
+// and every subset ("Voronoi cell") is described by integer moments
 //     S0 = sum omega,  S1_l = sum omega c_l,  S2_l = sum omega c_l^2.
-// The coefficient of variation (Eqs. cv_x, cv_p) is compared exactly:
+// The coefficient of variation (Eqs. cv_x, cv_p) is compared as an exact rational:
 //     Delta_l^2 = V_l / D_l,  V_l = S0 S2_l - S1_l^2,  D = 2^32 S0^2 (positions), S1_l^2 (momenta)
 // Step 3 (stop when all six CVs <= tolerance), Step 4 (largest CV, ties to the lowest axis) and
-// Step 5 (cut q <= Q, i.e. c S0 <= S1) are all integer operations, so the partition does not
-// depend on summation order or launch shape.
+// Step 5 (cut q <= Q, i.e. c S0 <= S1) are decided exactly, so the partition does not depend on
+// summation order or launch shape.  S0 and S1 are exact in FP64 (they stay below 2^53); S2 is
+// accumulated with FP64 FMAs, and every comparison is first made in FP64 with a proven error
+// bound.  Only a comparison that falls inside its bound is redone with exact 128/256-bit integer
+// moments recomputed from the codes, which gives the same answer the exact rule would.
 //
-// Splitting is level-synchronous.  Every unfinished subset of a level is handled by a group of
-// g lanes inside one wavefront (g a power of two chosen from the subset size): the group counts
-// the lower side, compacts the subset stably with ballots into the other index buffer (Step 6),
-// sums the moments of both children and its first two lanes decide the children.
+// Splitting is level-synchronous inside the wave.  Every unfinished subset of a level is handled
+// by a group of g lanes (g a power of two chosen from the subset size): the group counts the lower
+// side, compacts the subset stably with ballots into the other index buffer (Step 6), sums the
+// moments of both children, and its first two lanes decide the children.
 //
-// Replacement (Step 7): each finished subset of at least min_subset particles is merged from
-// the FP32 data with order-independent int64 fixed-point sums (weight, weighted position,
-// weighted momentum offset from the subset's first particle, weighted energy offset) and an
-// FP64 solve for the centroid or the energy-conserving pair.
+// Replacement (Step 7): each finished subset of at least min_subset particles is merged from the
+// FP32 data with order-independent int64 fixed-point sums and an FP64 solve for the centroid or
+// the energy-conserving pair.
 #include "vpm_device.hpp"
 #include "vpm_internal.h"
 
 namespace vpm {
 namespace {
 
-constexpr int BLOCK = 256;          // threads per workgroup
 constexpr int PPL = 8;              // target particles per lane when sizing a group
 
 // info byte per slot once its final subset is known
@@ -46,74 +48,70 @@ struct Frame {
     float lo[3], hi[3], pmax[3], wmax;
     int ew, ep[3], pzero[3];
     int ext_e[3];        // frexp exponent of the cell's extent per position axis
-    int eb;              // frexp exponent of a bound on |eps_i - eps_pivot| over the cell
-    int bad;
+    int eb;              // frexp exponent of a bound on |eps_i - eps_j| over the cell
+    int amask;           // bit l: the codes of axis l are not all equal in the cell
 };
 
-struct Sums {
-    uint32_t s0;
-    int64_t s1[6];
-    int64_t s2p[3];      // positions: <= 2^61
-    U128 s2m[3];         // momenta:   <= 2^75
-};
+// ------------------------------------------------------------------------------------------
+// Moments
+// ------------------------------------------------------------------------------------------
 
-VPM_DEV void sums_zero(Sums& S) {
-    S.s0 = 0;
+// FP64 moments: s0 and s1 hold exact integers (|S1| <= 2^53); s2 is rounded.
+struct FSums { double s0, s1[6], s2[6]; };
+
+VPM_DEV void fsums_zero(FSums& S) {
+    S.s0 = 0.0;
 #pragma unroll
-    for (int l = 0; l < 6; ++l) S.s1[l] = 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) { S.s2p[a] = 0; S.s2m[a] = u128_make(0, 0); }
+    for (int l = 0; l < 6; ++l) { S.s1[l] = 0.0; S.s2[l] = 0.0; }
 }
 
-VPM_DEV void sums_add(Sums& S, uint32_t om, int c0, int c1, int c2, int c3, int c4, int c5) {
+VPM_DEV void fsums_add(FSums& S, int amask, int om, int c0, int c1, int c2, int c3, int c4, int c5) {
+    const double o = (double)om;
+    const int c[6] = {c0, c1, c2, c3, c4, c5};
+    S.s0 += o;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        if (!((amask >> l) & 1)) continue;
+        const double cl = (double)c[l];
+        const double t = o * cl;                  // exact: |t| <= 2^37
+        S.s1[l] += t;                             // exact while the partial sum stays below 2^53
+        S.s2[l] = fma(t, cl, S.s2[l]);
+    }
+}
+
+VPM_DEV void fsums_group_reduce(FSums& S, int g) {
+    for (int m = 1; m < g; m <<= 1) {
+        S.s0 += __shfl_xor(S.s0, m);
+#pragma unroll
+        for (int l = 0; l < 6; ++l) { S.s1[l] += __shfl_xor(S.s1[l], m); S.s2[l] += __shfl_xor(S.s2[l], m); }
+    }
+}
+
+// Exact integer moments (used only when an FP64 comparison is too close to call).
+struct ISums { uint32_t s0; int64_t s1[6]; int64_t s2p[3]; U128 s2m[3]; };
+
+VPM_DEV void isums_add(ISums& S, uint32_t om, const int c[6]) {
     S.s0 += om;
     const int64_t o = (int64_t)om;
-    const int cp[3] = {c0, c1, c2};
-    const int cm[3] = {c3, c4, c5};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int64_t t = (int64_t)((int32_t)om * cp[a]);     // |t| <= 2^30
+        const int64_t t = o * c[a];                       // |t| <= 2^30
         S.s1[a] += t;
-        S.s2p[a] += t * cp[a];
+        S.s2p[a] += t * c[a];
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int64_t t = o * cm[a];                         // |t| <= 2^37
+        const int64_t t = o * c[3 + a];                   // |t| <= 2^37
         S.s1[3 + a] += t;
-        const uint64_t q = (uint64_t)(t * cm[a]);            // <= 2^59
+        const uint64_t q = (uint64_t)(t * c[3 + a]);      // <= 2^59
         const uint64_t lo = S.s2m[a].lo + q;
         S.s2m[a].hi += (lo < q) ? 1u : 0u;
         S.s2m[a].lo = lo;
     }
 }
 
-VPM_DEV void sums_merge(Sums& A, const Sums& B) {
-    A.s0 += B.s0;
-#pragma unroll
-    for (int l = 0; l < 6; ++l) A.s1[l] += B.s1[l];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) { A.s2p[a] += B.s2p[a]; A.s2m[a] = add128(A.s2m[a], B.s2m[a]); }
-}
-
-VPM_DEV Sums sums_shfl_xor(const Sums& S, int m) {
-    Sums R;
-    R.s0 = __shfl_xor(S.s0, m);
-#pragma unroll
-    for (int l = 0; l < 6; ++l) R.s1[l] = __shfl_xor(S.s1[l], m);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        R.s2p[a] = __shfl_xor(S.s2p[a], m);
-        R.s2m[a] = u128_make(__shfl_xor(S.s2m[a].lo, m), __shfl_xor(S.s2m[a].hi, m));
-    }
-    return R;
-}
-
-VPM_DEV void sums_group_reduce(Sums& S, int g) {
-    for (int m = 1; m < g; m <<= 1) sums_merge(S, sums_shfl_xor(S, m));
-}
-
 // ------------------------------------------------------------------------------------------
-// Decisions (Steps 3-5), exact.
+// Decisions (Steps 3-5)
 // ------------------------------------------------------------------------------------------
 
 enum { D_SPLIT = 0, D_MERGED = 1, D_COPY = 2 };
@@ -122,16 +120,25 @@ struct Decision { int kind, axis, thr, jdir; };
 
 VPM_DEV uint64_t uabs64(int64_t v) { return v < 0 ? (uint64_t)(-v) : (uint64_t)v; }
 
-// Pair-direction axis: the momentum component with the smallest |mean|, from the exact sums.
-VPM_DEV int pair_axis(const Sums& S, const Frame& F) {
+// Pair-direction axis: the momentum component with the smallest |mean| (exact: |S1| 2^e_a).
+VPM_DEV int pair_axis(const double s1[6], const Frame& F) {
     int best = 0;
     double bv = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double v = F.pzero[a] ? 0.0 : ldexp((double)uabs64(S.s1[3 + a]), F.ep[a]);
+        const double v = F.pzero[a] ? 0.0 : ldexp(fabs(s1[3 + a]), F.ep[a]);
         if (a == 0 || v < bv) { bv = v; best = a; }
     }
     return best;
+}
+
+// Step 5 threshold: c * S0 <= S1  <=>  c <= floor(S1 / S0), exact for |S1| <= 2^53, S0 <= 2^31.
+VPM_DEV int cut_threshold(double s1, double s0) {
+    const int64_t S1 = (int64_t)s1, S0 = (int64_t)s0;
+    int64_t t = (int64_t)floor(s1 / s0);
+    if (t * S0 > S1) t -= 1;
+    else if ((t + 1) * S0 <= S1) t += 1;
+    return (int)t;
 }
 
 // Is Delta_a^2 = Va/Da strictly larger than Delta_b^2 = Vb/Db?  D == 0 with V > 0 is +infinity.
@@ -145,11 +152,14 @@ VPM_DEV bool frac_gt(U128 Va, U128 Da, U128 Vb, U128 Db) {
     return cmp256(mul128(Va, Db), mul128(Vb, Da)) > 0;
 }
 
-VPM_DEV Decision decide(const Sums& S, int len, const FixedParams& P, const Frame& F) {
+// The exact rule on exact integer moments.
+VPM_DEV Decision decide_exact(const ISums& S, const FixedParams& P, const Frame& F) {
     Decision d;
-    d.axis = 0; d.thr = 0; d.jdir = 0;
-    if (len < P.min_subset) { d.kind = D_COPY; return d; }
-    d.jdir = pair_axis(S, F);
+    d.axis = 0; d.thr = 0;
+    double s1d[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) s1d[l] = (double)S.s1[l];
+    d.jdir = pair_axis(s1d, F);
     if (S.s0 == 0) { d.kind = D_MERGED; return d; }
     const uint64_t s0 = S.s0;
     const U128 s0sq = mul64(s0, s0);                 // <= 2^62
@@ -168,7 +178,6 @@ VPM_DEV Decision decide(const Sums& S, int len, const FixedParams& P, const Fram
         D[3 + a] = mul64(s1, s1);
         V[3 + a] = sub128(s0s2, D[3 + a]);
     }
-    // Step 3: all six CVs within tolerance?
     bool done = true;
     {
         const U128 rhs = mul64(P.that_x * P.that_x, s0sq.lo);     // That^2 S0^2
@@ -189,17 +198,85 @@ VPM_DEV Decision decide(const Sums& S, int len, const FixedParams& P, const Fram
         }
     }
     if (done) { d.kind = D_MERGED; return d; }
-    // Step 4: axis of the largest CV (ties to the lowest axis)
     int k = 0;
     U128 bV = V[0], bD = D[0];
-    int64_t s1 = S.s1[0];
+    double s1k = s1d[0];
 #pragma unroll
     for (int l = 1; l < 6; ++l)
-        if (frac_gt(V[l], D[l], bV, bD)) { k = l; bV = V[l]; bD = D[l]; s1 = S.s1[l]; }
-    // Step 5: c * S0 <= S1  <=>  c <= floor(S1 / S0)
-    int64_t t = (int64_t)floor((double)s1 / (double)s0);
-    if (t * (int64_t)s0 > s1) t -= 1;
-    else if ((t + 1) * (int64_t)s0 <= s1) t += 1;
+        if (frac_gt(V[l], D[l], bV, bD)) { k = l; bV = V[l]; bD = D[l]; s1k = s1d[l]; }
+    d.kind = D_SPLIT;
+    d.axis = k;
+    d.thr = cut_threshold(s1k, (double)S.s0);
+    return d;
+}
+
+// The same rule evaluated in floating point with error bounds.  Sets ok = false when a comparison
+// cannot be certified (the caller then applies the exact rule).
+//   V = S0 S2 - S1^2 in FP64 (S0, S1 exact; the FMA removes the rounding of S1^2):
+//       |V_fp64 - V| <= EV = fl(S0 S2) (len + 16) 2^-51   (S2 rounded over at most len + 6 operations)
+//   Step 3 thresholds R are within 2^-50 relative of the exact ones.
+//   Step 4: Delta^2 = V/D is bracketed in FP32 (conversions, a 1-ulp reciprocal and one product stay
+//   below 2^-21 relative; the bracket is widened by 2^-19).
+// `amask` has bit l set for the axes whose codes vary in the cell; the others have V = 0.
+VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, const Frame& F, int amask, bool& ok) {
+    Decision d;
+    d.axis = 0; d.thr = 0; d.jdir = 0;
+    ok = true;
+    const double s0 = S.s0;
+    if (s0 == 0.0) { d.kind = D_MERGED; d.jdir = pair_axis(S.s1, F); return d; }
+    const double slack = (double)(len + 16) * 0x1p-51;
+    const double s0sq = s0 * s0;
+    const double rx = P.tx2 * s0sq * 0x1p-16;
+    const float rdx = __builtin_amdgcn_rcpf((float)(s0sq * 0x1p32));
+    float lo[6], hi[6];
+    bool fail = false, unsure = false;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        lo[l] = 0.0f; hi[l] = 0.0f;
+        if (!((amask >> l) & 1)) continue;            // wave-uniform
+        const double s1 = S.s1[l], s2 = S.s2[l];
+        const double bh = s1 * s1;
+        const double bl = fma(s1, s1, -bh);
+        const double V = fma(s0, s2, -bh) - bl;
+        const double EV = s0 * s2 * slack;
+        const double vlo = V - EV, vhi = V + EV;
+        const bool vzero = vhi < 1.0;                 // V is an integer >= 0
+        const bool vpos = vlo > 0.0;
+        const bool inf_axis = l >= 3 && s1 == 0.0;    // D = 0
+        // Step 3 (branch-free)
+        const double R = l < 3 ? rx : P.tp2 * bh * 0x1p-48;
+        const bool f = inf_axis ? vpos : (vlo > R * (1.0 + 0x1p-50));
+        const bool p = inf_axis ? vzero : (vhi < R * (1.0 - 0x1p-50));
+        fail |= f;
+        unsure |= !(f || p);
+        // Step 4 bracket for Delta_l^2
+        const float rd = l < 3 ? rdx : __builtin_amdgcn_rcpf((float)bh);
+        const float lf = (float)fmax(vlo, 0.0) * rd * (1.0f - 0x1p-19f);
+        const float hf = (float)vhi * rd * (1.0f + 0x1p-19f);
+        lo[l] = vzero ? 0.0f : (inf_axis ? (vpos ? INFINITY : 0.0f) : lf);
+        hi[l] = vzero ? 0.0f : (inf_axis ? INFINITY : hf);
+    }
+    if (!fail) {
+        if (unsure) { ok = false; return d; }
+        d.kind = D_MERGED;
+        d.jdir = pair_axis(S.s1, F);
+        return d;
+    }
+    int k = 0;
+    float best = lo[0];
+#pragma unroll
+    for (int l = 1; l < 6; ++l) if (lo[l] > best) { best = lo[l]; k = l; }
+#pragma unroll
+    for (int l = 0; l < 6; ++l) if (l != k && !(best > hi[l])) ok = false;
+    if (!ok) return d;
+    double s1k = S.s1[0];
+#pragma unroll
+    for (int l = 1; l < 6; ++l) if (l == k) s1k = S.s1[l];
+    // Step 5 threshold floor(S1/S0): approximate quotient, then exact correction (all products
+    // below 2^53, so exact in FP64)
+    double t = floor(s1k * __builtin_amdgcn_rcp(s0));
+    while (t * s0 > s1k) t -= 1.0;
+    while ((t + 1.0) * s0 <= s1k) t += 1.0;
     d.kind = D_SPLIT;
     d.axis = k;
     d.thr = (int)t;
@@ -215,11 +292,11 @@ VPM_DEV Decision unpack_decision(int v) {
     return d;
 }
 
-VPM_DEV int group_size_for(int len) {
-    int want = (len + PPL - 1) / PPL;
-    int g = 1;
-    while (g < want && g < WAVE) g <<= 1;
-    return g;
+VPM_DEV int group_class_for(int len) {       // log2 of the group size
+    const int want = (len + PPL - 1) / PPL;
+    int c = 0;
+    while ((1 << c) < want && c < 6) ++c;
+    return c;
 }
 
 VPM_DEV void wave_fence() {
@@ -228,54 +305,75 @@ VPM_DEV void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+VPM_DEV int frexp_exp(float v) {
+    int e = 0;
+    if (v > 0.0f) frexpf(v, &e);
+    return e;
+}
+
+VPM_DEV int ceil_log2(int v) {
+    int b = 0;
+    while ((1 << b) < v) ++b;
+    return b;
+}
+
+// q(a*b, G): the exact FP32 x FP32 product, rounded to nearest on the grid 2^-G.
+VPM_DEV int64_t fixq(float a, float b, int G) {
+    return __double2ll_rn(ldexp((double)a * (double)b, G));
+}
+
 // ------------------------------------------------------------------------------------------
-// Per-cell memory (LDS or a global slab) and kernel arguments.
+// Per-cell memory (an LDS slice or a global slab) and kernel arguments.
 // ------------------------------------------------------------------------------------------
 
-template <typename IdxT>
-struct CellMem {
-    uint16_t* om;
-    int16_t *cp0, *cp1, *cp2;
-    int32_t *cm0, *cm1, *cm2;
-    IdxT *idx0, *idx1;
-    uint8_t* info;
-    IdxT* emit;                    // output slot per position; lane map while splitting
-    Node<IdxT> *nodes0, *nodes1;   // current / next level (also leaf tables at the end)
+struct WaveShared {          // per-wave bookkeeping
+    int nnext;
+    int nmerged;
+    int cls_cnt[8];
+    int cls_cur[8];
+    uint32_t flags;
 };
 
 template <typename IdxT>
-__host__ __device__ constexpr size_t cell_mem_bytes(int nmax) {
-    return (size_t)nmax * (2 + 6 + 12 + 2 * sizeof(IdxT) + 1 + sizeof(IdxT)) +
-           sizeof(IdxT) + 2 * ((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>) + 64;
+struct CellMem {
+    WaveShared* sh;
+    uint16_t* om;
+    int16_t* cp;                   // position codes, axis a at cp + a * sp
+    int32_t* cm;                   // momentum codes, axis a at cm + a * sm
+    int sp, sm;
+    IdxT *idx0, *idx1;
+    uint8_t* info;
+    IdxT* emit;                    // output slot per position; schedule table while splitting
+    Node<IdxT> *nodes0, *nodes1;   // current / next level (leaf tables at the end)
+};
+
+__host__ __device__ constexpr size_t rnd16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+template <typename IdxT>
+__host__ __device__ constexpr size_t slice_bytes(int nmax) {
+    return rnd16(sizeof(WaveShared)) + 2 * rnd16(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>)) +
+           3 * rnd16((size_t)nmax * 4) + 2 * rnd16((size_t)nmax * sizeof(IdxT)) +
+           rnd16(((size_t)nmax + 1) * sizeof(IdxT)) + 4 * rnd16((size_t)nmax * 2) + rnd16((size_t)nmax);
 }
 
 template <typename IdxT>
 VPM_DEV CellMem<IdxT> carve(uint8_t* base, int nmax) {
     CellMem<IdxT> M;
     size_t o = 0;
-    auto take = [&](size_t bytes) { uint8_t* p = base + o; o += (bytes + 15) & ~(size_t)15; return p; };
+    auto take = [&](size_t bytes) { uint8_t* p = base + o; o += rnd16(bytes); return p; };
+    M.sh = (WaveShared*)take(sizeof(WaveShared));
     M.nodes0 = (Node<IdxT>*)take(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>));
     M.nodes1 = (Node<IdxT>*)take(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>));
-    M.cm0 = (int32_t*)take((size_t)nmax * 4);
-    M.cm1 = (int32_t*)take((size_t)nmax * 4);
-    M.cm2 = (int32_t*)take((size_t)nmax * 4);
+    M.sm = (int)(rnd16((size_t)nmax * 4) / 4);
+    M.cm = (int32_t*)take((size_t)3 * M.sm * 4);
     M.idx0 = (IdxT*)take((size_t)nmax * sizeof(IdxT));
     M.idx1 = (IdxT*)take((size_t)nmax * sizeof(IdxT));
     M.emit = (IdxT*)take(((size_t)nmax + 1) * sizeof(IdxT));
     M.om = (uint16_t*)take((size_t)nmax * 2);
-    M.cp0 = (int16_t*)take((size_t)nmax * 2);
-    M.cp1 = (int16_t*)take((size_t)nmax * 2);
-    M.cp2 = (int16_t*)take((size_t)nmax * 2);
+    M.sp = (int)(rnd16((size_t)nmax * 2) / 2);
+    M.cp = (int16_t*)take((size_t)3 * M.sp * 2);
     M.info = (uint8_t*)take((size_t)nmax);
     return M;
-}
-
-template <typename IdxT>
-__host__ __device__ constexpr size_t carve_bytes(int nmax) {
-    auto r = [](size_t b) { return (b + 15) & ~(size_t)15; };
-    return 2 * r(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>)) + 3 * r((size_t)nmax * 4) +
-           2 * r((size_t)nmax * sizeof(IdxT)) + r(((size_t)nmax + 1) * sizeof(IdxT)) +
-           4 * r((size_t)nmax * 2) + r((size_t)nmax);
 }
 
 struct FixedArgs {
@@ -291,97 +389,121 @@ struct FixedArgs {
     uint8_t* cell_mode;
     uint32_t* flags;
     int32_t *perm, *subset_id, *n_subsets;
-    uint8_t* big;                  // global slabs for the big-cell path
+    uint8_t* big;                  // global slabs for the large-cell path
     int64_t big_stride;            // bytes per slab
-    int nslabs;
 };
-
-// Shared per-workgroup bookkeeping (always in LDS).
-struct Shared {
-    Frame F;
-    int cell;
-    int nnodes[2];
-    int cls_cnt[8], cls_base[8], cls_cur[8];
-    int total_lanes;
-    int nleaves, nmerged, out_total;
-    int root_dec;
-    uint32_t flags;
-    int64_t red64[16 * 2];
-    float redf[16 * 11];
-    Sums redS[BLOCK / WAVE];
-};
-
-// q(a*b, G): the exact FP32 x FP32 product, rounded to nearest on the grid 2^-G.
-VPM_DEV int64_t fixq(float a, float b, int G) {
-    return __double2ll_rn(ldexp((double)a * (double)b, G));
-}
 
 template <typename IdxT>
 VPM_DEV IdxT* idx_buf(const CellMem<IdxT>& M, int par) { return par ? M.idx1 : M.idx0; }
 
 template <typename IdxT>
 VPM_DEV int code_of(const CellMem<IdxT>& M, int k, int i) {
-    switch (k) {
-        case 0: return M.cp0[i];
-        case 1: return M.cp1[i];
-        case 2: return M.cp2[i];
-        case 3: return M.cm0[i];
-        case 4: return M.cm1[i];
-        default: return M.cm2[i];
-    }
+    return k < 3 ? (int)M.cp[k * M.sp + i] : M.cm[(k - 3) * M.sm + i];
 }
 
 template <typename IdxT>
-VPM_DEV void add_particle(Sums& S, const CellMem<IdxT>& M, int i) {
-    sums_add(S, M.om[i], M.cp0[i], M.cp1[i], M.cp2[i], M.cm0[i], M.cm1[i], M.cm2[i]);
+VPM_DEV void codes_of(const CellMem<IdxT>& M, int i, int c[6], int& om) {
+    om = M.om[i];
+    c[0] = M.cp[i]; c[1] = M.cp[M.sp + i]; c[2] = M.cp[2 * M.sp + i];
+    c[3] = M.cm[i]; c[4] = M.cm[M.sm + i]; c[5] = M.cm[2 * M.sm + i];
 }
 
-// Schedule `m` items (lengths from len_of(item)) onto power-of-two lane groups, largest first.
-// Writes the lane map (virtual lane -> item) and sets S.total_lanes.  All threads call.
+// Decide one subset [start, start+len) of buffer `buf` from its FP64 moments; falls back to
+// exact integer moments recomputed from the codes when the FP64 evaluation is inconclusive.
+template <typename IdxT>
+VPM_DEV Decision decide(const CellMem<IdxT>& M, const FSums& S, const IdxT* buf, int start, int len,
+                        const FixedParams& P, const Frame& F) {
+    Decision d;
+    if (len < P.min_subset) { d.kind = D_COPY; d.axis = 0; d.thr = 0; d.jdir = 0; return d; }
+    bool ok;
+    d = decide_fast(S, len, P, F, F.amask, ok);
+    if (ok) return d;
+    ISums E;
+    E.s0 = 0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) E.s1[l] = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { E.s2p[a] = 0; E.s2m[a] = u128_make(0, 0); }
+    for (int j = 0; j < len; ++j) {
+        int c[6], om;
+        codes_of(M, buf[start + j], c, om);
+        isums_add(E, (uint32_t)om, c);
+    }
+    return decide_exact(E, P, F);
+}
+
+// Sort the m items of a list into power-of-two lane-group classes (largest first).  Afterwards
+// the lane groups of class c occupy virtual lanes [lb[c], lb[c] + (cnt[c] << c)) and
+// sched[fb[c] + k] holds the k-th item of class c.  Whole wave calls.
+struct Sched { int lb[7], fb[7], cnt[7], total; };
+
 template <typename IdxT, typename LenFn>
-VPM_DEV void schedule(Shared& S, IdxT* lanemap, int m, LenFn len_of) {
-    const int tid = threadIdx.x;
-    if (tid < 8) { S.cls_cnt[tid] = 0; S.cls_cur[tid] = 0; }
-    __syncthreads();
-    for (int it = tid; it < m; it += BLOCK) {
-        const int g = group_size_for(len_of(it));
-        atomicAdd(&S.cls_cnt[__ffs(g) - 1], 1);
+VPM_DEV Sched schedule(const CellMem<IdxT>& M, IdxT* sched, int m, LenFn len_of) {
+    const int lane = lane_id();
+    if (lane < 8) { M.sh->cls_cnt[lane] = 0; M.sh->cls_cur[lane] = 0; }
+    wave_fence();
+    for (int it = lane; it < m; it += WAVE) atomicAdd(&M.sh->cls_cnt[group_class_for(len_of(it))], 1);
+    wave_fence();
+    Sched s;
+    int l = 0, f = 0;
+#pragma unroll
+    for (int c = 6; c >= 0; --c) {
+        s.cnt[c] = M.sh->cls_cnt[c];
+        s.lb[c] = l; s.fb[c] = f;
+        l += s.cnt[c] << c; f += s.cnt[c];
     }
-    __syncthreads();
-    if (tid == 0) {
-        int b = 0;
-        for (int c = 6; c >= 0; --c) { S.cls_base[c] = b; b += S.cls_cnt[c] << c; }
-        S.total_lanes = b;
+    s.total = l;
+    for (int it = lane; it < m; it += WAVE) {
+        const int c = group_class_for(len_of(it));
+        const int r = atomicAdd(&M.sh->cls_cur[c], 1);
+        int fbc = s.fb[0];
+#pragma unroll
+        for (int q = 1; q < 7; ++q) if (q == c) fbc = s.fb[q];
+        sched[fbc + r] = (IdxT)it;
     }
-    __syncthreads();
-    for (int it = tid; it < m; it += BLOCK) {
-        const int g = group_size_for(len_of(it));
-        const int c = __ffs(g) - 1;
-        const int r = atomicAdd(&S.cls_cur[c], 1);
-        const int off = S.cls_base[c] + (r << c);
-        for (int v = 0; v < g; ++v) lanemap[off + v] = (IdxT)it;
-    }
-    __syncthreads();
+    wave_fence();
+    return s;
 }
 
-// Process one unfinished subset with a lane group: compaction, child sums, child decisions.
+// Virtual lane v -> (item slot, class).  Returns false if v is past the last group.
+VPM_DEV bool sched_lookup(const Sched& s, int v, int& slot, int& cls) {
+    if (v >= s.total) return false;
+    cls = 0;
+    slot = 0;
+#pragma unroll
+    for (int c = 6; c >= 0; --c) {
+        if (v >= s.lb[c] && v < s.lb[c] + (s.cnt[c] << c)) { cls = c; slot = s.fb[c] + ((v - s.lb[c]) >> c); }
+    }
+    return true;
+}
+
+// Process one unfinished subset with a lane group: compaction, child moments, child decisions.
 template <typename IdxT>
-VPM_DEV void split_node(Shared& S, const CellMem<IdxT>& M, const FixedArgs& A, Node<IdxT> nd,
-                        int cur, int lid, int g, int gbase, Node<IdxT>* next, int nxt) {
+VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, Node<IdxT> nd,
+                        int cur, int lid, int g, int gbase, Node<IdxT>* next) {
     const int start = nd.start, len = nd.len;
     const int k = nd.thr_axis & 7;
     const int thr = nd.thr_axis >> 3;
     const IdxT* src = idx_buf(M, cur);
     IdxT* dst = idx_buf(M, cur ^ 1);
 
-    // pass 1: size of the lower side V1 = {c <= thr}
+    // size of the lower side V1 = {c <= thr}
     int nl = 0;
-    for (int j = lid; j < len; j += g) nl += code_of(M, k, src[start + j]) <= thr ? 1 : 0;
+    if (k < 3) {
+        const int16_t* ck = M.cp + k * M.sp;
+#pragma unroll 4
+        for (int j = lid; j < len; j += g) nl += ck[src[start + j]] <= thr ? 1 : 0;
+    } else {
+        const int32_t* ck = M.cm + (k - 3) * M.sm;
+#pragma unroll 4
+        for (int j = lid; j < len; j += g) nl += ck[src[start + j]] <= thr ? 1 : 0;
+    }
     nl = group_sum(nl, g);
 
-    // pass 2: stable compaction into the other buffer (Step 6)
+    // stable compaction into the other buffer (Step 6)
     const uint64_t below = lanes_below() >> gbase;
     int lb = 0, rb = 0;
+#pragma unroll 2
     for (int j0 = 0; j0 < len; j0 += g) {
         const int j = j0 + lid;
         const bool act = j < len;
@@ -402,26 +524,47 @@ VPM_DEV void split_node(Shared& S, const CellMem<IdxT>& M, const FixedArgs& A, N
     const int n1 = nl, n2 = len - nl;
     int dv0, dv1;
     if (n1 == 0 || n2 == 0) {
-        // Cannot happen with exact arithmetic (the chosen axis has V > 0); end the subset.
+        // Impossible under the exact rule (the chosen axis has V > 0); end the subset.
         Decision d; d.kind = D_MERGED; d.axis = 0; d.thr = 0; d.jdir = 0;
-        if (lid == 0) atomicOr(&S.flags, FLAG_INTERNAL);
+        if (lid == 0) atomicOr(&M.sh->flags, FLAG_INTERNAL);
         dv0 = pack_decision(d);
         dv1 = -1;
     } else {
-        Sums L, R;
-        sums_zero(L); sums_zero(R);
-        for (int j = lid; j < n1; j += g) add_particle(L, M, dst[start + j]);
-        for (int j = lid; j < n2; j += g) add_particle(R, M, dst[start + n1 + j]);
-        sums_group_reduce(L, g);
-        sums_group_reduce(R, g);
-        int mine = 0;
+        FSums L, R;
+        fsums_zero(L); fsums_zero(R);
+#pragma unroll 2
+        for (int j = lid; j < n1; j += g) {
+            int c[6], om;
+            codes_of(M, dst[start + j], c, om);
+            fsums_add(L, F.amask, om, c[0], c[1], c[2], c[3], c[4], c[5]);
+        }
+#pragma unroll 2
+        for (int j = lid; j < n2; j += g) {
+            int c[6], om;
+            codes_of(M, dst[start + n1 + j], c, om);
+            fsums_add(R, F.amask, om, c[0], c[1], c[2], c[3], c[4], c[5]);
+        }
+        fsums_group_reduce(L, g);
+        fsums_group_reduce(R, g);
+        // lane 0 of the group decides V1 and lane 1 decides V2 (a single lane decides both in turn)
+        int mine0 = 0, mine1 = 0;
+        for (int ch = 0; ch < (g == 1 ? 2 : 1); ++ch) {
+            const bool left = g == 1 ? ch == 0 : lid == 0;
+            if (g == 1 || lid < 2) {
+                FSums C;
+                C.s0 = left ? L.s0 : R.s0;
+#pragma unroll
+                for (int l = 0; l < 6; ++l) { C.s1[l] = left ? L.s1[l] : R.s1[l]; C.s2[l] = left ? L.s2[l] : R.s2[l]; }
+                const int v = pack_decision(decide(M, C, dst, left ? start : start + n1, left ? n1 : n2, A.P, F));
+                if (ch == 0) mine0 = v; else mine1 = v;
+            }
+        }
         if (g == 1) {
-            dv0 = pack_decision(decide(L, n1, A.P, S.F));
-            dv1 = pack_decision(decide(R, n2, A.P, S.F));
+            dv0 = mine0;
+            dv1 = mine1;
         } else {
-            if (lid < 2) mine = pack_decision(decide(lid == 0 ? L : R, lid == 0 ? n1 : n2, A.P, S.F));
-            dv0 = __shfl(mine, gbase);
-            dv1 = __shfl(mine, gbase + 1);
+            dv0 = __shfl(mine0, gbase);
+            dv1 = __shfl(mine0, gbase + 1);
         }
     }
 
@@ -434,7 +577,7 @@ VPM_DEV void split_node(Shared& S, const CellMem<IdxT>& M, const FixedArgs& A, N
         const int cl = (dv1 == -1) ? len : (ch == 0 ? n1 : n2);
         if (d.kind == D_SPLIT) {
             if (lid == 0) {
-                const int slot = atomicAdd(&S.nnodes[nxt], 1);
+                const int slot = atomicAdd(&M.sh->nnext, 1);
                 Node<IdxT> c;
                 c.start = (IdxT)cs; c.len = (IdxT)cl; c.thr_axis = (d.thr << 3) | d.axis;
                 next[slot] = c;
@@ -448,12 +591,6 @@ VPM_DEV void split_node(Shared& S, const CellMem<IdxT>& M, const FixedArgs& A, N
     }
 }
 
-VPM_DEV int ceil_log2(int v) {
-    int b = 0;
-    while ((1 << b) < v) ++b;
-    return b;
-}
-
 // Merge one finished subset with a lane group (Step 7) and write its 1 or 2 particles.
 //
 // Two passes over the subset, all sums exact int64 on fixed grids (so the result does not depend
@@ -464,9 +601,8 @@ VPM_DEV int ceil_log2(int v) {
 // eps_i - eps(pt) is formed as (|d|^2 + 2 pt.d) / (eps_i + eps(pt)), d = p - pt, which does not
 // cancel; the FP64 solve then forms r = mean(eps)^2 - m^2 - |P|^2 from these differences.
 template <typename IdxT>
-VPM_DEV void merge_leaf(const Shared& S, const CellMem<IdxT>& M, const FixedArgs& A, int64_t off,
+VPM_DEV void merge_leaf(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, int64_t off,
                         int start, int len, int lid, int g) {
-    const Frame& F = S.F;
     const uint8_t inf = M.info[start];
     const IdxT* src = idx_buf(M, inf & INF_PARITY);
     const int jdir = (inf >> INF_JSHIFT) & 3;
@@ -565,176 +701,183 @@ VPM_DEV void merge_leaf(const Shared& S, const CellMem<IdxT>& M, const FixedArgs
     }
 }
 
-VPM_DEV int frexp_exp(float v) {
-    int e = 0;
-    if (v > 0.0f) frexpf(v, &e);
-    return e;
+VPM_DEV float wave_max(float v) {
+    for (int m = 1; m < WAVE; m <<= 1) v = fmaxf(v, __shfl_xor(v, m));
+    return v;
 }
 
 // ------------------------------------------------------------------------------------------
-// The cell kernel.
+// The cell kernel: one wavefront per cell.
 // ------------------------------------------------------------------------------------------
 
-template <int NMAX, typename IdxT, bool IN_LDS>
-__global__ __launch_bounds__(BLOCK) void k_fixed_cells(FixedArgs A) {
+template <int NMAX, typename IdxT, bool IN_LDS, int WPB>
+__global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ Shared S;
-    const int tid = threadIdx.x;
-
-    CellMem<IdxT> M;
-    if (IN_LDS) M = carve<IdxT>(smem, NMAX);
-    else M = carve<IdxT>(A.big + (int64_t)blockIdx.x * A.big_stride, NMAX);
+    const int lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
+    constexpr size_t SLICE = slice_bytes<IdxT>(NMAX);
+    CellMem<IdxT> M = IN_LDS ? carve<IdxT>(smem + (size_t)wv * SLICE, NMAX)
+                             : carve<IdxT>(A.big + ((int64_t)blockIdx.x * WPB + wv) * A.big_stride, NMAX);
+    WaveShared& sh = *M.sh;
 
     for (;;) {
-        __syncthreads();
-        if (tid == 0) {
-            const int qi = atomicAdd(&A.counters[A.work_index], 1);
-            S.cell = qi < A.counters[A.qlen_index] ? A.queue[qi] : -1;
-            S.flags = 0;
-        }
-        __syncthreads();
-        const int c = S.cell;
-        if (c < 0) break;
+        int qi = 0;
+        if (lane == 0) qi = atomicAdd(&A.counters[A.work_index], 1);
+        qi = __shfl(qi, 0);
+        if (qi >= A.counters[A.qlen_index]) break;
+        const int c = A.queue[qi];
         const int64_t off = A.cell_off[c];
         const int n = (int)(A.cell_off[c + 1] - off);
 
         // ---- Step 1: collect the cell, validate, frame ----
-        {
-            float v[11];
-            v[0] = 0.0f;
-            for (int a = 0; a < 3; ++a) { v[1 + a] = INFINITY; v[4 + a] = -INFINITY; v[7 + a] = 0.0f; }
-            float bad = 0.0f;
-            for (int i = tid; i < n; i += BLOCK) {
-                const float w = A.in.w[off + i];
-                const float q[6] = {A.in.x[off + i], A.in.y[off + i], A.in.z[off + i],
-                                    A.in.px[off + i], A.in.py[off + i], A.in.pz[off + i]};
-                bool ok = w > 0.0f && isfinite(w);
-                for (int l = 0; l < 6; ++l) ok = ok && isfinite(q[l]);
-                if (!ok) bad = 1.0f;
-                v[0] = fmaxf(v[0], w);
-                for (int a = 0; a < 3; ++a) {
-                    v[1 + a] = fminf(v[1 + a], q[a]);
-                    v[4 + a] = fmaxf(v[4 + a], q[a]);
-                    v[7 + a] = fmaxf(v[7 + a], fabsf(q[3 + a]));
-                }
+        // The cell is read twice (the second pass hits the caches); keeping it in registers would
+        // cost occupancy.
+        constexpr int RC = 1;
+        float cache[RC][7];
+        auto load = [&](int i, float* q) {
+            q[0] = A.in.x[off + i]; q[1] = A.in.y[off + i]; q[2] = A.in.z[off + i];
+            q[3] = A.in.px[off + i]; q[4] = A.in.py[off + i]; q[5] = A.in.pz[off + i];
+            q[6] = A.in.w[off + i];
+        };
+        float vmax[11];
+        vmax[0] = 0.0f;
+        for (int a = 0; a < 3; ++a) { vmax[1 + a] = -INFINITY; vmax[4 + a] = -INFINITY; vmax[7 + a] = 0.0f; }
+        bool bad = false;
+        auto scan_particle = [&](const float* q) {
+            const float w = q[6];
+            bool ok = w > 0.0f && isfinite(w);
+            for (int l = 0; l < 6; ++l) ok = ok && isfinite(q[l]);
+            bad |= !ok;
+            vmax[0] = fmaxf(vmax[0], w);
+            for (int a = 0; a < 3; ++a) {
+                vmax[1 + a] = fmaxf(vmax[1 + a], -q[a]);
+                vmax[4 + a] = fmaxf(vmax[4 + a], q[a]);
+                vmax[7 + a] = fmaxf(vmax[7 + a], fabsf(q[3 + a]));
             }
-            v[10] = bad;
-            // workgroup max/min of the 11 values (min as max of negatives)
-            for (int a = 1; a < 4; ++a) v[a] = -v[a];
-            for (int r = 0; r < 11; ++r)
-                for (int m = 1; m < WAVE; m <<= 1) v[r] = fmaxf(v[r], __shfl_xor(v[r], m));
-            if (lane_id() == 0)
-                for (int r = 0; r < 11; ++r) S.redf[(tid / WAVE) * 11 + r] = v[r];
-            __syncthreads();
-            if (tid == 0) {
-                for (int w = 1; w < BLOCK / WAVE; ++w)
-                    for (int r = 0; r < 11; ++r) v[r] = fmaxf(v[r], S.redf[w * 11 + r]);
-                Frame& F = S.F;
-                F.wmax = v[0];
-                for (int a = 0; a < 3; ++a) { F.lo[a] = -v[1 + a]; F.hi[a] = v[4 + a]; F.pmax[a] = v[7 + a]; }
-                F.bad = v[10] != 0.0f;
-                F.ew = frexp_exp(F.wmax);
-                for (int a = 0; a < 3; ++a) {
-                    F.pzero[a] = F.pmax[a] == 0.0f;
-                    F.ep[a] = frexp_exp(F.pmax[a]);
-                    F.ext_e[a] = frexp_exp(F.hi[a] - F.lo[a]);
-                }
-                // |eps_i - eps_j| <= m + |p|_1 for any two particles of the cell; 4x margin
-                F.eb = frexp_exp(4.0f * ((float)A.P.mass + F.pmax[0] + F.pmax[1] + F.pmax[2]));
-                S.nnodes[0] = 0; S.nnodes[1] = 0;
+        };
+        if constexpr (RC > 1) {
+#pragma unroll
+            for (int r = 0; r < RC; ++r)
+                if (lane + r * WAVE < n) load(lane + r * WAVE, cache[r]);
+#pragma unroll
+            for (int r = 0; r < RC; ++r)
+                if (lane + r * WAVE < n) scan_particle(cache[r]);
+        } else {
+#pragma unroll 2
+            for (int i = lane; i < n; i += WAVE) {
+                float q[7];
+                load(i, q);
+                scan_particle(q);
             }
-            __syncthreads();
         }
-        if (S.F.bad) {
-            if (tid == 0) {
+        if (__ballot(bad) != 0) {
+            if (lane == 0) {
                 atomicOr(A.flags, FLAG_BAD_VALUE);
                 if (A.mode == 0) { A.out_count[c] = n; A.cell_mode[c] = CELL_UNTOUCHED; }
                 else A.n_subsets[c] = 0;
             }
             if (A.mode == 1)
-                for (int i = tid; i < n; i += BLOCK) { A.perm[off + i] = (int32_t)(off + i); A.subset_id[off + i] = -1; }
+                for (int i = lane; i < n; i += WAVE) { A.perm[off + i] = (int32_t)(off + i); A.subset_id[off + i] = -1; }
             continue;
         }
+#pragma unroll
+        for (int r = 0; r < 11; ++r) vmax[r] = wave_max(vmax[r]);
+        Frame F;
+        F.wmax = vmax[0];
+        F.ew = frexp_exp(F.wmax);
+        F.amask = 0;
+        for (int a = 0; a < 3; ++a) {
+            F.lo[a] = -vmax[1 + a];
+            F.hi[a] = vmax[4 + a];
+            F.pmax[a] = vmax[7 + a];
+            F.pzero[a] = F.pmax[a] == 0.0f;
+            F.ep[a] = frexp_exp(F.pmax[a]);
+            F.ext_e[a] = frexp_exp(F.hi[a] - F.lo[a]);
+            if (F.hi[a] > F.lo[a]) F.amask |= 1 << a;          // else every position code is equal
+            if (!F.pzero[a]) F.amask |= 1 << (3 + a);          // else every momentum code is 0
+        }
+        F.amask = __builtin_amdgcn_readfirstlane(F.amask);     // wave-uniform: scalar branches
+        // |eps_i - eps_j| <= m + |p|_1 for any two particles of the cell; 4x margin
+        F.eb = frexp_exp(4.0f * ((float)A.P.mass + F.pmax[0] + F.pmax[1] + F.pmax[2]));
+        if (lane == 0) { sh.flags = 0; sh.nnext = 0; }
 
         // ---- codes and the root's moments ----
-        {
-            const Frame& F = S.F;
-            Sums R;
-            sums_zero(R);
-            bool oob = false;
-            for (int i = tid; i < n; i += BLOCK) {
-                const float w = A.in.w[off + i];
-                const uint32_t om = (uint32_t)rintf(ldexpf(w, 15 - F.ew));
-                int cp[3], cm[3];
-                const float x[3] = {A.in.x[off + i], A.in.y[off + i], A.in.z[off + i]};
-                const float p[3] = {A.in.px[off + i], A.in.py[off + i], A.in.pz[off + i]};
-                for (int a = 0; a < 3; ++a) {
-                    const float d = x[a] - F.lo[a];
-                    float r = rintf(d * A.P.s[a]);
-                    if (r > 65536.0f) oob = true;
-                    r = fminf(r, 65535.0f);
-                    cp[a] = (int)r - 32768;
-                    cm[a] = F.pzero[a] ? 0 : (int)rintf(ldexpf(p[a], 22 - F.ep[a]));
-                }
-                M.om[i] = (uint16_t)om;
-                M.cp0[i] = (int16_t)cp[0]; M.cp1[i] = (int16_t)cp[1]; M.cp2[i] = (int16_t)cp[2];
-                M.cm0[i] = cm[0]; M.cm1[i] = cm[1]; M.cm2[i] = cm[2];
-                M.idx0[i] = (IdxT)i;
-                sums_add(R, om, cp[0], cp[1], cp[2], cm[0], cm[1], cm[2]);
+        FSums R;
+        fsums_zero(R);
+        bool oob = false;
+        auto encode = [&](int i, const float* q) {
+            const int om = (int)rintf(ldexpf(q[6], 15 - F.ew));
+            int cc[6];
+            for (int a = 0; a < 3; ++a) {
+                const float d = q[a] - F.lo[a];
+                float r = rintf(d * A.P.s[a]);
+                oob |= r > 65536.0f;
+                r = fminf(r, 65535.0f);
+                cc[a] = (int)r - 32768;
+                cc[3 + a] = F.pzero[a] ? 0 : (int)rintf(ldexpf(q[3 + a], 22 - F.ep[a]));
             }
-            if (oob) atomicOr(&S.flags, FLAG_OUT_OF_CELL);
-            sums_group_reduce(R, WAVE);
-            if (lane_id() == 0) S.redS[tid / WAVE] = R;
-            __syncthreads();
-            if (tid == 0) {
-                for (int w = 1; w < BLOCK / WAVE; ++w) sums_merge(R, S.redS[w]);
-                const Decision d = decide(R, n, A.P, S.F);
-                S.root_dec = pack_decision(d);
-                if (d.kind == D_SPLIT) {
-                    Node<IdxT> nd;
-                    nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (d.thr << 3) | d.axis;
-                    M.nodes0[0] = nd;
-                    S.nnodes[0] = 1;
-                }
+            M.om[i] = (uint16_t)om;
+            M.cp[i] = (int16_t)cc[0]; M.cp[M.sp + i] = (int16_t)cc[1]; M.cp[2 * M.sp + i] = (int16_t)cc[2];
+            M.cm[i] = cc[3]; M.cm[M.sm + i] = cc[4]; M.cm[2 * M.sm + i] = cc[5];
+            M.idx0[i] = (IdxT)i;
+            fsums_add(R, F.amask, om, cc[0], cc[1], cc[2], cc[3], cc[4], cc[5]);
+        };
+        if constexpr (RC > 1) {
+#pragma unroll
+            for (int r = 0; r < RC; ++r)
+                if (lane + r * WAVE < n) encode(lane + r * WAVE, cache[r]);
+        } else {
+#pragma unroll 2
+            for (int i = lane; i < n; i += WAVE) {
+                float q[7];
+                load(i, q);
+                encode(i, q);
             }
-            __syncthreads();
-            const Decision d = unpack_decision(S.root_dec);
-            if (d.kind != D_SPLIT) {
-                const uint8_t base = INF_SET | (d.kind == D_MERGED ? INF_MERGED : 0) |
-                                     (uint8_t)(d.jdir << INF_JSHIFT);
-                for (int i = tid; i < n; i += BLOCK) M.info[i] = base | (i == 0 ? INF_HEAD : 0);
-            }
-            __syncthreads();
         }
+        const bool any_oob = __ballot(oob) != 0;
+        fsums_group_reduce(R, WAVE);
+        wave_fence();
+        int rootv = 0;
+        if (lane == 0) rootv = pack_decision(decide(M, R, M.idx0, 0, n, A.P, F));
+        const Decision rd = unpack_decision(__shfl(rootv, 0));
+        int m = 0;
+        if (rd.kind == D_SPLIT) {
+            if (lane == 0) {
+                Node<IdxT> nd;
+                nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 3) | rd.axis;
+                M.nodes0[0] = nd;
+            }
+            m = 1;
+        } else {
+            const uint8_t base = INF_SET | (rd.kind == D_MERGED ? INF_MERGED : 0) | (uint8_t)(rd.jdir << INF_JSHIFT);
+            for (int i = lane; i < n; i += WAVE) M.info[i] = base | (i == 0 ? INF_HEAD : 0);
+        }
+        wave_fence();
 
         // ---- Steps 2-6, level by level ----
         int cur = 0;
-        while (S.nnodes[cur] > 0) {
-            const int m = S.nnodes[cur];
+        while (m > 0) {
             Node<IdxT>* curl = cur ? M.nodes1 : M.nodes0;
             Node<IdxT>* nextl = cur ? M.nodes0 : M.nodes1;
-            if (tid == 0) S.nnodes[cur ^ 1] = 0;
-            schedule<IdxT>(S, M.emit, m, [&](int it) { return (int)curl[it].len; });
-            const int total = S.total_lanes;
-            for (int r0 = 0; r0 < total; r0 += BLOCK) {
-                const int v = r0 + tid;
-                if (v < total) {
-                    const int it = M.emit[v];
-                    const Node<IdxT> nd = curl[it];
-                    const int g = group_size_for((int)nd.len);
-                    const int lid = v & (g - 1);
-                    const int gbase = lane_id() & ~(g - 1);
-                    split_node<IdxT>(S, M, A, nd, cur, lid, g, gbase, nextl, cur ^ 1);
+            if (lane == 0) sh.nnext = 0;
+            const Sched s = schedule<IdxT>(M, M.emit, m, [&](int it) { return (int)curl[it].len; });
+            for (int r0 = 0; r0 < s.total; r0 += WAVE) {
+                int slot, cls;
+                if (sched_lookup(s, r0 + lane, slot, cls)) {
+                    const Node<IdxT> nd = curl[M.emit[slot]];
+                    const int g = 1 << cls;
+                    split_node<IdxT>(M, A, F, nd, cur, lane & (g - 1), g, lane & ~(g - 1), nextl);
                 }
             }
-            __syncthreads();
+            wave_fence();
+            m = sh.nnext;
             cur ^= 1;
         }
 
         // ---- output ----
-        // per slot: leaf ordinal and output slot, by one scan over the cell's slots
-        const int per = (n + BLOCK - 1) / BLOCK;
-        const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+        // one scan over the cell's slots gives leaf ordinals and output slots
+        const int per = (n + WAVE - 1) / WAVE;
+        const int b0 = min(n, lane * per), b1 = min(n, b0 + per);
         const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
         int64_t loc = 0;
         for (int p = b0; p < b1; ++p) {
@@ -742,16 +885,19 @@ __global__ __launch_bounds__(BLOCK) void k_fixed_cells(FixedArgs A) {
             const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
             loc += ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
         }
-        int64_t tot;
-        int64_t pre = block_exclusive_scan<BLOCK>(loc, S.red64, &tot);
+        int64_t inc = loc;
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int64_t o = __shfl_up(inc, d);
+            if (lane >= d) inc += o;
+        }
+        const int64_t tot = __shfl(inc, WAVE - 1);
+        int64_t pre = inc - loc;
         const int nleaves = (int)(tot >> 32);
         const int out_total = (int)(tot & 0xffffffff);
-        // the node lists and the momentum codes are free now
         IdxT* leaf_start = (IdxT*)M.nodes0;                // first slot of each final subset
         IdxT* mlist = (IdxT*)M.nodes1;                     // ordinals of the merged subsets
-        IdxT* lanemap = (IdxT*)M.cm0;
-        if (tid == 0) { S.nmerged = 0; }
-        __syncthreads();
+        if (lane == 0) sh.nmerged = 0;
+        wave_fence();
         for (int p = b0; p < b1; ++p) {
             const uint8_t inf = M.info[p];
             const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
@@ -764,24 +910,23 @@ __global__ __launch_bounds__(BLOCK) void k_fixed_cells(FixedArgs A) {
             }
             if (inf & INF_HEAD) {
                 leaf_start[ord] = (IdxT)p;
-                if ((inf & INF_MERGED) && A.mode == 0) {
-                    const int s = atomicAdd(&S.nmerged, 1);
-                    mlist[s] = (IdxT)ord;
-                }
+                if ((inf & INF_MERGED) && A.mode == 0) mlist[atomicAdd(&sh.nmerged, 1)] = (IdxT)ord;
             }
             pre += ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
         }
-        if (tid == 0) leaf_start[nleaves] = (IdxT)n;
-        __syncthreads();
+        if (lane == 0) leaf_start[nleaves] = (IdxT)n;
+        wave_fence();
+        const uint32_t fl = sh.flags | (any_oob ? FLAG_OUT_OF_CELL : 0u);
         if (A.mode == 1) {
-            if (tid == 0) {
+            if (lane == 0) {
                 A.n_subsets[c] = nleaves;
-                if (S.flags) atomicOr(A.flags, S.flags);
+                if (fl) atomicOr(A.flags, fl);
             }
             continue;
         }
         // copied particles (subsets below min_subset)
-        for (int p = tid; p < n; p += BLOCK) {
+#pragma unroll 4
+        for (int p = lane; p < n; p += WAVE) {
             const uint8_t inf = M.info[p];
             if (inf & INF_MERGED) continue;
             const int64_t i = off + idx_buf(M, inf & INF_PARITY)[p];
@@ -791,45 +936,49 @@ __global__ __launch_bounds__(BLOCK) void k_fixed_cells(FixedArgs A) {
             A.tmp.w[o] = A.in.w[i];
         }
         // merged subsets (Step 7)
-        const int nm = S.nmerged;
+        const int nm = sh.nmerged;
         if (nm > 0) {
-            schedule<IdxT>(S, lanemap, nm, [&](int it) {
+            IdxT* sched = (IdxT*)M.cm;                     // momentum codes are free now
+            const Sched s = schedule<IdxT>(M, sched, nm, [&](int it) {
                 const int ord = mlist[it];
                 return (int)(leaf_start[ord + 1] - leaf_start[ord]);
             });
-            const int total = S.total_lanes;
-            for (int r0 = 0; r0 < total; r0 += BLOCK) {
-                const int v = r0 + tid;
-                if (v < total) {
-                    const int ord = mlist[lanemap[v]];
+            for (int r0 = 0; r0 < s.total; r0 += WAVE) {
+                int slot, cls;
+                if (sched_lookup(s, r0 + lane, slot, cls)) {
+                    const int ord = mlist[sched[slot]];
                     const int st = leaf_start[ord];
                     const int ln = leaf_start[ord + 1] - st;
-                    const int g = group_size_for(ln);
-                    merge_leaf<IdxT>(S, M, A, off, st, ln, v & (g - 1), g);
+                    const int g = 1 << cls;
+                    merge_leaf<IdxT>(M, A, F, off, st, ln, lane & (g - 1), g);
                 }
             }
         }
-        if (tid == 0) {
+        if (lane == 0) {
             A.out_count[c] = out_total;
             A.cell_mode[c] = CELL_PROCESSED;
-            if (S.flags) atomicOr(A.flags, S.flags);
+            if (fl) atomicOr(A.flags, fl);
         }
     }
 }
 
+constexpr int WPB_A = 1, WPB_B = 1, WPB_BIG = 1;
+
 }  // namespace
 
-int fixed_lds_bytes(int nmax) {
-    return (int)(nmax <= NMAX_A ? carve_bytes<uint16_t>(NMAX_A) : carve_bytes<uint16_t>(NMAX_B));
+int fixed_lds_bytes(int which) {
+    return which == 0 ? (int)(slice_bytes<uint16_t>(NMAX_A) * WPB_A) : (int)(slice_bytes<uint16_t>(NMAX_B) * WPB_B);
 }
 
-int64_t fixed_big_slab_bytes() { return (int64_t)carve_bytes<uint32_t>(NMAX_BIG); }
+int64_t fixed_big_slab_bytes() { return (int64_t)slice_bytes<uint32_t>(NMAX_BIG); }
 
 const void* fixed_kernel_ptr(int which) {
-    if (which == 0) return (const void*)k_fixed_cells<NMAX_A, uint16_t, true>;
-    if (which == 1) return (const void*)k_fixed_cells<NMAX_B, uint16_t, true>;
-    return (const void*)k_fixed_cells<NMAX_BIG, uint32_t, false>;
+    if (which == 0) return (const void*)k_fixed_cells<NMAX_A, uint16_t, true, WPB_A>;
+    if (which == 1) return (const void*)k_fixed_cells<NMAX_B, uint16_t, true, WPB_B>;
+    return (const void*)k_fixed_cells<NMAX_BIG, uint32_t, false, WPB_BIG>;
 }
+
+int fixed_block_threads(int which) { return WAVE * (which == 0 ? WPB_A : which == 1 ? WPB_B : WPB_BIG); }
 
 hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
                               const int64_t* cell_off, const FixedParams& fp, int mode,
@@ -848,25 +997,23 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
     A.perm = perm; A.subset_id = subset_id; A.n_subsets = n_subsets;
     A.big = ws.big;
     A.big_stride = fixed_big_slab_bytes();
-    A.nslabs = lc.grid_big;
 
-    struct Bin { int q; const void* fn; int grid; size_t lds; const char* name; };
-    const Bin bins[3] = {
-        {Q_BIG, fixed_kernel_ptr(2), lc.grid_big, 0, "fixed_cells_big"},
-        {Q_B, fixed_kernel_ptr(1), lc.grid_b, carve_bytes<uint16_t>(NMAX_B), "fixed_cells_4096"},
-        {Q_A, fixed_kernel_ptr(0), lc.grid_a, carve_bytes<uint16_t>(NMAX_A), "fixed_cells_1024"},
-    };
+    struct Bin { int q; const char* name; };
+    const Bin bins[3] = {{Q_BIG, "fixed_cells_big"}, {Q_B, "fixed_cells_2048"}, {Q_A, "fixed_cells_640"}};
     for (const Bin& b : bins) {
         A.queue = ws.queue[b.q];
         A.qlen_index = b.q;
         A.work_index = 8 + b.q;
         if (lc.pre) lc.pre(lc.prof, b.name, lc.stream);
         if (b.q == Q_A)
-            hipLaunchKernelGGL((k_fixed_cells<NMAX_A, uint16_t, true>), dim3(b.grid), dim3(BLOCK), b.lds, lc.stream, A);
+            hipLaunchKernelGGL((k_fixed_cells<NMAX_A, uint16_t, true, WPB_A>), dim3(lc.grid_a), dim3(WAVE * WPB_A),
+                               fixed_lds_bytes(0), lc.stream, A);
         else if (b.q == Q_B)
-            hipLaunchKernelGGL((k_fixed_cells<NMAX_B, uint16_t, true>), dim3(b.grid), dim3(BLOCK), b.lds, lc.stream, A);
+            hipLaunchKernelGGL((k_fixed_cells<NMAX_B, uint16_t, true, WPB_B>), dim3(lc.grid_b), dim3(WAVE * WPB_B),
+                               fixed_lds_bytes(1), lc.stream, A);
         else
-            hipLaunchKernelGGL((k_fixed_cells<NMAX_BIG, uint32_t, false>), dim3(b.grid), dim3(BLOCK), 0, lc.stream, A);
+            hipLaunchKernelGGL((k_fixed_cells<NMAX_BIG, uint32_t, false, WPB_BIG>), dim3(lc.grid_big),
+                               dim3(WAVE * WPB_BIG), 0, lc.stream, A);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (lc.post) lc.post(lc.prof, b.name, lc.stream);

@@ -13,10 +13,6 @@
 
 using namespace vpm;
 
-namespace vpm {
-int64_t fixed_big_slab_bytes();
-}
-
 struct vpm_ctx {
     int device = 0;
     int cu_count = 0;
@@ -135,6 +131,8 @@ FixedParams fixed_params(const vpm_params* p) {
     FixedParams f;
     f.that_x = (uint64_t)llrint(p->tol_x * 16777216.0);
     f.that_p = (uint64_t)llrint(p->tol_p * 16777216.0);
+    f.tx2 = (double)f.that_x * (double)f.that_x;
+    f.tp2 = (double)f.that_p * (double)f.that_p;
     for (int a = 0; a < 3; ++a) f.s[a] = (float)(65536.0 / p->cell_len[a]);
     f.min_subset = p->min_subset;
     f.merge_mode = p->merge_mode;
@@ -213,10 +211,10 @@ vpm_status vpm_create(vpm_ctx** out, int device) {
     hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device);
     if (c->cu_count <= 0) c->cu_count = 256;
     int nb = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(0), 256, fixed_lds_bytes(NMAX_A));
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(0), fixed_block_threads(0), fixed_lds_bytes(0));
     c->grid_a = c->cu_count * (nb > 0 ? nb : 1);
     nb = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(1), 256, fixed_lds_bytes(NMAX_B));
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(1), fixed_block_threads(1), fixed_lds_bytes(1));
     c->grid_b = c->cu_count * (nb > 0 ? nb : 1);
     c->grid_big = c->cu_count;
     c->grid_fp64 = c->cu_count * 16;
@@ -257,7 +255,7 @@ vpm_status vpm_reserve(vpm_ctx* ctx, int64_t max_particles, int64_t max_cells) {
     alloc((void**)&ws.counters, 4096);
     alloc((void**)&ws.flags, 256);
     alloc((void**)&ws.scan_blocks, (size_t)(nc / 4096 + 2) * 8);
-    ws.big_bytes = fixed_big_slab_bytes() * ctx->grid_big;
+    ws.big_bytes = fixed_big_slab_bytes() * ctx->grid_big * (fixed_block_threads(2) / 64);
     alloc((void**)&ws.big, (size_t)ws.big_bytes);
     alloc((void**)&ws.perm2, (size_t)np * 2 * 4);
     alloc((void**)&ws.stack, (size_t)np * 8);

@@ -12,9 +12,9 @@ namespace vpm {
 enum CellMode : uint8_t { CELL_PROCESSED = 0, CELL_UNTOUCHED = 1 };
 
 // Size bins of the fixed-point path.
-constexpr int NMAX_A = 1024;    // workgroup per cell, everything in LDS
-constexpr int NMAX_B = 4096;    // workgroup per cell, everything in LDS (one workgroup per CU)
-constexpr int NMAX_BIG = 65536; // workgroup per cell, working set in global scratch
+constexpr int NMAX_A = 640;     // wavefront per cell, working set in an LDS slice
+constexpr int NMAX_B = 2048;    // wavefront per cell, working set in an LDS slice
+constexpr int NMAX_BIG = 65536; // wavefront per cell, working set in a global slab
 enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_BIG = 3, Q_COUNT = 4 };
 
 // Status bits (mirrors VPM_FLAG_* plus one internal bit).
@@ -45,6 +45,7 @@ struct Workspace {
 // Fixed-point decision parameters derived on the host from vpm_params.
 struct FixedParams {
     uint64_t that_x, that_p;        // round(T * 2^24)
+    double tx2, tp2;                // fl(that_x^2), fl(that_p^2)
     float s[3];                     // fl32(65536 / L_a)
     int32_t min_subset;
     int32_t merge_mode;
@@ -86,8 +87,10 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
                               const int64_t* cell_off, int64_t n_cells, int32_t n_min_cell,
                               const FixedParams& fp, const int32_t* perm,
                               const int32_t* subset_id, const int32_t* n_subsets);
-int fixed_lds_bytes(int nmax);
+int fixed_lds_bytes(int which);           // dynamic LDS per workgroup: 0 = bin A, 1 = bin B
 const void* fixed_kernel_ptr(int which);   // for occupancy queries: 0 = A, 1 = B, 2 = big
+int fixed_block_threads(int which);
+int64_t fixed_big_slab_bytes();            // one slab per wavefront of the big-cell kernel
 
 // ---- plain FP64 path (vpm_fp64.hip) ----
 struct Fp64Params {

@@ -245,3 +245,20 @@ def test_fp64_path_cloud(merge):
 def test_fp64_path_two_stream():
     wl = W.two_stream_grid(nx=32, ny=32, seed=2)
     assert _fp64_check(wl, wl.params) <= 2
+
+
+@pytest.mark.parametrize("fname", ["px_bisection_6.txt", "corners_tie_4.txt", "px_ladder_8.txt"])
+def test_golden_cells_on_gpu(fname):
+    """The hand-worked cells (one holds an exact CV tie, which the FP64 filter cannot settle and
+    hands to the exact integer rule) give the expected subsets on the GPU."""
+    from tests.helpers import load_golden, subsets_of
+    arr, prm, merge, subsets, merged = load_golden(fname)
+    params = dict(prm, cell_len=(1.0, 1.0, 1.0))
+    wl = W.from_cells([arr], params=params, dtype=np.float32)
+    mm = vpm.VPM_MERGE_CENTROID if merge == "centroid" else vpm.VPM_MERGE_PAIR
+    perm, sid, nsub = gpu_partition(wl, params, merge=mm)
+    got = subsets_of(perm, sid, wl.cell_off, 0)
+    assert [list(map(int, s)) for s in got] == subsets
+    out, out_off, tot = gpu_run(wl, params, merge=mm)
+    g = np.stack([out[f] for f in ("w", "x", "y", "z", "px", "py", "pz")], axis=1)
+    np.testing.assert_allclose(g, merged, rtol=1e-6, atol=1e-6)
