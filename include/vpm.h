@@ -65,6 +65,8 @@ typedef enum { VPM_MERGE_PAIR = 0, VPM_MERGE_CENTROID = 1 } vpm_merge_mode;
                                          lowest coordinate; its position code was clamped (FIXED)  */
 #define VPM_FLAG_CELL_TOO_LARGE 0x4u  /* a cell above 65,536 particles: passed through            */
 #define VPM_FLAG_BAD_OFFSETS    0x8u  /* cell_off decreasing or not ending at n_particles          */
+#define VPM_FLAG_BAD_PARTITION  0x10u /* vpm_merge: a cell's perm/subset_id/n_subsets is not a
+                                         partition of that cell; the cell was copied unchanged     */
 
 typedef struct {
     double  tol_x;        /* T_X >= 0: position tolerance (Step 3)                            */

@@ -600,12 +600,10 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
 //           subset's own W, so subsets of light particles keep full precision.
 // eps_i - eps(pt) is formed as (|d|^2 + 2 pt.d) / (eps_i + eps(pt)), d = p - pt, which does not
 // cancel; the FP64 solve then forms r = mean(eps)^2 - m^2 - |P|^2 from these differences.
-template <typename IdxT>
-VPM_DEV void merge_leaf(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, int64_t off,
-                        int start, int len, int lid, int g) {
-    const uint8_t inf = M.info[start];
-    const IdxT* src = idx_buf(M, inf & INF_PARITY);
-    const int jdir = (inf >> INF_JSHIFT) & 3;
+// gidx(j) gives the global index of the j-th member; the result goes to output slot `o` (and o+1).
+template <typename IdxFn>
+VPM_DEV void merge_subset(const FixedArgs& A, const Frame& F, IdxFn gidx, int len, int jdir, int64_t o,
+                          int lid, int g) {
     const int gb = 62 - ceil_log2(len);          // |term| < 2^gb keeps the sum below 2^62
 
     // pass 1
@@ -613,7 +611,7 @@ VPM_DEV void merge_leaf(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     const int g1x = gb - F.ew - F.ep[0], g1y = gb - F.ew - F.ep[1], g1z = gb - F.ew - F.ep[2];
     int64_t sw = 0, s1x = 0, s1y = 0, s1z = 0;
     for (int j = lid; j < len; j += g) {
-        const int64_t i = off + src[start + j];
+        const int64_t i = gidx(j);
         const float w = A.in.w[i];
         sw += fixq(w, 1.0f, gw);
         s1x += fixq(w, A.in.px[i], g1x);
@@ -638,7 +636,7 @@ VPM_DEV void merge_leaf(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     const float e0f = sqrtf(m2 + (q0 * q0 + q1 * q1 + q2 * q2));
     int64_t sx0 = 0, sx1 = 0, sx2 = 0, sd0 = 0, sd1 = 0, sd2 = 0, se = 0;
     for (int j = lid; j < len; j += g) {
-        const int64_t i = off + src[start + j];
+        const int64_t i = gidx(j);
         const float w = A.in.w[i];
         const float x = A.in.x[i] - F.lo[0], y = A.in.y[i] - F.lo[1], z = A.in.z[i] - F.lo[2];
         const float px = A.in.px[i], py = A.in.py[i], pz = A.in.pz[i];
@@ -664,7 +662,6 @@ VPM_DEV void merge_leaf(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     const double Pm[3] = {pt[0] + ldexp((double)sd0, -gd0) / W,
                           pt[1] + ldexp((double)sd1, -gd1) / W,
                           pt[2] + ldexp((double)sd2, -gd2) / W};
-    const int64_t o = off + M.emit[start];
     if (A.P.merge_mode == VPM_MERGE_CENTROID) {
         A.tmp.w[o] = (float)W;
         A.tmp.x[o] = (float)X[0]; A.tmp.y[o] = (float)X[1]; A.tmp.z[o] = (float)X[2];
@@ -706,6 +703,148 @@ VPM_DEV float wave_max(float v) {
     return v;
 }
 
+// Step 1 for one cell (whole wave): validate the values and build the cell frame.  Returns false
+// if some weight is not positive or some value is not finite.
+VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, float mass, Frame& F) {
+    const int lane = lane_id();
+    float vmax[11];
+    vmax[0] = 0.0f;
+    for (int a = 0; a < 3; ++a) { vmax[1 + a] = -INFINITY; vmax[4 + a] = -INFINITY; vmax[7 + a] = 0.0f; }
+    bool bad = false;
+#pragma unroll 2
+    for (int i = lane; i < n; i += WAVE) {
+        const float q[7] = {in.x[off + i], in.y[off + i], in.z[off + i], in.px[off + i], in.py[off + i],
+                            in.pz[off + i], in.w[off + i]};
+        const float w = q[6];
+        bool ok = w > 0.0f && isfinite(w);
+        for (int l = 0; l < 6; ++l) ok = ok && isfinite(q[l]);
+        bad |= !ok;
+        vmax[0] = fmaxf(vmax[0], w);
+        for (int a = 0; a < 3; ++a) {
+            vmax[1 + a] = fmaxf(vmax[1 + a], -q[a]);
+            vmax[4 + a] = fmaxf(vmax[4 + a], q[a]);
+            vmax[7 + a] = fmaxf(vmax[7 + a], fabsf(q[3 + a]));
+        }
+    }
+    if (__ballot(bad) != 0) return false;
+#pragma unroll
+    for (int r = 0; r < 11; ++r) vmax[r] = wave_max(vmax[r]);
+    F.wmax = vmax[0];
+    F.ew = frexp_exp(F.wmax);
+    F.amask = 0;
+    for (int a = 0; a < 3; ++a) {
+        F.lo[a] = -vmax[1 + a];
+        F.hi[a] = vmax[4 + a];
+        F.pmax[a] = vmax[7 + a];
+        F.pzero[a] = F.pmax[a] == 0.0f;
+        F.ep[a] = frexp_exp(F.pmax[a]);
+        F.ext_e[a] = frexp_exp(F.hi[a] - F.lo[a]);
+        if (F.hi[a] > F.lo[a]) F.amask |= 1 << a;          // else every position code is equal
+        if (!F.pzero[a]) F.amask |= 1 << (3 + a);          // else every momentum code is 0
+    }
+    F.amask = __builtin_amdgcn_readfirstlane(F.amask);     // wave-uniform: scalar branches
+    // |eps_i - eps_j| <= m + |p|_1 for any two particles of the cell; 4x margin
+    F.eb = frexp_exp(4.0f * (mass + F.pmax[0] + F.pmax[1] + F.pmax[2]));
+    return true;
+}
+
+// ------------------------------------------------------------------------------------------
+// Replacement from a given partition (vpm_merge): one wavefront per cell, one lane per subset.
+// ------------------------------------------------------------------------------------------
+
+struct MergeArgs {
+    FixedArgs A;                   // in, params, tmp, out_count, cell_mode, flags
+    const int32_t *perm, *subset_id, *n_subsets;
+    int32_t* starts;               // scratch: first slot of every subset, indexed by input position
+};
+
+__global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs G) {
+    const FixedArgs& A = G.A;
+    const int lane = lane_id();
+    const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
+    for (;;) {
+        int qi = 0;
+        if (lane == 0) qi = atomicAdd(&A.counters[A.work_index], 1);
+        qi = __shfl(qi, 0);
+        if (qi >= A.counters[A.qlen_index]) break;
+        const int c = A.queue[qi];
+        const int64_t off = A.cell_off[c];
+        const int n = (int)(A.cell_off[c + 1] - off);
+        const int nsub = G.n_subsets[c];
+        // the partition must be one of this cell's: members inside the cell, subset ordinals
+        // 0, 1, ..., nsub-1 in runs; otherwise (or for an untouched cell) copy the cell unchanged
+        bool ok = nsub >= 1 && nsub <= n;
+        for (int p = lane; p < n && ok; p += WAVE) {
+            const int32_t m = G.perm[off + p];
+            const int32_t sd = G.subset_id[off + p];
+            const int32_t prev = p == 0 ? -1 : G.subset_id[off + p - 1];
+            ok = m >= off && m < off + n && sd >= 0 && sd < nsub && (sd == prev || sd == prev + 1) &&
+                 (p != n - 1 || sd == nsub - 1);
+        }
+        const bool part_ok = __ballot(!ok) == 0;
+        Frame F;
+        const bool vals_ok = part_ok && cell_frame(A.in, off, n, (float)A.P.mass, F);
+        if (!vals_ok) {
+            if (lane == 0) {
+                if (part_ok || nsub >= 1) atomicOr(A.flags, part_ok ? FLAG_BAD_VALUE : FLAG_BAD_PARTITION);
+                A.out_count[c] = n;
+                A.cell_mode[c] = CELL_UNTOUCHED;
+            }
+            continue;
+        }
+        int32_t* st = G.starts + off;
+        for (int p = lane; p < n; p += WAVE)
+            if (p == 0 || G.subset_id[off + p] != G.subset_id[off + p - 1]) st[G.subset_id[off + p]] = p;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        int64_t base = 0;
+        for (int s0 = 0; s0 < nsub; s0 += WAVE) {
+            const int sidx = s0 + lane;
+            int b = 0, len = 0, e = 0;
+            if (sidx < nsub) {
+                b = st[sidx];
+                len = (sidx + 1 < nsub ? st[sidx + 1] : n) - b;
+                e = len >= A.P.min_subset ? npair : len;
+            }
+            int inc = e;
+            for (int d = 1; d < WAVE; d <<= 1) {
+                const int o = __shfl_up(inc, d);
+                if (lane >= d) inc += o;
+            }
+            const int64_t slot = base + inc - e;
+            base += __shfl(inc, WAVE - 1);
+            if (sidx >= nsub) continue;
+            const int32_t* mem = G.perm + off + b;
+            if (len < A.P.min_subset) {
+                for (int j = 0; j < len; ++j) {
+                    const int64_t i = mem[j];
+                    const int64_t o = off + slot + j;
+                    A.tmp.x[o] = A.in.x[i]; A.tmp.y[o] = A.in.y[i]; A.tmp.z[o] = A.in.z[i];
+                    A.tmp.px[o] = A.in.px[i]; A.tmp.py[o] = A.in.py[i]; A.tmp.pz[o] = A.in.pz[i];
+                    A.tmp.w[o] = A.in.w[i];
+                }
+                continue;
+            }
+            // pair direction from the momentum codes, exactly as the partition kernel does
+            double s1[6] = {0, 0, 0, 0, 0, 0};
+            for (int j = 0; j < len; ++j) {
+                const int64_t i = mem[j];
+                const double om = rintf(ldexpf(A.in.w[i], 15 - F.ew));
+                const float pv[3] = {A.in.px[i], A.in.py[i], A.in.pz[i]};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    s1[3 + a] += om * (F.pzero[a] ? 0.0 : (double)rintf(ldexpf(pv[a], 22 - F.ep[a])));
+            }
+            merge_subset(A, F, [&](int j) { return (int64_t)mem[j]; }, len, pair_axis(s1, F), off + slot, 0, 1);
+        }
+        if (lane == 0) {
+            A.out_count[c] = base;
+            A.cell_mode[c] = CELL_PROCESSED;
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // The cell kernel: one wavefront per cell.
 // ------------------------------------------------------------------------------------------
@@ -730,47 +869,8 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         const int n = (int)(A.cell_off[c + 1] - off);
 
         // ---- Step 1: collect the cell, validate, frame ----
-        // The cell is read twice (the second pass hits the caches); keeping it in registers would
-        // cost occupancy.
-        constexpr int RC = 1;
-        float cache[RC][7];
-        auto load = [&](int i, float* q) {
-            q[0] = A.in.x[off + i]; q[1] = A.in.y[off + i]; q[2] = A.in.z[off + i];
-            q[3] = A.in.px[off + i]; q[4] = A.in.py[off + i]; q[5] = A.in.pz[off + i];
-            q[6] = A.in.w[off + i];
-        };
-        float vmax[11];
-        vmax[0] = 0.0f;
-        for (int a = 0; a < 3; ++a) { vmax[1 + a] = -INFINITY; vmax[4 + a] = -INFINITY; vmax[7 + a] = 0.0f; }
-        bool bad = false;
-        auto scan_particle = [&](const float* q) {
-            const float w = q[6];
-            bool ok = w > 0.0f && isfinite(w);
-            for (int l = 0; l < 6; ++l) ok = ok && isfinite(q[l]);
-            bad |= !ok;
-            vmax[0] = fmaxf(vmax[0], w);
-            for (int a = 0; a < 3; ++a) {
-                vmax[1 + a] = fmaxf(vmax[1 + a], -q[a]);
-                vmax[4 + a] = fmaxf(vmax[4 + a], q[a]);
-                vmax[7 + a] = fmaxf(vmax[7 + a], fabsf(q[3 + a]));
-            }
-        };
-        if constexpr (RC > 1) {
-#pragma unroll
-            for (int r = 0; r < RC; ++r)
-                if (lane + r * WAVE < n) load(lane + r * WAVE, cache[r]);
-#pragma unroll
-            for (int r = 0; r < RC; ++r)
-                if (lane + r * WAVE < n) scan_particle(cache[r]);
-        } else {
-#pragma unroll 2
-            for (int i = lane; i < n; i += WAVE) {
-                float q[7];
-                load(i, q);
-                scan_particle(q);
-            }
-        }
-        if (__ballot(bad) != 0) {
+        Frame F;
+        if (!cell_frame(A.in, off, n, (float)A.P.mass, F)) {
             if (lane == 0) {
                 atomicOr(A.flags, FLAG_BAD_VALUE);
                 if (A.mode == 0) { A.out_count[c] = n; A.cell_mode[c] = CELL_UNTOUCHED; }
@@ -780,25 +880,6 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
                 for (int i = lane; i < n; i += WAVE) { A.perm[off + i] = (int32_t)(off + i); A.subset_id[off + i] = -1; }
             continue;
         }
-#pragma unroll
-        for (int r = 0; r < 11; ++r) vmax[r] = wave_max(vmax[r]);
-        Frame F;
-        F.wmax = vmax[0];
-        F.ew = frexp_exp(F.wmax);
-        F.amask = 0;
-        for (int a = 0; a < 3; ++a) {
-            F.lo[a] = -vmax[1 + a];
-            F.hi[a] = vmax[4 + a];
-            F.pmax[a] = vmax[7 + a];
-            F.pzero[a] = F.pmax[a] == 0.0f;
-            F.ep[a] = frexp_exp(F.pmax[a]);
-            F.ext_e[a] = frexp_exp(F.hi[a] - F.lo[a]);
-            if (F.hi[a] > F.lo[a]) F.amask |= 1 << a;          // else every position code is equal
-            if (!F.pzero[a]) F.amask |= 1 << (3 + a);          // else every momentum code is 0
-        }
-        F.amask = __builtin_amdgcn_readfirstlane(F.amask);     // wave-uniform: scalar branches
-        // |eps_i - eps_j| <= m + |p|_1 for any two particles of the cell; 4x margin
-        F.eb = frexp_exp(4.0f * ((float)A.P.mass + F.pmax[0] + F.pmax[1] + F.pmax[2]));
         if (lane == 0) { sh.flags = 0; sh.nnext = 0; }
 
         // ---- codes and the root's moments ----
@@ -822,17 +903,11 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             M.idx0[i] = (IdxT)i;
             fsums_add(R, F.amask, om, cc[0], cc[1], cc[2], cc[3], cc[4], cc[5]);
         };
-        if constexpr (RC > 1) {
-#pragma unroll
-            for (int r = 0; r < RC; ++r)
-                if (lane + r * WAVE < n) encode(lane + r * WAVE, cache[r]);
-        } else {
 #pragma unroll 2
-            for (int i = lane; i < n; i += WAVE) {
-                float q[7];
-                load(i, q);
-                encode(i, q);
-            }
+        for (int i = lane; i < n; i += WAVE) {
+            const float q[7] = {A.in.x[off + i], A.in.y[off + i], A.in.z[off + i], A.in.px[off + i],
+                                A.in.py[off + i], A.in.pz[off + i], A.in.w[off + i]};
+            encode(i, q);
         }
         const bool any_oob = __ballot(oob) != 0;
         fsums_group_reduce(R, WAVE);
@@ -950,7 +1025,10 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
                     const int st = leaf_start[ord];
                     const int ln = leaf_start[ord + 1] - st;
                     const int g = 1 << cls;
-                    merge_leaf<IdxT>(M, A, F, off, st, ln, lane & (g - 1), g);
+                    const uint8_t inf = M.info[st];
+                    const IdxT* src = idx_buf(M, inf & INF_PARITY);
+                    merge_subset(A, F, [&](int j) { return off + (int64_t)src[st + j]; }, ln,
+                                 (inf >> INF_JSHIFT) & 3, off + M.emit[st], lane & (g - 1), g);
                 }
             }
         }
@@ -979,6 +1057,41 @@ const void* fixed_kernel_ptr(int which) {
 }
 
 int fixed_block_threads(int which) { return WAVE * (which == 0 ? WPB_A : which == 1 ? WPB_B : WPB_BIG); }
+
+hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
+                              const int64_t* cell_off, int64_t n_cells, int32_t n_min_cell,
+                              const FixedParams& fp, const int32_t* perm,
+                              const int32_t* subset_id, const int32_t* n_subsets) {
+    (void)n_cells; (void)n_min_cell;
+    MergeArgs G;
+    FixedArgs& A = G.A;
+    A.in = in;
+    A.cell_off = cell_off;
+    A.counters = ws.counters;
+    A.P = fp;
+    A.mode = 0;
+    A.tmp = Soa32Out{(float*)ws.tmp[0], (float*)ws.tmp[1], (float*)ws.tmp[2], (float*)ws.tmp[3],
+                     (float*)ws.tmp[4], (float*)ws.tmp[5], (float*)ws.tmp[6]};
+    A.out_count = ws.out_count;
+    A.cell_mode = ws.cell_mode;
+    A.flags = ws.flags;
+    A.perm = nullptr; A.subset_id = nullptr; A.n_subsets = nullptr;
+    A.big = nullptr; A.big_stride = 0;
+    G.perm = perm; G.subset_id = subset_id; G.n_subsets = n_subsets;
+    G.starts = ws.perm2;
+    const int qs[3] = {Q_BIG, Q_B, Q_A};
+    for (int q : qs) {
+        A.queue = ws.queue[q];
+        A.qlen_index = q;
+        A.work_index = 8 + q;
+        if (lc.pre) lc.pre(lc.prof, "fixed_merge", lc.stream);
+        hipLaunchKernelGGL(k_fixed_merge, dim3(lc.grid_fp64), dim3(WAVE), 0, lc.stream, G);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (lc.post) lc.post(lc.prof, "fixed_merge", lc.stream);
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
                               const int64_t* cell_off, const FixedParams& fp, int mode,

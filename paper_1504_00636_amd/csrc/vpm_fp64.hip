@@ -61,6 +61,55 @@ VPM_DEV double qval(const Soa64& in, int l, int64_t i) {
     }
 }
 
+// Replace a finished subset (Step 7) in FP64: the whole wave sums; lane 0 writes slot o (and o+1).
+// W and mean[6] are the subset's weight and centroid; gidx(j) is the global index of member j.
+template <typename IdxFn>
+VPM_DEV void fp64_merge_out(const Fp64Args& A, int64_t o, double W, const double mean[6], IdxFn gidx, int len) {
+    const int lane = threadIdx.x;
+    const double m = A.P.mass;
+    const double P[3] = {mean[3], mean[4], mean[5]};
+    const double P2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
+    const double e0 = sqrt(m * m + P2);
+    double a = 0;
+    for (int j = lane; j < len; j += WAVE) {
+        const int64_t i = gidx(j);
+        const double p0 = A.in.px[i], p1 = A.in.py[i], p2 = A.in.pz[i];
+        const double ei = sqrt(m * m + (p0 * p0 + p1 * p1 + p2 * p2));
+        const double num = (p0 - P[0]) * (p0 + P[0]) + (p1 - P[1]) * (p1 + P[1]) + (p2 - P[2]) * (p2 + P[2]);
+        const double den = ei + e0;
+        if (den > 0.0) a += A.in.w[i] * num / den;
+    }
+    const double Am = wsum(a) / W;
+    double r = Am * (Am + 2.0 * e0);
+    if (!(r > 0.0)) r = 0.0;
+    if (lane != 0) return;
+    if (A.P.merge_mode == VPM_MERGE_CENTROID) {
+        A.tmp.w[o] = W;
+        A.tmp.x[o] = mean[0]; A.tmp.y[o] = mean[1]; A.tmp.z[o] = mean[2];
+        A.tmp.px[o] = P[0]; A.tmp.py[o] = P[1]; A.tmp.pz[o] = P[2];
+        return;
+    }
+    int jd = 0;
+    double bv = 0;
+    for (int q = 0; q < 3; ++q) {
+        const double v = fabs(mean[3 + q] * W);
+        if (q == 0 || v < bv) { bv = v; jd = q; }
+    }
+    double u[3] = {jd == 0 ? 1.0 : 0.0, jd == 1 ? 1.0 : 0.0, jd == 2 ? 1.0 : 0.0};
+    const double pj = jd == 0 ? P[0] : (jd == 1 ? P[1] : P[2]);
+    if (P2 > 0) for (int q = 0; q < 3; ++q) u[q] -= pj * P[q] / P2;
+    const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const double s = sqrt(r) / un;
+    for (int h = 0; h < 2; ++h) {
+        const double sg = h == 0 ? s : -s;
+        A.tmp.w[o + h] = W / 2;
+        A.tmp.x[o + h] = mean[0]; A.tmp.y[o + h] = mean[1]; A.tmp.z[o + h] = mean[2];
+        A.tmp.px[o + h] = P[0] + sg * u[0];
+        A.tmp.py[o + h] = P[1] + sg * u[1];
+        A.tmp.pz[o + h] = P[2] + sg * u[2];
+    }
+}
+
 __global__ __launch_bounds__(64) void k_fp64_cells(Fp64Args A) {
     const int lane = threadIdx.x;
     for (;;) {
@@ -187,50 +236,7 @@ __global__ __launch_bounds__(64) void k_fp64_cells(Fp64Args A) {
                 }
                 out_pos += len;
             } else {
-                const double m = A.P.mass;
-                const double P[3] = {mean[3], mean[4], mean[5]};
-                const double P2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
-                const double e0 = sqrt(m * m + P2);
-                double a = 0;
-                for (int j = lane; j < len; j += WAVE) {
-                    const int64_t i = off + src[start + j];
-                    const double p0 = A.in.px[i], p1 = A.in.py[i], p2 = A.in.pz[i];
-                    const double ei = sqrt(m * m + (p0 * p0 + p1 * p1 + p2 * p2));
-                    const double num = (p0 - P[0]) * (p0 + P[0]) + (p1 - P[1]) * (p1 + P[1]) + (p2 - P[2]) * (p2 + P[2]);
-                    const double den = ei + e0;
-                    if (den > 0.0) a += A.in.w[i] * num / den;
-                }
-                const double Am = wsum(a) / W;
-                double r = Am * (Am + 2.0 * e0);
-                if (!(r > 0.0)) r = 0.0;
-                if (lane == 0) {
-                    const int64_t o = off + out_pos;
-                    if (A.P.merge_mode == VPM_MERGE_CENTROID) {
-                        A.tmp.w[o] = W;
-                        A.tmp.x[o] = mean[0]; A.tmp.y[o] = mean[1]; A.tmp.z[o] = mean[2];
-                        A.tmp.px[o] = P[0]; A.tmp.py[o] = P[1]; A.tmp.pz[o] = P[2];
-                    } else {
-                        int jd = 0;
-                        double bv = 0;
-                        for (int q = 0; q < 3; ++q) {
-                            const double v = fabs(mean[3 + q] * W);
-                            if (q == 0 || v < bv) { bv = v; jd = q; }
-                        }
-                        double u[3] = {0, 0, 0};
-                        u[jd] = 1.0;
-                        if (P2 > 0) for (int q = 0; q < 3; ++q) u[q] -= P[jd] * P[q] / P2;
-                        const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-                        const double s = sqrt(r) / un;
-                        for (int h = 0; h < 2; ++h) {
-                            const double sg = h == 0 ? s : -s;
-                            A.tmp.w[o + h] = W / 2;
-                            A.tmp.x[o + h] = mean[0]; A.tmp.y[o + h] = mean[1]; A.tmp.z[o + h] = mean[2];
-                            A.tmp.px[o + h] = P[0] + sg * u[0];
-                            A.tmp.py[o + h] = P[1] + sg * u[1];
-                            A.tmp.pz[o + h] = P[2] + sg * u[2];
-                        }
-                    }
-                }
+                fp64_merge_out(A, off + out_pos, W, mean, [&](int j) { return off + (int64_t)src[start + j]; }, len);
                 out_pos += npair;
             }
             ++nleaf;
@@ -239,6 +245,88 @@ __global__ __launch_bounds__(64) void k_fp64_cells(Fp64Args A) {
             if (A.mode == 0) { A.out_count[c] = out_pos; A.cell_mode[c] = CELL_PROCESSED; }
             else A.n_subsets[c] = nleaf;
         }
+    }
+}
+
+
+// Replacement from a given partition (vpm_merge, FP64): one wavefront per cell, subsets in order.
+struct Fp64MergeArgs {
+    Fp64Args A;
+    const int32_t *perm, *subset_id, *n_subsets;
+};
+
+__global__ __launch_bounds__(64) void k_fp64_merge(Fp64MergeArgs G) {
+    const Fp64Args& A = G.A;
+    const int lane = threadIdx.x;
+    const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
+    for (;;) {
+        int qi = 0;
+        if (lane == 0) qi = atomicAdd(&A.counters[A.work_index], 1);
+        qi = __shfl(qi, 0);
+        if (qi >= A.counters[A.qlen_index]) break;
+        const int c = A.queue[qi];
+        const int64_t off = A.cell_off[c];
+        const int n = (int)(A.cell_off[c + 1] - off);
+        const int nsub = G.n_subsets[c];
+        bool ok = nsub >= 1 && nsub <= n;
+        for (int p = lane; p < n && ok; p += WAVE) {
+            const int32_t mm = G.perm[off + p];
+            const int32_t sd = G.subset_id[off + p];
+            const int32_t prev = p == 0 ? -1 : G.subset_id[off + p - 1];
+            const double wv = ok && mm >= off && mm < off + n ? A.in.w[mm] : 0.0;
+            ok = mm >= off && mm < off + n && sd >= 0 && sd < nsub && (sd == prev || sd == prev + 1) &&
+                 (p != n - 1 || sd == nsub - 1) && wv > 0.0 && isfinite(wv);
+            for (int l = 0; ok && l < 6; ++l) ok = isfinite(qval(A.in, l, mm));
+        }
+        if (__ballot(!ok) != 0) {
+            if (lane == 0) {
+                if (nsub >= 1) atomicOr(A.flags, FLAG_BAD_PARTITION);
+                A.out_count[c] = n;
+                A.cell_mode[c] = CELL_UNTOUCHED;
+            }
+            continue;
+        }
+        int out_pos = 0, b = 0;
+        while (b < n) {
+            // the subset starting at slot b ends where the ordinal changes
+            const int sd = G.subset_id[off + b];
+            int e = b + 1;
+            while (e < n) {
+                const int j = e + lane;
+                const bool same = j < n && G.subset_id[off + j] == sd;
+                const uint64_t notsame = __ballot(!same);
+                if (notsame != 0) { e += __ffsll((unsigned long long)notsame) - 1; break; }
+                e += WAVE;
+            }
+            if (e > n) e = n;
+            const int len = e - b;
+            const int32_t* mem = G.perm + off + b;
+            if (len < A.P.min_subset) {
+                for (int j = lane; j < len; j += WAVE) {
+                    const int64_t i = mem[j];
+                    const int64_t o = off + out_pos + j;
+                    A.tmp.x[o] = A.in.x[i]; A.tmp.y[o] = A.in.y[i]; A.tmp.z[o] = A.in.z[i];
+                    A.tmp.px[o] = A.in.px[i]; A.tmp.py[o] = A.in.py[i]; A.tmp.pz[o] = A.in.pz[i];
+                    A.tmp.w[o] = A.in.w[i];
+                }
+                out_pos += len;
+            } else {
+                double s[7] = {0, 0, 0, 0, 0, 0, 0};
+                for (int j = lane; j < len; j += WAVE) {
+                    const int64_t i = mem[j];
+                    const double w = A.in.w[i];
+                    s[6] += w;
+                    for (int l = 0; l < 6; ++l) s[l] += w * qval(A.in, l, i);
+                }
+                const double W = wsum(s[6]);
+                double mean[6];
+                for (int l = 0; l < 6; ++l) mean[l] = wsum(s[l]) / W;
+                fp64_merge_out(A, off + out_pos, W, mean, [&](int j) { return (int64_t)mem[j]; }, len);
+                out_pos += npair;
+            }
+            b = e;
+        }
+        if (lane == 0) { A.out_count[c] = out_pos; A.cell_mode[c] = CELL_PROCESSED; }
     }
 }
 
@@ -273,6 +361,41 @@ hipError_t launch_fp64_cells(const Workspace& ws, const LaunchCfg& lc, const Soa
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (lc.post) lc.post(lc.prof, "fp64_cells", lc.stream);
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fp64_merge(const Workspace& ws, const LaunchCfg& lc, const Soa64& in, const int64_t* cell_off,
+                             int64_t n_cells, const Fp64Params& fp, const int32_t* perm, const int32_t* subset_id,
+                             const int32_t* n_subsets) {
+    (void)n_cells;
+    Fp64MergeArgs G;
+    Fp64Args& A = G.A;
+    A.in = in;
+    A.cell_off = cell_off;
+    A.counters = ws.counters;
+    A.P = fp;
+    A.mode = 0;
+    A.tmp = Soa64Out{(double*)ws.tmp[0], (double*)ws.tmp[1], (double*)ws.tmp[2], (double*)ws.tmp[3],
+                     (double*)ws.tmp[4], (double*)ws.tmp[5], (double*)ws.tmp[6]};
+    A.out_count = ws.out_count;
+    A.cell_mode = ws.cell_mode;
+    A.perm2 = ws.perm2;
+    A.cap = ws.cap_particles;
+    A.stack = ws.stack;
+    A.perm = nullptr; A.subset_id = nullptr; A.n_subsets = nullptr;
+    A.flags = ws.flags;
+    G.perm = perm; G.subset_id = subset_id; G.n_subsets = n_subsets;
+    const int qs[3] = {Q_BIG, Q_B, Q_A};
+    for (int q : qs) {
+        A.queue = ws.queue[q];
+        A.qlen_index = q;
+        A.work_index = 8 + q;
+        if (lc.pre) lc.pre(lc.prof, "fp64_merge", lc.stream);
+        hipLaunchKernelGGL(k_fp64_merge, dim3(lc.grid_fp64), dim3(64), 0, lc.stream, G);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (lc.post) lc.post(lc.prof, "fp64_merge", lc.stream);
     }
     return hipSuccess;
 }

@@ -22,6 +22,7 @@ constexpr uint32_t FLAG_BAD_VALUE = VPM_FLAG_BAD_VALUE;
 constexpr uint32_t FLAG_OUT_OF_CELL = VPM_FLAG_OUT_OF_CELL;
 constexpr uint32_t FLAG_TOO_LARGE = VPM_FLAG_CELL_TOO_LARGE;
 constexpr uint32_t FLAG_BAD_OFFSETS = VPM_FLAG_BAD_OFFSETS;
+constexpr uint32_t FLAG_BAD_PARTITION = VPM_FLAG_BAD_PARTITION;
 constexpr uint32_t FLAG_INTERNAL = 0x80000000u;  // a cut left one side empty (never expected)
 
 // Device workspace, allocated by vpm_reserve.

@@ -21,6 +21,7 @@ VPM_F32, VPM_F64 = 0, 1
 VPM_DECIDE_FIXED, VPM_DECIDE_FP64 = 0, 1
 VPM_MERGE_PAIR, VPM_MERGE_CENTROID = 0, 1
 VPM_FLAG_BAD_VALUE, VPM_FLAG_OUT_OF_CELL, VPM_FLAG_CELL_TOO_LARGE, VPM_FLAG_BAD_OFFSETS = 1, 2, 4, 8
+VPM_FLAG_BAD_PARTITION = 16
 
 EXPORTS = ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_partition",
            "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read",
@@ -64,7 +65,7 @@ def lib():
     L.vpm_check_params.argtypes = [P(VpmParams)]
     L.vpm_run.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), P(VpmSoa), vp, vp, vp]
     L.vpm_partition.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, vp]
-    L.vpm_merge.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, P(VpmSoa), vp, vp, vp, vp]
+    L.vpm_merge.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, P(VpmSoa), vp, vp, vp]
     L.vpm_device_status.argtypes = [vp, P(C.c_uint32), C.c_int]
     L.vpm_profile_enable.argtypes = [vp, C.c_int]
     L.vpm_profile_read.argtypes = [vp, C.c_int, vp, P(C.c_int64), P(C.c_double), P(C.c_int), C.c_int]

@@ -86,3 +86,23 @@ def test_entry_points_reject_null_context():
     assert L.vpm_run(None, None, None, 0, 0, C.byref(p), None, None, None, None) == vpm.VPM_ERR_INVALID_ARG
     assert L.vpm_partition(None, None, None, 0, 0, C.byref(p), None, None, None, None) == vpm.VPM_ERR_INVALID_ARG
     assert L.vpm_reserve(None, 1, 1) == vpm.VPM_ERR_INVALID_ARG
+
+
+def _declared_arity():
+    src = open(os.path.join(ROOT, "include", "vpm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(vpm_[a-z_]+)\s*\(([^;{]*?)\)\s*;", src, flags=re.S):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    L = vpm.lib()
+    ar = _declared_arity()
+    assert ar["vpm_merge"] == 13 and ar["vpm_run"] == 10
+    for name, n in ar.items():
+        at = getattr(L, name).argtypes
+        if at is not None:
+            assert len(at) == n, (name, len(at), n)

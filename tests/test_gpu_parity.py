@@ -262,3 +262,58 @@ def test_golden_cells_on_gpu(fname):
     out, out_off, tot = gpu_run(wl, params, merge=mm)
     g = np.stack([out[f] for f in ("w", "x", "y", "z", "px", "py", "pz")], axis=1)
     np.testing.assert_allclose(g, merged, rtol=1e-6, atol=1e-6)
+
+
+def _gpu_merge(wl, params, perm, sid, nsub, decide=vpm.VPM_DECIDE_FIXED, merge=vpm.VPM_MERGE_PAIR):
+    from tests.gpu_common import ctx
+    c = ctx(max(wl.n, 1), max(wl.n_cells, 1))
+    dt = torch.float32 if decide == vpm.VPM_DECIDE_FIXED else torch.float64
+    arrs, off = vpm.upload(wl, dtype=dt)
+    n = wl.n
+    out = [torch.empty_like(a) for a in arrs]
+    out_off = torch.empty(wl.n_cells + 1, dtype=torch.int64, device="cuda")
+    tot = torch.empty(1, dtype=torch.int64, device="cuda")
+    p = vpm.make_params(merge_mode=merge, decide=decide, **params)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+    c.merge(arrs, off, n, p, t(perm), t(sid), t(nsub), out, out_off, tot)
+    torch.cuda.synchronize()
+    k = int(tot.item())
+    return {f: out[i][:k].cpu().numpy().astype(np.float64) for i, f in enumerate(FIELDS)}, out_off.cpu().numpy(), k
+
+
+@pytest.mark.parametrize("decide", [vpm.VPM_DECIDE_FIXED, vpm.VPM_DECIDE_FP64])
+@pytest.mark.parametrize("merge", MERGES)
+def test_merge_of_partition_equals_run(decide, merge):
+    dt = np.float32 if decide == vpm.VPM_DECIDE_FIXED else np.float64
+    wl = cloud_cells([300, 57, 1000, 5, 0, 3000, 9000, 2], seed=9, dtype=dt)
+    params = dict(CLOUD, min_subset=4 if merge == vpm.VPM_MERGE_PAIR else 2)
+    perm, sid, nsub = gpu_partition(wl, params, decide=decide, merge=merge)
+    got, got_off, tot = _gpu_merge(wl, params, perm, sid, nsub, decide, merge)
+    ref, ref_off, rtot = gpu_run(wl, params, decide=decide, merge=merge)
+    assert tot == rtot
+    np.testing.assert_array_equal(got_off, ref_off)
+    for f in FIELDS:
+        np.testing.assert_array_equal(got[f], ref[f])
+
+
+@pytest.mark.parametrize("merge", MERGES)
+def test_merge_of_oracle_partition(merge):
+    wl = cloud_cells([400, 64, 7, 2500], seed=10)
+    params = dict(CLOUD, min_subset=4 if merge == vpm.VPM_MERGE_PAIR else 2)
+    ref = oracle.run_workload(wl, merge_mode=merge, **oracle_params(params))
+    got, got_off, tot = _gpu_merge(wl, params, ref.perm, ref.subset_id, ref.n_subsets, merge=merge)
+    assert tot == ref.out_total
+    check_merged_values(wl, params, merge, got, got_off, ref)
+
+
+def test_merge_rejects_inconsistent_partition():
+    from tests.gpu_common import ctx
+    wl = cloud_cells([50, 50], seed=11)
+    perm, sid, nsub = gpu_partition(wl, CLOUD)
+    perm = perm.copy()
+    perm[3] = 70                                  # a member from the other cell
+    ctx().device_status(clear=True)
+    got, got_off, tot = _gpu_merge(wl, CLOUD, perm, sid, nsub)
+    assert ctx().device_status(clear=True) & vpm.VPM_FLAG_BAD_PARTITION
+    assert got_off[1] - got_off[0] == 50          # copied unchanged
+    np.testing.assert_array_equal(got["x"][:50], wl.x[:50].astype(np.float64))
