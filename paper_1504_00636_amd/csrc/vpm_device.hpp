@@ -101,19 +101,48 @@ VPM_DEV uint64_t group_bits(uint64_t ballot, int gbase, int g) {
     return (ballot >> gbase) & m;
 }
 
+// Partner value for step m of a butterfly sum inside aligned groups of lanes.  Steps 1 and 2 are
+// DPP quad permutes; steps 4 and 8 are the DPP half-row and row mirrors, which pair each lane with
+// one of the other half of its 8- or 16-lane block (equivalent to xor for a sum, because after the
+// earlier steps every lane of a half holds the same partial); step 16 is a swizzle with xor 16;
+// step 32 a cross-half permute.  Every partner lies in the caller's group, so it is active.
+template <int M>
+VPM_DEV int xchg32(int v) {
+    if constexpr (M == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (M == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (M == 4) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+    else if constexpr (M == 8) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+    else if constexpr (M == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+    else return __shfl_xor(v, 32);
+}
+
+template <int M>
+VPM_DEV int xchg(int v) { return xchg32<M>(v); }
+template <int M>
+VPM_DEV uint32_t xchg(uint32_t v) { return (uint32_t)xchg32<M>((int)v); }
+template <int M>
+VPM_DEV int64_t xchg(int64_t v) {
+    const int lo = xchg32<M>((int)(uint32_t)(uint64_t)v), hi = xchg32<M>((int)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int M>
+VPM_DEV uint64_t xchg(uint64_t v) { return (uint64_t)xchg<M>((int64_t)v); }
+template <int M>
+VPM_DEV double xchg(double v) { return __longlong_as_double(xchg<M>((int64_t)__double_as_longlong(v))); }
+
+// Sum over an aligned group of g lanes (g a power of two, the same for all lanes of a group);
+// every lane of the group receives the total.
 template <typename V>
 VPM_DEV V group_sum(V v, int g) {
-    for (int m = 1; m < g; m <<= 1) v += __shfl_xor(v, m);
+    if (g > 1) v += xchg<1>(v);
+    if (g > 2) v += xchg<2>(v);
+    if (g > 4) v += xchg<4>(v);
+    if (g > 8) v += xchg<8>(v);
+    if (g > 16) v += xchg<16>(v);
+    if (g > 32) v += xchg<32>(v);
     return v;
 }
 
-VPM_DEV U128 group_sum128(U128 v, int g) {
-    for (int m = 1; m < g; m <<= 1) {
-        U128 o = u128_make(__shfl_xor(v.lo, m), __shfl_xor(v.hi, m));
-        v = add128(v, o);
-    }
-    return v;
-}
 
 // ------------------------------------------------------------------------------------------
 // Workgroup helpers (all threads must call; `red` is LDS scratch of >= blockDim/64 slots).

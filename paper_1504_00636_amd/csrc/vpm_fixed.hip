@@ -32,7 +32,7 @@
 namespace vpm {
 namespace {
 
-constexpr int PPL = 8;              // target particles per lane when sizing a group
+constexpr int PPL = 16;             // target particles per lane when sizing a group
 
 // info byte per slot once its final subset is known
 constexpr uint8_t INF_PARITY = 0x01;   // index buffer that holds the final order
@@ -42,7 +42,9 @@ constexpr int INF_JSHIFT = 3;          // bits 3-4: pair-direction axis
 constexpr uint8_t INF_SET = 0x80;
 
 template <typename IdxT>
-struct Node { IdxT start, len; int32_t thr_axis; };   // thr_axis = (threshold << 3) | axis
+struct Node { IdxT start, len; int32_t thr_axis; };
+// thr_axis = (threshold << 4) | (reversed << 3) | axis; `reversed`: the subset's slots hold its
+// members in decreasing input order
 
 struct Frame {
     float lo[3], hi[3], pmax[3], wmax;
@@ -65,13 +67,13 @@ VPM_DEV void fsums_zero(FSums& S) {
     for (int l = 0; l < 6; ++l) { S.s1[l] = 0.0; S.s2[l] = 0.0; }
 }
 
-VPM_DEV void fsums_add(FSums& S, int amask, int om, int c0, int c1, int c2, int c3, int c4, int c5) {
+// Axes whose codes are all equal in the cell carry code 0, so their sums stay exactly 0.
+VPM_DEV void fsums_add(FSums& S, int om, int c0, int c1, int c2, int c3, int c4, int c5) {
     const double o = (double)om;
     const int c[6] = {c0, c1, c2, c3, c4, c5};
     S.s0 += o;
 #pragma unroll
     for (int l = 0; l < 6; ++l) {
-        if (!((amask >> l) & 1)) continue;
         const double cl = (double)c[l];
         const double t = o * cl;                  // exact: |t| <= 2^37
         S.s1[l] += t;                             // exact while the partial sum stays below 2^53
@@ -79,12 +81,20 @@ VPM_DEV void fsums_add(FSums& S, int amask, int om, int c0, int c1, int c2, int 
     }
 }
 
-VPM_DEV void fsums_group_reduce(FSums& S, int g) {
-    for (int m = 1; m < g; m <<= 1) {
-        S.s0 += __shfl_xor(S.s0, m);
+template <int M>
+VPM_DEV void fsums_step(FSums& S) {
+    S.s0 += xchg<M>(S.s0);
 #pragma unroll
-        for (int l = 0; l < 6; ++l) { S.s1[l] += __shfl_xor(S.s1[l], m); S.s2[l] += __shfl_xor(S.s2[l], m); }
-    }
+    for (int l = 0; l < 6; ++l) { S.s1[l] += xchg<M>(S.s1[l]); S.s2[l] += xchg<M>(S.s2[l]); }
+}
+
+VPM_DEV void fsums_group_reduce(FSums& S, int g) {
+    if (g > 1) fsums_step<1>(S);
+    if (g > 2) fsums_step<2>(S);
+    if (g > 4) fsums_step<4>(S);
+    if (g > 8) fsums_step<8>(S);
+    if (g > 16) fsums_step<16>(S);
+    if (g > 32) fsums_step<32>(S);
 }
 
 // Exact integer moments (used only when an FP64 comparison is too close to call).
@@ -483,24 +493,13 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
                         int cur, int lid, int g, int gbase, Node<IdxT>* next) {
     const int start = nd.start, len = nd.len;
     const int k = nd.thr_axis & 7;
-    const int thr = nd.thr_axis >> 3;
+    const int rev = (nd.thr_axis >> 3) & 1;
+    const int thr = nd.thr_axis >> 4;
     const IdxT* src = idx_buf(M, cur);
     IdxT* dst = idx_buf(M, cur ^ 1);
 
-    // size of the lower side V1 = {c <= thr}
-    int nl = 0;
-    if (k < 3) {
-        const int16_t* ck = M.cp + k * M.sp;
-#pragma unroll 4
-        for (int j = lid; j < len; j += g) nl += ck[src[start + j]] <= thr ? 1 : 0;
-    } else {
-        const int32_t* ck = M.cm + (k - 3) * M.sm;
-#pragma unroll 4
-        for (int j = lid; j < len; j += g) nl += ck[src[start + j]] <= thr ? 1 : 0;
-    }
-    nl = group_sum(nl, g);
-
-    // stable compaction into the other buffer (Step 6)
+    // Step 6 as one stable pass: the lower side V1 = {c <= thr} fills the range from the front in
+    // slot order, V2 from the back in reverse slot order (so V2's member order flips).
     const uint64_t below = lanes_below() >> gbase;
     int lb = 0, rb = 0;
 #pragma unroll 2
@@ -510,16 +509,19 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
         IdxT i = 0;
         bool right = false;
         if (act) { i = src[start + j]; right = code_of(M, k, i) > thr; }
-        const uint64_t bl = group_bits(__ballot(act && !right), gbase, g);
         const uint64_t br = group_bits(__ballot(act && right), gbase, g);
+        const int na = min(g, len - j0);
+        const uint64_t am = na == 64 ? ~0ull : ((1ull << na) - 1ull);
+        const uint64_t bl = am & ~br;
         if (act) {
-            const int d = right ? nl + rb + __popcll(br & below) : lb + __popcll(bl & below);
+            const int d = right ? len - 1 - (rb + __popcll(br & below)) : lb + __popcll(bl & below);
             dst[start + d] = i;
         }
         lb += __popcll(bl);
         rb += __popcll(br);
     }
     wave_fence();
+    const int nl = lb;
 
     const int n1 = nl, n2 = len - nl;
     int dv0, dv1;
@@ -532,17 +534,19 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     } else {
         FSums L, R;
         fsums_zero(L); fsums_zero(R);
+        // a child below min_subset is copied whatever its moments: skip its sums
+        const int e1 = n1 >= A.P.min_subset ? n1 : 0, e2 = n2 >= A.P.min_subset ? n2 : 0;
 #pragma unroll 2
-        for (int j = lid; j < n1; j += g) {
+        for (int j = lid; j < e1; j += g) {
             int c[6], om;
             codes_of(M, dst[start + j], c, om);
-            fsums_add(L, F.amask, om, c[0], c[1], c[2], c[3], c[4], c[5]);
+            fsums_add(L, om, c[0], c[1], c[2], c[3], c[4], c[5]);
         }
 #pragma unroll 2
-        for (int j = lid; j < n2; j += g) {
+        for (int j = lid; j < e2; j += g) {
             int c[6], om;
             codes_of(M, dst[start + n1 + j], c, om);
-            fsums_add(R, F.amask, om, c[0], c[1], c[2], c[3], c[4], c[5]);
+            fsums_add(R, om, c[0], c[1], c[2], c[3], c[4], c[5]);
         }
         fsums_group_reduce(L, g);
         fsums_group_reduce(R, g);
@@ -575,14 +579,24 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
         const Decision d = unpack_decision(dvv);
         const int cs = (dv1 == -1) ? start : (ch == 0 ? start : start + n1);
         const int cl = (dv1 == -1) ? len : (ch == 0 ? n1 : n2);
+        const int crev = (dv1 == -1) ? (n1 == 0 ? rev ^ 1 : rev) : (ch == 0 ? rev : rev ^ 1);
         if (d.kind == D_SPLIT) {
             if (lid == 0) {
                 const int slot = atomicAdd(&M.sh->nnext, 1);
                 Node<IdxT> c;
-                c.start = (IdxT)cs; c.len = (IdxT)cl; c.thr_axis = (d.thr << 3) | d.axis;
+                c.start = (IdxT)cs; c.len = (IdxT)cl; c.thr_axis = (d.thr << 4) | (crev << 3) | d.axis;
                 next[slot] = c;
             }
         } else {
+            // a final subset whose member order is observable (copied particles, or the partition
+            // output) is put back into increasing input order
+            if (crev && (d.kind == D_COPY || A.mode == 1)) {
+                for (int j = lid; j < cl / 2; j += g) {
+                    const IdxT a = dst[cs + j], b = dst[cs + cl - 1 - j];
+                    dst[cs + j] = b;
+                    dst[cs + cl - 1 - j] = a;
+                }
+            }
             const uint8_t base = INF_SET | (uint8_t)((cur ^ 1) & 1) |
                                  (d.kind == D_MERGED ? INF_MERGED : 0) |
                                  (uint8_t)(d.jdir << INF_JSHIFT);
@@ -894,14 +908,14 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
                 float r = rintf(d * A.P.s[a]);
                 oob |= r > 65536.0f;
                 r = fminf(r, 65535.0f);
-                cc[a] = (int)r - 32768;
+                cc[a] = ((F.amask >> a) & 1) ? (int)r - 32768 : 0;   // constant axis: code 0
                 cc[3 + a] = F.pzero[a] ? 0 : (int)rintf(ldexpf(q[3 + a], 22 - F.ep[a]));
             }
             M.om[i] = (uint16_t)om;
             M.cp[i] = (int16_t)cc[0]; M.cp[M.sp + i] = (int16_t)cc[1]; M.cp[2 * M.sp + i] = (int16_t)cc[2];
             M.cm[i] = cc[3]; M.cm[M.sm + i] = cc[4]; M.cm[2 * M.sm + i] = cc[5];
             M.idx0[i] = (IdxT)i;
-            fsums_add(R, F.amask, om, cc[0], cc[1], cc[2], cc[3], cc[4], cc[5]);
+            fsums_add(R, om, cc[0], cc[1], cc[2], cc[3], cc[4], cc[5]);
         };
 #pragma unroll 2
         for (int i = lane; i < n; i += WAVE) {
@@ -919,7 +933,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         if (rd.kind == D_SPLIT) {
             if (lane == 0) {
                 Node<IdxT> nd;
-                nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 3) | rd.axis;
+                nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 4) | rd.axis;
                 M.nodes0[0] = nd;
             }
             m = 1;
@@ -1112,7 +1126,7 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
     A.big_stride = fixed_big_slab_bytes();
 
     struct Bin { int q; const char* name; };
-    const Bin bins[3] = {{Q_BIG, "fixed_cells_big"}, {Q_B, "fixed_cells_2048"}, {Q_A, "fixed_cells_640"}};
+    const Bin bins[3] = {{Q_BIG, "fixed_cells_big"}, {Q_B, "fixed_cells_2048"}, {Q_A, "fixed_cells_576"}};
     for (const Bin& b : bins) {
         A.queue = ws.queue[b.q];
         A.qlen_index = b.q;

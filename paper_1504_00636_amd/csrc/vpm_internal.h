@@ -12,7 +12,7 @@ namespace vpm {
 enum CellMode : uint8_t { CELL_PROCESSED = 0, CELL_UNTOUCHED = 1 };
 
 // Size bins of the fixed-point path.
-constexpr int NMAX_A = 640;     // wavefront per cell, working set in an LDS slice
+constexpr int NMAX_A = 576;     // wavefront per cell, working set in an LDS slice (8 per CU)
 constexpr int NMAX_B = 2048;    // wavefront per cell, working set in an LDS slice
 constexpr int NMAX_BIG = 65536; // wavefront per cell, working set in a global slab
 enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_BIG = 3, Q_COUNT = 4 };
