@@ -224,9 +224,11 @@ VPM_DEV Decision decide_exact(const ISums& S, const FixedParams& P, const Frame&
 // cannot be certified (the caller then applies the exact rule).
 //   V = S0 S2 - S1^2 in FP64 (S0, S1 exact; the FMA removes the rounding of S1^2):
 //       |V_fp64 - V| <= EV = fl(S0 S2) (len + 16) 2^-51   (S2 rounded over at most len + 6 operations)
-//   Step 3 thresholds R are within 2^-50 relative of the exact ones.
-//   Step 4: Delta^2 = V/D is bracketed in FP32 (conversions, a 1-ulp reciprocal and one product stay
-//   below 2^-21 relative; the bracket is widened by 2^-19).
+//   Both Step 3 and Step 4 compare Delta_l^2 = V_l / D_l: Step 3 against tau^2 = (T^ / 2^24)^2 (given as
+//   an FP32 bracket), Step 4 against the other axes.  Delta_l^2 is bracketed in FP32 from [V - EV,
+//   V + EV] (conversions, a 1-ulp reciprocal and the products stay below 2^-21 relative; the
+//   bracket is widened by 2^-19).  A subtraction of two floats has the sign of the exact difference,
+//   so the maxima below decide the comparisons exactly.
 // `amask` has bit l set for the axes whose codes vary in the cell; the others have V = 0.
 VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, const Frame& F, int amask, bool& ok) {
     Decision d;
@@ -235,11 +237,11 @@ VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, cons
     const double s0 = S.s0;
     if (s0 == 0.0) { d.kind = D_MERGED; d.jdir = pair_axis(S.s1, F); return d; }
     const double slack = (double)(len + 16) * 0x1p-51;
-    const double s0sq = s0 * s0;
-    const double rx = P.tx2 * s0sq * 0x1p-16;
-    const float rdx = __builtin_amdgcn_rcpf((float)(s0sq * 0x1p32));
+    const float rdx = __builtin_amdgcn_rcpf((float)(s0 * s0 * 0x1p32));
+    const float rdx_lo = rdx * (1.0f - 0x1p-19f), rdx_hi = rdx * (1.0f + 0x1p-19f);
     float lo[6], hi[6];
-    bool fail = false, unsure = false;
+    float over = -INFINITY;     // max_l (lower bound of Delta_l^2 - upper bound of tau^2) > 0: some axis fails
+    float under = -INFINITY;    // max_l (upper bound of Delta_l^2 - lower bound of tau^2) <= 0: all pass
 #pragma unroll
     for (int l = 0; l < 6; ++l) {
         lo[l] = 0.0f; hi[l] = 0.0f;
@@ -250,24 +252,21 @@ VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, cons
         const double V = fma(s0, s2, -bh) - bl;
         const double EV = s0 * s2 * slack;
         const double vlo = V - EV, vhi = V + EV;
-        const bool vzero = vhi < 1.0;                 // V is an integer >= 0
-        const bool vpos = vlo > 0.0;
-        const bool inf_axis = l >= 3 && s1 == 0.0;    // D = 0
-        // Step 3 (branch-free)
-        const double R = l < 3 ? rx : P.tp2 * bh * 0x1p-48;
-        const bool f = inf_axis ? vpos : (vlo > R * (1.0 + 0x1p-50));
-        const bool p = inf_axis ? vzero : (vhi < R * (1.0 - 0x1p-50));
-        fail |= f;
-        unsure |= !(f || p);
-        // Step 4 bracket for Delta_l^2
-        const float rd = l < 3 ? rdx : __builtin_amdgcn_rcpf((float)bh);
-        const float lf = (float)fmax(vlo, 0.0) * rd * (1.0f - 0x1p-19f);
-        const float hf = (float)vhi * rd * (1.0f + 0x1p-19f);
-        lo[l] = vzero ? 0.0f : (inf_axis ? (vpos ? INFINITY : 0.0f) : lf);
-        hi[l] = vzero ? 0.0f : (inf_axis ? INFINITY : hf);
+        float rlo, rhi;
+        if (l < 3) {
+            rlo = rdx_lo; rhi = rdx_hi;
+        } else {                                       // D = S1^2; D = 0 gives +infinity
+            const float r = __builtin_amdgcn_rcpf((float)bh);
+            rlo = r * (1.0f - 0x1p-19f); rhi = r * (1.0f + 0x1p-19f);
+        }
+        const float lf = vlo > 0.0 ? (float)vlo * rlo : 0.0f;     // V > 0 certain
+        const float hf = vhi < 1.0 ? 0.0f : (float)vhi * rhi;     // V is an integer: vhi < 1 gives V = 0
+        lo[l] = lf; hi[l] = hf;
+        over = fmaxf(over, lf - (l < 3 ? P.t2x_hi : P.t2p_hi));
+        under = fmaxf(under, hf - (l < 3 ? P.t2x_lo : P.t2p_lo));
     }
-    if (!fail) {
-        if (unsure) { ok = false; return d; }
+    if (!(over > 0.0f)) {
+        if (under > 0.0f) { ok = false; return d; }   // an axis too close to its tolerance
         d.kind = D_MERGED;
         d.jdir = pair_axis(S.s1, F);
         return d;
@@ -276,9 +275,10 @@ VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, cons
     float best = lo[0];
 #pragma unroll
     for (int l = 1; l < 6; ++l) if (lo[l] > best) { best = lo[l]; k = l; }
+    float rival = -INFINITY;
 #pragma unroll
-    for (int l = 0; l < 6; ++l) if (l != k && !(best > hi[l])) ok = false;
-    if (!ok) return d;
+    for (int l = 0; l < 6; ++l) rival = fmaxf(rival, l == k ? -INFINITY : hi[l]);
+    if (!(best > rival)) { ok = false; return d; }
     double s1k = S.s1[0];
 #pragma unroll
     for (int l = 1; l < 6; ++l) if (l == k) s1k = S.s1[l];

@@ -131,8 +131,14 @@ FixedParams fixed_params(const vpm_params* p) {
     FixedParams f;
     f.that_x = (uint64_t)llrint(p->tol_x * 16777216.0);
     f.that_p = (uint64_t)llrint(p->tol_p * 16777216.0);
-    f.tx2 = (double)f.that_x * (double)f.that_x;
-    f.tp2 = (double)f.that_p * (double)f.that_p;
+    // (T^ / 2^24)^2 to double precision, then an FP32 bracket 2^-22 wide on each side
+    auto bracket = [](uint64_t t, float& lo, float& hi) {
+        const float f = (float)((double)t * (double)t * 0x1p-48);
+        lo = f * (1.0f - 0x1p-22f);
+        hi = f * (1.0f + 0x1p-22f);
+    };
+    bracket(f.that_x, f.t2x_lo, f.t2x_hi);
+    bracket(f.that_p, f.t2p_lo, f.t2p_hi);
     for (int a = 0; a < 3; ++a) f.s[a] = (float)(65536.0 / p->cell_len[a]);
     f.min_subset = p->min_subset;
     f.merge_mode = p->merge_mode;

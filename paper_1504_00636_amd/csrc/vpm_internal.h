@@ -46,7 +46,8 @@ struct Workspace {
 // Fixed-point decision parameters derived on the host from vpm_params.
 struct FixedParams {
     uint64_t that_x, that_p;        // round(T * 2^24)
-    double tx2, tp2;                // fl(that_x^2), fl(that_p^2)
+    float t2x_lo, t2x_hi;           // FP32 bracket of (that_x / 2^24)^2
+    float t2p_lo, t2p_hi;           // FP32 bracket of (that_p / 2^24)^2
     float s[3];                     // fl32(65536 / L_a)
     int32_t min_subset;
     int32_t merge_mode;
