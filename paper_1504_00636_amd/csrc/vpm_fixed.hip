@@ -336,17 +336,33 @@ VPM_DEV int64_t fixq(float a, float b, int G) {
 // Per-cell memory (an LDS slice or a global slab) and kernel arguments.
 // ------------------------------------------------------------------------------------------
 
-struct WaveShared {          // per-wave bookkeeping
+struct CellShared {          // per-cell bookkeeping, in LDS
     int nnext;
     int nmerged;
     int cls_cnt[8];
     int cls_cur[8];
     uint32_t flags;
+    int qi;                  // queue position of the current cell
+    int rootv;               // packed decision of the root
 };
+
+// Cross-wave scratch of a cell processed by WPB > 1 wavefronts.
+template <int WPB>
+struct BlockScratch {
+    float fmax[WPB][11];     // per-wave frame maxima
+    int bad[WPB];
+    double sums[WPB][13];    // per-wave root moments
+    int64_t scan[WPB];       // per-wave totals of the output scan
+};
+
+template <int WPB>
+__host__ __device__ constexpr size_t header_bytes() {
+    return ((sizeof(CellShared) + 15) & ~(size_t)15) + (WPB > 1 ? ((sizeof(BlockScratch<WPB>) + 15) & ~(size_t)15) : 0);
+}
 
 template <typename IdxT>
 struct CellMem {
-    WaveShared* sh;
+    CellShared* sh;
     uint16_t* om;
     int16_t* cp;                   // position codes, axis a at cp + a * sp
     int32_t* cm;                   // momentum codes, axis a at cm + a * sm
@@ -359,9 +375,10 @@ struct CellMem {
 
 __host__ __device__ constexpr size_t rnd16(size_t b) { return (b + 15) & ~(size_t)15; }
 
+// Bytes of the per-cell arrays (without the LDS header).
 template <typename IdxT>
 __host__ __device__ constexpr size_t slice_bytes(int nmax) {
-    return rnd16(sizeof(WaveShared)) + 2 * rnd16(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>)) +
+    return 2 * rnd16(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>)) +
            3 * rnd16((size_t)nmax * 4) + 2 * rnd16((size_t)nmax * sizeof(IdxT)) +
            rnd16(((size_t)nmax + 1) * sizeof(IdxT)) + 4 * rnd16((size_t)nmax * 2) + rnd16((size_t)nmax);
 }
@@ -371,7 +388,7 @@ VPM_DEV CellMem<IdxT> carve(uint8_t* base, int nmax) {
     CellMem<IdxT> M;
     size_t o = 0;
     auto take = [&](size_t bytes) { uint8_t* p = base + o; o += rnd16(bytes); return p; };
-    M.sh = (WaveShared*)take(sizeof(WaveShared));
+    M.sh = nullptr;
     M.nodes0 = (Node<IdxT>*)take(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>));
     M.nodes1 = (Node<IdxT>*)take(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>));
     M.sm = (int)(rnd16((size_t)nmax * 4) / 4);
@@ -442,18 +459,25 @@ VPM_DEV Decision decide(const CellMem<IdxT>& M, const FSums& S, const IdxT* buf,
     return decide_exact(E, P, F);
 }
 
+// Make the cell's shared memory writes visible to all wavefronts working on the cell.
+template <int WPB>
+VPM_DEV void cell_sync() {
+    if constexpr (WPB == 1) wave_fence();
+    else __syncthreads();
+}
+
 // Sort the m items of a list into power-of-two lane-group classes (largest first).  Afterwards
 // the lane groups of class c occupy virtual lanes [lb[c], lb[c] + (cnt[c] << c)) and
-// sched[fb[c] + k] holds the k-th item of class c.  Whole wave calls.
+// sched[fb[c] + k] holds the k-th item of class c.  All threads of the cell call.
 struct Sched { int lb[7], fb[7], cnt[7], total; };
 
-template <typename IdxT, typename LenFn>
+template <int WPB, typename IdxT, typename LenFn>
 VPM_DEV Sched schedule(const CellMem<IdxT>& M, IdxT* sched, int m, LenFn len_of) {
-    const int lane = lane_id();
-    if (lane < 8) { M.sh->cls_cnt[lane] = 0; M.sh->cls_cur[lane] = 0; }
-    wave_fence();
-    for (int it = lane; it < m; it += WAVE) atomicAdd(&M.sh->cls_cnt[group_class_for(len_of(it))], 1);
-    wave_fence();
+    const int tid = threadIdx.x;
+    if (tid < 8) { M.sh->cls_cnt[tid] = 0; M.sh->cls_cur[tid] = 0; }
+    cell_sync<WPB>();
+    for (int it = tid; it < m; it += WAVE * WPB) atomicAdd(&M.sh->cls_cnt[group_class_for(len_of(it))], 1);
+    cell_sync<WPB>();
     Sched s;
     int l = 0, f = 0;
 #pragma unroll
@@ -463,7 +487,7 @@ VPM_DEV Sched schedule(const CellMem<IdxT>& M, IdxT* sched, int m, LenFn len_of)
         l += s.cnt[c] << c; f += s.cnt[c];
     }
     s.total = l;
-    for (int it = lane; it < m; it += WAVE) {
+    for (int it = tid; it < m; it += WAVE * WPB) {
         const int c = group_class_for(len_of(it));
         const int r = atomicAdd(&M.sh->cls_cur[c], 1);
         int fbc = s.fb[0];
@@ -471,7 +495,7 @@ VPM_DEV Sched schedule(const CellMem<IdxT>& M, IdxT* sched, int m, LenFn len_of)
         for (int q = 1; q < 7; ++q) if (q == c) fbc = s.fb[q];
         sched[fbc + r] = (IdxT)it;
     }
-    wave_fence();
+    cell_sync<WPB>();
     return s;
 }
 
@@ -717,49 +741,101 @@ VPM_DEV float wave_max(float v) {
     return v;
 }
 
-// Step 1 for one cell (whole wave): validate the values and build the cell frame.  Returns false
-// if some weight is not positive or some value is not finite.
-VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, float mass, Frame& F) {
-    const int lane = lane_id();
-    float vmax[11];
-    vmax[0] = 0.0f;
-    for (int a = 0; a < 3; ++a) { vmax[1 + a] = -INFINITY; vmax[4 + a] = -INFINITY; vmax[7 + a] = 0.0f; }
-    bool bad = false;
-#pragma unroll 2
-    for (int i = lane; i < n; i += WAVE) {
-        const float q[7] = {in.x[off + i], in.y[off + i], in.z[off + i], in.px[off + i], in.py[off + i],
-                            in.pz[off + i], in.w[off + i]};
-        const float w = q[6];
-        bool ok = w > 0.0f && isfinite(w);
-        for (int l = 0; l < 6; ++l) ok = ok && isfinite(q[l]);
-        bad |= !ok;
-        vmax[0] = fmaxf(vmax[0], w);
-        for (int a = 0; a < 3; ++a) {
-            vmax[1 + a] = fmaxf(vmax[1 + a], -q[a]);
-            vmax[4 + a] = fmaxf(vmax[4 + a], q[a]);
-            vmax[7 + a] = fmaxf(vmax[7 + a], fabsf(q[3 + a]));
-        }
+// Step 1 accumulators: validity and the cell's extreme values.
+struct FrameAcc {
+    float v[11];     // max w; max -x_a (so min x_a); max x_a; max |p_a|
+    bool bad;
+};
+
+VPM_DEV void facc_init(FrameAcc& a) {
+    a.v[0] = 0.0f;
+    for (int k = 0; k < 3; ++k) { a.v[1 + k] = -INFINITY; a.v[4 + k] = -INFINITY; a.v[7 + k] = 0.0f; }
+    a.bad = false;
+}
+
+VPM_DEV void facc_add(FrameAcc& a, const float q[7]) {
+    const float w = q[6];
+    bool ok = w > 0.0f && isfinite(w);
+    for (int l = 0; l < 6; ++l) ok = ok && isfinite(q[l]);
+    a.bad |= !ok;
+    a.v[0] = fmaxf(a.v[0], w);
+    for (int k = 0; k < 3; ++k) {
+        a.v[1 + k] = fmaxf(a.v[1 + k], -q[k]);
+        a.v[4 + k] = fmaxf(a.v[4 + k], q[k]);
+        a.v[7 + k] = fmaxf(a.v[7 + k], fabsf(q[3 + k]));
     }
-    if (__ballot(bad) != 0) return false;
-#pragma unroll
-    for (int r = 0; r < 11; ++r) vmax[r] = wave_max(vmax[r]);
-    F.wmax = vmax[0];
+}
+
+VPM_DEV void facc_load(FrameAcc& a, const Soa32& in, int64_t i) {
+    const float q[7] = {in.x[i], in.y[i], in.z[i], in.px[i], in.py[i], in.pz[i], in.w[i]};
+    facc_add(a, q);
+}
+
+// The frame from the cell maxima v (identical in every lane).
+VPM_DEV void frame_from(const float v[11], float mass, Frame& F) {
+    F.wmax = v[0];
     F.ew = frexp_exp(F.wmax);
     F.amask = 0;
-    for (int a = 0; a < 3; ++a) {
-        F.lo[a] = -vmax[1 + a];
-        F.hi[a] = vmax[4 + a];
-        F.pmax[a] = vmax[7 + a];
-        F.pzero[a] = F.pmax[a] == 0.0f;
-        F.ep[a] = frexp_exp(F.pmax[a]);
-        F.ext_e[a] = frexp_exp(F.hi[a] - F.lo[a]);
-        if (F.hi[a] > F.lo[a]) F.amask |= 1 << a;          // else every position code is equal
-        if (!F.pzero[a]) F.amask |= 1 << (3 + a);          // else every momentum code is 0
+    for (int k = 0; k < 3; ++k) {
+        F.lo[k] = -v[1 + k];
+        F.hi[k] = v[4 + k];
+        F.pmax[k] = v[7 + k];
+        F.pzero[k] = F.pmax[k] == 0.0f;
+        F.ep[k] = frexp_exp(F.pmax[k]);
+        F.ext_e[k] = frexp_exp(F.hi[k] - F.lo[k]);
+        if (F.hi[k] > F.lo[k]) F.amask |= 1 << k;          // else every position code is equal
+        if (!F.pzero[k]) F.amask |= 1 << (3 + k);          // else every momentum code is 0
     }
     F.amask = __builtin_amdgcn_readfirstlane(F.amask);     // wave-uniform: scalar branches
     // |eps_i - eps_j| <= m + |p|_1 for any two particles of the cell; 4x margin
     F.eb = frexp_exp(4.0f * (mass + F.pmax[0] + F.pmax[1] + F.pmax[2]));
+}
+
+// Step 1 for one cell (whole wave): validate the values and build the cell frame.  Returns false
+// if some weight is not positive or some value is not finite.
+VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, float mass, Frame& F) {
+    FrameAcc acc;
+    facc_init(acc);
+#pragma unroll 2
+    for (int i = lane_id(); i < n; i += WAVE) facc_load(acc, in, off + i);
+    if (__ballot(acc.bad) != 0) return false;
+#pragma unroll
+    for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
+    frame_from(acc.v, mass, F);
     return true;
+}
+
+// The same for a cell shared by WPB wavefronts (all threads call; the result is the same in all).
+template <int WPB>
+VPM_DEV bool cell_frame_block(const Soa32& in, int64_t off, int n, float mass, Frame& F, BlockScratch<WPB>* bs) {
+    if constexpr (WPB == 1) {
+        return cell_frame(in, off, n, mass, F);
+    } else {
+        const int wv = threadIdx.x / WAVE;
+        FrameAcc acc;
+        facc_init(acc);
+#pragma unroll 2
+        for (int i = threadIdx.x; i < n; i += WAVE * WPB) facc_load(acc, in, off + i);
+        const bool bad = __ballot(acc.bad) != 0;
+#pragma unroll
+        for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
+        if (lane_id() == 0) {
+            bs->bad[wv] = bad;
+            for (int r = 0; r < 11; ++r) bs->fmax[wv][r] = acc.v[r];
+        }
+        __syncthreads();
+        bool any_bad = false;
+        float v[11];
+        for (int r = 0; r < 11; ++r) v[r] = bs->fmax[0][r];
+        for (int w = 0; w < WPB; ++w) {
+            any_bad |= bs->bad[w] != 0;
+            for (int r = 0; r < 11; ++r) v[r] = fmaxf(v[r], bs->fmax[w][r]);
+        }
+        __syncthreads();                                   // the scratch is reused below
+        if (any_bad) return false;
+        frame_from(v, mass, F);
+        return true;
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -860,23 +936,40 @@ __global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs G) {
 }
 
 // ------------------------------------------------------------------------------------------
-// The cell kernel: one wavefront per cell.
+// The cell kernel: one cell per workgroup of WPB wavefronts (one wavefront for the small bin).
+// The subsets of a level are spread over the lane groups of all wavefronts; workgroup barriers
+// separate the phases.
 // ------------------------------------------------------------------------------------------
 
 template <int NMAX, typename IdxT, bool IN_LDS, int WPB>
 __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
     extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x;
     const int lane = lane_id();
-    const int wv = threadIdx.x / WAVE;
-    constexpr size_t SLICE = slice_bytes<IdxT>(NMAX);
-    CellMem<IdxT> M = IN_LDS ? carve<IdxT>(smem + (size_t)wv * SLICE, NMAX)
-                             : carve<IdxT>(A.big + ((int64_t)blockIdx.x * WPB + wv) * A.big_stride, NMAX);
-    WaveShared& sh = *M.sh;
+    const int wv = tid / WAVE;
+    constexpr int NT = WAVE * WPB;
+    constexpr size_t HDR = header_bytes<WPB>();
+    CellMem<IdxT> M = IN_LDS ? carve<IdxT>(smem + HDR, NMAX)
+                             : carve<IdxT>(A.big + (int64_t)blockIdx.x * A.big_stride, NMAX);
+    M.sh = (CellShared*)smem;
+    BlockScratch<WPB>* bs = (BlockScratch<WPB>*)(smem + ((sizeof(CellShared) + 15) & ~(size_t)15));
+    CellShared& sh = *M.sh;
 
     for (;;) {
         int qi = 0;
-        if (lane == 0) qi = atomicAdd(&A.counters[A.work_index], 1);
-        qi = __shfl(qi, 0);
+        if constexpr (WPB == 1) {
+            if (lane == 0) qi = atomicAdd(&A.counters[A.work_index], 1);
+            qi = __shfl(qi, 0);
+        } else {
+            __syncthreads();                               // the previous cell is finished
+            if (tid == 0) {
+                sh.qi = atomicAdd(&A.counters[A.work_index], 1);
+                sh.flags = 0;
+                sh.nnext = 0;
+            }
+            __syncthreads();
+            qi = sh.qi;
+        }
         if (qi >= A.counters[A.qlen_index]) break;
         const int c = A.queue[qi];
         const int64_t off = A.cell_off[c];
@@ -884,17 +977,19 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
 
         // ---- Step 1: collect the cell, validate, frame ----
         Frame F;
-        if (!cell_frame(A.in, off, n, (float)A.P.mass, F)) {
-            if (lane == 0) {
+        if (!cell_frame_block<WPB>(A.in, off, n, (float)A.P.mass, F, bs)) {
+            if (tid == 0) {
                 atomicOr(A.flags, FLAG_BAD_VALUE);
                 if (A.mode == 0) { A.out_count[c] = n; A.cell_mode[c] = CELL_UNTOUCHED; }
                 else A.n_subsets[c] = 0;
             }
             if (A.mode == 1)
-                for (int i = lane; i < n; i += WAVE) { A.perm[off + i] = (int32_t)(off + i); A.subset_id[off + i] = -1; }
+                for (int i = tid; i < n; i += NT) { A.perm[off + i] = (int32_t)(off + i); A.subset_id[off + i] = -1; }
             continue;
         }
-        if (lane == 0) { sh.flags = 0; sh.nnext = 0; }
+        if constexpr (WPB == 1) {
+            if (lane == 0) { sh.flags = 0; sh.nnext = 0; }
+        }
 
         // ---- codes and the root's moments ----
         FSums R;
@@ -918,20 +1013,39 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             fsums_add(R, om, cc[0], cc[1], cc[2], cc[3], cc[4], cc[5]);
         };
 #pragma unroll 2
-        for (int i = lane; i < n; i += WAVE) {
+        for (int i = tid; i < n; i += NT) {
             const float q[7] = {A.in.x[off + i], A.in.y[off + i], A.in.z[off + i], A.in.px[off + i],
                                 A.in.py[off + i], A.in.pz[off + i], A.in.w[off + i]};
             encode(i, q);
         }
         const bool any_oob = __ballot(oob) != 0;
         fsums_group_reduce(R, WAVE);
-        wave_fence();
-        int rootv = 0;
-        if (lane == 0) rootv = pack_decision(decide(M, R, M.idx0, 0, n, A.P, F));
-        const Decision rd = unpack_decision(__shfl(rootv, 0));
+        if constexpr (WPB > 1) {
+            if (lane == 0) {
+                bs->sums[wv][0] = R.s0;
+                for (int l = 0; l < 6; ++l) { bs->sums[wv][1 + l] = R.s1[l]; bs->sums[wv][7 + l] = R.s2[l]; }
+                if (any_oob) atomicOr(&sh.flags, FLAG_OUT_OF_CELL);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                fsums_zero(R);
+                for (int w = 0; w < WPB; ++w) {
+                    R.s0 += bs->sums[w][0];
+                    for (int l = 0; l < 6; ++l) { R.s1[l] += bs->sums[w][1 + l]; R.s2[l] += bs->sums[w][7 + l]; }
+                }
+                sh.rootv = pack_decision(decide(M, R, M.idx0, 0, n, A.P, F));
+            }
+            __syncthreads();
+        } else {
+            if (any_oob && lane == 0) sh.flags |= FLAG_OUT_OF_CELL;
+            wave_fence();
+            if (lane == 0) sh.rootv = pack_decision(decide(M, R, M.idx0, 0, n, A.P, F));
+            wave_fence();
+        }
+        const Decision rd = unpack_decision(sh.rootv);
         int m = 0;
         if (rd.kind == D_SPLIT) {
-            if (lane == 0) {
+            if (tid == 0) {
                 Node<IdxT> nd;
                 nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 4) | rd.axis;
                 M.nodes0[0] = nd;
@@ -939,18 +1053,18 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             m = 1;
         } else {
             const uint8_t base = INF_SET | (rd.kind == D_MERGED ? INF_MERGED : 0) | (uint8_t)(rd.jdir << INF_JSHIFT);
-            for (int i = lane; i < n; i += WAVE) M.info[i] = base | (i == 0 ? INF_HEAD : 0);
+            for (int i = tid; i < n; i += NT) M.info[i] = base | (i == 0 ? INF_HEAD : 0);
         }
-        wave_fence();
+        cell_sync<WPB>();
 
         // ---- Steps 2-6, level by level ----
         int cur = 0;
         while (m > 0) {
             Node<IdxT>* curl = cur ? M.nodes1 : M.nodes0;
             Node<IdxT>* nextl = cur ? M.nodes0 : M.nodes1;
-            if (lane == 0) sh.nnext = 0;
-            const Sched s = schedule<IdxT>(M, M.emit, m, [&](int it) { return (int)curl[it].len; });
-            for (int r0 = 0; r0 < s.total; r0 += WAVE) {
+            if (tid == 0) sh.nnext = 0;
+            const Sched s = schedule<WPB, IdxT>(M, M.emit, m, [&](int it) { return (int)curl[it].len; });
+            for (int r0 = wv * WAVE; r0 < s.total; r0 += NT) {
                 int slot, cls;
                 if (sched_lookup(s, r0 + lane, slot, cls)) {
                     const Node<IdxT> nd = curl[M.emit[slot]];
@@ -958,15 +1072,16 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
                     split_node<IdxT>(M, A, F, nd, cur, lane & (g - 1), g, lane & ~(g - 1), nextl);
                 }
             }
-            wave_fence();
+            cell_sync<WPB>();
             m = sh.nnext;
             cur ^= 1;
+            if constexpr (WPB > 1) __syncthreads();        // nnext is read before it is reset
         }
 
         // ---- output ----
         // one scan over the cell's slots gives leaf ordinals and output slots
-        const int per = (n + WAVE - 1) / WAVE;
-        const int b0 = min(n, lane * per), b1 = min(n, b0 + per);
+        const int per = (n + NT - 1) / NT;
+        const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
         const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
         int64_t loc = 0;
         for (int p = b0; p < b1; ++p) {
@@ -979,14 +1094,25 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             const int64_t o = __shfl_up(inc, d);
             if (lane >= d) inc += o;
         }
-        const int64_t tot = __shfl(inc, WAVE - 1);
-        int64_t pre = inc - loc;
+        int64_t tot, wbase = 0;
+        if constexpr (WPB > 1) {
+            if (lane == WAVE - 1) bs->scan[wv] = inc;
+            __syncthreads();
+            tot = 0;
+            for (int w = 0; w < WPB; ++w) {
+                if (w < wv) wbase += bs->scan[w];
+                tot += bs->scan[w];
+            }
+        } else {
+            tot = __shfl(inc, WAVE - 1);
+        }
+        int64_t pre = wbase + inc - loc;
         const int nleaves = (int)(tot >> 32);
         const int out_total = (int)(tot & 0xffffffff);
         IdxT* leaf_start = (IdxT*)M.nodes0;                // first slot of each final subset
         IdxT* mlist = (IdxT*)M.nodes1;                     // ordinals of the merged subsets
-        if (lane == 0) sh.nmerged = 0;
-        wave_fence();
+        if (tid == 0) sh.nmerged = 0;
+        cell_sync<WPB>();
         for (int p = b0; p < b1; ++p) {
             const uint8_t inf = M.info[p];
             const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
@@ -1003,11 +1129,11 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             }
             pre += ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
         }
-        if (lane == 0) leaf_start[nleaves] = (IdxT)n;
-        wave_fence();
-        const uint32_t fl = sh.flags | (any_oob ? FLAG_OUT_OF_CELL : 0u);
+        if (tid == 0) leaf_start[nleaves] = (IdxT)n;
+        cell_sync<WPB>();
+        const uint32_t fl = sh.flags;
         if (A.mode == 1) {
-            if (lane == 0) {
+            if (tid == 0) {
                 A.n_subsets[c] = nleaves;
                 if (fl) atomicOr(A.flags, fl);
             }
@@ -1015,7 +1141,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         }
         // copied particles (subsets below min_subset)
 #pragma unroll 4
-        for (int p = lane; p < n; p += WAVE) {
+        for (int p = tid; p < n; p += NT) {
             const uint8_t inf = M.info[p];
             if (inf & INF_MERGED) continue;
             const int64_t i = off + idx_buf(M, inf & INF_PARITY)[p];
@@ -1028,11 +1154,11 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         const int nm = sh.nmerged;
         if (nm > 0) {
             IdxT* sched = (IdxT*)M.cm;                     // momentum codes are free now
-            const Sched s = schedule<IdxT>(M, sched, nm, [&](int it) {
+            const Sched s = schedule<WPB, IdxT>(M, sched, nm, [&](int it) {
                 const int ord = mlist[it];
                 return (int)(leaf_start[ord + 1] - leaf_start[ord]);
             });
-            for (int r0 = 0; r0 < s.total; r0 += WAVE) {
+            for (int r0 = wv * WAVE; r0 < s.total; r0 += NT) {
                 int slot, cls;
                 if (sched_lookup(s, r0 + lane, slot, cls)) {
                     const int ord = mlist[sched[slot]];
@@ -1046,31 +1172,42 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
                 }
             }
         }
-        if (lane == 0) {
+        if (tid == 0) {
             A.out_count[c] = out_total;
             A.cell_mode[c] = CELL_PROCESSED;
             if (fl) atomicOr(A.flags, fl);
         }
+        if constexpr (WPB == 1) wave_fence();
     }
 }
 
-constexpr int WPB_A = 1, WPB_B = 1, WPB_BIG = 1;
+constexpr int WPB_A = 1, WPB_B = 4, WPB_C = 8, WPB_BIG = 8;
 
 }  // namespace
 
 int fixed_lds_bytes(int which) {
-    return which == 0 ? (int)(slice_bytes<uint16_t>(NMAX_A) * WPB_A) : (int)(slice_bytes<uint16_t>(NMAX_B) * WPB_B);
+    switch (which) {
+        case 0: return (int)(header_bytes<WPB_A>() + slice_bytes<uint16_t>(NMAX_A));
+        case 1: return (int)(header_bytes<WPB_B>() + slice_bytes<uint16_t>(NMAX_B));
+        case 2: return (int)(header_bytes<WPB_C>() + slice_bytes<uint16_t>(NMAX_C));
+        default: return (int)header_bytes<WPB_BIG>();
+    }
 }
 
 int64_t fixed_big_slab_bytes() { return (int64_t)slice_bytes<uint32_t>(NMAX_BIG); }
 
 const void* fixed_kernel_ptr(int which) {
-    if (which == 0) return (const void*)k_fixed_cells<NMAX_A, uint16_t, true, WPB_A>;
-    if (which == 1) return (const void*)k_fixed_cells<NMAX_B, uint16_t, true, WPB_B>;
-    return (const void*)k_fixed_cells<NMAX_BIG, uint32_t, false, WPB_BIG>;
+    switch (which) {
+        case 0: return (const void*)k_fixed_cells<NMAX_A, uint16_t, true, WPB_A>;
+        case 1: return (const void*)k_fixed_cells<NMAX_B, uint16_t, true, WPB_B>;
+        case 2: return (const void*)k_fixed_cells<NMAX_C, uint16_t, true, WPB_C>;
+        default: return (const void*)k_fixed_cells<NMAX_BIG, uint32_t, false, WPB_BIG>;
+    }
 }
 
-int fixed_block_threads(int which) { return WAVE * (which == 0 ? WPB_A : which == 1 ? WPB_B : WPB_BIG); }
+int fixed_block_threads(int which) {
+    return WAVE * (which == 0 ? WPB_A : which == 1 ? WPB_B : which == 2 ? WPB_C : WPB_BIG);
+}
 
 hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
                               const int64_t* cell_off, int64_t n_cells, int32_t n_min_cell,
@@ -1093,7 +1230,7 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
     A.big = nullptr; A.big_stride = 0;
     G.perm = perm; G.subset_id = subset_id; G.n_subsets = n_subsets;
     G.starts = ws.perm2;
-    const int qs[3] = {Q_BIG, Q_B, Q_A};
+    const int qs[4] = {Q_BIG, Q_C, Q_B, Q_A};
     for (int q : qs) {
         A.queue = ws.queue[q];
         A.qlen_index = q;
@@ -1125,27 +1262,49 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
     A.big = ws.big;
     A.big_stride = fixed_big_slab_bytes();
 
-    struct Bin { int q; const char* name; };
-    const Bin bins[3] = {{Q_BIG, "fixed_cells_big"}, {Q_B, "fixed_cells_2048"}, {Q_A, "fixed_cells_576"}};
+    // The three bins touch disjoint cells, queues and counters, so they may run concurrently: the
+    // large-cell and 2048 bins go first on the side streams (their cells are the longest), the
+    // 576 bin fills the rest of the chip on the caller's stream, and the caller's stream then waits
+    // for both side streams.
+    bool forked = lc.fork != nullptr;
+    for (int i = 0; i < 3; ++i) forked = forked && lc.side[i] && lc.join[i];
+    hipError_t e = hipSuccess;
+    if (forked) {
+        e = hipEventRecord(lc.fork, lc.stream);
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(lc.side[i], lc.fork, 0);
+        if (e != hipSuccess) return e;
+    }
+    struct Bin { int q; const char* name; hipStream_t s; };
+    const Bin bins[4] = {{Q_BIG, "fixed_cells_big", forked ? lc.side[0] : lc.stream},
+                         {Q_C, "fixed_cells_4352", forked ? lc.side[1] : lc.stream},
+                         {Q_B, "fixed_cells_2048", forked ? lc.side[2] : lc.stream},
+                         {Q_A, "fixed_cells_576", lc.stream}};
     for (const Bin& b : bins) {
         A.queue = ws.queue[b.q];
         A.qlen_index = b.q;
         A.work_index = 8 + b.q;
-        if (lc.pre) lc.pre(lc.prof, b.name, lc.stream);
+        if (lc.pre) lc.pre(lc.prof, b.name, b.s);
         if (b.q == Q_A)
             hipLaunchKernelGGL((k_fixed_cells<NMAX_A, uint16_t, true, WPB_A>), dim3(lc.grid_a), dim3(WAVE * WPB_A),
-                               fixed_lds_bytes(0), lc.stream, A);
+                               fixed_lds_bytes(0), b.s, A);
         else if (b.q == Q_B)
             hipLaunchKernelGGL((k_fixed_cells<NMAX_B, uint16_t, true, WPB_B>), dim3(lc.grid_b), dim3(WAVE * WPB_B),
-                               fixed_lds_bytes(1), lc.stream, A);
+                               fixed_lds_bytes(1), b.s, A);
+        else if (b.q == Q_C)
+            hipLaunchKernelGGL((k_fixed_cells<NMAX_C, uint16_t, true, WPB_C>), dim3(lc.grid_c), dim3(WAVE * WPB_C),
+                               fixed_lds_bytes(2), b.s, A);
         else
             hipLaunchKernelGGL((k_fixed_cells<NMAX_BIG, uint32_t, false, WPB_BIG>), dim3(lc.grid_big),
-                               dim3(WAVE * WPB_BIG), 0, lc.stream, A);
-        hipError_t e = hipGetLastError();
+                               dim3(WAVE * WPB_BIG), fixed_lds_bytes(3), b.s, A);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (lc.post) lc.post(lc.prof, b.name, lc.stream);
+        if (lc.post) lc.post(lc.prof, b.name, b.s);
     }
-    return hipSuccess;
+    if (forked) {
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventRecord(lc.join[i], lc.side[i]);
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(lc.stream, lc.join[i], 0);
+    }
+    return e;
 }
 
 }  // namespace vpm

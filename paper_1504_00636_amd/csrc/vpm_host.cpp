@@ -3,6 +3,7 @@
 // vpm_destroy, vpm_device_status and vpm_profile_read.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -17,7 +18,9 @@ struct vpm_ctx {
     int device = 0;
     int cu_count = 0;
     Workspace ws;
-    int grid_a = 0, grid_b = 0, grid_big = 0, grid_fp64 = 0;
+    int grid_a = 0, grid_b = 0, grid_c = 0, grid_big = 0, grid_fp64 = 0;
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     std::string last_error;
     // profiling
     bool profiling = false;
@@ -84,8 +87,11 @@ LaunchCfg make_cfg(vpm_ctx* c, hipStream_t s) {
     lc.stream = s;
     lc.grid_a = c->grid_a;
     lc.grid_b = c->grid_b;
+    lc.grid_c = c->grid_c;
     lc.grid_big = c->grid_big;
     lc.grid_fp64 = c->grid_fp64;
+    for (int i = 0; i < 3; ++i) { lc.side[i] = c->side[i]; lc.join[i] = c->join[i]; }
+    lc.fork = c->fork;
     lc.pre = c->profiling ? prof_pre : nullptr;
     lc.post = c->profiling ? prof_post : nullptr;
     lc.prof = c;
@@ -216,14 +222,30 @@ vpm_status vpm_create(vpm_ctx** out, int device) {
     if (e != hipSuccess) { delete c; return VPM_ERR_HIP; }
     hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device);
     if (c->cu_count <= 0) c->cu_count = 256;
-    int nb = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(0), fixed_block_threads(0), fixed_lds_bytes(0));
-    c->grid_a = c->cu_count * (nb > 0 ? nb : 1);
-    nb = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(1), fixed_block_threads(1), fixed_lds_bytes(1));
-    c->grid_b = c->cu_count * (nb > 0 ? nb : 1);
-    c->grid_big = c->cu_count;
+    // persistent grids: as many workgroups as fit on the chip at once
+    int* grids[3] = {&c->grid_a, &c->grid_b, &c->grid_c};
+    for (int b = 0; b < 3; ++b) {
+        int nb = 0;
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(b), fixed_block_threads(b), fixed_lds_bytes(b));
+        *grids[b] = c->cu_count * (nb > 0 ? nb : 1);
+    }
+    c->grid_big = 1;                       // sized by vpm_reserve from the particle capacity
     c->grid_fp64 = c->cu_count * 16;
+    // side streams and events for running the size bins concurrently
+    bool side_ok = true;
+    for (int i = 0; i < 3 && side_ok; ++i)
+        side_ok = hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming) == hipSuccess;
+    if (side_ok) side_ok = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
+    if (!side_ok) {
+        for (int i = 0; i < 3; ++i) {
+            if (c->side[i]) hipStreamDestroy(c->side[i]);
+            if (c->join[i]) hipEventDestroy(c->join[i]);
+            c->side[i] = nullptr; c->join[i] = nullptr;
+        }
+        if (c->fork) hipEventDestroy(c->fork);
+        c->fork = nullptr;
+    }
     *out = c;
     return VPM_OK;
 }
@@ -235,6 +257,11 @@ vpm_status vpm_destroy(vpm_ctx* ctx) {
     free_ws(ctx->ws);
     for (auto& r : ctx->pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
     for (auto e : ctx->pool) hipEventDestroy(e);
+    for (int i = 0; i < 3; ++i) {
+        if (ctx->side[i]) hipStreamDestroy(ctx->side[i]);
+        if (ctx->join[i]) hipEventDestroy(ctx->join[i]);
+    }
+    if (ctx->fork) hipEventDestroy(ctx->fork);
     delete ctx;
     return VPM_OK;
 }
@@ -261,7 +288,10 @@ vpm_status vpm_reserve(vpm_ctx* ctx, int64_t max_particles, int64_t max_cells) {
     alloc((void**)&ws.counters, 4096);
     alloc((void**)&ws.flags, 256);
     alloc((void**)&ws.scan_blocks, (size_t)(nc / 4096 + 2) * 8);
-    ws.big_bytes = fixed_big_slab_bytes() * ctx->grid_big * (fixed_block_threads(2) / 64);
+    // one global slab per workgroup of the large-cell kernel: one per CU, but never more than the
+    // number of cells above the LDS bins that the capacity allows
+    ctx->grid_big = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->cu_count, np / (NMAX_C + 1)));
+    ws.big_bytes = fixed_big_slab_bytes() * ctx->grid_big;
     alloc((void**)&ws.big, (size_t)ws.big_bytes);
     alloc((void**)&ws.perm2, (size_t)np * 2 * 4);
     alloc((void**)&ws.stack, (size_t)np * 8);

@@ -12,10 +12,11 @@ namespace vpm {
 enum CellMode : uint8_t { CELL_PROCESSED = 0, CELL_UNTOUCHED = 1 };
 
 // Size bins of the fixed-point path.
-constexpr int NMAX_A = 576;     // wavefront per cell, working set in an LDS slice (8 per CU)
-constexpr int NMAX_B = 2048;    // wavefront per cell, working set in an LDS slice
-constexpr int NMAX_BIG = 65536; // wavefront per cell, working set in a global slab
-enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_BIG = 3, Q_COUNT = 4 };
+constexpr int NMAX_A = 576;     // 1 wavefront per cell, working set in LDS (8 cells per CU)
+constexpr int NMAX_B = 2048;    // 4 wavefronts per cell, working set in LDS (2 cells per CU)
+constexpr int NMAX_C = 4352;    // 8 wavefronts per cell, working set in LDS (1 cell per CU)
+constexpr int NMAX_BIG = 65536; // 8 wavefronts per cell, working set in a global slab
+enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_C = 3, Q_BIG = 4, Q_COUNT = 5 };
 
 // Status bits (mirrors VPM_FLAG_* plus one internal bit).
 constexpr uint32_t FLAG_BAD_VALUE = VPM_FLAG_BAD_VALUE;
@@ -56,7 +57,11 @@ struct FixedParams {
 
 struct LaunchCfg {
     hipStream_t stream;
-    int grid_a, grid_b, grid_big, grid_fp64;   // persistent grid sizes
+    int grid_a, grid_b, grid_c, grid_big, grid_fp64;   // persistent grid sizes
+    // Optional fork/join for the size bins: bins run concurrently on two side streams (default
+    // priority) that wait on `fork` (recorded on `stream`) and are joined back through `join`.
+    hipStream_t side[3];
+    hipEvent_t fork, join[3];
     // profiling hooks (may be null)
     void (*pre)(void* prof, const char* name, hipStream_t s);
     void (*post)(void* prof, const char* name, hipStream_t s);
@@ -89,10 +94,11 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
                               const int64_t* cell_off, int64_t n_cells, int32_t n_min_cell,
                               const FixedParams& fp, const int32_t* perm,
                               const int32_t* subset_id, const int32_t* n_subsets);
-int fixed_lds_bytes(int which);           // dynamic LDS per workgroup: 0 = bin A, 1 = bin B
-const void* fixed_kernel_ptr(int which);   // for occupancy queries: 0 = A, 1 = B, 2 = big
+// bins: 0 = A, 1 = B, 2 = C (LDS), 3 = big (global slabs)
+int fixed_lds_bytes(int which);            // dynamic LDS per workgroup
+const void* fixed_kernel_ptr(int which);   // for occupancy queries
 int fixed_block_threads(int which);
-int64_t fixed_big_slab_bytes();            // one slab per wavefront of the big-cell kernel
+int64_t fixed_big_slab_bytes();            // one slab per workgroup of the big-cell kernel
 
 // ---- plain FP64 path (vpm_fp64.hip) ----
 struct Fp64Params {
