@@ -4,15 +4,21 @@ One step = one merge event (vpm_run: bin cells, partition every cell, merge, com
 synthetic two-stream population: 256 x 256 cells, Poisson(512) electrons per cell (33.5M particles),
 two drifting Maxwellians, tolerances T_X 0.1, T_P 0.05, minimum subset 4.  Inputs are resident in
 HBM before timing.  The batched fixed-point FP32 form is the measured line; the plain FP64 form
-(one wavefront per cell) is timed on the same population for the speedup, and both forms' conserved
-totals (weight, momentum, energy) are compared with their inputs.
+(one wavefront per cell, FP64 statistics) is timed on the same population for the speedup, and both
+forms' conserved totals (weight, momentum, energy) are compared with their inputs.  Two more
+workloads are reported beside the headline: the shower-shaped 64^3 population (lognormal cell
+occupancy up to 32,768, gamma^-2 momenta) and the two-stream population at the paper's own
+two-stream tolerances.
 
-Prints one JSON line.  `--copy-calib` instead runs a plain device copy of known size (for scaling
-rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes).
+Prints one JSON line.  Tooling modes: `--copy-calib` runs a plain device copy of known size (for
+scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes); `--traffic-summary` turns four
+rocprofv3 counter runs into the traffic record under profiles/.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
@@ -27,10 +33,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fixed_cells_two_stream.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_00636_amd", "csrc", "vpm_fixed.hip")
+DOMINANT = "fixed_cells_576"          # the one-wavefront-per-cell bin: every two-stream cell but ~0.2 %
+DOMINANT_SYMBOL = "k_fixed_cells<576"  # how rocprofv3 names it
+BIN_A_MAX = 576
+COPY_BYTES = 1 << 30
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
 
 
 def conservation_error(arrs_in, arrs_out, n_out, mass):
@@ -55,23 +69,127 @@ def traffic_from_profiles():
         return None
     try:
         t = json.load(open(TRAFFIC_FILE))
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-        if t.get("kernel_source_sha256") != sha:
+        if t.get("kernel_source_sha256") != kernel_source_sha():
             return None
         return float(t["fetch_bytes_per_launch"]) + float(t["write_bytes_per_launch"])
     except Exception:
         return None
 
 
-def copy_calibration(nbytes=1 << 30, reps=5):
+def copy_calibration(reps=5):
     import torch
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(reps):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_calibration_bytes_read": nbytes, "copy_calibration_bytes_written": nbytes,
+    print(json.dumps({"copy_calibration_bytes_read": COPY_BYTES, "copy_calibration_bytes_written": COPY_BYTES,
                       "launches": reps}))
+
+
+def _counter_means(d, counter, kernel_pred):
+    vals = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter and kernel_pred(r["Kernel_Name"]):
+                vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no {counter} rows for the kernel in {d}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic_summary(fetch_dir, write_dir, calib_fetch_dir, calib_write_dir):
+    """Scale FETCH_SIZE / WRITE_SIZE of the dominant kernel by the same counters on a plain copy of
+    COPY_BYTES bytes, and write the traffic record (bytes per launch) under profiles/."""
+    is_dom = lambda k: DOMINANT_SYMBOL in k.replace(" ", "")
+    is_copy = lambda k: "copy" in k.lower() and "fill" not in k.lower()
+    f_k, nf = _counter_means(fetch_dir, "FETCH_SIZE", is_dom)
+    w_k, nw = _counter_means(write_dir, "WRITE_SIZE", is_dom)
+    f_c, _ = _counter_means(calib_fetch_dir, "FETCH_SIZE", is_copy)
+    w_c, _ = _counter_means(calib_write_dir, "WRITE_SIZE", is_copy)
+    fetch_scale = COPY_BYTES / f_c
+    write_scale = COPY_BYTES / w_c
+    rec = {
+        "kernel": DOMINANT, "workload": "two_stream_256x256_poisson512",
+        "kernel_source_sha256": kernel_source_sha(),
+        "fetch_bytes_per_launch": f_k * fetch_scale, "write_bytes_per_launch": w_k * write_scale,
+        "fetch_counter_per_launch": f_k, "write_counter_per_launch": w_k, "launches": [nf, nw],
+        "copy_calibration": {"bytes": COPY_BYTES, "fetch_counter": f_c, "write_counter": w_c,
+                             "fetch_bytes_per_count": fetch_scale, "write_bytes_per_count": write_scale},
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --no-cpu --no-fp64 --no-extra --steps 3 --warmup 1",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --no-cpu --no-fp64 --no-extra --steps 3 --warmup 1",
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --copy-calib",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --copy-calib",
+            "python3 bench.py --traffic-summary <fetch> <write> <calib-fetch> <calib-write>",
+        ],
+    }
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def time_fixed(ctx, vpm, arrs, off, n, p, steps, warmup, profile):
+    """Time `steps` merge events of the fixed-point FP32 form; returns (ms/step, outputs, kernels)."""
+    import torch
+    n_cells = off.numel() - 1
+    out = [torch.empty_like(a) for a in arrs]
+    out_off = torch.empty(n_cells + 1, dtype=torch.int64, device="cuda")
+    out_total = torch.empty(1, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.run(arrs, off, n, p, out, out_off, out_total, stream)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.profile_enable(True)
+        ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run(arrs, off, n, p, out, out_off, out_total, stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    kernels = {}
+    if profile:
+        prof = ctx.profile_read(reset=True)
+        ctx.profile_enable(False)
+        kernels = {k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1)) for k, v in prof.items()}
+    return ms, out, out_off, int(out_total.item()), kernels
+
+
+def time_plain(ctx, vpm, wl64, prm, steps):
+    import torch
+    arrs64, off64 = vpm.upload(wl64)
+    n = wl64.n
+    p64 = vpm.make_params(decide=vpm.VPM_DECIDE_FP64, **prm)
+    ms, out64, _, n_out, _ = time_fixed(ctx, vpm, arrs64, off64, n, p64, steps, 1, False)
+    cons = conservation_error(arrs64, out64, n_out, prm["mass"])
+    del arrs64, out64
+    torch.cuda.empty_cache()
+    return dict(ms_per_step=ms, value=n / (ms * 1e-3), n_out=n_out, conservation=cons)
+
+
+def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps):
+    """One more population: FIXED FP32 timing and, unless fp64_steps == 0, the plain FP64 form."""
+    import torch
+    n = wl32.n
+    arrs, off = vpm.upload(wl32)
+    p32 = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
+    ms, out, _, n_out, kernels = time_fixed(ctx, vpm, arrs, off, n, p32, steps, 2, True)
+    rec = dict(workload=name, n_particles=n, n_cells=wl32.n_cells, ms_per_step=ms, value=n / (ms * 1e-3),
+               unit="particles/s", merge_ratio=n_out / n,
+               conservation=conservation_error(arrs, out, n_out, prm["mass"]),
+               kernels={k: round(v["avg_ms"], 4) for k, v in kernels.items()},
+               params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset")})
+    del arrs, out
+    torch.cuda.empty_cache()
+    if fp64_steps > 0 and wl64 is not None:
+        pl = time_plain(ctx, vpm, wl64, prm, fp64_steps)
+        pl["speedup_batched_over_plain"] = pl["ms_per_step"] / ms
+        rec["plain_fp64"] = pl
+    log(f"[bench] {name}: {ms:.3f} ms/step ({rec['value']:.3g} particles/s), rho {rec['merge_ratio']:.4f}")
+    return rec
 
 
 def main():
@@ -82,10 +200,15 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 form")
+    ap.add_argument("--no-extra", action="store_true", help="skip the shower and paper-tolerance workloads")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CALIB_FETCH", "CALIB_WRITE"))
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
 
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: a merge event is cell-local, and this benchmark times the "
               "single-MI355X form; run it without --gpus or with --gpus 1", file=sys.stderr)
@@ -106,64 +229,35 @@ def main():
     log(f"[bench] generated {n} particles in {n_cells} cells ({time.time() - t0:.1f}s)")
 
     ctx = vpm.Context(0)
-    ctx.reserve(n, n_cells)
+    ctx.reserve(52_000_000, 64 ** 3)
     arrs32, off = vpm.upload(wl32)
-    out32 = [torch.empty_like(a) for a in arrs32]
-    out_off = torch.empty(n_cells + 1, dtype=torch.int64, device="cuda")
-    out_total = torch.empty(1, dtype=torch.int64, device="cuda")
     p32 = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        ctx.run(arrs32, off, n, p32, out32, out_off, out_total, stream)
-    torch.cuda.synchronize()
-    log("[bench] warmup done")
-
-    ctx.profile_enable(True)
-    ctx.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.run(arrs32, off, n, p32, out32, out_off, out_total, stream)
-    torch.cuda.synchronize()
-    t_end = time.perf_counter()
-    prof = ctx.profile_read(reset=True)
-    ctx.profile_enable(False)
-    ms_step = (t_end - t_start) * 1e3 / args.steps
-    n_out = int(out_total.item())
+    ms_step, out32, out_off, n_out, kernels = time_fixed(ctx, vpm, arrs32, off, n, p32, args.steps,
+                                                         args.warmup, True)
     rho = n_out / n
     flags = ctx.device_status(clear=True)
     log(f"[bench] fixed-point FP32: {ms_step:.3f} ms/step, out {n_out} (rho {rho:.4f}), flags {flags}")
 
-    kernels = {k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1)) for k, v in prof.items()}
-    # the dominant kernel: the partition/merge kernel with the largest time per step
-    dom_name = max((k for k in kernels if k.startswith("fixed_cells")), key=lambda k: kernels[k]["avg_ms"])
-    dom = kernels[dom_name]
-    # algorithmic bytes: read every input particle (7 x FP32), write every output particle (7 x FP32)
-    bytes_per_step = 28.0 * n * (1.0 + rho)
-    achieved = bytes_per_step / (dom["avg_ms"] * 1e-3) / 1e9
+    # Roofline of the dominant kernel (the one-wavefront-per-cell bin): algorithmic bytes of the cells
+    # it processes (read 7 x FP32 per input particle, write 7 x FP32 per output particle) over its
+    # average duration, timed with HIP events on the stream it runs on.
+    counts = np.diff(wl32.cell_off)
+    out_counts = np.diff(out_off.cpu().numpy())
+    in_a = (counts > prm["n_min_cell"]) & (counts <= BIN_A_MAX)
+    bytes_dom = 28.0 * float(counts[in_a].sum() + out_counts[in_a].sum())
+    dom = kernels[DOMINANT]
+    achieved = bytes_dom / (dom["avg_ms"] * 1e-3) / 1e9
     traffic = traffic_from_profiles()
-
+    bytes_step = 28.0 * n * (1.0 + rho)
     cons32 = conservation_error(arrs32, out32, n_out, prm["mass"])
+    del out32
+    torch.cuda.empty_cache()
 
     plain = None
     if not args.no_fp64:
-        arrs64, _ = vpm.upload(wl64)
-        out64 = [torch.empty_like(a) for a in arrs64]
-        p64 = vpm.make_params(decide=vpm.VPM_DECIDE_FP64, **prm)
-        ctx.run(arrs64, off, n, p64, out64, out_off, out_total, stream)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(args.fp64_steps):
-            ctx.run(arrs64, off, n, p64, out64, out_off, out_total, stream)
-        torch.cuda.synchronize()
-        ms64 = (time.perf_counter() - ta) * 1e3 / args.fp64_steps
-        n_out64 = int(out_total.item())
-        cons64 = conservation_error(arrs64, out64, n_out64, prm["mass"])
-        plain = dict(ms_per_step=ms64, value=n / (ms64 * 1e-3), n_out=n_out64, conservation=cons64,
-                     speedup_batched_over_plain=ms64 / ms_step)
-        log(f"[bench] plain FP64: {ms64:.3f} ms/step, speedup {ms64 / ms_step:.1f}x")
-        del arrs64, out64
+        plain = time_plain(ctx, vpm, wl64, prm, args.fp64_steps)
+        plain["speedup_batched_over_plain"] = plain["ms_per_step"] / ms_step
+        log(f"[bench] plain FP64: {plain['ms_per_step']:.3f} ms/step, speedup {plain['speedup_batched_over_plain']:.1f}x")
 
     cpu = None
     if not args.no_cpu:
@@ -173,9 +267,25 @@ def main():
         oracle.run_workload(wl32, decide=oracle.FIXED, n_threads=cores)
         dt = time.perf_counter() - ta
         cpu = dict(value=n / dt, unit="particles/s", cores=cores, kind="oracle",
-                   sample=f"all {n_cells} cells ({n} particles), fixed-point decisions, pair merge, "
-                          f"{dt:.2f} s wall on {cores} threads")
+                   sample=f"all {n_cells} cells ({n} particles) of the same workload, fixed-point decisions, "
+                          f"pair merge, {dt:.2f} s wall on {cores} threads")
         log(f"[bench] oracle: {dt:.2f} s on {cores} threads")
+
+    extra = None
+    if not args.no_extra:
+        del arrs32
+        torch.cuda.empty_cache()
+        extra = {}
+        ts_paper = W.two_stream_grid(nx=256, ny=256, mean=512, seed=args.seed, params=W.TWO_STREAM_PAPER_PARAMS)
+        extra["two_stream_paper_tolerances"] = extra_workload(
+            ctx, vpm, "two_stream_256x256_poisson512_T0.8_0.15_Nmin200", ts_paper.astype(np.float32), None,
+            dict(ts_paper.params), 10, 0)
+        del ts_paper
+        sh = W.shower_grid(nc=64, seed=args.seed)
+        sh64 = sh.astype(np.float64) if not args.no_fp64 else None
+        extra["shower"] = extra_workload(ctx, vpm, "shower_64cubed_lognormal64", sh, sh64, dict(sh.params), 5,
+                                         0 if args.no_fp64 else 1)
+        del sh, sh64
 
     line = {
         "metric": "input particles merged/sec + % HBM peak; batched-FP32 vs plain-FP64 at equal cons. err",
@@ -194,15 +304,16 @@ def main():
                    "tol_x": prm["tol_x"], "tol_p": prm["tol_p"], "min_subset": prm["min_subset"],
                    "n_min_cell": prm["n_min_cell"], "decide": "fixed", "merge": "pair", "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom_name,
-                     "kernel_avg_ms": dom["avg_ms"], "algorithmic_bytes_per_launch": bytes_per_step},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": DOMINANT,
+                     "kernel_avg_ms": dom["avg_ms"], "algorithmic_bytes_per_launch": bytes_dom},
         "cpu_baseline": cpu,
         "merge_ratio": rho,
-        "pipeline_GBps": bytes_per_step / (ms_step * 1e-3) / 1e9,
+        "pipeline_GBps": bytes_step / (ms_step * 1e-3) / 1e9,
         "kernels": kernels,
         "conservation": cons32,
         "plain_fp64": plain,
         "device_flags": flags,
+        "workloads": extra,
     }
     print(json.dumps(line))
 
