@@ -192,6 +192,60 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps):
     return rec
 
 
+def cascade(ctx, vpm, W, steps, seed):
+    """Repeated merge events: the 512 x 512 cascade (256 particles per cell at the start, every particle
+    split in two between events, cells above 1,024 particles merged).  The merge event is captured
+    once in a HIP graph and replayed for every step; the population size is read on the device."""
+    import torch
+    cap = 540_000_000
+    wl = W.cascade_initial(seed=seed)
+    prm = dict(wl.params)
+    n_cells = wl.n_cells
+    ctx.reserve(cap, n_cells)
+    P = [torch.empty(cap, dtype=torch.float32, device="cuda") for _ in range(7)]
+    Q = [torch.empty(cap, dtype=torch.float32, device="cuda") for _ in range(7)]
+    offP = torch.from_numpy(wl.cell_off).cuda()
+    offQ = torch.empty_like(offP)
+    for t, a in zip(P, wl.arrays()):
+        t[:wl.n].copy_(torch.from_numpy(a))
+    n = wl.n
+    del wl
+    out_total = torch.empty(1, dtype=torch.int64, device="cuda")
+    p = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
+    g = None
+    recs = []
+    for step in range(steps):
+        if 2 * n > cap:
+            break
+        n2 = W.cascade_split_device(P, offP, n, step, Q, offQ, seed=seed)
+        torch.cuda.synchronize()
+        if g is None:                       # capture the merge event once (capturing runs nothing)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                ctx.run(Q, offQ, cap, p, P, offP, out_total)
+            torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        n_out = int(out_total.item())
+        counts = (offQ[1:] - offQ[:-1])
+        recs.append(dict(step=step, n_in=n2, n_out=n_out, cells_merged=int((counts > prm["n_min_cell"]).sum().item()),
+                         ms=ms, value=n2 / (ms * 1e-3)))
+        log(f"[bench] cascade step {step}: {n2} -> {n_out} particles, {ms:.2f} ms")
+        n = n_out
+    flags = ctx.device_status(clear=True)
+    del P, Q
+    torch.cuda.empty_cache()
+    return dict(workload="cascade_512x512_from256", params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset")},
+                capacity=cap, graph_replayed=True, steps=recs, device_flags=flags,
+                note="the population doubles between events; merged cells keep nearly all particles under "
+                     "the per-component momentum CV, so the run stops when the next split would exceed "
+                     "the capacity")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +258,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CALIB_FETCH", "CALIB_WRITE"))
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cascade-steps", type=int, default=3)
     args = ap.parse_args()
 
     if args.traffic_summary:
@@ -286,6 +341,8 @@ def main():
         extra["shower"] = extra_workload(ctx, vpm, "shower_64cubed_lognormal64", sh, sh64, dict(sh.params), 5,
                                          0 if args.no_fp64 else 1)
         del sh, sh64
+        if args.cascade_steps > 0:
+            extra["cascade"] = cascade(ctx, vpm, W, args.cascade_steps, args.seed)
 
     line = {
         "metric": "input particles merged/sec + % HBM peak; batched-FP32 vs plain-FP64 at equal cons. err",

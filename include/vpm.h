@@ -16,10 +16,16 @@
  *  - Particles are a structure of arrays (vpm_soa) of 7 DEVICE arrays x,y,z,px,py,pz,w of one
  *    element type (vpm_params.dtype), sorted by cell.  Momenta are in units of m_e c.
  *  - cell_off is a DEVICE array of n_cells+1 int64 offsets: cell c owns particles
- *    cell_off[c] .. cell_off[c+1]-1; cell_off[0] = 0 and cell_off[n_cells] = n_particles.
+ *    cell_off[c] .. cell_off[c+1]-1; cell_off[0] = 0 and cell_off[n_cells] <= n_particles.
+ *    n_particles is the length of the particle (and output) arrays; particles from
+ *    cell_off[n_cells] on are ignored.  Because the population size is read from the device, one
+ *    captured sequence of calls (a HIP graph) can be replayed for merge events whose particle
+ *    counts differ, as long as the buffers, n_cells and n_particles stay the same.
  *  - All device buffers are owned by the caller.  Entry points enqueue work on `stream` and
  *    return without synchronising; results are valid once the stream has completed.  They
- *    never allocate: the context's workspace is allocated by vpm_reserve only.
+ *    never allocate: the context's workspace is allocated by vpm_reserve only.  vpm_run,
+ *    vpm_partition and vpm_merge may be captured into a HIP graph (with profiling disabled);
+ *    internally they fork to the context's side streams and join back before returning.
  *  - A context may be used by one host thread and one stream at a time.
  *  - Host-checkable argument errors are returned immediately and nothing is enqueued.
  *    Data-dependent problems found on the device (bad values, offsets that decrease,
@@ -64,7 +70,7 @@ typedef enum { VPM_MERGE_PAIR = 0, VPM_MERGE_CENTROID = 1 } vpm_merge_mode;
 #define VPM_FLAG_OUT_OF_CELL    0x2u  /* a particle lay more than one cell length from the cell's
                                          lowest coordinate; its position code was clamped (FIXED)  */
 #define VPM_FLAG_CELL_TOO_LARGE 0x4u  /* a cell above 65,536 particles: passed through            */
-#define VPM_FLAG_BAD_OFFSETS    0x8u  /* cell_off decreasing or not ending at n_particles          */
+#define VPM_FLAG_BAD_OFFSETS    0x8u  /* cell_off decreasing, not starting at 0, or past n_particles */
 #define VPM_FLAG_BAD_PARTITION  0x10u /* vpm_merge: a cell's perm/subset_id/n_subsets is not a
                                          partition of that cell; the cell was copied unchanged     */
 

@@ -29,7 +29,6 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
         const bool range_ok = lo >= 0 && hi >= lo && hi <= n_particles;
         if (!range_ok) { f |= FLAG_BAD_OFFSETS; n = 0; }     // never read outside the arrays
         if (c == 0 && lo != 0) f |= FLAG_BAD_OFFSETS;
-        if (c == n_cells - 1 && hi != n_particles) f |= FLAG_BAD_OFFSETS;
         if (n > NMAX_BIG) f |= FLAG_TOO_LARGE;
         if (f) atomicOr(flags, f);
         if (n == 0 || n <= n_min_cell || n > NMAX_BIG || !range_ok) {

@@ -250,3 +250,40 @@ def cascade_split(wl: Workload, step: int, seed: int = 0) -> Workload:
         pair[1::2] = np.asarray(new, dtype=dt)
         out[f] = pair
     return Workload(wl.name, cell_off=wl.cell_off * 2, cell_id=None, params=dict(wl.params), **out)
+
+
+def cascade_split_device(arrs, cell_off, n: int, step: int, out_arrs, out_off, nx: int = 512, seed: int = 0):
+    """The cascade growth step of `cascade_split` on device tensors (torch's Philox generator, so the
+    random numbers differ from the host version; the recipe is the same).  Reads n particles from
+    `arrs` (7 tensors) with offsets `cell_off`, writes 2n particles to `out_arrs` and the doubled
+    offsets to `out_off`.  Returns 2n."""
+    import torch
+    dev = arrs[0].device
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed * 1000003 + step + 1)
+    n_cells = cell_off.numel() - 1
+    counts = cell_off[1:] - cell_off[:-1]
+    cid = torch.repeat_interleave(torch.arange(n_cells, device=dev), counts, output_size=n)
+    u = lambda: torch.rand(n, generator=g, device=dev, dtype=torch.float64)
+    fresh_x = (cid % nx).double() + u()
+    fresh_y = torch.div(cid, nx, rounding_mode="floor").double() + u()
+    del cid
+    gamma = 1.0 / (1.0 - u() * (1.0 - 1e-4))
+    pmag = torch.sqrt(torch.clamp(gamma * gamma - 1.0, min=0.0))
+    del gamma
+    cos_t = float(np.cos(0.1)) + (1.0 - float(np.cos(0.1))) * u()
+    sin_t = torch.sqrt(torch.clamp(1.0 - cos_t * cos_t, min=0.0))
+    phi = 2.0 * np.pi * u()
+    fresh = [fresh_x, fresh_y, None, pmag * cos_t, pmag * sin_t * torch.cos(phi), pmag * sin_t * torch.sin(phi)]
+    for k in range(7):
+        dst = out_arrs[k]
+        old = arrs[k][:n]
+        if k == 6:
+            half = old * 0.5
+            dst[0:2 * n:2] = half
+            dst[1:2 * n:2] = half
+        else:
+            dst[0:2 * n:2] = old
+            dst[1:2 * n:2] = 0.0 if fresh[k] is None else fresh[k].to(dst.dtype)
+    out_off.copy_(cell_off * 2)
+    return 2 * n
