@@ -35,7 +35,6 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fixed_cells_two_stream.js
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_00636_amd", "csrc", "vpm_fixed.hip")
 DOMINANT = "fixed_cells_576"          # the one-wavefront-per-cell bin: every two-stream cell but ~0.2 %
 DOMINANT_SYMBOL = "k_fixed_cells<576"  # how rocprofv3 names it
-BIN_A_MAX = 576
 COPY_BYTES = 1 << 30
 
 
@@ -130,6 +129,21 @@ def traffic_summary(fetch_dir, write_dir, calib_fetch_dir, calib_write_dir):
     print(json.dumps(rec))
 
 
+def autotune(ctx, vpm, arrs, off, n, p):
+    """Let the library pick lane-group sizing and bin limits for this population (timed on the GPU);
+    returns (tuning dict, seconds spent)."""
+    import torch
+    out = [torch.empty_like(a) for a in arrs]
+    out_off = torch.empty(off.numel(), dtype=torch.int64, device="cuda")
+    out_total = torch.empty(1, dtype=torch.int64, device="cuda")
+    t0 = time.perf_counter()
+    best = ctx.autotune(arrs, off, n, p, out, out_off, out_total)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del out
+    return best.as_dict(), dt
+
+
 def time_fixed(ctx, vpm, arrs, off, n, p, steps, warmup, profile):
     """Time `steps` merge events of the fixed-point FP32 form; returns (ms/step, outputs, kernels)."""
     import torch
@@ -176,8 +190,10 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps):
     n = wl32.n
     arrs, off = vpm.upload(wl32)
     p32 = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
+    tuning, tune_s = autotune(ctx, vpm, arrs, off, n, p32)
     ms, out, _, n_out, kernels = time_fixed(ctx, vpm, arrs, off, n, p32, steps, 2, True)
     rec = dict(workload=name, n_particles=n, n_cells=wl32.n_cells, ms_per_step=ms, value=n / (ms * 1e-3),
+               tuning=tuning, autotune_s=tune_s,
                unit="particles/s", merge_ratio=n_out / n,
                conservation=conservation_error(arrs, out, n_out, prm["mass"]),
                kernels={k: round(v["avg_ms"], 4) for k, v in kernels.items()},
@@ -202,6 +218,7 @@ def cascade(ctx, vpm, W, steps, seed):
     prm = dict(wl.params)
     n_cells = wl.n_cells
     ctx.reserve(cap, n_cells)
+    ctx.set_tuning(vpm.make_tuning())       # default batching (the early steps merge nothing to tune on)
     P = [torch.empty(cap, dtype=torch.float32, device="cuda") for _ in range(7)]
     Q = [torch.empty(cap, dtype=torch.float32, device="cuda") for _ in range(7)]
     offP = torch.from_numpy(wl.cell_off).cuda()
@@ -287,6 +304,8 @@ def main():
     ctx.reserve(52_000_000, 64 ** 3)
     arrs32, off = vpm.upload(wl32)
     p32 = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
+    tuning, tune_s = autotune(ctx, vpm, arrs32, off, n, p32)
+    log(f"[bench] autotuned in {tune_s:.2f}s: {tuning}")
     ms_step, out32, out_off, n_out, kernels = time_fixed(ctx, vpm, arrs32, off, n, p32, args.steps,
                                                          args.warmup, True)
     rho = n_out / n
@@ -298,7 +317,7 @@ def main():
     # average duration, timed with HIP events on the stream it runs on.
     counts = np.diff(wl32.cell_off)
     out_counts = np.diff(out_off.cpu().numpy())
-    in_a = (counts > prm["n_min_cell"]) & (counts <= BIN_A_MAX)
+    in_a = (counts > prm["n_min_cell"]) & (counts <= tuning["bin_a_max"])
     bytes_dom = 28.0 * float(counts[in_a].sum() + out_counts[in_a].sum())
     dom = kernels[DOMINANT]
     achieved = bytes_dom / (dom["avg_ms"] * 1e-3) / 1e9
@@ -364,6 +383,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": DOMINANT,
                      "kernel_avg_ms": dom["avg_ms"], "algorithmic_bytes_per_launch": bytes_dom},
         "cpu_baseline": cpu,
+        "tuning": tuning,
+        "autotune_s": tune_s,
         "merge_ratio": rho,
         "pipeline_GBps": bytes_step / (ms_step * 1e-3) / 1e9,
         "kernels": kernels,

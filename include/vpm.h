@@ -140,6 +140,37 @@ vpm_status vpm_merge(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
                      const int32_t *subset_id, const int32_t *n_subsets, vpm_soa *out,
                      int64_t *out_off, int64_t *out_total, hipStream_t stream);
 
+/* Launch configuration of the fixed-point path (batching, not arithmetic: every configuration gives
+ * bit-identical results).  A cell of n particles (n > N_min) is processed by
+ *   one wavefront, working set in LDS             if n <= bin_a_max  (bin_a_max <= 576)
+ *   four wavefronts, working set in LDS           if n <= bin_b_max  (bin_b_max <= 2048)
+ *   eight wavefronts, working set in LDS          if n <= bin_c_max  (bin_c_max <= 4352)
+ *   eight wavefronts, working set in global memory otherwise (n <= 65,536);
+ * a subset of len particles is handled by a group of about len / ppl lanes (ppl = 8, 16 or 32;
+ * at most 64 lanes).  Limits must satisfy 1 <= bin_a_max <= bin_b_max <= bin_c_max.            */
+typedef struct {
+    int32_t ppl;
+    int32_t bin_a_max;
+    int32_t bin_b_max;
+    int32_t bin_c_max;
+} vpm_tuning;
+
+/* Host-only validation of a tuning block (no device needed). */
+vpm_status vpm_check_tuning(const vpm_tuning *t);
+
+/* The context's current tuning (initially ppl 16, limits 576 / 2048 / 4352). */
+vpm_status vpm_get_tuning(vpm_ctx *ctx, vpm_tuning *t);
+vpm_status vpm_set_tuning(vpm_ctx *ctx, const vpm_tuning *t);
+
+/* Choose the tuning for a population: runs vpm_run with candidate configurations on the given
+ * data (coordinate search over ppl and the three bin limits), times each on `stream` with HIP
+ * events, keeps the fastest in the context and returns it in *best (host, may be NULL).  Leaves
+ * vpm_run's result of the chosen configuration in out / out_off / out_total.  Synchronises
+ * `stream`; cannot be captured in a graph.  Arguments as vpm_run (FIXED decisions only).      */
+vpm_status vpm_autotune(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, int64_t n_cells,
+                        int64_t n_particles, const vpm_params *p, vpm_soa *out, int64_t *out_off,
+                        int64_t *out_total, hipStream_t stream, vpm_tuning *best);
+
 /* Read (and, if clear != 0, reset) the sticky device flags.  Synchronises the device. */
 vpm_status vpm_device_status(vpm_ctx *ctx, uint32_t *flags_out, int clear);
 

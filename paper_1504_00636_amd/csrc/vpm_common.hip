@@ -19,7 +19,7 @@ __global__ void k_reset(int32_t* counters) {
 __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_cells, int64_t n_particles,
                                              int32_t n_min_cell, int32_t* counters, int32_t* q_untouched,
                                              int32_t* q_a, int32_t* q_b, int32_t* q_c, int32_t* q_big, int64_t* out_count,
-                                             uint8_t* cell_mode, uint32_t* flags) {
+                                             uint8_t* cell_mode, uint32_t* flags, BinLimits lim) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int cls = -1;
     if (c < n_cells) {
@@ -35,11 +35,11 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
             cls = Q_UNTOUCHED;
             out_count[c] = n;
             cell_mode[c] = CELL_UNTOUCHED;
-        } else if (n <= NMAX_A) {
+        } else if (n <= lim.a) {
             cls = Q_A;
-        } else if (n <= NMAX_B) {
+        } else if (n <= lim.b) {
             cls = Q_B;
-        } else if (n <= NMAX_C) {
+        } else if (n <= lim.c) {
             cls = Q_C;
         } else {
             cls = Q_BIG;
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void k_identity(const int64_t* cell_off, int64
 }  // namespace
 
 hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off, int64_t n_cells,
-                      int64_t n_particles, int32_t n_min_cell) {
+                      int64_t n_particles, int32_t n_min_cell, BinLimits lim) {
     if (lc.pre) lc.pre(lc.prof, "reset", lc.stream);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, lc.stream, ws.counters);
     if (lc.post) lc.post(lc.prof, "reset", lc.stream);
@@ -178,7 +178,7 @@ hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* c
     const int64_t blocks = (n_cells + 255) / 256;
     hipLaunchKernelGGL(k_bin, dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells, n_particles,
                        n_min_cell, ws.counters, ws.queue[Q_UNTOUCHED], ws.queue[Q_A], ws.queue[Q_B],
-                       ws.queue[Q_C], ws.queue[Q_BIG], ws.out_count, ws.cell_mode, ws.flags);
+                       ws.queue[Q_C], ws.queue[Q_BIG], ws.out_count, ws.cell_mode, ws.flags, lim);
     if (lc.post) lc.post(lc.prof, "bin", lc.stream);
     return hipGetLastError();
 }

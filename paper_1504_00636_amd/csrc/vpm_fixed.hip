@@ -32,7 +32,6 @@
 namespace vpm {
 namespace {
 
-constexpr int PPL = 16;             // target particles per lane when sizing a group
 
 // info byte per slot once its final subset is known
 constexpr uint8_t INF_PARITY = 0x01;   // index buffer that holds the final order
@@ -302,8 +301,10 @@ VPM_DEV Decision unpack_decision(int v) {
     return d;
 }
 
-VPM_DEV int group_class_for(int len) {       // log2 of the group size
-    const int want = (len + PPL - 1) / PPL;
+// log2 of the lane-group size for a subset of len particles: about 2^ppl_shift particles per lane,
+// at most one wavefront.
+VPM_DEV int group_class_for(int len, int ppl_shift) {
+    const int want = (len + (1 << ppl_shift) - 1) >> ppl_shift;
     int c = 0;
     while ((1 << c) < want && c < 6) ++c;
     return c;
@@ -472,11 +473,11 @@ VPM_DEV void cell_sync() {
 struct Sched { int lb[7], fb[7], cnt[7], total; };
 
 template <int WPB, typename IdxT, typename LenFn>
-VPM_DEV Sched schedule(const CellMem<IdxT>& M, IdxT* sched, int m, LenFn len_of) {
+VPM_DEV Sched schedule(const CellMem<IdxT>& M, IdxT* sched, int m, int ppl_shift, LenFn len_of) {
     const int tid = threadIdx.x;
     if (tid < 8) { M.sh->cls_cnt[tid] = 0; M.sh->cls_cur[tid] = 0; }
     cell_sync<WPB>();
-    for (int it = tid; it < m; it += WAVE * WPB) atomicAdd(&M.sh->cls_cnt[group_class_for(len_of(it))], 1);
+    for (int it = tid; it < m; it += WAVE * WPB) atomicAdd(&M.sh->cls_cnt[group_class_for(len_of(it), ppl_shift)], 1);
     cell_sync<WPB>();
     Sched s;
     int l = 0, f = 0;
@@ -488,7 +489,7 @@ VPM_DEV Sched schedule(const CellMem<IdxT>& M, IdxT* sched, int m, LenFn len_of)
     }
     s.total = l;
     for (int it = tid; it < m; it += WAVE * WPB) {
-        const int c = group_class_for(len_of(it));
+        const int c = group_class_for(len_of(it), ppl_shift);
         const int r = atomicAdd(&M.sh->cls_cur[c], 1);
         int fbc = s.fb[0];
 #pragma unroll
@@ -1063,7 +1064,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             Node<IdxT>* curl = cur ? M.nodes1 : M.nodes0;
             Node<IdxT>* nextl = cur ? M.nodes0 : M.nodes1;
             if (tid == 0) sh.nnext = 0;
-            const Sched s = schedule<WPB, IdxT>(M, M.emit, m, [&](int it) { return (int)curl[it].len; });
+            const Sched s = schedule<WPB, IdxT>(M, M.emit, m, A.P.ppl_shift, [&](int it) { return (int)curl[it].len; });
             for (int r0 = wv * WAVE; r0 < s.total; r0 += NT) {
                 int slot, cls;
                 if (sched_lookup(s, r0 + lane, slot, cls)) {
@@ -1154,7 +1155,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         const int nm = sh.nmerged;
         if (nm > 0) {
             IdxT* sched = (IdxT*)M.cm;                     // momentum codes are free now
-            const Sched s = schedule<WPB, IdxT>(M, sched, nm, [&](int it) {
+            const Sched s = schedule<WPB, IdxT>(M, sched, nm, A.P.ppl_shift, [&](int it) {
                 const int ord = mlist[it];
                 return (int)(leaf_start[ord + 1] - leaf_start[ord]);
             });

@@ -19,6 +19,7 @@ struct vpm_ctx {
     int cu_count = 0;
     Workspace ws;
     int grid_a = 0, grid_b = 0, grid_c = 0, grid_big = 0, grid_fp64 = 0;
+    vpm_tuning tune = {16, NMAX_A, NMAX_B, NMAX_C};
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     std::string last_error;
@@ -133,7 +134,15 @@ vpm_status common_checks(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_of
     return VPM_OK;
 }
 
-FixedParams fixed_params(const vpm_params* p) {
+int ilog2(int v) {
+    int s = 0;
+    while ((1 << (s + 1)) <= v) ++s;
+    return s;
+}
+
+BinLimits bin_limits(const vpm_ctx* c) { return BinLimits{c->tune.bin_a_max, c->tune.bin_b_max, c->tune.bin_c_max}; }
+
+FixedParams fixed_params(const vpm_params* p, const vpm_tuning& t) {
     FixedParams f;
     f.that_x = (uint64_t)llrint(p->tol_x * 16777216.0);
     f.that_p = (uint64_t)llrint(p->tol_p * 16777216.0);
@@ -148,6 +157,7 @@ FixedParams fixed_params(const vpm_params* p) {
     for (int a = 0; a < 3; ++a) f.s[a] = (float)(65536.0 / p->cell_len[a]);
     f.min_subset = p->min_subset;
     f.merge_mode = p->merge_mode;
+    f.ppl_shift = ilog2(t.ppl);
     f.mass = p->mass;
     return f;
 }
@@ -314,10 +324,10 @@ vpm_status vpm_run(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int
     if (check_soa(out) != VPM_OK || !out_off || !out_total) return VPM_ERR_INVALID_ARG;
     hipSetDevice(ctx->device);
     LaunchCfg lc = make_cfg(ctx, stream);
-    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell);
+    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx));
     if (e != hipSuccess) return hip_fail(ctx, e, "bin");
     if (p->decide == VPM_DECIDE_FIXED)
-        e = launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fixed_params(p), 0, nullptr, nullptr, nullptr);
+        e = launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fixed_params(p, ctx->tune), 0, nullptr, nullptr, nullptr);
     else
         e = launch_fp64_cells(ctx->ws, lc, soa64(in), cell_off, n_cells, fp64_params(p), 0, nullptr, nullptr, nullptr);
     if (e != hipSuccess) return hip_fail(ctx, e, "cells");
@@ -339,10 +349,10 @@ vpm_status vpm_partition(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_of
     if (!perm || !subset_id || !n_subsets) return VPM_ERR_INVALID_ARG;
     hipSetDevice(ctx->device);
     LaunchCfg lc = make_cfg(ctx, stream);
-    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell);
+    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx));
     if (e != hipSuccess) return hip_fail(ctx, e, "bin");
     if (p->decide == VPM_DECIDE_FIXED)
-        e = launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fixed_params(p), 1, perm, subset_id, n_subsets);
+        e = launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fixed_params(p, ctx->tune), 1, perm, subset_id, n_subsets);
     else
         e = launch_fp64_cells(ctx->ws, lc, soa64(in), cell_off, n_cells, fp64_params(p), 1, perm, subset_id,
                               n_subsets);
@@ -362,10 +372,10 @@ vpm_status vpm_merge(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, i
         return VPM_ERR_INVALID_ARG;
     hipSetDevice(ctx->device);
     LaunchCfg lc = make_cfg(ctx, stream);
-    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell);
+    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx));
     if (e != hipSuccess) return hip_fail(ctx, e, "bin");
     if (p->decide == VPM_DECIDE_FIXED)
-        e = launch_fixed_merge(ctx->ws, lc, soa32(in), cell_off, n_cells, p->n_min_cell, fixed_params(p), perm,
+        e = launch_fixed_merge(ctx->ws, lc, soa32(in), cell_off, n_cells, p->n_min_cell, fixed_params(p, ctx->tune), perm,
                                subset_id, n_subsets);
     else
         e = launch_fp64_merge(ctx->ws, lc, soa64(in), cell_off, n_cells, fp64_params(p), perm, subset_id,
@@ -379,6 +389,99 @@ vpm_status vpm_merge(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, i
                        p->dtype == VPM_F32 ? 4 : 8);
     if (e != hipSuccess) return hip_fail(ctx, e, "scatter");
     return VPM_OK;
+}
+
+vpm_status vpm_check_tuning(const vpm_tuning* t) {
+    if (!t) return VPM_ERR_INVALID_ARG;
+    if (t->ppl != 8 && t->ppl != 16 && t->ppl != 32) return VPM_ERR_INVALID_ARG;
+    if (t->bin_a_max < 1 || t->bin_a_max > NMAX_A) return VPM_ERR_INVALID_ARG;
+    if (t->bin_b_max < t->bin_a_max || t->bin_b_max > NMAX_B) return VPM_ERR_INVALID_ARG;
+    if (t->bin_c_max < t->bin_b_max || t->bin_c_max > NMAX_C) return VPM_ERR_INVALID_ARG;
+    return VPM_OK;
+}
+
+vpm_status vpm_get_tuning(vpm_ctx* ctx, vpm_tuning* t) {
+    if (!ctx || !t) return VPM_ERR_INVALID_ARG;
+    *t = ctx->tune;
+    return VPM_OK;
+}
+
+vpm_status vpm_set_tuning(vpm_ctx* ctx, const vpm_tuning* t) {
+    if (!ctx) return VPM_ERR_INVALID_ARG;
+    vpm_status st = vpm_check_tuning(t);
+    if (st != VPM_OK) return st;
+    ctx->tune = *t;
+    return VPM_OK;
+}
+
+vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int64_t n_cells,
+                        int64_t n_particles, const vpm_params* p, vpm_soa* out, int64_t* out_off,
+                        int64_t* out_total, hipStream_t stream, vpm_tuning* best) {
+    vpm_status st = common_checks(ctx, in, cell_off, n_cells, n_particles, p);
+    if (st != VPM_OK) return st;
+    if (p->decide != VPM_DECIDE_FIXED) return VPM_ERR_UNSUPPORTED;
+    if (check_soa(out) != VPM_OK || !out_off || !out_total) return VPM_ERR_INVALID_ARG;
+    hipSetDevice(ctx->device);
+    const bool was_profiling = ctx->profiling;
+    ctx->profiling = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        ctx->profiling = was_profiling;
+        return hip_fail(ctx, hipGetLastError(), "vpm_autotune");
+    }
+    // time one configuration: one untimed run, then the best of two timed runs
+    auto time_cfg = [&](const vpm_tuning& t, float& ms) -> vpm_status {
+        ctx->tune = t;
+        float bestms = 1e30f;
+        for (int r = 0; r < 3; ++r) {
+            hipEventRecord(e0, stream);
+            vpm_status s = vpm_run(ctx, in, cell_off, n_cells, n_particles, p, out, out_off, out_total, stream);
+            if (s != VPM_OK) return s;
+            hipEventRecord(e1, stream);
+            hipError_t e = hipEventSynchronize(e1);
+            if (e != hipSuccess) return hip_fail(ctx, e, "vpm_autotune");
+            float m = 0.f;
+            hipEventElapsedTime(&m, e0, e1);
+            if (r > 0 && m < bestms) bestms = m;
+        }
+        ms = bestms;
+        return VPM_OK;
+    };
+    vpm_tuning cur = {16, NMAX_A, NMAX_B, NMAX_C};
+    float cur_ms = 0.f;
+    st = time_cfg(cur, cur_ms);
+    // coordinate search: each parameter in turn over its candidates, keeping the others
+    const int ppls[3] = {8, 16, 32};
+    const int as[5] = {320, 384, 448, 512, NMAX_A};
+    const int bs[3] = {1024, 1536, NMAX_B};
+    const int cs[3] = {2560, 3456, NMAX_C};
+    for (int dim = 0; dim < 4 && st == VPM_OK; ++dim) {
+        const int* cand = dim == 0 ? ppls : dim == 1 ? as : dim == 2 ? bs : cs;
+        const int nc = dim == 1 ? 5 : 3;
+        for (int k = 0; k < nc && st == VPM_OK; ++k) {
+            vpm_tuning t = cur;
+            if (dim == 0) t.ppl = cand[k];
+            else if (dim == 1) t.bin_a_max = cand[k];
+            else if (dim == 2) t.bin_b_max = cand[k];
+            else t.bin_c_max = cand[k];
+            if (vpm_check_tuning(&t) != VPM_OK) continue;
+            if (t.ppl == cur.ppl && t.bin_a_max == cur.bin_a_max && t.bin_b_max == cur.bin_b_max &&
+                t.bin_c_max == cur.bin_c_max)
+                continue;
+            float ms = 0.f;
+            st = time_cfg(t, ms);
+            if (st == VPM_OK && ms < cur_ms * 0.99f) { cur = t; cur_ms = ms; }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->profiling = was_profiling;
+    if (st != VPM_OK) return st;
+    ctx->tune = cur;
+    if (best) *best = cur;
+    // leave the chosen configuration's result in the outputs
+    return vpm_run(ctx, in, cell_off, n_cells, n_particles, p, out, out_off, out_total, stream);
 }
 
 vpm_status vpm_device_status(vpm_ctx* ctx, uint32_t* flags_out, int clear) {

@@ -52,8 +52,13 @@ struct FixedParams {
     float s[3];                     // fl32(65536 / L_a)
     int32_t min_subset;
     int32_t merge_mode;
+    int32_t ppl_shift;              // log2 of the target particles per lane of a lane group
     double mass;
 };
+
+// Routing thresholds of the size bins: cells of up to `a` particles go to bin A, up to `b` to B,
+// up to `c` to C, larger ones to the global-memory bin.
+struct BinLimits { int32_t a, b, c; };
 
 struct LaunchCfg {
     hipStream_t stream;
@@ -75,7 +80,7 @@ struct Soa64Out { double *x, *y, *z, *px, *py, *pz, *w; };
 
 // ---- launchers (vpm_common.hip) ----
 hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,
-                      int64_t n_cells, int64_t n_particles, int32_t n_min_cell);
+                      int64_t n_cells, int64_t n_particles, int32_t n_min_cell, BinLimits lim);
 hipError_t launch_scan_offsets(const Workspace& ws, const LaunchCfg& lc, int64_t n_cells,
                                int64_t* out_off, int64_t* out_total);
 hipError_t launch_scatter(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,

@@ -25,6 +25,7 @@ VPM_FLAG_BAD_PARTITION = 16
 
 EXPORTS = ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_partition",
            "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read",
+           "vpm_check_tuning", "vpm_get_tuning", "vpm_set_tuning", "vpm_autotune",
            "vpm_status_string", "vpm_last_error", "vpm_version")
 
 
@@ -34,6 +35,19 @@ class VpmParams(C.Structure):
                 ("cell_len", C.c_double * 3), ("mass", C.c_double),
                 ("merge_mode", C.c_int32), ("decide", C.c_int32),
                 ("dtype", C.c_int32), ("reserved", C.c_int32)]
+
+
+class VpmTuning(C.Structure):
+    _fields_ = [("ppl", C.c_int32), ("bin_a_max", C.c_int32), ("bin_b_max", C.c_int32), ("bin_c_max", C.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+def make_tuning(ppl=16, bin_a_max=576, bin_b_max=2048, bin_c_max=4352) -> VpmTuning:
+    t = VpmTuning()
+    t.ppl, t.bin_a_max, t.bin_b_max, t.bin_c_max = int(ppl), int(bin_a_max), int(bin_b_max), int(bin_c_max)
+    return t
 
 
 class VpmSoa(C.Structure):
@@ -67,6 +81,10 @@ def lib():
     L.vpm_partition.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, vp]
     L.vpm_merge.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, P(VpmSoa), vp, vp, vp]
     L.vpm_device_status.argtypes = [vp, P(C.c_uint32), C.c_int]
+    L.vpm_check_tuning.argtypes = [P(VpmTuning)]
+    L.vpm_get_tuning.argtypes = [vp, P(VpmTuning)]
+    L.vpm_set_tuning.argtypes = [vp, P(VpmTuning)]
+    L.vpm_autotune.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), P(VpmSoa), vp, vp, vp, P(VpmTuning)]
     L.vpm_profile_enable.argtypes = [vp, C.c_int]
     L.vpm_profile_read.argtypes = [vp, C.c_int, vp, P(C.c_int64), P(C.c_double), P(C.c_int), C.c_int]
     L.vpm_status_string.argtypes = [C.c_int]
@@ -75,7 +93,8 @@ def lib():
     L.vpm_last_error.restype = C.c_char_p
     L.vpm_version.restype = C.c_char_p
     for f in ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_partition",
-              "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read"):
+              "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read", "vpm_check_tuning",
+              "vpm_get_tuning", "vpm_set_tuning", "vpm_autotune"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -108,6 +127,11 @@ def make_params(tol_x, tol_p, n_min_cell=0, min_subset=4, cell_len=(1.0, 1.0, 1.
 def vpm_check_params(p: VpmParams) -> int:
     """Host-only parameter validation; returns the status code."""
     return int(lib().vpm_check_params(C.byref(p)))
+
+
+def vpm_check_tuning(t: VpmTuning) -> int:
+    """Host-only tuning validation; returns the status code."""
+    return int(lib().vpm_check_tuning(C.byref(t)))
 
 
 # ------------------------------------------------------------------------------------------
@@ -216,6 +240,29 @@ class Context:
                              _dev(out_total, torch.int64, 1, "out_total"), _stream(stream))
         self._check(st, "vpm_merge")
 
+    def get_tuning(self) -> VpmTuning:
+        t = VpmTuning()
+        self._check(lib().vpm_get_tuning(self.h, C.byref(t)), "vpm_get_tuning")
+        return t
+
+    def set_tuning(self, t: VpmTuning):
+        self._check(lib().vpm_set_tuning(self.h, C.byref(t)), "vpm_set_tuning")
+
+    def autotune(self, inp, cell_off, n_particles: int, p: VpmParams, out, out_off, out_total,
+                 stream=None) -> VpmTuning:
+        import torch
+        n_cells = cell_off.numel() - 1
+        dt = _torch_dtype(p)
+        si = _soa(inp, dt, n_particles, "in")
+        so = _soa(out, dt, n_particles, "out")
+        best = VpmTuning()
+        st = lib().vpm_autotune(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"), n_cells,
+                                int(n_particles), C.byref(p), C.byref(so),
+                                _dev(out_off, torch.int64, n_cells + 1, "out_off"),
+                                _dev(out_total, torch.int64, 1, "out_total"), _stream(stream), C.byref(best))
+        self._check(st, "vpm_autotune")
+        return best
+
     def device_status(self, clear: bool = False) -> int:
         f = C.c_uint32(0)
         self._check(lib().vpm_device_status(self.h, C.byref(f), int(clear)), "vpm_device_status")
@@ -261,6 +308,18 @@ def vpm_merge(ctx: Context, *a, **k):
 
 def vpm_device_status(ctx: Context, clear: bool = False) -> int:
     return ctx.device_status(clear)
+
+
+def vpm_get_tuning(ctx: Context) -> VpmTuning:
+    return ctx.get_tuning()
+
+
+def vpm_set_tuning(ctx: Context, t: VpmTuning):
+    ctx.set_tuning(t)
+
+
+def vpm_autotune(ctx: Context, *a, **k) -> VpmTuning:
+    return ctx.autotune(*a, **k)
 
 
 def vpm_destroy(ctx: Context):
