@@ -100,7 +100,8 @@ vpm_status vpm_create(vpm_ctx **ctx, int device);
 vpm_status vpm_destroy(vpm_ctx *ctx);
 
 /* Allocate the context's device workspace for up to max_particles particles and max_cells
- * cells per call (about 40 bytes per particle plus 32 bytes per cell).  The only call that
+ * cells per call (about 76 bytes per particle plus 32 bytes per cell, and up to one 2.9 MB slab
+ * per compute unit for cells above 4,352 particles).  The only call that
  * allocates device memory.  May be called again to grow; it synchronises the device. */
 vpm_status vpm_reserve(vpm_ctx *ctx, int64_t max_particles, int64_t max_cells);
 
