@@ -148,23 +148,26 @@ vpm_status vpm_merge(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
  *   eight wavefronts, working set in LDS          if n <= bin_c_max  (bin_c_max <= 4352)
  *   eight wavefronts, working set in global memory otherwise (n <= 65,536);
  * a subset of len particles is handled by a group of about len / ppl lanes (ppl = 8, 16 or 32;
- * at most 64 lanes).  Limits must satisfy 1 <= bin_a_max <= bin_b_max <= bin_c_max.            */
+ * at most 64 lanes).  Limits must satisfy 1 <= bin_a_max <= bin_b_max <= bin_c_max.
+ * concurrent_bins = 1 runs the four bins at once on the context's side streams (forked from and
+ * joined back to the caller's stream), 0 runs them one after another on the caller's stream.    */
 typedef struct {
     int32_t ppl;
     int32_t bin_a_max;
     int32_t bin_b_max;
     int32_t bin_c_max;
+    int32_t concurrent_bins;
 } vpm_tuning;
 
 /* Host-only validation of a tuning block (no device needed). */
 vpm_status vpm_check_tuning(const vpm_tuning *t);
 
-/* The context's current tuning (initially ppl 16, limits 576 / 2048 / 4352). */
+/* The context's current tuning (initially ppl 16, limits 576 / 2048 / 4352, bins in sequence). */
 vpm_status vpm_get_tuning(vpm_ctx *ctx, vpm_tuning *t);
 vpm_status vpm_set_tuning(vpm_ctx *ctx, const vpm_tuning *t);
 
 /* Choose the tuning for a population: runs vpm_run with candidate configurations on the given
- * data (coordinate search over ppl and the three bin limits), times each on `stream` with HIP
+ * data (coordinate search over ppl, the three bin limits and concurrent_bins), times each on `stream` with HIP
  * events, keeps the fastest in the context and returns it in *best (host, may be NULL).  Leaves
  * vpm_run's result of the chosen configuration in out / out_off / out_total.  Synchronises
  * `stream`; cannot be captured in a graph.  Arguments as vpm_run (FIXED decisions only).      */

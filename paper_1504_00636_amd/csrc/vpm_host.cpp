@@ -19,7 +19,7 @@ struct vpm_ctx {
     int cu_count = 0;
     Workspace ws;
     int grid_a = 0, grid_b = 0, grid_c = 0, grid_big = 0, grid_fp64 = 0;
-    vpm_tuning tune = {16, NMAX_A, NMAX_B, NMAX_C};
+    vpm_tuning tune = {16, NMAX_A, NMAX_B, NMAX_C, 0};
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     std::string last_error;
@@ -91,8 +91,9 @@ LaunchCfg make_cfg(vpm_ctx* c, hipStream_t s) {
     lc.grid_c = c->grid_c;
     lc.grid_big = c->grid_big;
     lc.grid_fp64 = c->grid_fp64;
-    for (int i = 0; i < 3; ++i) { lc.side[i] = c->side[i]; lc.join[i] = c->join[i]; }
-    lc.fork = c->fork;
+    const bool fork = c->tune.concurrent_bins != 0;
+    for (int i = 0; i < 3; ++i) { lc.side[i] = fork ? c->side[i] : nullptr; lc.join[i] = fork ? c->join[i] : nullptr; }
+    lc.fork = fork ? c->fork : nullptr;
     lc.pre = c->profiling ? prof_pre : nullptr;
     lc.post = c->profiling ? prof_post : nullptr;
     lc.prof = c;
@@ -397,6 +398,7 @@ vpm_status vpm_check_tuning(const vpm_tuning* t) {
     if (t->bin_a_max < 1 || t->bin_a_max > NMAX_A) return VPM_ERR_INVALID_ARG;
     if (t->bin_b_max < t->bin_a_max || t->bin_b_max > NMAX_B) return VPM_ERR_INVALID_ARG;
     if (t->bin_c_max < t->bin_b_max || t->bin_c_max > NMAX_C) return VPM_ERR_INVALID_ARG;
+    if (t->concurrent_bins != 0 && t->concurrent_bins != 1) return VPM_ERR_INVALID_ARG;
     return VPM_OK;
 }
 
@@ -448,7 +450,7 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
         ms = bestms;
         return VPM_OK;
     };
-    vpm_tuning cur = {16, NMAX_A, NMAX_B, NMAX_C};
+    vpm_tuning cur = {16, NMAX_A, NMAX_B, NMAX_C, 0};
     float cur_ms = 0.f;
     st = time_cfg(cur, cur_ms);
     // coordinate search: each parameter in turn over its candidates, keeping the others
@@ -456,18 +458,20 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
     const int as[5] = {320, 384, 448, 512, NMAX_A};
     const int bs[3] = {1024, 1536, NMAX_B};
     const int cs[3] = {2560, 3456, NMAX_C};
-    for (int dim = 0; dim < 4 && st == VPM_OK; ++dim) {
-        const int* cand = dim == 0 ? ppls : dim == 1 ? as : dim == 2 ? bs : cs;
-        const int nc = dim == 1 ? 5 : 3;
+    const int conc[2] = {0, 1};
+    for (int dim = 0; dim < 5 && st == VPM_OK; ++dim) {
+        const int* cand = dim == 0 ? ppls : dim == 1 ? as : dim == 2 ? bs : dim == 3 ? cs : conc;
+        const int nc = dim == 1 ? 5 : dim == 4 ? 2 : 3;
         for (int k = 0; k < nc && st == VPM_OK; ++k) {
             vpm_tuning t = cur;
             if (dim == 0) t.ppl = cand[k];
             else if (dim == 1) t.bin_a_max = cand[k];
             else if (dim == 2) t.bin_b_max = cand[k];
-            else t.bin_c_max = cand[k];
+            else if (dim == 3) t.bin_c_max = cand[k];
+            else t.concurrent_bins = cand[k];
             if (vpm_check_tuning(&t) != VPM_OK) continue;
             if (t.ppl == cur.ppl && t.bin_a_max == cur.bin_a_max && t.bin_b_max == cur.bin_b_max &&
-                t.bin_c_max == cur.bin_c_max)
+                t.bin_c_max == cur.bin_c_max && t.concurrent_bins == cur.concurrent_bins)
                 continue;
             float ms = 0.f;
             st = time_cfg(t, ms);

@@ -41,13 +41,24 @@ def load(wl, bufs, off_buf):
     off_buf.copy_(torch.from_numpy(wl.cell_off))
 
 
-@pytest.mark.parametrize("merge", [vpm.VPM_MERGE_PAIR, vpm.VPM_MERGE_CENTROID])
-def test_graph_replay_matches_eager(merge):
+@pytest.mark.parametrize("merge,concurrent", [(vpm.VPM_MERGE_PAIR, 0), (vpm.VPM_MERGE_CENTROID, 0),
+                                              (vpm.VPM_MERGE_PAIR, 1)])
+def test_graph_replay_matches_eager(merge, concurrent):
+    """concurrent = 1: the size bins run on forked side streams inside the captured graph."""
     sizes1 = [300, 40, 3, 0, 700, 2100, 64, 5000, 17]
     sizes2 = [20, 600, 0, 1, 580, 900, 4400, 12, 64]          # same cell count, other sizes
     wl1, wl2 = population(sizes1, 11), population(sizes2, 12)
     cap = max(wl1.n, wl2.n) + 37
     c = ctx(cap, len(sizes1))
+    default = c.get_tuning()
+    c.set_tuning(vpm.make_tuning(concurrent_bins=concurrent))
+    try:
+        _graph_replay(c, wl1, wl2, sizes1, cap, merge)
+    finally:
+        c.set_tuning(default)
+
+
+def _graph_replay(c, wl1, wl2, sizes1, cap, merge):
     refs = {1: eager(c, wl1, merge), 2: eager(c, wl2, merge)}
     # the eager result is the oracle's (so a replay that matches it matches the oracle)
     orc = oracle.run_workload(wl1, decide=oracle.FIXED, merge_mode=merge, **oracle_params(PARAMS))

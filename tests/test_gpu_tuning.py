@@ -13,8 +13,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 SIZES = [1, 2, 5, 17, 64, 200, 575, 577, 900, 2047, 2049, 3000, 4353, 6000, 300, 12]
-TUNINGS = [(16, 576, 2048, 4352), (8, 64, 512, 1024), (32, 320, 1024, 2560), (8, 1, 1, 1), (32, 576, 576, 576),
-           (16, 100, 2048, 2048)]
+TUNINGS = [(16, 576, 2048, 4352), (8, 64, 512, 1024, 1), (32, 320, 1024, 2560), (8, 1, 1, 1), (32, 576, 576, 576, 1),
+           (16, 100, 2048, 2048), (16, 576, 2048, 4352, 1)]
 
 
 def _run(c, arrs, off, n, p):
