@@ -956,22 +956,36 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
     BlockScratch<WPB>* bs = (BlockScratch<WPB>*)(smem + ((sizeof(CellShared) + 15) & ~(size_t)15));
     CellShared& sh = *M.sh;
 
+    // Cells are claimed K consecutive queue entries at a time, so the shared work counter sees about
+    // 16 claims per workgroup over the launch instead of one per cell (many small cells otherwise
+    // queue on that one atomic); the tail of the launch is then at most 1/16 of a workgroup's work.
+    const int qlen = A.counters[A.qlen_index];
+    const int K = max(1, min(16, qlen / (int)(gridDim.x * 16)));
+    int qnext = 0, qend = 0;
     for (;;) {
         int qi = 0;
         if constexpr (WPB == 1) {
-            if (lane == 0) qi = atomicAdd(&A.counters[A.work_index], 1);
-            qi = __shfl(qi, 0);
+            if (qnext >= qend) {
+                if (lane == 0) qnext = atomicAdd(&A.counters[A.work_index], K);
+                qnext = __shfl(qnext, 0);
+                qend = min(qnext + K, qlen);
+            }
+            qi = qnext++;
         } else {
             __syncthreads();                               // the previous cell is finished
             if (tid == 0) {
-                sh.qi = atomicAdd(&A.counters[A.work_index], 1);
+                if (qnext >= qend) {
+                    qnext = atomicAdd(&A.counters[A.work_index], K);
+                    qend = min(qnext + K, qlen);
+                }
+                sh.qi = qnext++;
                 sh.flags = 0;
                 sh.nnext = 0;
             }
             __syncthreads();
             qi = sh.qi;
         }
-        if (qi >= A.counters[A.qlen_index]) break;
+        if (qi >= qlen) break;
         const int c = A.queue[qi];
         const int64_t off = A.cell_off[c];
         const int n = (int)(A.cell_off[c + 1] - off);
