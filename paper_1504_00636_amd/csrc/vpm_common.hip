@@ -110,11 +110,13 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int64_t* cnt, i
 template <typename T>
 struct Tables { const T* tmp[7]; const T* in[7]; T* out[7]; };
 
+constexpr int SC_PER = 8, SC_CACHE = 256;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_scatter(const int64_t* cell_off, int64_t n_cells, const int64_t* out_off,
                                                  const uint8_t* cell_mode, Tables<T> tb) {
     const int64_t total = out_off[n_cells];
-    const int64_t per_block = (int64_t)blockDim.x * 4;
+    const int64_t per_block = (int64_t)blockDim.x * SC_PER;
     const int64_t o0 = (int64_t)blockIdx.x * per_block;
     if (o0 >= total) return;
     __shared__ int64_t s_lo, s_hi;
@@ -133,22 +135,46 @@ __global__ __launch_bounds__(256) void k_scatter(const int64_t* cell_off, int64_
     }
     __syncthreads();
     const int64_t clo = s_lo, chi = s_hi;
-    for (int k = 0; k < 4; ++k) {
+    // the block's cells: output offsets, input offsets and modes cached in LDS when they fit
+    __shared__ int64_t s_oo[SC_CACHE + 1], s_co[SC_CACHE + 1];
+    __shared__ uint8_t s_md[SC_CACHE];
+    const int64_t ncell = chi - clo + 1;
+    const bool cached = ncell <= SC_CACHE;
+    if (cached) {
+        for (int64_t k = threadIdx.x; k <= ncell; k += blockDim.x) {
+            s_oo[k] = out_off[clo + k];
+            s_co[k] = cell_off[clo + k];
+            if (k < ncell) s_md[k] = cell_mode[clo + k];
+        }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < SC_PER; ++k) {
         const int64_t o = o0 + (int64_t)k * blockDim.x + threadIdx.x;
         if (o >= total) break;
-        int64_t lo = clo, hi = chi;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (out_off[mid] <= o) lo = mid; else hi = mid - 1;
-        }
-        const int64_t c = lo;
-        const int64_t src = cell_off[c] + (o - out_off[c]);
-        if (cell_mode[c] == CELL_UNTOUCHED) {
-#pragma unroll
-            for (int f = 0; f < 7; ++f) tb.out[f][o] = tb.in[f][src];
+        int64_t src;
+        bool untouched;
+        if (cached) {
+            int lo = 0, hi = (int)ncell - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_oo[mid] <= o) lo = mid; else hi = mid - 1;
+            }
+            src = s_co[lo] + (o - s_oo[lo]);
+            untouched = s_md[lo] == CELL_UNTOUCHED;
         } else {
+            int64_t lo = clo, hi = chi;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (out_off[mid] <= o) lo = mid; else hi = mid - 1;
+            }
+            src = cell_off[lo] + (o - out_off[lo]);
+            untouched = cell_mode[lo] == CELL_UNTOUCHED;
+        }
 #pragma unroll
-            for (int f = 0; f < 7; ++f) tb.out[f][o] = tb.tmp[f][src];
+        for (int f = 0; f < 7; ++f) {
+            const T* from = untouched ? tb.in[f] : tb.tmp[f];
+            __builtin_nontemporal_store(__builtin_nontemporal_load(from + src), tb.out[f] + o);
         }
     }
 }
@@ -202,7 +228,7 @@ hipError_t launch_scatter(const Workspace& ws, const LaunchCfg& lc, const int64_
                           int64_t n_particles, const int64_t* out_off, const void* const in[7], void* const out[7],
                           int elem_size) {
     if (n_cells == 0 || n_particles == 0) return hipSuccess;
-    const int64_t blocks = (n_particles + 1023) / 1024;     // out_total <= n_particles
+    const int64_t blocks = (n_particles + 256 * SC_PER - 1) / (256 * SC_PER);   // out_total <= n_particles
     if (lc.pre) lc.pre(lc.prof, "scatter", lc.stream);
     if (elem_size == 4) {
         Tables<float> tb;
