@@ -208,6 +208,67 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps):
     return rec
 
 
+def subset_labels(perm, sid, n_subsets_cell_off):
+    """Canonical label of every particle's final subset: the smallest input index among its members
+    (-1 for particles of cells that were not processed).  perm / subset_id as vpm_partition writes
+    them (subsets contiguous per cell)."""
+    import torch
+    cell_off = n_subsets_cell_off
+    n = perm.numel()
+    counts = (cell_off[1:] - cell_off[:-1])
+    cid = torch.repeat_interleave(torch.arange(counts.numel(), device=perm.device), counts, output_size=n)
+    key = cid * (1 << 20) + sid.long().clamp(min=0)                  # (cell, subset) -> one key
+    uniq, inv = torch.unique_consecutive(key, return_inverse=True)
+    first = torch.full((uniq.numel(),), 1 << 62, dtype=torch.int64, device=perm.device)
+    first.scatter_reduce_(0, inv, perm.long(), reduce="amin")
+    lab = torch.empty(n, dtype=torch.int64, device=perm.device)
+    lab[perm.long()] = first[inv]
+    lab[perm.long()[sid < 0]] = -1
+    return lab
+
+
+def precision_sweep(ctx, vpm, W, means, seed):
+    """The two-stream population at several densities: the batched fixed-point FP32 form against the
+    plain FP64 form on the same particles: time, conserved-total error of each against the exact
+    input totals, and the fraction of particles whose final subset is the same in both."""
+    import torch
+    recs = []
+    for mean in means:
+        wl64 = W.two_stream_grid(nx=256, ny=256, mean=mean, seed=seed)
+        wl32 = wl64.astype(np.float32)
+        prm = dict(wl64.params)
+        n = wl64.n
+        ctx.reserve(n, wl64.n_cells)
+        arrs, off = vpm.upload(wl32)
+        p32 = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
+        ms32, out32, _, n_out32, _ = time_fixed(ctx, vpm, arrs, off, n, p32, 5, 1, False)
+        cons32 = conservation_error(arrs, out32, n_out32, prm["mass"])
+        del out32
+        perm = torch.empty(n, dtype=torch.int32, device="cuda")
+        sid = torch.empty(n, dtype=torch.int32, device="cuda")
+        nsub = torch.empty(wl64.n_cells, dtype=torch.int32, device="cuda")
+        ctx.partition(arrs, off, n, p32, perm, sid, nsub)
+        lab32 = subset_labels(perm, sid, off)
+        del arrs
+        torch.cuda.empty_cache()
+        # the plain FP64 form runs on the FP32-rounded particles, so both see the same input
+        arrs64, off64 = vpm.upload(wl32, dtype=torch.float64)
+        p64 = vpm.make_params(decide=vpm.VPM_DECIDE_FP64, **prm)
+        ms64, out64, _, n_out64, _ = time_fixed(ctx, vpm, arrs64, off64, n, p64, 1, 1, False)
+        cons64 = conservation_error(arrs64, out64, n_out64, prm["mass"])
+        del out64
+        ctx.partition(arrs64, off64, n, p64, perm, sid, nsub)
+        lab64 = subset_labels(perm, sid, off64)
+        agree = float((lab32 == lab64).double().mean().item())
+        del arrs64, lab32, lab64, perm, sid, nsub
+        torch.cuda.empty_cache()
+        recs.append(dict(mean_per_cell=mean, n_particles=n, fixed_fp32_ms=ms32, plain_fp64_ms=ms64,
+                         speedup=ms64 / ms32, fixed_fp32_conservation=cons32, plain_fp64_conservation=cons64,
+                         merge_ratio_fp32=n_out32 / n, merge_ratio_fp64=n_out64 / n, partition_agreement=agree))
+        log(f"[bench] precision sweep, mean {mean}: FP32 {ms32:.2f} ms, FP64 {ms64:.2f} ms, agreement {agree:.5f}")
+    return dict(workload="two_stream_256x256_poisson_mean", tolerances=[0.1, 0.05], points=recs)
+
+
 def cascade(ctx, vpm, W, steps, seed):
     """Repeated merge events: the 512 x 512 cascade (256 particles per cell at the start, every particle
     split in two between events, cells above 1,024 particles merged).  The merge event is captured
@@ -362,6 +423,8 @@ def main():
         del sh, sh64
         if args.cascade_steps > 0:
             extra["cascade"] = cascade(ctx, vpm, W, args.cascade_steps, args.seed)
+        if not args.no_fp64:
+            extra["precision_sweep"] = precision_sweep(ctx, vpm, W, [128, 512, 2048], args.seed)
 
     line = {
         "metric": "input particles merged/sec + % HBM peak; batched-FP32 vs plain-FP64 at equal cons. err",
