@@ -371,6 +371,7 @@ struct CellMem {
     IdxT *idx0, *idx1;
     uint8_t* info;
     IdxT* emit;                    // output slot per position; schedule table while splitting
+    IdxT* dummy;                   // a slot no reader uses (emit[nmax]): target of masked-off stores
     Node<IdxT> *nodes0, *nodes1;   // current / next level (leaf tables at the end)
 };
 
@@ -397,6 +398,7 @@ VPM_DEV CellMem<IdxT> carve(uint8_t* base, int nmax) {
     M.idx0 = (IdxT*)take((size_t)nmax * sizeof(IdxT));
     M.idx1 = (IdxT*)take((size_t)nmax * sizeof(IdxT));
     M.emit = (IdxT*)take(((size_t)nmax + 1) * sizeof(IdxT));
+    M.dummy = M.emit + nmax;
     M.om = (uint16_t*)take((size_t)nmax * 2);
     M.sp = (int)(rnd16((size_t)nmax * 2) / 2);
     M.cp = (int16_t*)take((size_t)3 * M.sp * 2);
@@ -524,26 +526,31 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     IdxT* dst = idx_buf(M, cur ^ 1);
 
     // Step 6 as one stable pass: the lower side V1 = {c <= thr} fills the range from the front in
-    // slot order, V2 from the back in reverse slot order (so V2's member order flips).
-    const uint64_t below = lanes_below() >> gbase;
+    // slot order, V2 from the back in reverse slot order (so V2's member order flips).  The body is
+    // branch-free: past the end of the subset a lane reads the last slot again and stores to the
+    // dummy slot; ranks come from the wave ballots restricted to the lane's group.
+    const uint64_t gmask = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << gbase;
+    const uint64_t bel = lanes_below() & gmask;                // group lanes below this one
+    // the axis-k code of particle i is one aligned 32-bit load either way: the int32 momentum code,
+    // or the 32-bit word holding the int16 position code (then its half is selected and sign-extended)
+    const bool kpos = k < 3;
+    const uint8_t* cbase = kpos ? (const uint8_t*)(M.cp + min(k, 2) * M.sp) : (const uint8_t*)(M.cm + max(k - 3, 0) * M.sm);
     int lb = 0, rb = 0;
 #pragma unroll 2
     for (int j0 = 0; j0 < len; j0 += g) {
         const int j = j0 + lid;
         const bool act = j < len;
-        IdxT i = 0;
-        bool right = false;
-        if (act) { i = src[start + j]; right = code_of(M, k, i) > thr; }
-        const uint64_t br = group_bits(__ballot(act && right), gbase, g);
-        const int na = min(g, len - j0);
-        const uint64_t am = na == 64 ? ~0ull : ((1ull << na) - 1ull);
-        const uint64_t bl = am & ~br;
-        if (act) {
-            const int d = right ? len - 1 - (rb + __popcll(br & below)) : lb + __popcll(bl & below);
-            dst[start + d] = i;
-        }
-        lb += __popcll(bl);
-        rb += __popcll(br);
+        const IdxT i = src[start + min(j, len - 1)];
+        const int w = *(const int32_t*)(cbase + (kpos ? ((uint32_t)i & ~1u) * 2u : (uint32_t)i * 4u));
+        const int cv = kpos ? ((w << (16 - 16 * (int)(i & 1))) >> 16) : w;
+        const bool right = act && cv > thr;
+        const uint64_t bra = __ballot(right), baa = __ballot(act);
+        const int rr = __popcll(bra & bel), ra = __popcll(baa & bel);
+        const int d = right ? len - 1 - (rb + rr) : lb + (ra - rr);
+        *(act ? dst + start + d : M.dummy) = i;
+        const int nr = __popcll(bra & gmask), na = __popcll(baa & gmask);
+        lb += na - nr;
+        rb += nr;
     }
     wave_fence();
     const int nl = lb;
