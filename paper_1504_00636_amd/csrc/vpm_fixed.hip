@@ -361,13 +361,13 @@ __host__ __device__ constexpr size_t header_bytes() {
     return ((sizeof(CellShared) + 15) & ~(size_t)15) + (WPB > 1 ? ((sizeof(BlockScratch<WPB>) + 15) & ~(size_t)15) : 0);
 }
 
+// Codes of particle i: rec[i] = {c_px, c_py, c_pz, omega | c_x << 16} (16 bytes, one 128-bit load)
+// and pyz[i] = c_y | c_z << 16 (position codes are int16, momentum codes int32).
 template <typename IdxT>
 struct CellMem {
     CellShared* sh;
-    uint16_t* om;
-    int16_t* cp;                   // position codes, axis a at cp + a * sp
-    int32_t* cm;                   // momentum codes, axis a at cm + a * sm
-    int sp, sm;
+    int4* rec;
+    int32_t* pyz;
     IdxT *idx0, *idx1;
     uint8_t* info;
     IdxT* emit;                    // output slot per position; schedule table while splitting
@@ -380,9 +380,9 @@ __host__ __device__ constexpr size_t rnd16(size_t b) { return (b + 15) & ~(size_
 // Bytes of the per-cell arrays (without the LDS header).
 template <typename IdxT>
 __host__ __device__ constexpr size_t slice_bytes(int nmax) {
-    return 2 * rnd16(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>)) +
-           3 * rnd16((size_t)nmax * 4) + 2 * rnd16((size_t)nmax * sizeof(IdxT)) +
-           rnd16(((size_t)nmax + 1) * sizeof(IdxT)) + 4 * rnd16((size_t)nmax * 2) + rnd16((size_t)nmax);
+    return 2 * rnd16(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>)) + rnd16((size_t)nmax * 16) +
+           rnd16((size_t)nmax * 4) + 2 * rnd16((size_t)nmax * sizeof(IdxT)) +
+           rnd16(((size_t)nmax + 1) * sizeof(IdxT)) + rnd16((size_t)nmax);
 }
 
 template <typename IdxT>
@@ -393,15 +393,12 @@ VPM_DEV CellMem<IdxT> carve(uint8_t* base, int nmax) {
     M.sh = nullptr;
     M.nodes0 = (Node<IdxT>*)take(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>));
     M.nodes1 = (Node<IdxT>*)take(((size_t)nmax / 2 + 2) * sizeof(Node<IdxT>));
-    M.sm = (int)(rnd16((size_t)nmax * 4) / 4);
-    M.cm = (int32_t*)take((size_t)3 * M.sm * 4);
+    M.rec = (int4*)take((size_t)nmax * 16);
+    M.pyz = (int32_t*)take((size_t)nmax * 4);
     M.idx0 = (IdxT*)take((size_t)nmax * sizeof(IdxT));
     M.idx1 = (IdxT*)take((size_t)nmax * sizeof(IdxT));
     M.emit = (IdxT*)take(((size_t)nmax + 1) * sizeof(IdxT));
     M.dummy = M.emit + nmax;
-    M.om = (uint16_t*)take((size_t)nmax * 2);
-    M.sp = (int)(rnd16((size_t)nmax * 2) / 2);
-    M.cp = (int16_t*)take((size_t)3 * M.sp * 2);
     M.info = (uint8_t*)take((size_t)nmax);
     return M;
 }
@@ -426,16 +423,14 @@ struct FixedArgs {
 template <typename IdxT>
 VPM_DEV IdxT* idx_buf(const CellMem<IdxT>& M, int par) { return par ? M.idx1 : M.idx0; }
 
-template <typename IdxT>
-VPM_DEV int code_of(const CellMem<IdxT>& M, int k, int i) {
-    return k < 3 ? (int)M.cp[k * M.sp + i] : M.cm[(k - 3) * M.sm + i];
-}
 
 template <typename IdxT>
 VPM_DEV void codes_of(const CellMem<IdxT>& M, int i, int c[6], int& om) {
-    om = M.om[i];
-    c[0] = M.cp[i]; c[1] = M.cp[M.sp + i]; c[2] = M.cp[2 * M.sp + i];
-    c[3] = M.cm[i]; c[4] = M.cm[M.sm + i]; c[5] = M.cm[2 * M.sm + i];
+    const int4 r = M.rec[i];
+    const int v = M.pyz[i];
+    om = r.w & 0xffff;
+    c[0] = r.w >> 16; c[1] = (v << 16) >> 16; c[2] = v >> 16;
+    c[3] = r.x; c[4] = r.y; c[5] = r.z;
 }
 
 // Decide one subset [start, start+len) of buffer `buf` from its FP64 moments; falls back to
@@ -531,18 +526,21 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     // dummy slot; ranks come from the wave ballots restricted to the lane's group.
     const uint64_t gmask = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << gbase;
     const uint64_t bel = lanes_below() & gmask;                // group lanes below this one
-    // the axis-k code of particle i is one aligned 32-bit load either way: the int32 momentum code,
-    // or the 32-bit word holding the int16 position code (then its half is selected and sign-extended)
-    const bool kpos = k < 3;
-    const uint8_t* cbase = kpos ? (const uint8_t*)(M.cp + min(k, 2) * M.sp) : (const uint8_t*)(M.cm + max(k - 3, 0) * M.sm);
+    // the axis-k code of particle i is one aligned 32-bit load: a word of rec[i] (x: its upper half,
+    // momenta: whole words) or pyz[i] (y: lower half, z: upper half), then half-selected and
+    // sign-extended for the int16 position codes
+    const bool kpyz = k == 1 || k == 2;
+    const uint8_t* cbase = kpyz ? (const uint8_t*)M.pyz : (const uint8_t*)M.rec + (k == 0 ? 12 : 4 * (k - 3));
+    const uint32_t cstride = kpyz ? 4u : 16u;
+    const int cshift = k == 1 ? 16 : (k == 0 || k == 2) ? 0 : -1;   // left shift before >> 16; -1: whole
     int lb = 0, rb = 0;
 #pragma unroll 2
     for (int j0 = 0; j0 < len; j0 += g) {
         const int j = j0 + lid;
         const bool act = j < len;
         const IdxT i = src[start + min(j, len - 1)];
-        const int w = *(const int32_t*)(cbase + (kpos ? ((uint32_t)i & ~1u) * 2u : (uint32_t)i * 4u));
-        const int cv = kpos ? ((w << (16 - 16 * (int)(i & 1))) >> 16) : w;
+        const int w = *(const int32_t*)(cbase + (uint32_t)i * cstride);
+        const int cv = cshift < 0 ? w : ((w << cshift) >> 16);
         const bool right = act && cv > thr;
         const uint64_t bra = __ballot(right), baa = __ballot(act);
         const int rr = __popcll(bra & bel), ra = __popcll(baa & bel);
@@ -1028,9 +1026,8 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
                 cc[a] = ((F.amask >> a) & 1) ? (int)r - 32768 : 0;   // constant axis: code 0
                 cc[3 + a] = F.pzero[a] ? 0 : (int)rintf(ldexpf(q[3 + a], 22 - F.ep[a]));
             }
-            M.om[i] = (uint16_t)om;
-            M.cp[i] = (int16_t)cc[0]; M.cp[M.sp + i] = (int16_t)cc[1]; M.cp[2 * M.sp + i] = (int16_t)cc[2];
-            M.cm[i] = cc[3]; M.cm[M.sm + i] = cc[4]; M.cm[2 * M.sm + i] = cc[5];
+            M.rec[i] = make_int4(cc[3], cc[4], cc[5], (om & 0xffff) | (cc[0] << 16));
+            M.pyz[i] = (cc[1] & 0xffff) | (cc[2] << 16);
             M.idx0[i] = (IdxT)i;
             fsums_add(R, om, cc[0], cc[1], cc[2], cc[3], cc[4], cc[5]);
         };
@@ -1175,7 +1172,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         // merged subsets (Step 7)
         const int nm = sh.nmerged;
         if (nm > 0) {
-            IdxT* sched = (IdxT*)M.cm;                     // momentum codes are free now
+            IdxT* sched = (IdxT*)M.rec;                    // the codes are free now
             const Sched s = schedule<WPB, IdxT>(M, sched, nm, A.P.ppl_shift, [&](int it) {
                 const int ord = mlist[it];
                 return (int)(leaf_start[ord + 1] - leaf_start[ord]);
