@@ -142,8 +142,10 @@ vpm_status vpm_merge(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
                      int64_t *out_off, int64_t *out_total, hipStream_t stream);
 
 /* Launch configuration of the fixed-point path (batching, not arithmetic: every configuration gives
- * bit-identical results).  A cell of n particles (n > N_min) is processed by
- *   one wavefront, working set in LDS             if n <= bin_a_max  (bin_a_max <= 576)
+ * bit-identical results).  A cell of n particles (n > N_min) is processed
+ *   in a batch with other small cells by one wavefront (up to 16 cells, 512 particles, in LDS)
+ *                                                  if n <= bin_s_max  (bin_s_max <= 256; 0: none)
+ *   by one wavefront, working set in LDS          if n <= bin_a_max  (bin_a_max <= 576)
  *   four wavefronts, working set in LDS           if n <= bin_b_max  (bin_b_max <= 2048)
  *   eight wavefronts, working set in LDS          if n <= bin_c_max  (bin_c_max <= 4352)
  *   eight wavefronts, working set in global memory otherwise (n <= 65,536);
@@ -157,17 +159,19 @@ typedef struct {
     int32_t bin_b_max;
     int32_t bin_c_max;
     int32_t concurrent_bins;
+    int32_t bin_s_max;
 } vpm_tuning;
 
 /* Host-only validation of a tuning block (no device needed). */
 vpm_status vpm_check_tuning(const vpm_tuning *t);
 
-/* The context's current tuning (initially ppl 16, limits 576 / 2048 / 4352, bins in sequence). */
+/* The context's current tuning (initially ppl 16, limits 576 / 2048 / 4352, bins in sequence,
+ * small-cell batches for cells of up to 128 particles). */
 vpm_status vpm_get_tuning(vpm_ctx *ctx, vpm_tuning *t);
 vpm_status vpm_set_tuning(vpm_ctx *ctx, const vpm_tuning *t);
 
 /* Choose the tuning for a population: runs vpm_run with candidate configurations on the given
- * data (coordinate search over ppl, the three bin limits and concurrent_bins), times each on `stream` with HIP
+ * data (coordinate search over ppl, the bin limits, concurrent_bins and bin_s_max), times each on `stream` with HIP
  * events, keeps the fastest in the context and returns it in *best (host, may be NULL).  Leaves
  * vpm_run's result of the chosen configuration in out / out_off / out_total.  Synchronises
  * `stream`; cannot be captured in a graph.  Arguments as vpm_run (FIXED decisions only).      */

@@ -18,7 +18,8 @@ __global__ void k_reset(int32_t* counters) {
 // Classify every cell by size and append it to its queue (wave-aggregated atomics).
 __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_cells, int64_t n_particles,
                                              int32_t n_min_cell, int32_t* counters, int32_t* q_untouched,
-                                             int32_t* q_a, int32_t* q_b, int32_t* q_c, int32_t* q_big, int64_t* out_count,
+                                             int32_t* q_a, int32_t* q_b, int32_t* q_c, int32_t* q_big, int32_t* q_s,
+                                             int64_t* out_count,
                                              uint8_t* cell_mode, uint32_t* flags, BinLimits lim) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int cls = -1;
@@ -35,6 +36,8 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
             cls = Q_UNTOUCHED;
             out_count[c] = n;
             cell_mode[c] = CELL_UNTOUCHED;
+        } else if (n <= lim.s) {
+            cls = Q_S;
         } else if (n <= lim.a) {
             cls = Q_A;
         } else if (n <= lim.b) {
@@ -45,7 +48,7 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
             cls = Q_BIG;
         }
     }
-    int32_t* qs[Q_COUNT] = {q_untouched, q_a, q_b, q_c, q_big};
+    int32_t* qs[Q_COUNT] = {q_untouched, q_a, q_b, q_c, q_big, q_s};
 #pragma unroll
     for (int q = 0; q < Q_COUNT; ++q) {
         const uint64_t m = __ballot(cls == q);
@@ -204,7 +207,7 @@ hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* c
     const int64_t blocks = (n_cells + 255) / 256;
     hipLaunchKernelGGL(k_bin, dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells, n_particles,
                        n_min_cell, ws.counters, ws.queue[Q_UNTOUCHED], ws.queue[Q_A], ws.queue[Q_B],
-                       ws.queue[Q_C], ws.queue[Q_BIG], ws.out_count, ws.cell_mode, ws.flags, lim);
+                       ws.queue[Q_C], ws.queue[Q_BIG], ws.queue[Q_S], ws.out_count, ws.cell_mode, ws.flags, lim);
     if (lc.post) lc.post(lc.prof, "bin", lc.stream);
     return hipGetLastError();
 }

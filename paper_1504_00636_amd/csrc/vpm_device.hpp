@@ -129,6 +129,19 @@ template <int M>
 VPM_DEV uint64_t xchg(uint64_t v) { return (uint64_t)xchg<M>((int64_t)v); }
 template <int M>
 VPM_DEV double xchg(double v) { return __longlong_as_double(xchg<M>((int64_t)__double_as_longlong(v))); }
+template <int M>
+VPM_DEV float xchg(float v) { return __int_as_float(xchg32<M>(__float_as_int(v))); }
+
+// Maximum over an aligned group of g lanes (every lane of the group receives it).
+VPM_DEV float group_max(float v, int g) {
+    if (g > 1) v = fmaxf(v, xchg<1>(v));
+    if (g > 2) v = fmaxf(v, xchg<2>(v));
+    if (g > 4) v = fmaxf(v, xchg<4>(v));
+    if (g > 8) v = fmaxf(v, xchg<8>(v));
+    if (g > 16) v = fmaxf(v, xchg<16>(v));
+    if (g > 32) v = fmaxf(v, xchg<32>(v));
+    return v;
+}
 
 // Sum over an aligned group of g lanes (g a power of two, the same for all lanes of a group);
 // every lane of the group receives the total.

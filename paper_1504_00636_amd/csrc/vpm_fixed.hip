@@ -42,7 +42,8 @@ constexpr uint8_t INF_SET = 0x80;
 
 template <typename IdxT>
 struct Node { IdxT start, len; int32_t thr_axis; };
-// thr_axis = (threshold << 4) | (reversed << 3) | axis; `reversed`: the subset's slots hold its
+// thr_axis = (threshold << 8) | (cell << 4) | (reversed << 3) | axis; `cell`: index of the subset's
+// cell within a batch of small cells (0 otherwise); `reversed`: the subset's slots hold its
 // members in decreasing input order
 
 struct Frame {
@@ -511,12 +512,14 @@ VPM_DEV bool sched_lookup(const Sched& s, int v, int& slot, int& cls) {
 
 // Process one unfinished subset with a lane group: compaction, child moments, child decisions.
 template <typename IdxT>
-VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, Node<IdxT> nd,
+VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F0, const Frame* frames, Node<IdxT> nd,
                         int cur, int lid, int g, int gbase, Node<IdxT>* next) {
     const int start = nd.start, len = nd.len;
     const int k = nd.thr_axis & 7;
     const int rev = (nd.thr_axis >> 3) & 1;
-    const int thr = nd.thr_axis >> 4;
+    const int cell = (nd.thr_axis >> 4) & 15;
+    const int thr = nd.thr_axis >> 8;
+    const Frame& F = frames ? frames[cell] : F0;            // the frame of the subset's cell
     const IdxT* src = idx_buf(M, cur);
     IdxT* dst = idx_buf(M, cur ^ 1);
 
@@ -614,7 +617,8 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
             if (lid == 0) {
                 const int slot = atomicAdd(&M.sh->nnext, 1);
                 Node<IdxT> c;
-                c.start = (IdxT)cs; c.len = (IdxT)cl; c.thr_axis = (d.thr << 4) | (crev << 3) | d.axis;
+                c.start = (IdxT)cs; c.len = (IdxT)cl;
+                c.thr_axis = (d.thr << 8) | (cell << 4) | (crev << 3) | d.axis;
                 next[slot] = c;
             }
         } else {
@@ -792,7 +796,6 @@ VPM_DEV void frame_from(const float v[11], float mass, Frame& F) {
         if (F.hi[k] > F.lo[k]) F.amask |= 1 << k;          // else every position code is equal
         if (!F.pzero[k]) F.amask |= 1 << (3 + k);          // else every momentum code is 0
     }
-    F.amask = __builtin_amdgcn_readfirstlane(F.amask);     // wave-uniform: scalar branches
     // |eps_i - eps_j| <= m + |p|_1 for any two particles of the cell; 4x margin
     F.eb = frexp_exp(4.0f * (mass + F.pmax[0] + F.pmax[1] + F.pmax[2]));
 }
@@ -808,6 +811,7 @@ VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, float mass, Frame& 
 #pragma unroll
     for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
     frame_from(acc.v, mass, F);
+    F.amask = __builtin_amdgcn_readfirstlane(F.amask);     // wave-uniform: scalar branches
     return true;
 }
 
@@ -840,6 +844,7 @@ VPM_DEV bool cell_frame_block(const Soa32& in, int64_t off, int n, float mass, F
         __syncthreads();                                   // the scratch is reused below
         if (any_bad) return false;
         frame_from(v, mass, F);
+        F.amask = __builtin_amdgcn_readfirstlane(F.amask);
         return true;
     }
 }
@@ -941,6 +946,28 @@ __global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs G) {
     }
 }
 
+// The fixed-point codes of one particle (values q = x, y, z, px, py, pz, w) into slot i, and its
+// contribution to the moments R; `oob` is set if a position lies more than one cell length above
+// the cell's lowest one.
+template <typename IdxT>
+VPM_DEV void encode_particle(const CellMem<IdxT>& M, const FixedParams& P, const Frame& F, int i, const float* q,
+                             FSums& R, bool& oob) {
+    const int om = (int)rintf(ldexpf(q[6], 15 - F.ew));
+    int cc[6];
+    for (int a = 0; a < 3; ++a) {
+        const float d = q[a] - F.lo[a];
+        float r = rintf(d * P.s[a]);
+        oob |= r > 65536.0f;
+        r = fminf(r, 65535.0f);
+        cc[a] = ((F.amask >> a) & 1) ? (int)r - 32768 : 0;   // constant axis: code 0
+        cc[3 + a] = F.pzero[a] ? 0 : (int)rintf(ldexpf(q[3 + a], 22 - F.ep[a]));
+    }
+    M.rec[i] = make_int4(cc[3], cc[4], cc[5], (om & 0xffff) | (cc[0] << 16));
+    M.pyz[i] = (cc[1] & 0xffff) | (cc[2] << 16);
+    M.idx0[i] = (IdxT)i;
+    fsums_add(R, om, cc[0], cc[1], cc[2], cc[3], cc[4], cc[5]);
+}
+
 // ------------------------------------------------------------------------------------------
 // The cell kernel: one cell per workgroup of WPB wavefronts (one wavefront for the small bin).
 // The subsets of a level are spread over the lane groups of all wavefronts; workgroup barriers
@@ -1015,22 +1042,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         FSums R;
         fsums_zero(R);
         bool oob = false;
-        auto encode = [&](int i, const float* q) {
-            const int om = (int)rintf(ldexpf(q[6], 15 - F.ew));
-            int cc[6];
-            for (int a = 0; a < 3; ++a) {
-                const float d = q[a] - F.lo[a];
-                float r = rintf(d * A.P.s[a]);
-                oob |= r > 65536.0f;
-                r = fminf(r, 65535.0f);
-                cc[a] = ((F.amask >> a) & 1) ? (int)r - 32768 : 0;   // constant axis: code 0
-                cc[3 + a] = F.pzero[a] ? 0 : (int)rintf(ldexpf(q[3 + a], 22 - F.ep[a]));
-            }
-            M.rec[i] = make_int4(cc[3], cc[4], cc[5], (om & 0xffff) | (cc[0] << 16));
-            M.pyz[i] = (cc[1] & 0xffff) | (cc[2] << 16);
-            M.idx0[i] = (IdxT)i;
-            fsums_add(R, om, cc[0], cc[1], cc[2], cc[3], cc[4], cc[5]);
-        };
+        auto encode = [&](int i, const float* q) { encode_particle(M, A.P, F, i, q, R, oob); };
 #pragma unroll 2
         for (int i = tid; i < n; i += NT) {
             const float q[7] = {A.in.x[off + i], A.in.y[off + i], A.in.z[off + i], A.in.px[off + i],
@@ -1066,7 +1078,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         if (rd.kind == D_SPLIT) {
             if (tid == 0) {
                 Node<IdxT> nd;
-                nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 4) | rd.axis;
+                nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 8) | rd.axis;
                 M.nodes0[0] = nd;
             }
             m = 1;
@@ -1088,7 +1100,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
                 if (sched_lookup(s, r0 + lane, slot, cls)) {
                     const Node<IdxT> nd = curl[M.emit[slot]];
                     const int g = 1 << cls;
-                    split_node<IdxT>(M, A, F, nd, cur, lane & (g - 1), g, lane & ~(g - 1), nextl);
+                    split_node<IdxT>(M, A, F, nullptr, nd, cur, lane & (g - 1), g, lane & ~(g - 1), nextl);
                 }
             }
             cell_sync<WPB>();
@@ -1200,12 +1212,301 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Small cells: one wavefront processes a batch of up to SMALL_CELLS cells (at most NMAX_S particles
+// together).  Each cell of the batch is a root subset handled by a lane group: its frame, codes,
+// moments and decision (Step 1).  The levels below proceed as for a single cell, the subsets of all
+// cells of the batch sharing the lane groups; a subset carries its cell's index.
+// ------------------------------------------------------------------------------------------
+
+constexpr int SMALL_CELLS = 16;
+constexpr uint8_t INF_SKIP = 0x40;     // slot of a batch cell that is passed through (invalid values)
+
+struct SmallShared {
+    int nc;                             // cells in the batch
+    int cell[SMALL_CELLS];
+    int base[SMALL_CELLS + 1];          // first slot of each cell; base[nc] = slots in use
+    int64_t off[SMALL_CELLS];           // the cell's first particle
+    int64_t pbase[SMALL_CELLS + 1];     // output-scan value (leaves << 32 | outputs) at each first slot
+    uint32_t cflags[SMALL_CELLS];
+    Frame frame[SMALL_CELLS];
+};
+
+__host__ __device__ constexpr size_t small_header_bytes() {
+    return rnd16(sizeof(CellShared)) + rnd16(sizeof(SmallShared));
+}
+
+// Index of the batch cell that owns slot p.
+VPM_DEV int small_cell_of(const SmallShared& ss, int p) {
+    int lo = 0, hi = ss.nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ss.base[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Step 1 for batch cell j with a lane group: validity, frame, codes, root moments and decision.
+VPM_DEV void small_root(const CellMem<uint16_t>& M, const FixedArgs& A, SmallShared& ss, int j, int g, int lid,
+                        int gbase) {
+    const int b = ss.base[j], n = ss.base[j + 1] - b;
+    const int64_t off = ss.off[j];
+    const uint64_t gm = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << gbase;
+    FrameAcc acc;
+    facc_init(acc);
+    for (int p = lid; p < n; p += g) facc_load(acc, A.in, off + p);
+    if ((__ballot(acc.bad) & gm) != 0) {
+        if (lid == 0) ss.cflags[j] = FLAG_BAD_VALUE;
+        for (int p = lid; p < n; p += g) M.info[b + p] = INF_SKIP;
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 11; ++r) acc.v[r] = group_max(acc.v[r], g);
+    Frame F;
+    frame_from(acc.v, (float)A.P.mass, F);
+    if (lid == 0) ss.frame[j] = F;
+    FSums R;
+    fsums_zero(R);
+    bool oob = false;
+    for (int p = lid; p < n; p += g) {
+        const int64_t i = off + p;
+        const float q[7] = {A.in.x[i], A.in.y[i], A.in.z[i], A.in.px[i], A.in.py[i], A.in.pz[i], A.in.w[i]};
+        encode_particle(M, A.P, F, b + p, q, R, oob);
+    }
+    fsums_group_reduce(R, g);
+    if ((__ballot(oob) & gm) != 0 && lid == 0) atomicOr(&ss.cflags[j], FLAG_OUT_OF_CELL);
+    wave_fence();
+    int dv = 0;
+    if (lid == 0) {
+        const Decision d = decide(M, R, M.idx0, b, n, A.P, F);
+        dv = pack_decision(d);
+        if (d.kind == D_SPLIT) {
+            const int slot = atomicAdd(&M.sh->nnext, 1);
+            Node<uint16_t> nd;
+            nd.start = (uint16_t)b; nd.len = (uint16_t)n; nd.thr_axis = (d.thr << 8) | (j << 4) | d.axis;
+            M.nodes0[slot] = nd;
+        }
+    }
+    const Decision d = unpack_decision(__shfl(dv, gbase));
+    if (d.kind != D_SPLIT) {
+        const uint8_t base = INF_SET | (d.kind == D_MERGED ? INF_MERGED : 0) | (uint8_t)(d.jdir << INF_JSHIFT);
+        for (int p = lid; p < n; p += g) M.info[b + p] = base | (p == 0 ? INF_HEAD : 0);
+    }
+}
+
+__global__ __launch_bounds__(WAVE, 2) void k_fixed_small(FixedArgs A) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    using IdxT = uint16_t;
+    const int lane = lane_id();
+    CellShared& sh = *(CellShared*)smem;
+    SmallShared& ss = *(SmallShared*)(smem + rnd16(sizeof(CellShared)));
+    CellMem<IdxT> M = carve<IdxT>(smem + small_header_bytes(), NMAX_S);
+    M.sh = &sh;
+    const int qlen = A.counters[A.qlen_index];
+    const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
+    int qnext = 0, qend = 0;
+    for (;;) {
+        if (qnext >= qend) {
+            if (lane == 0) qnext = atomicAdd(&A.counters[A.work_index], SMALL_CELLS);
+            qnext = __shfl(qnext, 0);
+            qend = min(qnext + SMALL_CELLS, qlen);
+        }
+        if (qnext >= qlen) break;
+
+        // ---- a batch: the claimed entries in queue order, as many as fit NMAX_S slots ----
+        const int avail = qend - qnext;
+        int my_c = 0, my_n = 0;
+        int64_t my_off = 0;
+        if (lane < avail) {
+            my_c = A.queue[qnext + lane];
+            my_off = A.cell_off[my_c];
+            my_n = (int)(A.cell_off[my_c + 1] - my_off);
+        }
+        int take = 0, tot = 0;
+        for (int t = 0; t < avail; ++t) {             // every cell of this bin has at most NMAX_S / 2
+            const int nt = __shfl(my_n, t);
+            if (tot + nt > NMAX_S) break;
+            tot += nt;
+            ++take;
+        }
+        int inc = lane < take ? my_n : 0;
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int o = __shfl_up(inc, d);
+            if (lane >= d) inc += o;
+        }
+        if (lane < take) {
+            ss.cell[lane] = my_c;
+            ss.off[lane] = my_off;
+            ss.base[lane] = inc - my_n;
+            ss.cflags[lane] = 0;
+        }
+        if (lane == 0) { ss.base[take] = tot; ss.nc = take; sh.nnext = 0; sh.flags = 0; }
+        qnext += take;
+        wave_fence();
+
+        // ---- Step 1 for every cell of the batch ----
+        {
+            const Sched s0 = schedule<1, IdxT>(M, M.emit, take, A.P.ppl_shift,
+                                               [&](int it) { return ss.base[it + 1] - ss.base[it]; });
+            for (int r0 = 0; r0 < s0.total; r0 += WAVE) {
+                int slot, cls;
+                if (sched_lookup(s0, r0 + lane, slot, cls)) {
+                    const int g = 1 << cls;
+                    small_root(M, A, ss, M.emit[slot], g, lane & (g - 1), lane & ~(g - 1));
+                }
+            }
+            wave_fence();
+        }
+        int m = sh.nnext;
+
+        // ---- Steps 2-6, level by level, all cells of the batch together ----
+        int cur = 0;
+        while (m > 0) {
+            Node<IdxT>* curl = cur ? M.nodes1 : M.nodes0;
+            Node<IdxT>* nextl = cur ? M.nodes0 : M.nodes1;
+            if (lane == 0) sh.nnext = 0;
+            const Sched s = schedule<1, IdxT>(M, M.emit, m, A.P.ppl_shift, [&](int it) { return (int)curl[it].len; });
+            for (int r0 = 0; r0 < s.total; r0 += WAVE) {
+                int slot, cls;
+                if (sched_lookup(s, r0 + lane, slot, cls)) {
+                    const Node<IdxT> nd = curl[M.emit[slot]];
+                    const int g = 1 << cls;
+                    split_node<IdxT>(M, A, ss.frame[0], ss.frame, nd, cur, lane & (g - 1), g, lane & ~(g - 1), nextl);
+                }
+            }
+            wave_fence();
+            m = sh.nnext;
+            cur ^= 1;
+        }
+
+        // ---- output: one scan over the batch's slots; each cell's values relative to its first slot ----
+        const int per = (tot + WAVE - 1) / WAVE;
+        const int b0 = min(tot, lane * per), b1 = min(tot, b0 + per);
+        auto slot_value = [&](uint8_t inf) -> int64_t {
+            if (inf & INF_SKIP) return 0;
+            const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
+            return ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
+        };
+        int64_t loc = 0;
+        for (int p = b0; p < b1; ++p) loc += slot_value(M.info[p]);
+        int64_t sinc = loc;
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int64_t o = __shfl_up(sinc, d);
+            if (lane >= d) sinc += o;
+        }
+        const int64_t total = __shfl(sinc, WAVE - 1);
+        const int64_t pre = sinc - loc;
+        {
+            int64_t run = pre;
+            for (int p = b0; p < b1; ++p) {
+                const int jj = small_cell_of(ss, p);
+                if (ss.base[jj] == p) ss.pbase[jj] = run;
+                run += slot_value(M.info[p]);
+            }
+            if (lane == 0) ss.pbase[ss.nc] = total;
+        }
+        IdxT* leaf_start = (IdxT*)M.nodes0;                // first slot of each final subset (batch-wide)
+        IdxT* mlist = (IdxT*)M.nodes1;                     // batch-wide ordinals of the merged subsets
+        if (lane == 0) sh.nmerged = 0;
+        wave_fence();
+        {
+            int64_t run = pre;
+            for (int p = b0; p < b1; ++p) {
+                const uint8_t inf = M.info[p];
+                const int64_t v = slot_value(inf);
+                if (!(inf & INF_SKIP)) {
+                    const int jj = small_cell_of(ss, p);
+                    const int64_t rel = run - ss.pbase[jj];
+                    const int head = (inf & INF_HEAD) ? 1 : 0;
+                    const int ordg = (int)(run >> 32) + head - 1;
+                    if (A.mode == 0) {
+                        M.emit[p] = (IdxT)(rel & 0xffffffff);
+                    } else {
+                        const int64_t o = ss.off[jj] - ss.base[jj];
+                        A.perm[o + p] = (int32_t)(o + idx_buf(M, inf & INF_PARITY)[p]);
+                        A.subset_id[o + p] = (int)(rel >> 32) + head - 1;
+                    }
+                    if (head) {
+                        leaf_start[ordg] = (IdxT)p;
+                        if ((inf & INF_MERGED) && A.mode == 0) mlist[atomicAdd(&sh.nmerged, 1)] = (IdxT)ordg;
+                    }
+                }
+                run += v;
+            }
+        }
+        if (lane == 0) leaf_start[(int)(total >> 32)] = (IdxT)tot;
+        wave_fence();
+        if (lane < ss.nc) {
+            const int c = ss.cell[lane];
+            const int n = ss.base[lane + 1] - ss.base[lane];
+            const uint32_t cf = ss.cflags[lane];
+            if (cf & FLAG_BAD_VALUE) {
+                if (A.mode == 0) { A.out_count[c] = n; A.cell_mode[c] = CELL_UNTOUCHED; }
+                else {
+                    A.n_subsets[c] = 0;
+                    for (int i = 0; i < n; ++i) {
+                        A.perm[ss.off[lane] + i] = (int32_t)(ss.off[lane] + i);
+                        A.subset_id[ss.off[lane] + i] = -1;
+                    }
+                }
+            } else {
+                const int64_t d = ss.pbase[lane + 1] - ss.pbase[lane];
+                if (A.mode == 0) { A.out_count[c] = d & 0xffffffff; A.cell_mode[c] = CELL_PROCESSED; }
+                else A.n_subsets[c] = (int)(d >> 32);
+            }
+            const uint32_t fl = cf | (lane == 0 ? sh.flags : 0u);
+            if (fl) atomicOr(A.flags, fl);
+        }
+        if (A.mode == 1) { wave_fence(); continue; }
+
+        // copied particles (subsets below min_subset)
+        for (int p = lane; p < tot; p += WAVE) {
+            const uint8_t inf = M.info[p];
+            if (inf & (INF_MERGED | INF_SKIP)) continue;
+            const int jj = small_cell_of(ss, p);
+            const int64_t o0 = ss.off[jj] - ss.base[jj];
+            const int64_t i = o0 + idx_buf(M, inf & INF_PARITY)[p];
+            const int64_t o = ss.off[jj] + M.emit[p];
+            A.tmp.x[o] = A.in.x[i]; A.tmp.y[o] = A.in.y[i]; A.tmp.z[o] = A.in.z[i];
+            A.tmp.px[o] = A.in.px[i]; A.tmp.py[o] = A.in.py[i]; A.tmp.pz[o] = A.in.pz[i];
+            A.tmp.w[o] = A.in.w[i];
+        }
+        // merged subsets (Step 7)
+        const int nm = sh.nmerged;
+        if (nm > 0) {
+            IdxT* sched = (IdxT*)M.rec;                    // the codes are free now
+            auto leaf_len = [&](int ord) {
+                const int st = leaf_start[ord];
+                return min((int)leaf_start[ord + 1], ss.base[small_cell_of(ss, st) + 1]) - st;
+            };
+            const Sched s = schedule<1, IdxT>(M, sched, nm, A.P.ppl_shift, [&](int it) { return leaf_len(mlist[it]); });
+            for (int r0 = 0; r0 < s.total; r0 += WAVE) {
+                int slot, cls;
+                if (sched_lookup(s, r0 + lane, slot, cls)) {
+                    const int ord = mlist[sched[slot]];
+                    const int st = leaf_start[ord];
+                    const int ln = leaf_len(ord);
+                    const int jj = small_cell_of(ss, st);
+                    const int64_t o0 = ss.off[jj] - ss.base[jj];
+                    const int g = 1 << cls;
+                    const uint8_t inf = M.info[st];
+                    const IdxT* src = idx_buf(M, inf & INF_PARITY);
+                    merge_subset(A, ss.frame[jj], [&](int x) { return o0 + (int64_t)src[st + x]; }, ln,
+                                 (inf >> INF_JSHIFT) & 3, ss.off[jj] + M.emit[st], lane & (g - 1), g);
+                }
+            }
+        }
+        wave_fence();
+    }
+}
+
 constexpr int WPB_A = 1, WPB_B = 4, WPB_C = 8, WPB_BIG = 8;
 
 }  // namespace
 
 int fixed_lds_bytes(int which) {
     switch (which) {
+        case 4: return (int)(small_header_bytes() + slice_bytes<uint16_t>(NMAX_S));
         case 0: return (int)(header_bytes<WPB_A>() + slice_bytes<uint16_t>(NMAX_A));
         case 1: return (int)(header_bytes<WPB_B>() + slice_bytes<uint16_t>(NMAX_B));
         case 2: return (int)(header_bytes<WPB_C>() + slice_bytes<uint16_t>(NMAX_C));
@@ -1217,6 +1518,7 @@ int64_t fixed_big_slab_bytes() { return (int64_t)slice_bytes<uint32_t>(NMAX_BIG)
 
 const void* fixed_kernel_ptr(int which) {
     switch (which) {
+        case 4: return (const void*)k_fixed_small;
         case 0: return (const void*)k_fixed_cells<NMAX_A, uint16_t, true, WPB_A>;
         case 1: return (const void*)k_fixed_cells<NMAX_B, uint16_t, true, WPB_B>;
         case 2: return (const void*)k_fixed_cells<NMAX_C, uint16_t, true, WPB_C>;
@@ -1225,7 +1527,7 @@ const void* fixed_kernel_ptr(int which) {
 }
 
 int fixed_block_threads(int which) {
-    return WAVE * (which == 0 ? WPB_A : which == 1 ? WPB_B : which == 2 ? WPB_C : WPB_BIG);
+    return WAVE * (which == 0 || which == 4 ? 1 : which == 1 ? WPB_B : which == 2 ? WPB_C : WPB_BIG);
 }
 
 hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
@@ -1249,7 +1551,7 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
     A.big = nullptr; A.big_stride = 0;
     G.perm = perm; G.subset_id = subset_id; G.n_subsets = n_subsets;
     G.starts = ws.perm2;
-    const int qs[4] = {Q_BIG, Q_C, Q_B, Q_A};
+    const int qs[5] = {Q_BIG, Q_C, Q_B, Q_S, Q_A};
     for (int q : qs) {
         A.queue = ws.queue[q];
         A.qlen_index = q;
@@ -1294,9 +1596,10 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
         if (e != hipSuccess) return e;
     }
     struct Bin { int q; const char* name; hipStream_t s; };
-    const Bin bins[4] = {{Q_BIG, "fixed_cells_big", forked ? lc.side[0] : lc.stream},
+    const Bin bins[5] = {{Q_BIG, "fixed_cells_big", forked ? lc.side[0] : lc.stream},
                          {Q_C, "fixed_cells_4352", forked ? lc.side[1] : lc.stream},
                          {Q_B, "fixed_cells_2048", forked ? lc.side[2] : lc.stream},
+                         {Q_S, "fixed_cells_small", lc.stream},
                          {Q_A, "fixed_cells_576", lc.stream}};
     for (const Bin& b : bins) {
         A.queue = ws.queue[b.q];
@@ -1309,6 +1612,8 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
         else if (b.q == Q_B)
             hipLaunchKernelGGL((k_fixed_cells<NMAX_B, uint16_t, true, WPB_B>), dim3(lc.grid_b), dim3(WAVE * WPB_B),
                                fixed_lds_bytes(1), b.s, A);
+        else if (b.q == Q_S)
+            hipLaunchKernelGGL(k_fixed_small, dim3(lc.grid_s), dim3(WAVE), fixed_lds_bytes(4), b.s, A);
         else if (b.q == Q_C)
             hipLaunchKernelGGL((k_fixed_cells<NMAX_C, uint16_t, true, WPB_C>), dim3(lc.grid_c), dim3(WAVE * WPB_C),
                                fixed_lds_bytes(2), b.s, A);

@@ -18,8 +18,8 @@ struct vpm_ctx {
     int device = 0;
     int cu_count = 0;
     Workspace ws;
-    int grid_a = 0, grid_b = 0, grid_c = 0, grid_big = 0, grid_fp64 = 0;
-    vpm_tuning tune = {16, NMAX_A, NMAX_B, NMAX_C, 0};
+    int grid_a = 0, grid_b = 0, grid_c = 0, grid_big = 0, grid_s = 0, grid_fp64 = 0;
+    vpm_tuning tune = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128};
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     std::string last_error;
@@ -89,6 +89,7 @@ LaunchCfg make_cfg(vpm_ctx* c, hipStream_t s) {
     lc.grid_a = c->grid_a;
     lc.grid_b = c->grid_b;
     lc.grid_c = c->grid_c;
+    lc.grid_s = c->grid_s;
     lc.grid_big = c->grid_big;
     lc.grid_fp64 = c->grid_fp64;
     const bool fork = c->tune.concurrent_bins != 0;
@@ -141,7 +142,9 @@ int ilog2(int v) {
     return s;
 }
 
-BinLimits bin_limits(const vpm_ctx* c) { return BinLimits{c->tune.bin_a_max, c->tune.bin_b_max, c->tune.bin_c_max}; }
+BinLimits bin_limits(const vpm_ctx* c) {
+    return BinLimits{c->tune.bin_a_max, c->tune.bin_b_max, c->tune.bin_c_max, c->tune.bin_s_max};
+}
 
 FixedParams fixed_params(const vpm_params* p, const vpm_tuning& t) {
     FixedParams f;
@@ -234,8 +237,9 @@ vpm_status vpm_create(vpm_ctx** out, int device) {
     hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device);
     if (c->cu_count <= 0) c->cu_count = 256;
     // persistent grids: as many workgroups as fit on the chip at once
-    int* grids[3] = {&c->grid_a, &c->grid_b, &c->grid_c};
-    for (int b = 0; b < 3; ++b) {
+    int* grids[5] = {&c->grid_a, &c->grid_b, &c->grid_c, nullptr, &c->grid_s};
+    for (int b = 0; b < 5; ++b) {
+        if (!grids[b]) continue;
         int nb = 0;
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(b), fixed_block_threads(b), fixed_lds_bytes(b));
         *grids[b] = c->cu_count * (nb > 0 ? nb : 1);
@@ -399,6 +403,7 @@ vpm_status vpm_check_tuning(const vpm_tuning* t) {
     if (t->bin_b_max < t->bin_a_max || t->bin_b_max > NMAX_B) return VPM_ERR_INVALID_ARG;
     if (t->bin_c_max < t->bin_b_max || t->bin_c_max > NMAX_C) return VPM_ERR_INVALID_ARG;
     if (t->concurrent_bins != 0 && t->concurrent_bins != 1) return VPM_ERR_INVALID_ARG;
+    if (t->bin_s_max < 0 || t->bin_s_max > SMALL_MAX) return VPM_ERR_INVALID_ARG;
     return VPM_OK;
 }
 
@@ -450,7 +455,7 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
         ms = bestms;
         return VPM_OK;
     };
-    vpm_tuning cur = {16, NMAX_A, NMAX_B, NMAX_C, 0};
+    vpm_tuning cur = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128};
     float cur_ms = 0.f;
     st = time_cfg(cur, cur_ms);
     // coordinate search: each parameter in turn over its candidates, keeping the others
@@ -459,19 +464,21 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
     const int bs[3] = {1024, 1536, NMAX_B};
     const int cs[3] = {2560, 3456, NMAX_C};
     const int conc[2] = {0, 1};
-    for (int dim = 0; dim < 5 && st == VPM_OK; ++dim) {
-        const int* cand = dim == 0 ? ppls : dim == 1 ? as : dim == 2 ? bs : dim == 3 ? cs : conc;
-        const int nc = dim == 1 ? 5 : dim == 4 ? 2 : 3;
+    const int ss[5] = {0, 32, 64, 128, SMALL_MAX};
+    for (int dim = 0; dim < 6 && st == VPM_OK; ++dim) {
+        const int* cand = dim == 0 ? ppls : dim == 1 ? as : dim == 2 ? bs : dim == 3 ? cs : dim == 4 ? conc : ss;
+        const int nc = dim == 1 || dim == 5 ? 5 : dim == 4 ? 2 : 3;
         for (int k = 0; k < nc && st == VPM_OK; ++k) {
             vpm_tuning t = cur;
             if (dim == 0) t.ppl = cand[k];
             else if (dim == 1) t.bin_a_max = cand[k];
             else if (dim == 2) t.bin_b_max = cand[k];
             else if (dim == 3) t.bin_c_max = cand[k];
-            else t.concurrent_bins = cand[k];
+            else if (dim == 4) t.concurrent_bins = cand[k];
+            else t.bin_s_max = cand[k];
             if (vpm_check_tuning(&t) != VPM_OK) continue;
             if (t.ppl == cur.ppl && t.bin_a_max == cur.bin_a_max && t.bin_b_max == cur.bin_b_max &&
-                t.bin_c_max == cur.bin_c_max && t.concurrent_bins == cur.concurrent_bins)
+                t.bin_c_max == cur.bin_c_max && t.concurrent_bins == cur.concurrent_bins && t.bin_s_max == cur.bin_s_max)
                 continue;
             float ms = 0.f;
             st = time_cfg(t, ms);

@@ -16,7 +16,9 @@ constexpr int NMAX_A = 576;     // 1 wavefront per cell, working set in LDS (8 c
 constexpr int NMAX_B = 2048;    // 4 wavefronts per cell, working set in LDS (2 cells per CU)
 constexpr int NMAX_C = 4352;    // 8 wavefronts per cell, working set in LDS (1 cell per CU)
 constexpr int NMAX_BIG = 65536; // 8 wavefronts per cell, working set in a global slab
-enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_C = 3, Q_BIG = 4, Q_COUNT = 5 };
+constexpr int NMAX_S = 512;     // batches of small cells: 1 wavefront, up to 512 particles in LDS
+constexpr int SMALL_MAX = 256;  // largest cell the small-cell bin may take
+enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_C = 3, Q_BIG = 4, Q_S = 5, Q_COUNT = 6 };
 
 // Status bits (mirrors VPM_FLAG_* plus one internal bit).
 constexpr uint32_t FLAG_BAD_VALUE = VPM_FLAG_BAD_VALUE;
@@ -56,13 +58,13 @@ struct FixedParams {
     double mass;
 };
 
-// Routing thresholds of the size bins: cells of up to `a` particles go to bin A, up to `b` to B,
-// up to `c` to C, larger ones to the global-memory bin.
-struct BinLimits { int32_t a, b, c; };
+// Routing thresholds of the size bins: cells of up to `s` particles go to the small-cell batches,
+// up to `a` to bin A, up to `b` to B, up to `c` to C, larger ones to the global-memory bin.
+struct BinLimits { int32_t a, b, c, s; };
 
 struct LaunchCfg {
     hipStream_t stream;
-    int grid_a, grid_b, grid_c, grid_big, grid_fp64;   // persistent grid sizes
+    int grid_a, grid_b, grid_c, grid_big, grid_s, grid_fp64;   // persistent grid sizes
     // Optional fork/join for the size bins: bins run concurrently on two side streams (default
     // priority) that wait on `fork` (recorded on `stream`) and are joined back through `join`.
     hipStream_t side[3];
@@ -99,7 +101,7 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
                               const int64_t* cell_off, int64_t n_cells, int32_t n_min_cell,
                               const FixedParams& fp, const int32_t* perm,
                               const int32_t* subset_id, const int32_t* n_subsets);
-// bins: 0 = A, 1 = B, 2 = C (LDS), 3 = big (global slabs)
+// bins: 0 = A, 1 = B, 2 = C (LDS), 3 = big (global slabs), 4 = small-cell batches
 int fixed_lds_bytes(int which);            // dynamic LDS per workgroup
 const void* fixed_kernel_ptr(int which);   // for occupancy queries
 int fixed_block_threads(int which);

@@ -113,7 +113,9 @@ def test_binding_argument_counts_match_header():
     ((4, 576, 2048, 4352), False), ((12, 576, 2048, 4352), False), ((16, 0, 2048, 4352), False),
     ((16, 577, 2048, 4352), False), ((16, 576, 575, 4352), False), ((16, 576, 2049, 4352), False),
     ((16, 576, 2048, 2047), False), ((16, 576, 2048, 4353), False),
-    ((16, 576, 2048, 4352, 1), True), ((16, 576, 2048, 4352, 2), False), ((16, 576, 2048, 4352, -1), False)])
+    ((16, 576, 2048, 4352, 1), True), ((16, 576, 2048, 4352, 2), False), ((16, 576, 2048, 4352, -1), False),
+    ((16, 576, 2048, 4352, 0, 0), True), ((16, 576, 2048, 4352, 0, 256), True), ((16, 576, 2048, 4352, 0, 257), False),
+    ((16, 576, 2048, 4352, 0, -1), False)])
 def test_check_tuning(t, ok):
     st = vpm.vpm_check_tuning(vpm.make_tuning(*t))
     assert (st == vpm.VPM_OK) == ok, (t, st)

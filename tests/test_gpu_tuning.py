@@ -12,9 +12,11 @@ from tests.test_gpu_graph import PARAMS, population
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-SIZES = [1, 2, 5, 17, 64, 200, 575, 577, 900, 2047, 2049, 3000, 4353, 6000, 300, 12]
-TUNINGS = [(16, 576, 2048, 4352), (8, 64, 512, 1024, 1), (32, 320, 1024, 2560), (8, 1, 1, 1), (32, 576, 576, 576, 1),
-           (16, 100, 2048, 2048), (16, 576, 2048, 4352, 1)]
+SIZES = [1, 2, 5, 17, 64, 200, 575, 577, 900, 2047, 2049, 3000, 4353, 6000, 300, 12, 128, 129, 255, 256, 257,
+         3, 4, 9, 33, 90, 110, 7, 40, 60]
+TUNINGS = [(16, 576, 2048, 4352), (8, 64, 512, 1024, 1), (32, 320, 1024, 2560), (8, 1, 1, 1, 0, 0),
+           (32, 576, 576, 576, 1), (16, 100, 2048, 2048), (16, 576, 2048, 4352, 1), (16, 576, 2048, 4352, 0, 0),
+           (8, 576, 2048, 4352, 0, 256), (32, 576, 2048, 4352, 1, 17)]
 
 
 def _run(c, arrs, off, n, p):
