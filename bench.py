@@ -116,8 +116,8 @@ def traffic_summary(fetch_dir, write_dir, calib_fetch_dir, calib_write_dir):
         "copy_calibration": {"bytes": COPY_BYTES, "fetch_counter": f_c, "write_counter": w_c,
                              "fetch_bytes_per_count": fetch_scale, "write_bytes_per_count": write_scale},
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --no-cpu --no-fp64 --no-extra --steps 3 --warmup 1",
-            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --no-cpu --no-fp64 --no-extra --steps 3 --warmup 1",
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --no-cpu --no-fp64 --no-extra --no-autotune --steps 3 --warmup 1",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --no-cpu --no-fp64 --no-extra --no-autotune --steps 3 --warmup 1",
             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --copy-calib",
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python3 bench.py --copy-calib",
             "python3 bench.py --traffic-summary <fetch> <write> <calib-fetch> <calib-write>",
@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CALIB_FETCH", "CALIB_WRITE"))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cascade-steps", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default batching configuration (profiling runs: one kernel configuration only)")
     args = ap.parse_args()
 
     if args.traffic_summary:
@@ -365,8 +367,11 @@ def main():
     ctx.reserve(52_000_000, 64 ** 3)
     arrs32, off = vpm.upload(wl32)
     p32 = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
-    tuning, tune_s = autotune(ctx, vpm, arrs32, off, n, p32)
-    log(f"[bench] autotuned in {tune_s:.2f}s: {tuning}")
+    if args.no_autotune:
+        tuning, tune_s = ctx.get_tuning().as_dict(), 0.0
+    else:
+        tuning, tune_s = autotune(ctx, vpm, arrs32, off, n, p32)
+    log(f"[bench] tuning ({tune_s:.2f}s autotune): {tuning}")
     ms_step, out32, out_off, n_out, kernels = time_fixed(ctx, vpm, arrs32, off, n, p32, args.steps,
                                                          args.warmup, True)
     rho = n_out / n
