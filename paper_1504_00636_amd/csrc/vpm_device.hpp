@@ -95,12 +95,6 @@ VPM_DEV uint64_t lanes_below() {                 // bit mask of the lanes below 
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Bits of `ballot` that belong to this lane's group, shifted down to bit 0.
-VPM_DEV uint64_t group_bits(uint64_t ballot, int gbase, int g) {
-    const uint64_t m = g == 64 ? ~0ull : ((1ull << g) - 1ull);
-    return (ballot >> gbase) & m;
-}
-
 // Partner value for step m of a butterfly sum inside aligned groups of lanes.  Steps 1 and 2 are
 // DPP quad permutes; steps 4 and 8 are the DPP half-row and row mirrors, which pair each lane with
 // one of the other half of its 8- or 16-lane block (equivalent to xor for a sum, because after the
@@ -160,25 +154,6 @@ VPM_DEV V group_sum(V v, int g) {
 // ------------------------------------------------------------------------------------------
 // Workgroup helpers (all threads must call; `red` is LDS scratch of >= blockDim/64 slots).
 // ------------------------------------------------------------------------------------------
-
-template <typename V, typename Op>
-VPM_DEV V wave_reduce(V v, Op op) {
-    for (int m = 1; m < WAVE; m <<= 1) v = op(v, __shfl_xor(v, m));
-    return v;
-}
-
-template <int T, typename V, typename Op>
-VPM_DEV V block_reduce(V v, Op op, V* red) {
-    v = wave_reduce(v, op);
-    const int w = threadIdx.x / WAVE;
-    __syncthreads();
-    if (lane_id() == 0) red[w] = v;
-    __syncthreads();
-    V r = red[0];
-#pragma unroll
-    for (int i = 1; i < T / WAVE; ++i) r = op(r, red[i]);
-    return r;
-}
 
 // Exclusive scan of one value per thread across the workgroup; returns the prefix and sets
 // *total.  `red` needs T/64 + 1 slots.
