@@ -639,6 +639,40 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     }
 }
 
+// Copy particles unchanged from the input to the staging arrays.  For positions p = first,
+// first + stride, ... below end, slot(p, src, dst) gives the input index and the staging slot, or
+// dst < 0 for nothing (src must then still be a valid input index).  The loads of CB positions are
+// all issued before their stores: the two arrays never overlap, but the compiler cannot know that
+// and would otherwise wait for every load before the next store.  Positions past the end reload the
+// batch's first particle and store nothing.
+constexpr int COPY_BATCH = 4;          // particles per lane whose loads are in flight together
+
+template <int CB, typename SlotFn>
+VPM_DEV void copy_particles(const Soa32& in, const Soa32Out& out, int first, int end, int stride, SlotFn slot) {
+    for (int p0 = first; p0 < end; p0 += CB * stride) {
+        float v[CB][7];
+        int64_t so[CB];
+        int64_t si0 = 0;
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            const int p = p0 + u * stride;
+            int64_t si = si0;
+            so[u] = -1;
+            if (u == 0 || p < end) slot(p, si, so[u]);
+            if (u == 0) si0 = si;
+            v[u][0] = in.x[si]; v[u][1] = in.y[si]; v[u][2] = in.z[si];
+            v[u][3] = in.px[si]; v[u][4] = in.py[si]; v[u][5] = in.pz[si]; v[u][6] = in.w[si];
+        }
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            if (so[u] < 0) continue;
+            const int64_t o = so[u];
+            out.x[o] = v[u][0]; out.y[o] = v[u][1]; out.z[o] = v[u][2];
+            out.px[o] = v[u][3]; out.py[o] = v[u][4]; out.pz[o] = v[u][5]; out.w[o] = v[u][6];
+        }
+    }
+}
+
 // Merge one finished subset with a lane group (Step 7) and write its 1 or 2 particles.
 //
 // Two passes over the subset, all sums exact int64 on fixed grids (so the result does not depend
@@ -918,13 +952,10 @@ __global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs G) {
             if (sidx >= nsub) continue;
             const int32_t* mem = G.perm + off + b;
             if (len < A.P.min_subset) {
-                for (int j = 0; j < len; ++j) {
-                    const int64_t i = mem[j];
-                    const int64_t o = off + slot + j;
-                    A.tmp.x[o] = A.in.x[i]; A.tmp.y[o] = A.in.y[i]; A.tmp.z[o] = A.in.z[i];
-                    A.tmp.px[o] = A.in.px[i]; A.tmp.py[o] = A.in.py[i]; A.tmp.pz[o] = A.in.pz[i];
-                    A.tmp.w[o] = A.in.w[i];
-                }
+                copy_particles<4>(A.in, A.tmp, 0, len, 1, [&](int j, int64_t& si, int64_t& so) {
+                    si = mem[j];
+                    so = off + slot + j;
+                });
                 continue;
             }
             // pair direction from the momentum codes, exactly as the partition kernel does
@@ -1171,16 +1202,11 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             continue;
         }
         // copied particles (subsets below min_subset)
-#pragma unroll 4
-        for (int p = tid; p < n; p += NT) {
+        copy_particles<COPY_BATCH>(A.in, A.tmp, tid, n, NT, [&](int p, int64_t& si, int64_t& so) {
             const uint8_t inf = M.info[p];
-            if (inf & INF_MERGED) continue;
-            const int64_t i = off + idx_buf(M, inf & INF_PARITY)[p];
-            const int64_t o = off + M.emit[p];
-            A.tmp.x[o] = A.in.x[i]; A.tmp.y[o] = A.in.y[i]; A.tmp.z[o] = A.in.z[i];
-            A.tmp.px[o] = A.in.px[i]; A.tmp.py[o] = A.in.py[i]; A.tmp.pz[o] = A.in.pz[i];
-            A.tmp.w[o] = A.in.w[i];
-        }
+            si = off + idx_buf(M, inf & INF_PARITY)[p];
+            so = (inf & INF_MERGED) ? -1 : off + M.emit[p];
+        });
         // merged subsets (Step 7)
         const int nm = sh.nmerged;
         if (nm > 0) {
@@ -1460,17 +1486,13 @@ __global__ __launch_bounds__(WAVE, 2) void k_fixed_small(FixedArgs A) {
         if (A.mode == 1) { wave_fence(); continue; }
 
         // copied particles (subsets below min_subset)
-        for (int p = lane; p < tot; p += WAVE) {
+        copy_particles<COPY_BATCH>(A.in, A.tmp, lane, tot, WAVE, [&](int p, int64_t& si, int64_t& so) {
             const uint8_t inf = M.info[p];
-            if (inf & (INF_MERGED | INF_SKIP)) continue;
             const int jj = small_cell_of(ss, p);
-            const int64_t o0 = ss.off[jj] - ss.base[jj];
-            const int64_t i = o0 + idx_buf(M, inf & INF_PARITY)[p];
-            const int64_t o = ss.off[jj] + M.emit[p];
-            A.tmp.x[o] = A.in.x[i]; A.tmp.y[o] = A.in.y[i]; A.tmp.z[o] = A.in.z[i];
-            A.tmp.px[o] = A.in.px[i]; A.tmp.py[o] = A.in.py[i]; A.tmp.pz[o] = A.in.pz[i];
-            A.tmp.w[o] = A.in.w[i];
-        }
+            const bool keep = !(inf & (INF_MERGED | INF_SKIP));       // skipped cells have no index lists
+            si = ss.off[jj] - ss.base[jj] + (keep ? (int)idx_buf(M, inf & INF_PARITY)[p] : p);
+            so = keep ? ss.off[jj] + M.emit[p] : -1;
+        });
         // merged subsets (Step 7)
         const int nm = sh.nmerged;
         if (nm > 0) {
