@@ -151,34 +151,43 @@ __global__ __launch_bounds__(256) void k_scatter(const int64_t* cell_off, int64_
         }
     }
     __syncthreads();
-#pragma unroll 4
+    // all of a thread's slots are located first, then all their loads issued, then the stores (the
+    // compiler cannot tell that the source and output arrays never overlap, and would otherwise wait
+    // on each load before the next store)
+    int64_t src[SC_PER];
+    bool untouched[SC_PER];
+#pragma unroll
     for (int k = 0; k < SC_PER; ++k) {
-        const int64_t o = o0 + (int64_t)k * blockDim.x + threadIdx.x;
-        if (o >= total) break;
-        int64_t src;
-        bool untouched;
+        const int64_t o = min(o0 + (int64_t)k * blockDim.x + threadIdx.x, total - 1);
         if (cached) {
             int lo = 0, hi = (int)ncell - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (s_oo[mid] <= o) lo = mid; else hi = mid - 1;
             }
-            src = s_co[lo] + (o - s_oo[lo]);
-            untouched = s_md[lo] == CELL_UNTOUCHED;
+            src[k] = s_co[lo] + (o - s_oo[lo]);
+            untouched[k] = s_md[lo] == CELL_UNTOUCHED;
         } else {
             int64_t lo = clo, hi = chi;
             while (lo < hi) {
                 const int64_t mid = (lo + hi + 1) >> 1;
                 if (out_off[mid] <= o) lo = mid; else hi = mid - 1;
             }
-            src = cell_off[lo] + (o - out_off[lo]);
-            untouched = cell_mode[lo] == CELL_UNTOUCHED;
+            src[k] = cell_off[lo] + (o - out_off[lo]);
+            untouched[k] = cell_mode[lo] == CELL_UNTOUCHED;
         }
+    }
+    T v[SC_PER][7];
 #pragma unroll
-        for (int f = 0; f < 7; ++f) {
-            const T* from = untouched ? tb.in[f] : tb.tmp[f];
-            __builtin_nontemporal_store(__builtin_nontemporal_load(from + src), tb.out[f] + o);
-        }
+    for (int k = 0; k < SC_PER; ++k)
+#pragma unroll
+        for (int f = 0; f < 7; ++f) v[k][f] = __builtin_nontemporal_load((untouched[k] ? tb.in[f] : tb.tmp[f]) + src[k]);
+#pragma unroll
+    for (int k = 0; k < SC_PER; ++k) {
+        const int64_t o = o0 + (int64_t)k * blockDim.x + threadIdx.x;
+        if (o >= total) break;
+#pragma unroll
+        for (int f = 0; f < 7; ++f) __builtin_nontemporal_store(v[k][f], tb.out[f] + o);
     }
 }
 
