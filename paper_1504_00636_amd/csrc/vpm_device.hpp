@@ -90,9 +90,23 @@ VPM_DEV int cmp256(U256 a, U256 b) {
 
 VPM_DEV int lane_id() { return __lane_id(); }
 
-VPM_DEV uint64_t lanes_below() {                 // bit mask of the lanes below this one
-    const int l = lane_id();
+VPM_DEV uint64_t lanes_below_of(int l) {         // bit mask of the lanes below lane l
     return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+VPM_DEV uint64_t lanes_below() { return lanes_below_of(lane_id()); }
+
+// The lane index as a value the compiler cannot precompute: values derived from it are then formed
+// where they are used instead of being hoisted out of the kernel's outer loops, where they would
+// occupy registers for the whole kernel.
+VPM_DEV int opaque_lane() {
+    int l = lane_id();
+    asm volatile("" : "+v"(l));
+    return l;
+}
+VPM_DEV int opaque_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
 }
 
 // Partner value for step m of a butterfly sum inside aligned groups of lanes.  Steps 1 and 2 are

@@ -528,7 +528,7 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     // branch-free: past the end of the subset a lane reads the last slot again and stores to the
     // dummy slot; ranks come from the wave ballots restricted to the lane's group.
     const uint64_t gmask = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << gbase;
-    const uint64_t bel = lanes_below() & gmask;                // group lanes below this one
+    const uint64_t bel = lanes_below_of(gbase + lid) & gmask;  // group lanes below this one
     // the axis-k code of particle i is one aligned 32-bit load: a word of rec[i] (x: its upper half,
     // momenta: whole words) or pyz[i] (y: lower half, z: upper half), then half-selected and
     // sign-extended for the int16 position codes
@@ -536,14 +536,26 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     const uint8_t* cbase = kpyz ? (const uint8_t*)M.pyz : (const uint8_t*)M.rec + (k == 0 ? 12 : 4 * (k - 3));
     const uint32_t cstride = kpyz ? 4u : 16u;
     const int cshift = k == 1 ? 16 : (k == 0 || k == 2) ? 0 : -1;   // left shift before >> 16; -1: whole
+    auto code_of = [&](IdxT i) {
+        const int w = *(const int32_t*)(cbase + (uint32_t)i * cstride);
+        return cshift < 0 ? w : ((w << cshift) >> 16);
+    };
+    // software-pipelined: the code of the next position and the index of the one after it are loaded
+    // while the current position is placed (reads past the subset's end repeat its last slot)
+    const IdxT* sp = src + start;
+    const int last = len - 1;
+    IdxT i_nxt = sp[min(g + lid, last)];
+    IdxT i_cur = sp[min(lid, last)];
+    int cv_cur = code_of(i_cur);
     int lb = 0, rb = 0;
-#pragma unroll 2
     for (int j0 = 0; j0 < len; j0 += g) {
         const int j = j0 + lid;
         const bool act = j < len;
-        const IdxT i = src[start + min(j, len - 1)];
-        const int w = *(const int32_t*)(cbase + (uint32_t)i * cstride);
-        const int cv = cshift < 0 ? w : ((w << cshift) >> 16);
+        const IdxT i = i_cur;
+        const int cv = cv_cur;
+        i_cur = i_nxt;
+        cv_cur = code_of(i_nxt);
+        i_nxt = sp[min(j + 2 * g, last)];
         const bool right = act && cv > thr;
         const uint64_t bra = __ballot(right), baa = __ballot(act);
         const int rr = __popcll(bra & bel), ra = __popcll(baa & bel);
@@ -780,8 +792,17 @@ VPM_DEV void merge_subset(const FixedArgs& A, const Frame& F, IdxFn gidx, int le
     }
 }
 
-VPM_DEV float wave_max(float v) {
-    for (int m = 1; m < WAVE; m <<= 1) v = fmaxf(v, __shfl_xor(v, m));
+VPM_DEV float wave_max(float v) { return group_max(v, WAVE); }
+
+// Inclusive scan over the wavefront; `ln` is this lane's index (passed in so that the exchange
+// addresses are formed here rather than precomputed for the whole kernel).
+template <typename V>
+VPM_DEV V wave_incl_scan(V v, int ln) {
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const V o = __shfl(v, ln - d);
+        if (ln >= d) v += o;
+    }
     return v;
 }
 
@@ -810,9 +831,29 @@ VPM_DEV void facc_add(FrameAcc& a, const float q[7]) {
     }
 }
 
-VPM_DEV void facc_load(FrameAcc& a, const Soa32& in, int64_t i) {
-    const float q[7] = {in.x[i], in.y[i], in.z[i], in.px[i], in.py[i], in.pz[i], in.w[i]};
-    facc_add(a, q);
+// Reads particles off + p for p = first, first + stride, ... below n, LOAD_BATCH positions per lane at
+// a time with every load of a batch unconditional (a position past the end reads particle n - 1
+// again), so that a batch's loads are in flight together; fn(p, q, in_range) sees each of them.
+constexpr int LOAD_BATCH = 4;
+
+template <typename Fn>
+VPM_DEV void load_particles(const Soa32& in, int64_t off, int first, int n, int stride, Fn fn) {
+    for (int p0 = first; p0 < n; p0 += LOAD_BATCH * stride) {
+        float q[LOAD_BATCH][7];
+#pragma unroll
+        for (int u = 0; u < LOAD_BATCH; ++u) {
+            const int64_t i = off + min(p0 + u * stride, n - 1);
+            q[u][0] = in.x[i]; q[u][1] = in.y[i]; q[u][2] = in.z[i];
+            q[u][3] = in.px[i]; q[u][4] = in.py[i]; q[u][5] = in.pz[i]; q[u][6] = in.w[i];
+        }
+#pragma unroll
+        for (int u = 0; u < LOAD_BATCH; ++u) fn(p0 + u * stride, q[u], p0 + u * stride < n);
+    }
+}
+
+// Frame accumulation over positions first, first + stride, ... of a cell (duplicates change nothing).
+VPM_DEV void facc_cell(FrameAcc& a, const Soa32& in, int64_t off, int first, int n, int stride) {
+    load_particles(in, off, first, n, stride, [&](int, const float* q, bool) { facc_add(a, q); });
 }
 
 // The frame from the cell maxima v (identical in every lane).
@@ -834,19 +875,23 @@ VPM_DEV void frame_from(const float v[11], float mass, Frame& F) {
     F.eb = frexp_exp(4.0f * (mass + F.pmax[0] + F.pmax[1] + F.pmax[2]));
 }
 
-// Step 1 for one cell (whole wave): validate the values and build the cell frame.  Returns false
-// if some weight is not positive or some value is not finite.
-VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, float mass, Frame& F) {
-    FrameAcc acc;
-    facc_init(acc);
-#pragma unroll 2
-    for (int i = lane_id(); i < n; i += WAVE) facc_load(acc, in, off + i);
+// The frame of a cell from the accumulators of a whole wavefront.  Returns false if some weight is
+// not positive or some value is not finite.
+VPM_DEV bool frame_of_wave(FrameAcc& acc, float mass, Frame& F) {
     if (__ballot(acc.bad) != 0) return false;
 #pragma unroll
     for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
     frame_from(acc.v, mass, F);
     F.amask = __builtin_amdgcn_readfirstlane(F.amask);     // wave-uniform: scalar branches
     return true;
+}
+
+// Step 1 for one cell (whole wave): validate the values and build the cell frame.
+VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, float mass, Frame& F) {
+    FrameAcc acc;
+    facc_init(acc);
+    facc_cell(acc, in, off, lane_id(), n, WAVE);
+    return frame_of_wave(acc, mass, F);
 }
 
 // The same for a cell shared by WPB wavefronts (all threads call; the result is the same in all).
@@ -858,8 +903,7 @@ VPM_DEV bool cell_frame_block(const Soa32& in, int64_t off, int n, float mass, F
         const int wv = threadIdx.x / WAVE;
         FrameAcc acc;
         facc_init(acc);
-#pragma unroll 2
-        for (int i = threadIdx.x; i < n; i += WAVE * WPB) facc_load(acc, in, off + i);
+        facc_cell(acc, in, off, threadIdx.x, n, WAVE * WPB);
         const bool bad = __ballot(acc.bad) != 0;
 #pragma unroll
         for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
@@ -1052,10 +1096,14 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         const int c = A.queue[qi];
         const int64_t off = A.cell_off[c];
         const int n = (int)(A.cell_off[c + 1] - off);
+        // the lane and thread indices as values formed anew for each cell (see opaque_lane)
+        const int lane = opaque_lane();
+        const int tid = WPB == 1 ? lane : opaque_tid();
 
         // ---- Step 1: collect the cell, validate, frame ----
         Frame F;
-        if (!cell_frame_block<WPB>(A.in, off, n, (float)A.P.mass, F, bs)) {
+        const bool valid = cell_frame_block<WPB>(A.in, off, n, (float)A.P.mass, F, bs);
+        if (!valid) {
             if (tid == 0) {
                 atomicOr(A.flags, FLAG_BAD_VALUE);
                 if (A.mode == 0) { A.out_count[c] = n; A.cell_mode[c] = CELL_UNTOUCHED; }
@@ -1074,12 +1122,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         fsums_zero(R);
         bool oob = false;
         auto encode = [&](int i, const float* q) { encode_particle(M, A.P, F, i, q, R, oob); };
-#pragma unroll 2
-        for (int i = tid; i < n; i += NT) {
-            const float q[7] = {A.in.x[off + i], A.in.y[off + i], A.in.z[off + i], A.in.px[off + i],
-                                A.in.py[off + i], A.in.pz[off + i], A.in.w[off + i]};
-            encode(i, q);
-        }
+        load_particles(A.in, off, tid, n, NT, [&](int i, const float* q, bool ok) { if (ok) encode(i, q); });
         const bool any_oob = __ballot(oob) != 0;
         fsums_group_reduce(R, WAVE);
         if constexpr (WPB > 1) {
@@ -1128,10 +1171,11 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             const Sched s = schedule<WPB, IdxT>(M, M.emit, m, A.P.ppl_shift, [&](int it) { return (int)curl[it].len; });
             for (int r0 = wv * WAVE; r0 < s.total; r0 += NT) {
                 int slot, cls;
-                if (sched_lookup(s, r0 + lane, slot, cls)) {
+                const int ln = opaque_lane();
+                if (sched_lookup(s, r0 + ln, slot, cls)) {
                     const Node<IdxT> nd = curl[M.emit[slot]];
                     const int g = 1 << cls;
-                    split_node<IdxT>(M, A, F, nullptr, nd, cur, lane & (g - 1), g, lane & ~(g - 1), nextl);
+                    split_node<IdxT>(M, A, F, nullptr, nd, cur, ln & (g - 1), g, ln & ~(g - 1), nextl);
                 }
             }
             cell_sync<WPB>();
@@ -1151,11 +1195,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
             loc += ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
         }
-        int64_t inc = loc;
-        for (int d = 1; d < WAVE; d <<= 1) {
-            const int64_t o = __shfl_up(inc, d);
-            if (lane >= d) inc += o;
-        }
+        const int64_t inc = wave_incl_scan(loc, lane);
         int64_t tot, wbase = 0;
         if constexpr (WPB > 1) {
             if (lane == WAVE - 1) bs->scan[wv] = inc;
@@ -1280,7 +1320,7 @@ VPM_DEV void small_root(const CellMem<uint16_t>& M, const FixedArgs& A, SmallSha
     const uint64_t gm = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << gbase;
     FrameAcc acc;
     facc_init(acc);
-    for (int p = lid; p < n; p += g) facc_load(acc, A.in, off + p);
+    facc_cell(acc, A.in, off, lid, n, g);
     if ((__ballot(acc.bad) & gm) != 0) {
         if (lid == 0) ss.cflags[j] = FLAG_BAD_VALUE;
         for (int p = lid; p < n; p += g) M.info[b + p] = INF_SKIP;
@@ -1294,11 +1334,9 @@ VPM_DEV void small_root(const CellMem<uint16_t>& M, const FixedArgs& A, SmallSha
     FSums R;
     fsums_zero(R);
     bool oob = false;
-    for (int p = lid; p < n; p += g) {
-        const int64_t i = off + p;
-        const float q[7] = {A.in.x[i], A.in.y[i], A.in.z[i], A.in.px[i], A.in.py[i], A.in.pz[i], A.in.w[i]};
-        encode_particle(M, A.P, F, b + p, q, R, oob);
-    }
+    load_particles(A.in, off, lid, n, g, [&](int p, const float* q, bool ok) {
+        if (ok) encode_particle(M, A.P, F, b + p, q, R, oob);
+    });
     fsums_group_reduce(R, g);
     if ((__ballot(oob) & gm) != 0 && lid == 0) atomicOr(&ss.cflags[j], FLAG_OUT_OF_CELL);
     wave_fence();
