@@ -372,7 +372,6 @@ struct CellMem {
     IdxT *idx0, *idx1;
     uint8_t* info;
     IdxT* emit;                    // output slot per position; schedule table while splitting
-    IdxT* dummy;                   // a slot no reader uses (emit[nmax]): target of masked-off stores
     Node<IdxT> *nodes0, *nodes1;   // current / next level (leaf tables at the end)
 };
 
@@ -399,7 +398,6 @@ VPM_DEV CellMem<IdxT> carve(uint8_t* base, int nmax) {
     M.idx0 = (IdxT*)take((size_t)nmax * sizeof(IdxT));
     M.idx1 = (IdxT*)take((size_t)nmax * sizeof(IdxT));
     M.emit = (IdxT*)take(((size_t)nmax + 1) * sizeof(IdxT));
-    M.dummy = M.emit + nmax;
     M.info = (uint8_t*)take((size_t)nmax);
     return M;
 }
@@ -478,16 +476,31 @@ VPM_DEV Sched schedule(const CellMem<IdxT>& M, IdxT* sched, int m, int ppl_shift
     for (int it = tid; it < m; it += WAVE * WPB) atomicAdd(&M.sh->cls_cnt[group_class_for(len_of(it), ppl_shift)], 1);
     cell_sync<WPB>();
     Sched s;
-    int l = 0, f = 0;
+    int l = 0, f = 0, top = 0;
 #pragma unroll
     for (int c = 6; c >= 0; --c) {
         s.cnt[c] = M.sh->cls_cnt[c];
         s.lb[c] = l; s.fb[c] = f;
         l += s.cnt[c] << c; f += s.cnt[c];
+        if (top == 0 && s.cnt[c] != 0) top = c;
     }
     s.total = l;
+    // When the groups fill at most half of the cell's lanes, every group is widened by 2^bump (up
+    // to a wavefront) while they still fit: fewer trips per lane, the same result.
+    int bump = 0;
+    while (bump < 6 - top && (l << (bump + 1)) <= WAVE * WPB) ++bump;
+    if (bump > 0) {
+        l = 0; f = 0;
+#pragma unroll
+        for (int c = 6; c >= 0; --c) {
+            s.cnt[c] = c >= bump ? M.sh->cls_cnt[c - bump] : 0;
+            s.lb[c] = l; s.fb[c] = f;
+            l += s.cnt[c] << c; f += s.cnt[c];
+        }
+        s.total = l;
+    }
     for (int it = tid; it < m; it += WAVE * WPB) {
-        const int c = group_class_for(len_of(it), ppl_shift);
+        const int c = group_class_for(len_of(it), ppl_shift) + bump;
         const int r = atomicAdd(&M.sh->cls_cur[c], 1);
         int fbc = s.fb[0];
 #pragma unroll
@@ -524,9 +537,9 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     IdxT* dst = idx_buf(M, cur ^ 1);
 
     // Step 6 as one stable pass: the lower side V1 = {c <= thr} fills the range from the front in
-    // slot order, V2 from the back in reverse slot order (so V2's member order flips).  The body is
-    // branch-free: past the end of the subset a lane reads the last slot again and stores to the
-    // dummy slot; ranks come from the wave ballots restricted to the lane's group.
+    // slot order, V2 from the back in reverse slot order (so V2's member order flips).  Past the end
+    // of the subset a lane reads the last slot again and stores nothing; ranks come from the wave
+    // ballots restricted to the lane's group.
     const uint64_t gmask = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << gbase;
     const uint64_t bel = lanes_below_of(gbase + lid) & gmask;  // group lanes below this one
     // the axis-k code of particle i is one aligned 32-bit load: a word of rec[i] (x: its upper half,
@@ -556,13 +569,14 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
         i_cur = i_nxt;
         cv_cur = code_of(i_nxt);
         i_nxt = sp[min(j + 2 * g, last)];
-        const bool right = act && cv > thr;
-        const uint64_t bra = __ballot(right), baa = __ballot(act);
-        const int rr = __popcll(bra & bel), ra = __popcll(baa & bel);
-        const int d = right ? len - 1 - (rb + rr) : lb + (ra - rr);
-        *(act ? dst + start + d : M.dummy) = i;
-        const int nr = __popcll(bra & gmask), na = __popcll(baa & gmask);
-        lb += na - nr;
+        // the active lanes of a group are a prefix of it: an active lane has lid active lanes
+        // below it in the group, and the group has min(g, len - j0) active lanes
+        const bool right = cv > thr;
+        const uint64_t bra = __ballot(act && right);
+        const int rr = __popcll(bra & bel);
+        if (act) dst[start + (right ? len - 1 - (rb + rr) : lb + (lid - rr))] = i;
+        const int nr = __popcll(bra & gmask);
+        lb += min(g, len - j0) - nr;
         rb += nr;
     }
     wave_fence();
