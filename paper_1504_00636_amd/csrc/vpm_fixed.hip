@@ -88,6 +88,32 @@ VPM_DEV void fsums_step(FSums& S) {
     for (int l = 0; l < 6; ++l) { S.s1[l] += xchg<M>(S.s1[l]); S.s2[l] += xchg<M>(S.s2[l]); }
 }
 
+// Reduction of the two children's moments over an aligned group of g >= 2 lanes, ending with V1's
+// totals in the even lanes and V2's in the odd lanes, in L.  The first step trades the other
+// child's partials between the lanes of a pair; the later steps pair lanes of equal parity (exact
+// xor partners), so they reduce one set of moments instead of two.
+VPM_DEV void fsums_pair_reduce(FSums& L, const FSums& R, int lid, int g) {
+    const bool odd = lid & 1;
+    auto first = [&](double& l, double r) {
+        const double send = odd ? l : r;
+        l = (odd ? r : l) + xchg<1>(send);
+    };
+    first(L.s0, R.s0);
+#pragma unroll
+    for (int l = 0; l < 6; ++l) { first(L.s1[l], R.s1[l]); first(L.s2[l], R.s2[l]); }
+    auto step = [&](auto m) {
+        constexpr int M = decltype(m)::value;
+        L.s0 += xor_dbl<M>(L.s0);
+#pragma unroll
+        for (int l = 0; l < 6; ++l) { L.s1[l] += xor_dbl<M>(L.s1[l]); L.s2[l] += xor_dbl<M>(L.s2[l]); }
+    };
+    if (g > 2) step(std::integral_constant<int, 2>());
+    if (g > 4) step(std::integral_constant<int, 4>());
+    if (g > 8) step(std::integral_constant<int, 8>());
+    if (g > 16) step(std::integral_constant<int, 16>());
+    if (g > 32) step(std::integral_constant<int, 32>());
+}
+
 VPM_DEV void fsums_group_reduce(FSums& S, int g) {
     if (g > 1) fsums_step<1>(S);
     if (g > 2) fsums_step<2>(S);
@@ -607,21 +633,14 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
             codes_of(M, dst[start + n1 + j], c, om);
             fsums_add(R, om, c[0], c[1], c[2], c[3], c[4], c[5]);
         }
-        fsums_group_reduce(L, g);
-        fsums_group_reduce(R, g);
-        // lane 0 of the group decides V1 and lane 1 decides V2 (a single lane decides both in turn)
+        // lane 0 of the group decides V1 and lane 1 decides V2; a single lane decides both in turn
+        if (g > 1) fsums_pair_reduce(L, R, lid, g);
         int mine0 = 0, mine1 = 0;
-        for (int ch = 0; ch < (g == 1 ? 2 : 1); ++ch) {
-            const bool left = g == 1 ? ch == 0 : lid == 0;
-            if (g == 1 || lid < 2) {
-                FSums C;
-                C.s0 = left ? L.s0 : R.s0;
-#pragma unroll
-                for (int l = 0; l < 6; ++l) { C.s1[l] = left ? L.s1[l] : R.s1[l]; C.s2[l] = left ? L.s2[l] : R.s2[l]; }
-                const int v = pack_decision(decide(M, C, dst, left ? start : start + n1, left ? n1 : n2, A.P, F));
-                if (ch == 0) mine0 = v; else mine1 = v;
-            }
+        if (g == 1 || lid < 2) {
+            const bool second = g > 1 && lid == 1;
+            mine0 = pack_decision(decide(M, L, dst, second ? start + n1 : start, second ? n2 : n1, A.P, F));
         }
+        if (g == 1) mine1 = pack_decision(decide(M, R, dst, start + n1, n2, A.P, F));
         if (g == 1) {
             dv0 = mine0;
             dv1 = mine1;
