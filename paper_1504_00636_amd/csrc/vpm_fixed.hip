@@ -248,8 +248,9 @@ VPM_DEV Decision decide_exact(const ISums& S, const FixedParams& P, const Frame&
 
 // The same rule evaluated in floating point with error bounds.  Sets ok = false when a comparison
 // cannot be certified (the caller then applies the exact rule).
-//   V = S0 S2 - S1^2 in FP64 (S0, S1 exact; the FMA removes the rounding of S1^2):
-//       |V_fp64 - V| <= EV = fl(S0 S2) (len + 16) 2^-51   (S2 rounded over at most len + 6 operations)
+//   V = S0 S2 - S1^2 in FP64 (S0, S1 exact): S2 is rounded over at most len + 6 operations, the FMA
+//   and the rounding of S1^2 add at most 2 ulp of S0 S2 (S1^2 <= S0 S2), so
+//       |V_fp64 - V| <= S0 S2 (len + 9) 2^-53 < EV = S2 fl(S0 (len + 16) 2^-51)
 //   Both Step 3 and Step 4 compare Delta_l^2 = V_l / D_l: Step 3 against tau^2 = (T^ / 2^24)^2 (given as
 //   an FP32 bracket), Step 4 against the other axes.  Delta_l^2 is bracketed in FP32 from [V - EV,
 //   V + EV] (conversions, a 1-ulp reciprocal and the products stay below 2^-21 relative; the
@@ -262,7 +263,7 @@ VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, cons
     ok = true;
     const double s0 = S.s0;
     if (s0 == 0.0) { d.kind = D_MERGED; d.jdir = pair_axis(S.s1, F); return d; }
-    const double slack = (double)(len + 16) * 0x1p-51;
+    const double s0slack = s0 * ((double)(len + 16) * 0x1p-51);
     const float rdx = __builtin_amdgcn_rcpf((float)(s0 * s0 * 0x1p32));
     const float rdx_lo = rdx * (1.0f - 0x1p-19f), rdx_hi = rdx * (1.0f + 0x1p-19f);
     float lo[6], hi[6];
@@ -274,9 +275,8 @@ VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, cons
         if (!((amask >> l) & 1)) continue;            // wave-uniform
         const double s1 = S.s1[l], s2 = S.s2[l];
         const double bh = s1 * s1;
-        const double bl = fma(s1, s1, -bh);
-        const double V = fma(s0, s2, -bh) - bl;
-        const double EV = s0 * s2 * slack;
+        const double V = fma(s0, s2, -bh);
+        const double EV = s2 * s0slack;
         const double vlo = V - EV, vhi = V + EV;
         float rlo, rhi;
         if (l < 3) {
@@ -538,14 +538,20 @@ VPM_DEV Sched schedule(const CellMem<IdxT>& M, IdxT* sched, int m, int ppl_shift
 }
 
 // Virtual lane v -> (item slot, class).  Returns false if v is past the last group.
+// The classes' lane ranges follow each other from class 6 (at 0) down to class 0, so v lies in the
+// lowest class whose range starts at or before v (an empty class starts where the next one does).
 VPM_DEV bool sched_lookup(const Sched& s, int v, int& slot, int& cls) {
     if (v >= s.total) return false;
-    cls = 0;
-    slot = 0;
+    int c0 = 6, lbv = 0, fbv = 0;
 #pragma unroll
-    for (int c = 6; c >= 0; --c) {
-        if (v >= s.lb[c] && v < s.lb[c] + (s.cnt[c] << c)) { cls = c; slot = s.fb[c] + ((v - s.lb[c]) >> c); }
+    for (int c = 5; c >= 0; --c) {
+        const bool in = v >= s.lb[c];
+        c0 = in ? c : c0;
+        lbv = in ? s.lb[c] : lbv;
+        fbv = in ? s.fb[c] : fbv;
     }
+    cls = c0;
+    slot = fbv + ((v - lbv) >> c0);
     return true;
 }
 
@@ -688,25 +694,27 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
 // first + stride, ... below end, slot(p, src, dst) gives the input index and the staging slot, or
 // dst < 0 for nothing (src must then still be a valid input index).  The loads of CB positions are
 // all issued before their stores: the two arrays never overlap, but the compiler cannot know that
-// and would otherwise wait for every load before the next store.  Positions past the end reload the
-// batch's first particle and store nothing.
+// and would otherwise wait for every load before the next store.  The slots are looked up without
+// branches (positions past the end look up the last one and store nothing), so that no branch
+// separates the loads of a batch.
 constexpr int COPY_BATCH = 4;          // particles per lane whose loads are in flight together
 
 template <int CB, typename SlotFn>
 VPM_DEV void copy_particles(const Soa32& in, const Soa32Out& out, int first, int end, int stride, SlotFn slot) {
     for (int p0 = first; p0 < end; p0 += CB * stride) {
-        float v[CB][7];
-        int64_t so[CB];
-        int64_t si0 = 0;
+        int64_t si[CB], so[CB];
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
             const int p = p0 + u * stride;
-            int64_t si = si0;
-            so[u] = -1;
-            if (u == 0 || p < end) slot(p, si, so[u]);
-            if (u == 0) si0 = si;
-            v[u][0] = in.x[si]; v[u][1] = in.y[si]; v[u][2] = in.z[si];
-            v[u][3] = in.px[si]; v[u][4] = in.py[si]; v[u][5] = in.pz[si]; v[u][6] = in.w[si];
+            slot(min(p, end - 1), si[u], so[u]);
+            if (p >= end) so[u] = -1;
+        }
+        float v[CB][7];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            const int64_t i = si[u];
+            v[u][0] = in.x[i]; v[u][1] = in.y[i]; v[u][2] = in.z[i];
+            v[u][3] = in.px[i]; v[u][4] = in.py[i]; v[u][5] = in.pz[i]; v[u][6] = in.w[i];
         }
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
