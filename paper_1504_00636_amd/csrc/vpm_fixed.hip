@@ -332,9 +332,7 @@ VPM_DEV Decision unpack_decision(int v) {
 // at most one wavefront.
 VPM_DEV int group_class_for(int len, int ppl_shift) {
     const int want = (len + (1 << ppl_shift) - 1) >> ppl_shift;
-    int c = 0;
-    while ((1 << c) < want && c < 6) ++c;
-    return c;
+    return want <= 1 ? 0 : min(32 - __clz(want - 1), 6);        // ceil(log2(want)), at most 6
 }
 
 VPM_DEV void wave_fence() {
@@ -573,7 +571,6 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     // of the subset a lane reads the last slot again and stores nothing; ranks come from the wave
     // ballots restricted to the lane's group.
     const uint64_t gmask = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << gbase;
-    const uint64_t bel = lanes_below_of(gbase + lid) & gmask;  // group lanes below this one
     // the axis-k code of particle i is one aligned 32-bit load: a word of rec[i] (x: its upper half,
     // momenta: whole words) or pyz[i] (y: lower half, z: upper half), then half-selected and
     // sign-extended for the int16 position codes
@@ -604,10 +601,10 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
         // the active lanes of a group are a prefix of it: an active lane has lid active lanes
         // below it in the group, and the group has min(g, len - j0) active lanes
         const bool right = cv > thr;
-        const uint64_t bra = __ballot(act && right);
-        const int rr = __popcll(bra & bel);
+        const uint64_t bra = __ballot(act && right) & gmask;            // this group's lanes only
+        const int rr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bra >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bra, 0u));
         if (act) dst[start + (right ? len - 1 - (rb + rr) : lb + (lid - rr))] = i;
-        const int nr = __popcll(bra & gmask);
+        const int nr = __popcll(bra);
         lb += min(g, len - j0) - nr;
         rb += nr;
     }
