@@ -556,7 +556,7 @@ VPM_DEV bool sched_lookup(const Sched& s, int v, int& slot, int& cls) {
 // Process one unfinished subset with a lane group: compaction, child moments, child decisions.
 template <typename IdxT>
 VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F0, const Frame* frames, Node<IdxT> nd,
-                        int cur, int lid, int g, int gbase, Node<IdxT>* next) {
+                        int cur, int lid, int g, int gbase, Node<IdxT>* next, bool solo) {
     const int start = nd.start, len = nd.len;
     const int k = nd.thr_axis & 7;
     const int rev = (nd.thr_axis >> 3) & 1;
@@ -590,6 +590,20 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     IdxT i_cur = sp[min(lid, last)];
     int cv_cur = code_of(i_cur);
     int lb = 0, rb = 0;
+    if (solo) {
+        // every group of the round is a single lane (a wave-uniform fact): no ranks to exchange
+        for (int j = 0; j < len; ++j) {
+            const IdxT i = i_cur;
+            const int cv = cv_cur;
+            i_cur = i_nxt;
+            cv_cur = code_of(i_nxt);
+            i_nxt = sp[min(j + 2, last)];
+            const bool right = cv > thr;
+            dst[start + (right ? last - rb : lb)] = i;
+            rb += right ? 1 : 0;
+            lb += right ? 0 : 1;
+        }
+    } else
     for (int j0 = 0; j0 < len; j0 += g) {
         const int j = j0 + lid;
         const bool act = j < len;
@@ -1207,13 +1221,14 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             Node<IdxT>* nextl = cur ? M.nodes0 : M.nodes1;
             if (tid == 0) sh.nnext = 0;
             const Sched s = schedule<WPB, IdxT>(M, M.emit, m, A.P.ppl_shift, [&](int it) { return (int)curl[it].len; });
+            const bool solo = __builtin_amdgcn_readfirstlane(s.total == s.cnt[0] ? 1 : 0) != 0;   // only 1-lane groups
             for (int r0 = wv * WAVE; r0 < s.total; r0 += NT) {
                 int slot, cls;
                 const int ln = opaque_lane();
                 if (sched_lookup(s, r0 + ln, slot, cls)) {
                     const Node<IdxT> nd = curl[M.emit[slot]];
                     const int g = 1 << cls;
-                    split_node<IdxT>(M, A, F, nullptr, nd, cur, ln & (g - 1), g, ln & ~(g - 1), nextl);
+                    split_node<IdxT>(M, A, F, nullptr, nd, cur, ln & (g - 1), g, ln & ~(g - 1), nextl, solo);
                 }
             }
             cell_sync<WPB>();
@@ -1468,12 +1483,13 @@ __global__ __launch_bounds__(WAVE, 2) void k_fixed_small(FixedArgs A) {
             Node<IdxT>* nextl = cur ? M.nodes0 : M.nodes1;
             if (lane == 0) sh.nnext = 0;
             const Sched s = schedule<1, IdxT>(M, M.emit, m, A.P.ppl_shift, [&](int it) { return (int)curl[it].len; });
+            const bool solo = __builtin_amdgcn_readfirstlane(s.total == s.cnt[0] ? 1 : 0) != 0;   // only 1-lane groups
             for (int r0 = 0; r0 < s.total; r0 += WAVE) {
                 int slot, cls;
                 if (sched_lookup(s, r0 + lane, slot, cls)) {
                     const Node<IdxT> nd = curl[M.emit[slot]];
                     const int g = 1 << cls;
-                    split_node<IdxT>(M, A, ss.frame[0], ss.frame, nd, cur, lane & (g - 1), g, lane & ~(g - 1), nextl);
+                    split_node<IdxT>(M, A, ss.frame[0], ss.frame, nd, cur, lane & (g - 1), g, lane & ~(g - 1), nextl, solo);
                 }
             }
             wave_fence();
