@@ -124,25 +124,18 @@ VPM_DEV int xchg32(int v) {
     else return __shfl_xor(v, 32);
 }
 
-// Partner value at lane l ^ M exactly (M = 1, 2, 4, 8): quad permutes for 1 and 2; for 4 and 8 two
-// row shifts, each written only to the 4-lane banks whose partner lies on that side.
+// Partner value at lane l ^ M exactly (M = 1 ... 16): a swizzle in xor mode (the LDS unit's
+// crossbar, no VALU move; the kernels are bound by VALU issue).
 template <int M>
 VPM_DEV int xor32(int v) {
-    if constexpr (M == 1 || M == 2) return xchg32<M>(v);
-    else if constexpr (M == 4) {
-        const int t = __builtin_amdgcn_update_dpp(v, v, 0x104, 0xF, 0x5, false);    // row_shl:4 into banks 0, 2
-        return __builtin_amdgcn_update_dpp(t, v, 0x114, 0xF, 0xA, false);          // row_shr:4 into banks 1, 3
-    } else {
-        static_assert(M == 8, "exact xor partners for steps 1-8; 16 and 32 are exact in xchg32");
-        const int t = __builtin_amdgcn_update_dpp(v, v, 0x108, 0xF, 0x3, false);    // row_shl:8 into lanes 0-7
-        return __builtin_amdgcn_update_dpp(t, v, 0x118, 0xF, 0xC, false);          // row_shr:8 into lanes 8-15
-    }
+    static_assert(M >= 1 && M <= 16, "ds_swizzle exchanges within 32 lanes");
+    return __builtin_amdgcn_ds_swizzle(v, (M << 10) | 0x1F);       // and 0x1F, or 0, xor M
 }
 template <int M>
 VPM_DEV double xor_dbl(double v) {
     const int64_t u = __double_as_longlong(v);
     auto x = [](int w) {
-        if constexpr (M >= 16) return xchg32<M>(w);
+        if constexpr (M >= 32) return xchg32<M>(w);
         else return xor32<M>(w);
     };
     const int lo = x((int)(uint32_t)u), hi = x((int)((uint64_t)u >> 32));
