@@ -250,14 +250,17 @@ VPM_DEV Decision decide_exact(const ISums& S, const FixedParams& P, const Frame&
 // cannot be certified (the caller then applies the exact rule).
 //   V = S0 S2 - S1^2 in FP64 (S0, S1 exact): S2 is rounded over at most len + 6 operations, the FMA
 //   and the rounding of S1^2 add at most 2 ulp of S0 S2 (S1^2 <= S0 S2), so
-//       |V_fp64 - V| <= S0 S2 (len + 9) 2^-53 < EV = S2 fl(S0 (len + 16) 2^-51)
+//       |V_fp64 - V| <= S0 S2 (len + 9) 2^-53 < EV = S2 fl(S0 (len + 16) 2^-51).
+//   When S2 comes with its own error bound e2 (moments formed as a parent's minus a sibling's),
+//       |V_fp64 - V| <= S0 (e2 + |S2| 2^-52) (1 + 2^-52) < EV = S0 (e2 + |S2| 2^-51) (1 + 2^-40).
 //   Both Step 3 and Step 4 compare Delta_l^2 = V_l / D_l: Step 3 against tau^2 = (T^ / 2^24)^2 (given as
 //   an FP32 bracket), Step 4 against the other axes.  Delta_l^2 is bracketed in FP32 from [V - EV,
 //   V + EV] (conversions, a 1-ulp reciprocal and the products stay below 2^-21 relative; the
 //   bracket is widened by 2^-19).  A subtraction of two floats has the sign of the exact difference,
 //   so the maxima below decide the comparisons exactly.
 // `amask` has bit l set for the axes whose codes vary in the cell; the others have V = 0.
-VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, const Frame& F, int amask, bool& ok) {
+VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, const Frame& F, int amask, bool& ok,
+                             const double* e2 = nullptr) {
     Decision d;
     d.axis = 0; d.thr = 0; d.jdir = 0;
     ok = true;
@@ -276,7 +279,7 @@ VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, cons
         const double s1 = S.s1[l], s2 = S.s2[l];
         const double bh = s1 * s1;
         const double V = fma(s0, s2, -bh);
-        const double EV = s2 * s0slack;
+        const double EV = e2 ? s0 * (e2[l] + fabs(s2) * 0x1p-51) * (1.0 + 0x1p-40) : s2 * s0slack;
         const double vlo = V - EV, vhi = V + EV;
         float rlo, rhi;
         if (l < 3) {
@@ -460,11 +463,11 @@ VPM_DEV void codes_of(const CellMem<IdxT>& M, int i, int c[6], int& om) {
 // exact integer moments recomputed from the codes when the FP64 evaluation is inconclusive.
 template <typename IdxT>
 VPM_DEV Decision decide(const CellMem<IdxT>& M, const FSums& S, const IdxT* buf, int start, int len,
-                        const FixedParams& P, const Frame& F) {
+                        const FixedParams& P, const Frame& F, const double* e2 = nullptr) {
     Decision d;
     if (len < P.min_subset) { d.kind = D_COPY; d.axis = 0; d.thr = 0; d.jdir = 0; return d; }
     bool ok;
-    d = decide_fast(S, len, P, F, F.amask, ok);
+    d = decide_fast(S, len, P, F, F.amask, ok, e2);
     if (ok) return d;
     ISums E;
     E.s0 = 0;
@@ -553,16 +556,13 @@ VPM_DEV bool sched_lookup(const Sched& s, int v, int& slot, int& cls) {
     return true;
 }
 
-// Process one unfinished subset with a lane group: compaction, child moments, child decisions.
+// Step 6 for one unfinished subset with a lane group: its members split into V1 (front of the slot
+// range) and V2 (back); returns |V1|.  solo: every group of the round is a single lane.
 template <typename IdxT>
-VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F0, const Frame* frames, Node<IdxT> nd,
-                        int cur, int lid, int g, int gbase, Node<IdxT>* next, bool solo) {
+VPM_DEV int compact_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int lid, int g, int gbase, bool solo) {
     const int start = nd.start, len = nd.len;
     const int k = nd.thr_axis & 7;
-    const int rev = (nd.thr_axis >> 3) & 1;
-    const int cell = (nd.thr_axis >> 4) & 15;
     const int thr = nd.thr_axis >> 8;
-    const Frame& F = frames ? frames[cell] : F0;            // the frame of the subset's cell
     const IdxT* src = idx_buf(M, cur);
     IdxT* dst = idx_buf(M, cur ^ 1);
 
@@ -623,7 +623,39 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
         rb += nr;
     }
     wave_fence();
-    const int nl = lb;
+    return lb;
+
+}
+
+// A final subset [cs, cs + cl) of the new slot order: its flags for the output, and its members put
+// back into increasing input order where that order is observable (copied particles, or the
+// partition output).  Lanes lid < g of its group take part.
+template <typename IdxT>
+VPM_DEV void record_final(const CellMem<IdxT>& M, const FixedArgs& A, const Decision& d, int cs, int cl, int crev,
+                          int cur, int lid, int g) {
+    IdxT* dst = idx_buf(M, cur ^ 1);
+    if (crev && (d.kind == D_COPY || A.mode == 1)) {
+        for (int j = lid; j < cl / 2; j += g) {
+            const IdxT a = dst[cs + j], b = dst[cs + cl - 1 - j];
+            dst[cs + j] = b;
+            dst[cs + cl - 1 - j] = a;
+        }
+    }
+    const uint8_t base = INF_SET | (uint8_t)((cur ^ 1) & 1) | (d.kind == D_MERGED ? INF_MERGED : 0) |
+                         (uint8_t)(d.jdir << INF_JSHIFT);
+    for (int j = lid; j < cl; j += g) M.info[cs + j] = base | (j == 0 ? INF_HEAD : 0);
+}
+
+// Process one unfinished subset with a lane group: compaction, child moments, child decisions.
+template <typename IdxT>
+VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F0, const Frame* frames, Node<IdxT> nd,
+                        int cur, int lid, int g, int gbase, Node<IdxT>* next, bool solo) {
+    const int start = nd.start, len = nd.len;
+    const int rev = (nd.thr_axis >> 3) & 1;
+    const int cell = (nd.thr_axis >> 4) & 15;
+    const Frame& F = frames ? frames[cell] : F0;            // the frame of the subset's cell
+    IdxT* dst = idx_buf(M, cur ^ 1);
+    const int nl = compact_node(M, nd, cur, lid, g, gbase, solo);
 
     const int n1 = nl, n2 = len - nl;
     int dv0, dv1;
@@ -684,21 +716,118 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
                 next[slot] = c;
             }
         } else {
-            // a final subset whose member order is observable (copied particles, or the partition
-            // output) is put back into increasing input order
-            if (crev && (d.kind == D_COPY || A.mode == 1)) {
-                for (int j = lid; j < cl / 2; j += g) {
-                    const IdxT a = dst[cs + j], b = dst[cs + cl - 1 - j];
-                    dst[cs + j] = b;
-                    dst[cs + cl - 1 - j] = a;
-                }
-            }
-            const uint8_t base = INF_SET | (uint8_t)((cur ^ 1) & 1) |
-                                 (d.kind == D_MERGED ? INF_MERGED : 0) |
-                                 (uint8_t)(d.jdir << INF_JSHIFT);
-            for (int j = lid; j < cl; j += g) M.info[cs + j] = base | (j == 0 ? INF_HEAD : 0);
+            record_final(M, A, d, cs, cl, crev, cur, lid, g);
         }
     }
+}
+
+// Top levels without a scheduler.  Each unfinished subset owns an aligned group of g = 64 >> depth
+// lanes that already hold its moments (and a bound e2 on the rounding error of its S2 sums): V1
+// goes to the lower half of the group and V2 to the upper half, which then hold its moments.  Only
+// the smaller child is summed; the other child's moments are the parent's minus these (S0 and S1
+// exactly, S2 with its error bound carried along).
+template <typename IdxT>
+VPM_DEV void split_inherit(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, Node<IdxT>& nd, bool& act,
+                           FSums& P, double (&E2)[6], int cur, int lid, int g, int gbase) {
+    const int start = nd.start, len = nd.len;
+    const int rev = (nd.thr_axis >> 3) & 1;
+    IdxT* dst = idx_buf(M, cur ^ 1);
+    const int n1 = compact_node(M, nd, cur, lid, g, gbase, false);
+    const int n2 = len - n1;
+    act = false;
+    if (n1 == 0 || n2 == 0) {
+        // impossible under the exact rule (the chosen axis has V > 0); end the subset
+        if (lid == 0) atomicOr(&M.sh->flags, FLAG_INTERNAL);
+        Decision d; d.kind = D_MERGED; d.axis = 0; d.thr = 0; d.jdir = 0;
+        record_final(M, A, d, start, len, n1 == 0 ? rev ^ 1 : rev, cur, lid, g);
+        return;
+    }
+    const bool s_first = n1 <= n2;                       // V1 is the smaller child
+    const int ss = s_first ? start : start + n1, sl = s_first ? n1 : n2, ol = len - sl;
+    FSums S;
+    fsums_zero(S);
+    if (ol >= A.P.min_subset) {                           // else both children are copied
+#pragma unroll 2
+        for (int j = lid; j < sl; j += g) {
+            int c[6], om;
+            codes_of(M, dst[ss + j], c, om);
+            fsums_add(S, om, c[0], c[1], c[2], c[3], c[4], c[5]);
+        }
+        fsums_group_reduce(S, g);
+    }
+    double eS[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) eS[l] = S.s2[l] * ((double)(sl + 16) * 0x1p-51);
+    // the other child's moments and their S2 error bound
+    auto other = [&](FSums& O, double (&eO)[6]) {
+        O.s0 = P.s0 - S.s0;
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+            O.s1[l] = P.s1[l] - S.s1[l];
+            O.s2[l] = P.s2[l] - S.s2[l];
+            eO[l] = (E2[l] + eS[l] + fabs(O.s2[l]) * 0x1p-52) * (1.0 + 0x1p-40);
+        }
+    };
+    const int h = g >> 1;
+    const bool upper = lid >= h;                          // this lane's child: V2 if upper, else V1
+    const bool mine_s = upper != s_first;
+    // this lane's child's moments replace the parent's (P, E2), also for the next level
+    {
+        FSums O;
+        double eO[6];
+        other(O, eO);
+        P.s0 = mine_s ? S.s0 : O.s0;
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+            P.s1[l] = mine_s ? S.s1[l] : O.s1[l];
+            P.s2[l] = mine_s ? S.s2[l] : O.s2[l];
+            E2[l] = mine_s ? eS[l] : eO[l];
+        }
+    }
+    const int cs = upper ? start + n1 : start, cl = upper ? n2 : n1;
+    int mine = 0;
+    if ((lid & (h - 1)) == 0) mine = pack_decision(decide(M, P, dst, cs, cl, A.P, F, E2));
+    const Decision d = unpack_decision(__shfl(mine, gbase + (upper ? h : 0)));
+    const int crev = upper ? rev ^ 1 : rev;
+    if (d.kind == D_SPLIT) {
+        nd.start = (IdxT)cs; nd.len = (IdxT)cl;
+        nd.thr_axis = (d.thr << 8) | (crev << 3) | d.axis;
+        act = true;
+    } else {
+        record_final(M, A, d, cs, cl, crev, cur, lid & (h - 1), h);
+    }
+}
+
+// The inherited levels of a one-wavefront cell from its root (a split, moments R over n particles)
+// down to two lanes per subset, or until some subset would need more than INHERIT_PPL particles per
+// lane; the unfinished subsets then go to the scheduled levels.  Leaves in cur / m the level and
+// the number of subsets in its list.
+constexpr int INHERIT_PPL = 32;
+
+template <typename IdxT>
+VPM_DEV void inherit_levels(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, const FSums& R, int n,
+                            const Decision& rd, int lane, int& cur, int& m) {
+    Node<IdxT> nd;
+    nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 8) | rd.axis;
+    bool act = true;
+    FSums P = R;
+    double E2[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) E2[l] = R.s2[l] * ((double)(n + 16) * 0x1p-51);
+    int g = WAVE;
+    for (; g >= 2; g >>= 1) {
+        if (__ballot(act && (int)nd.len > INHERIT_PPL * g) != 0) break;
+        if (act) split_inherit(M, A, F, nd, act, P, E2, cur, lane & (g - 1), g, lane & ~(g - 1));
+        wave_fence();
+        cur ^= 1;
+    }
+    // the unfinished subsets, one per group of g lanes, to the scheduled levels
+    Node<IdxT>* list = cur ? M.nodes1 : M.nodes0;
+    const bool lead = act && (lane & (g - 1)) == 0;
+    const uint64_t b = __ballot(lead);
+    if (lead) list[__popcll(b & lanes_below_of(lane))] = nd;
+    m = __popcll(b);
+    wave_fence();
 }
 
 // Copy particles unchanged from the input to the staging arrays.  For positions p = first,
@@ -1201,7 +1330,10 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         }
         const Decision rd = unpack_decision(sh.rootv);
         int m = 0;
-        if (rd.kind == D_SPLIT) {
+        int cur = 0;
+        if (WPB == 1 && IN_LDS && rd.kind == D_SPLIT) {
+            inherit_levels<IdxT>(M, A, F, R, n, rd, lane, cur, m);
+        } else if (rd.kind == D_SPLIT) {
             if (tid == 0) {
                 Node<IdxT> nd;
                 nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 8) | rd.axis;
@@ -1215,7 +1347,6 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         cell_sync<WPB>();
 
         // ---- Steps 2-6, level by level ----
-        int cur = 0;
         while (m > 0) {
             Node<IdxT>* curl = cur ? M.nodes1 : M.nodes0;
             Node<IdxT>* nextl = cur ? M.nodes0 : M.nodes1;
