@@ -798,6 +798,61 @@ VPM_DEV void split_inherit(const CellMem<IdxT>& M, const FixedArgs& A, const Fra
     }
 }
 
+// The last inherited level: one lane per subset, which decides both children in turn and hands the
+// unfinished ones to the scheduled levels (list `next`).
+template <typename IdxT>
+VPM_DEV void split_inherit_solo(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, Node<IdxT> nd,
+                                const FSums& P, const double (&E2)[6], int cur, Node<IdxT>* next) {
+    const int start = nd.start, len = nd.len;
+    const int rev = (nd.thr_axis >> 3) & 1;
+    IdxT* dst = idx_buf(M, cur ^ 1);
+    const int n1 = compact_node(M, nd, cur, 0, 1, opaque_lane(), true);
+    const int n2 = len - n1;
+    if (n1 == 0 || n2 == 0) {
+        atomicOr(&M.sh->flags, FLAG_INTERNAL);
+        Decision d; d.kind = D_MERGED; d.axis = 0; d.thr = 0; d.jdir = 0;
+        record_final(M, A, d, start, len, n1 == 0 ? rev ^ 1 : rev, cur, 0, 1);
+        return;
+    }
+    const bool s_first = n1 <= n2;
+    const int ss = s_first ? start : start + n1, sl = s_first ? n1 : n2, ol = len - sl;
+    FSums S;
+    fsums_zero(S);
+    if (ol >= A.P.min_subset) {
+#pragma unroll 2
+        for (int j = 0; j < sl; ++j) {
+            int c[6], om;
+            codes_of(M, dst[ss + j], c, om);
+            fsums_add(S, om, c[0], c[1], c[2], c[3], c[4], c[5]);
+        }
+    }
+    FSums O;
+    double eO[6];
+    O.s0 = P.s0 - S.s0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        O.s1[l] = P.s1[l] - S.s1[l];
+        O.s2[l] = P.s2[l] - S.s2[l];
+        eO[l] = (E2[l] + S.s2[l] * ((double)(sl + 16) * 0x1p-51) + fabs(O.s2[l]) * 0x1p-52) * (1.0 + 0x1p-40);
+    }
+    const int os = s_first ? start + n1 : start;
+    const Decision dS = decide(M, S, dst, ss, sl, A.P, F);
+    const Decision dO = decide(M, O, dst, os, ol, A.P, F, eO);
+    for (int ch = 0; ch < 2; ++ch) {
+        const Decision d = (ch == 0) == s_first ? dS : dO;
+        const int cs = ch == 0 ? start : start + n1, cl = ch == 0 ? n1 : n2;
+        const int crev = ch == 0 ? rev : rev ^ 1;
+        if (d.kind == D_SPLIT) {
+            Node<IdxT> c;
+            c.start = (IdxT)cs; c.len = (IdxT)cl;
+            c.thr_axis = (d.thr << 8) | (crev << 3) | d.axis;
+            next[atomicAdd(&M.sh->nnext, 1)] = c;
+        } else {
+            record_final(M, A, d, cs, cl, crev, cur, 0, 1);
+        }
+    }
+}
+
 // The inherited levels of a one-wavefront cell from its root (a split, moments R over n particles)
 // down to two lanes per subset, or until some subset would need more than INHERIT_PPL particles per
 // lane; the unfinished subsets then go to the scheduled levels.  Leaves in cur / m the level and
@@ -820,6 +875,15 @@ VPM_DEV void inherit_levels(const CellMem<IdxT>& M, const FixedArgs& A, const Fr
         if (act) split_inherit(M, A, F, nd, act, P, E2, cur, lane & (g - 1), g, lane & ~(g - 1));
         wave_fence();
         cur ^= 1;
+    }
+    if (g == 1 && __ballot(act && (int)nd.len > INHERIT_PPL) == 0) {
+        if (lane == 0) M.sh->nnext = 0;
+        wave_fence();
+        if (act) split_inherit_solo(M, A, F, nd, P, E2, cur, cur ? M.nodes0 : M.nodes1);
+        wave_fence();
+        cur ^= 1;
+        m = M.sh->nnext;
+        return;
     }
     // the unfinished subsets, one per group of g lanes, to the scheduled levels
     Node<IdxT>* list = cur ? M.nodes1 : M.nodes0;

@@ -68,3 +68,25 @@ def test_zero_tolerances_and_large_min_subset():
     full_check(wl, dict(BASE, tol_x=0.0, tol_p=0.0, min_subset=2))
     ref = full_check(wl, dict(BASE, min_subset=5000))            # nothing is merged
     assert ref.out_total == wl.n
+
+
+def test_unbalanced_splits():
+    """Cells whose heavy particles pull the weighted mean to one side, so that splits peel off a few
+    particles at a time: some subsets keep most of the cell for several levels (the lane groups of
+    the top levels then hold far more particles than usual, and the scheduler takes over early)."""
+    r = np.random.Generator(np.random.Philox(34))
+    cells = []
+    for k in [140, 300, 520, 570]:
+        light = np.stack([0.4 * r.random(k), r.random(k), r.random(k), 1.0 + 0.01 * r.standard_normal(k),
+                          0.5 + 0.01 * r.standard_normal(k), 0.2 + 0.01 * r.standard_normal(k), np.ones(k)], axis=1)
+        h = 6
+        heavy = np.stack([0.95 - 0.05 * np.arange(h), r.random(h), r.random(h), np.full(h, 1.0), np.full(h, 0.5),
+                          np.full(h, 0.2), 2.0 ** (12 - np.arange(h))], axis=1)
+        c = np.concatenate([light, heavy])
+        r.shuffle(c)
+        cells.append(c[:k])
+    params = dict(BASE, tol_x=0.05, tol_p=0.005)
+    wl = W.from_cells(cells, params=params, dtype=np.float32)
+    for ms in (2, 4):
+        ref = full_check(wl, dict(params, min_subset=ms))
+        assert ref.stats["max_depth"].max() >= 10                  # deeper than a balanced tree
