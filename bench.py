@@ -144,32 +144,66 @@ def autotune(ctx, vpm, arrs, off, n, p):
     return best.as_dict(), dt
 
 
-def time_fixed(ctx, vpm, arrs, off, n, p, steps, warmup, profile):
-    """Time `steps` merge events of the fixed-point FP32 form; returns (ms/step, outputs, kernels)."""
+def time_fixed(ctx, vpm, arrs, off, n, p, steps, warmup, profile, graph=False):
+    """Time `steps` merge events of one form; returns (ms/step, outputs, out_off, n_out, kernels, extra).
+
+    graph: the event is captured once in a HIP graph and the timed steps replay it (the library's
+    launches have no host-side dependencies, so the graph holds the whole event); the replayed
+    output must equal an eager call's bit for bit.  profile: a separate eager pass after the timed
+    steps records every internal kernel with HIP events on the stream it runs on (never inside the
+    timed steps)."""
     import torch
     n_cells = off.numel() - 1
     out = [torch.empty_like(a) for a in arrs]
     out_off = torch.empty(n_cells + 1, dtype=torch.int64, device="cuda")
     out_total = torch.empty(1, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
+    extra = {}
     for _ in range(warmup):
         ctx.run(arrs, off, n, p, out, out_off, out_total, stream)
     torch.cuda.synchronize()
+    if graph:
+        eager = [t.clone() for t in out], out_off.clone(), int(out_total.item())
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run(arrs, off, n, p, out, out_off, out_total, stream)
+        torch.cuda.synchronize()
+        extra["eager_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / steps
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx.run(arrs, off, n, p, out, out_off, out_total)
+        for _ in range(max(warmup, 1)):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        tot = int(out_total.item())
+        same = tot == eager[2] and torch.equal(out_off, eager[1]) and all(
+            torch.equal(a[:tot].view(torch.int32), b[:tot].view(torch.int32)) for a, b in zip(out, eager[0]))
+        if not same:
+            raise RuntimeError("graph-replayed merge event differs from the eager call")
+        extra["graph_replay_equals_eager"] = True
+        del g
+    else:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run(arrs, off, n, p, out, out_off, out_total, stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+    kernels = {}
     if profile:
         ctx.profile_enable(True)
         ctx.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.run(arrs, off, n, p, out, out_off, out_total, stream)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    kernels = {}
-    if profile:
+        for _ in range(steps):
+            ctx.run(arrs, off, n, p, out, out_off, out_total, stream)
+        torch.cuda.synchronize()
         prof = ctx.profile_read(reset=True)
         ctx.profile_enable(False)
         kernels = {k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1)) for k, v in prof.items()}
-    return ms, out, out_off, int(out_total.item()), kernels
+    return ms, out, out_off, int(out_total.item()), kernels, extra
 
 
 def time_plain(ctx, vpm, wl64, prm, steps):
@@ -177,7 +211,7 @@ def time_plain(ctx, vpm, wl64, prm, steps):
     arrs64, off64 = vpm.upload(wl64)
     n = wl64.n
     p64 = vpm.make_params(decide=vpm.VPM_DECIDE_FP64, **prm)
-    ms, out64, _, n_out, _ = time_fixed(ctx, vpm, arrs64, off64, n, p64, steps, 1, False)
+    ms, out64, _, n_out, _, _ = time_fixed(ctx, vpm, arrs64, off64, n, p64, steps, 1, False)
     cons = conservation_error(arrs64, out64, n_out, prm["mass"])
     del arrs64, out64
     torch.cuda.empty_cache()
@@ -191,7 +225,7 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps):
     arrs, off = vpm.upload(wl32)
     p32 = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
     tuning, tune_s = autotune(ctx, vpm, arrs, off, n, p32)
-    ms, out, _, n_out, kernels = time_fixed(ctx, vpm, arrs, off, n, p32, steps, 2, True)
+    ms, out, _, n_out, kernels, _ = time_fixed(ctx, vpm, arrs, off, n, p32, steps, 2, True)
     rec = dict(workload=name, n_particles=n, n_cells=wl32.n_cells, ms_per_step=ms, value=n / (ms * 1e-3),
                tuning=tuning, autotune_s=tune_s,
                unit="particles/s", merge_ratio=n_out / n,
@@ -241,7 +275,7 @@ def precision_sweep(ctx, vpm, W, means, seed):
         ctx.reserve(n, wl64.n_cells)
         arrs, off = vpm.upload(wl32)
         p32 = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
-        ms32, out32, _, n_out32, _ = time_fixed(ctx, vpm, arrs, off, n, p32, 5, 1, False)
+        ms32, out32, _, n_out32, _, _ = time_fixed(ctx, vpm, arrs, off, n, p32, 5, 1, False)
         cons32 = conservation_error(arrs, out32, n_out32, prm["mass"])
         del out32
         perm = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -254,7 +288,7 @@ def precision_sweep(ctx, vpm, W, means, seed):
         # the plain FP64 form runs on the FP32-rounded particles, so both see the same input
         arrs64, off64 = vpm.upload(wl32, dtype=torch.float64)
         p64 = vpm.make_params(decide=vpm.VPM_DECIDE_FP64, **prm)
-        ms64, out64, _, n_out64, _ = time_fixed(ctx, vpm, arrs64, off64, n, p64, 1, 1, False)
+        ms64, out64, _, n_out64, _, _ = time_fixed(ctx, vpm, arrs64, off64, n, p64, 1, 1, False)
         cons64 = conservation_error(arrs64, out64, n_out64, prm["mass"])
         del out64
         ctx.partition(arrs64, off64, n, p64, perm, sid, nsub)
@@ -339,6 +373,8 @@ def main():
     ap.add_argument("--cascade-steps", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default batching configuration (profiling runs: one kernel configuration only)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of the merge event captured in a HIP graph (checked against an eager call)")
     args = ap.parse_args()
 
     if args.traffic_summary:
@@ -372,8 +408,8 @@ def main():
     else:
         tuning, tune_s = autotune(ctx, vpm, arrs32, off, n, p32)
     log(f"[bench] tuning ({tune_s:.2f}s autotune): {tuning}")
-    ms_step, out32, out_off, n_out, kernels = time_fixed(ctx, vpm, arrs32, off, n, p32, args.steps,
-                                                         args.warmup, True)
+    ms_step, out32, out_off, n_out, kernels, timing = time_fixed(ctx, vpm, arrs32, off, n, p32, args.steps,
+                                                                 args.warmup, True, graph=args.graph)
     rho = n_out / n
     flags = ctx.device_status(clear=True)
     log(f"[bench] fixed-point FP32: {ms_step:.3f} ms/step, out {n_out} (rho {rho:.4f}), flags {flags}")
@@ -451,6 +487,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": DOMINANT,
                      "kernel_avg_ms": dom["avg_ms"], "algorithmic_bytes_per_launch": bytes_dom},
         "cpu_baseline": cpu,
+        "timing": dict(mode="HIP graph replay of the whole merge event" if args.graph else
+                       "eager calls, no profiling events in the timed steps", **timing),
         "tuning": tuning,
         "autotune_s": tune_s,
         "merge_ratio": rho,
