@@ -685,11 +685,24 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
         // lane 0 of the group decides V1 and lane 1 decides V2; a single lane decides both in turn
         if (g > 1) fsums_pair_reduce(L, R, lid, g);
         int mine0 = 0, mine1 = 0;
+        const int ms = A.P.min_subset;
+        // a one-lane group decides the first child that needs a decision; a second pass runs only
+        // where both do
+        const bool pick_r = g == 1 && n1 < ms;                 // V1 is copied: decide V2 first
         if (g == 1 || lid < 2) {
-            const bool second = g > 1 && lid == 1;
-            mine0 = pack_decision(decide(M, L, dst, second ? start + n1 : start, second ? n2 : n1, A.P, F));
+            const bool second = (g > 1 && lid == 1) || pick_r;
+            FSums C;
+            C.s0 = pick_r ? R.s0 : L.s0;
+#pragma unroll
+            for (int l = 0; l < 6; ++l) { C.s1[l] = pick_r ? R.s1[l] : L.s1[l]; C.s2[l] = pick_r ? R.s2[l] : L.s2[l]; }
+            mine0 = pack_decision(decide(M, C, dst, second ? start + n1 : start, second ? n2 : n1, A.P, F));
         }
-        if (g == 1) mine1 = pack_decision(decide(M, R, dst, start + n1, n2, A.P, F));
+        if (g == 1) {
+            Decision cp; cp.kind = D_COPY; cp.axis = 0; cp.thr = 0; cp.jdir = 0;
+            if (pick_r) { mine1 = mine0; mine0 = pack_decision(cp); }
+            else if (n2 < ms) mine1 = pack_decision(cp);
+            else mine1 = pack_decision(decide(M, R, dst, start + n1, n2, A.P, F));
+        }
         if (g == 1) {
             dv0 = mine0;
             dv1 = mine1;
