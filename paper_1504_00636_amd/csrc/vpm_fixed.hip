@@ -1096,13 +1096,14 @@ constexpr int LOAD_BATCH = 4;
 
 template <typename Fn>
 VPM_DEV void load_particles(const Soa32& in, int64_t off, int first, int n, int stride, Fn fn) {
+    const float* const b[7] = {in.x + off, in.y + off, in.z + off, in.px + off, in.py + off, in.pz + off, in.w + off};
     for (int p0 = first; p0 < n; p0 += LOAD_BATCH * stride) {
         float q[LOAD_BATCH][7];
 #pragma unroll
         for (int u = 0; u < LOAD_BATCH; ++u) {
-            const int64_t i = off + min(p0 + u * stride, n - 1);
-            q[u][0] = in.x[i]; q[u][1] = in.y[i]; q[u][2] = in.z[i];
-            q[u][3] = in.px[i]; q[u][4] = in.py[i]; q[u][5] = in.pz[i]; q[u][6] = in.w[i];
+            const uint32_t i = (uint32_t)min(p0 + u * stride, n - 1);
+#pragma unroll
+            for (int f = 0; f < 7; ++f) q[u][f] = b[f][i];
         }
 #pragma unroll
         for (int u = 0; u < LOAD_BATCH; ++u) fn(p0 + u * stride, q[u], p0 + u * stride < n);
@@ -1332,7 +1333,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         if constexpr (WPB == 1) {
             if (qnext >= qend) {
                 if (lane == 0) qnext = atomicAdd(&A.counters[A.work_index], K);
-                qnext = __shfl(qnext, 0);
+                qnext = __builtin_amdgcn_readfirstlane(__shfl(qnext, 0));   // wave-uniform: scalar loads
                 qend = min(qnext + K, qlen);
             }
             qi = qnext++;
@@ -1348,7 +1349,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
                 sh.nnext = 0;
             }
             __syncthreads();
-            qi = sh.qi;
+            qi = __builtin_amdgcn_readfirstlane(sh.qi);
         }
         if (qi >= qlen) break;
         const int c = A.queue[qi];
@@ -1502,12 +1503,37 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             }
             continue;
         }
-        // copied particles (subsets below min_subset)
-        copy_particles<COPY_BATCH>(A.in, A.tmp, tid, n, NT, [&](int p, int64_t& si, int64_t& so) {
-            const uint8_t inf = M.info[p];
-            si = off + idx_buf(M, inf & INF_PARITY)[p];
-            so = (inf & INF_MERGED) ? -1 : off + M.emit[p];
-        });
+        // copied particles (subsets below min_subset): the cell's arrays from wave-uniform base
+        // pointers with 32-bit lane offsets (no 64-bit address arithmetic per access)
+        {
+            const float* const ib[7] = {A.in.x + off, A.in.y + off, A.in.z + off, A.in.px + off,
+                                        A.in.py + off, A.in.pz + off, A.in.w + off};
+            float* const ob[7] = {A.tmp.x + off, A.tmp.y + off, A.tmp.z + off, A.tmp.px + off,
+                                  A.tmp.py + off, A.tmp.pz + off, A.tmp.w + off};
+            for (int p0 = tid; p0 < n; p0 += COPY_BATCH * NT) {
+                uint32_t si[COPY_BATCH], so[COPY_BATCH];
+                bool keep[COPY_BATCH];
+#pragma unroll
+                for (int u = 0; u < COPY_BATCH; ++u) {
+                    const int p = min(p0 + u * NT, n - 1);
+                    const uint8_t inf = M.info[p];
+                    si[u] = idx_buf(M, inf & INF_PARITY)[p];
+                    so[u] = M.emit[p];
+                    keep[u] = p0 + u * NT < n && !(inf & INF_MERGED);
+                }
+                float v[COPY_BATCH][7];
+#pragma unroll
+                for (int u = 0; u < COPY_BATCH; ++u)
+#pragma unroll
+                    for (int f = 0; f < 7; ++f) v[u][f] = ib[f][si[u]];
+#pragma unroll
+                for (int u = 0; u < COPY_BATCH; ++u) {
+                    if (!keep[u]) continue;
+#pragma unroll
+                    for (int f = 0; f < 7; ++f) ob[f][so[u]] = v[u][f];
+                }
+            }
+        }
         // merged subsets (Step 7)
         const int nm = sh.nmerged;
         if (nm > 0) {
