@@ -1092,7 +1092,7 @@ VPM_DEV void facc_add(FrameAcc& a, const float q[7]) {
 // Reads particles off + p for p = first, first + stride, ... below n, LOAD_BATCH positions per lane at
 // a time with every load of a batch unconditional (a position past the end reads particle n - 1
 // again), so that a batch's loads are in flight together; fn(p, q, in_range) sees each of them.
-constexpr int LOAD_BATCH = 4;
+constexpr int LOAD_BATCH = 8;
 
 template <typename Fn>
 VPM_DEV void load_particles(const Soa32& in, int64_t off, int first, int n, int stride, Fn fn) {
