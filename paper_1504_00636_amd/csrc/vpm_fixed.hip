@@ -1200,11 +1200,13 @@ __global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs G) {
     const FixedArgs& A = G.A;
     const int lane = lane_id();
     const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
+    const int qlen = A.counters[A.qlen_index];
+    if (qlen == 0) return;                         // an empty bin claims nothing
     for (;;) {
         int qi = 0;
         if (lane == 0) qi = atomicAdd(&A.counters[A.work_index], 1);
         qi = __shfl(qi, 0);
-        if (qi >= A.counters[A.qlen_index]) break;
+        if (qi >= qlen) break;
         const int c = A.queue[qi];
         const int64_t off = A.cell_off[c];
         const int n = (int)(A.cell_off[c + 1] - off);
@@ -1326,6 +1328,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
     // 16 claims per workgroup over the launch instead of one per cell (many small cells otherwise
     // queue on that one atomic); the tail of the launch is then at most 1/16 of a workgroup's work.
     const int qlen = A.counters[A.qlen_index];
+    if (qlen == 0) return;                         // an empty bin claims nothing
     const int K = max(1, min(16, qlen / (int)(gridDim.x * 16)));
     int qnext = 0, qend = 0;
     for (;;) {
@@ -1654,6 +1657,7 @@ __global__ __launch_bounds__(WAVE, 2) void k_fixed_small(FixedArgs A) {
     CellMem<IdxT> M = carve<IdxT>(smem + small_header_bytes(), NMAX_S);
     M.sh = &sh;
     const int qlen = A.counters[A.qlen_index];
+    if (qlen == 0) return;                         // an empty bin claims nothing
     const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
     int qnext = 0, qend = 0;
     for (;;) {

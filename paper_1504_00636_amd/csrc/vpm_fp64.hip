@@ -112,11 +112,13 @@ VPM_DEV void fp64_merge_out(const Fp64Args& A, int64_t o, double W, const double
 
 __global__ __launch_bounds__(64) void k_fp64_cells(Fp64Args A) {
     const int lane = threadIdx.x;
+    const int qlen = A.counters[A.qlen_index];
+    if (qlen == 0) return;                         // an empty bin claims nothing
     for (;;) {
         int qi = 0;
         if (lane == 0) qi = atomicAdd(&A.counters[A.work_index], 1);
         qi = __shfl(qi, 0);
-        if (qi >= A.counters[A.qlen_index]) break;
+        if (qi >= qlen) break;
         const int c = A.queue[qi];
         const int64_t off = A.cell_off[c];
         const int n = (int)(A.cell_off[c + 1] - off);
@@ -259,11 +261,13 @@ __global__ __launch_bounds__(64) void k_fp64_merge(Fp64MergeArgs G) {
     const Fp64Args& A = G.A;
     const int lane = threadIdx.x;
     const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
+    const int qlen = A.counters[A.qlen_index];
+    if (qlen == 0) return;                         // an empty bin claims nothing
     for (;;) {
         int qi = 0;
         if (lane == 0) qi = atomicAdd(&A.counters[A.work_index], 1);
         qi = __shfl(qi, 0);
-        if (qi >= A.counters[A.qlen_index]) break;
+        if (qi >= qlen) break;
         const int c = A.queue[qi];
         const int64_t off = A.cell_off[c];
         const int n = (int)(A.cell_off[c + 1] - off);
