@@ -90,3 +90,16 @@ def test_unbalanced_splits():
     for ms in (2, 4):
         ref = full_check(wl, dict(params, min_subset=ms))
         assert ref.stats["max_depth"].max() >= 10                  # deeper than a balanced tree
+
+
+def test_massless_photons():
+    """Photons (mass 0, energy |p|) in shower-shaped cells, tolerances loose enough that subsets
+    merge: both merges on the fixed-point path, and the pair merge on the FP64 path."""
+    from tests.test_gpu_parity import _fp64_check, _sampled_check
+    wl = W.shower_grid(nc=10, seed=5)
+    params = dict(wl.params, mass=0.0, tol_p=1.0, tol_x=0.5)
+    sample = np.arange(0, wl.n_cells, 3)
+    for merge in (vpm.VPM_MERGE_PAIR, vpm.VPM_MERGE_CENTROID):
+        _sampled_check(wl, params, sample, merge)
+    small = W.shower_grid(nc=5, seed=6, dtype=np.float64)
+    assert _fp64_check(small, dict(params)) <= 1

@@ -44,7 +44,7 @@ def test_golden_cells(fname, decide):
     np.testing.assert_allclose(out, merged, rtol=tol, atol=tol)
 
 
-def _momentum_cloud(n_cells=20, n=300, seed=1):
+def _momentum_cloud(n_cells=20, n=300, seed=1, mass=1.0):
     """Cells whose momenta have clearly nonzero means in every component, so that merging happens."""
     r = np.random.Generator(np.random.Philox(seed))
     cells = []
@@ -57,20 +57,23 @@ def _momentum_cloud(n_cells=20, n=300, seed=1):
         w = 0.5 + r.random(k)
         cells.append(np.stack([x, y, z, px, py, pz, w], axis=1))
     return W.from_cells(cells, params=dict(tol_x=0.3, tol_p=0.08, n_min_cell=0, min_subset=4,
-                                           cell_len=(1, 1, 1), mass=1.0))
+                                           cell_len=(1, 1, 1), mass=mass))
 
 
+@pytest.mark.parametrize("mass", [1.0, 0.0])
 @pytest.mark.parametrize("decide", MODES)
 @pytest.mark.parametrize("merge", [oracle.PAIR, oracle.CENTROID])
-def test_conservation(decide, merge):
-    wl = _momentum_cloud()
+def test_conservation(decide, merge, mass):
+    """Weight and momentum are conserved by both merges, energy by the pair (Step 7 and the pair
+    variant after the algorithm), for massive particles and for photons (energy |p|)."""
+    wl = _momentum_cloud(mass=mass)
     if decide == oracle.FIXED:
         wl = wl.astype(np.float32)
     r = oracle.run_workload(wl, decide=decide, merge_mode=merge)
     assert r.stats["n_merged"].sum() > 100            # the case really merges
     assert r.out_total < wl.n
-    tin = conserved_totals(wl.arrays(), 1.0)
-    tout = conserved_totals([r.out[f] for f in FIELDS], 1.0)
+    tin = conserved_totals(wl.arrays(), mass)
+    tout = conserved_totals([r.out[f] for f in FIELDS], mass)
     scale = np.array([tin[0], *([np.sum(wl.w * np.abs(p)) for p in (wl.px, wl.py, wl.pz)]), tin[4]])
     err = np.abs(tout - tin) / scale
     assert err[:4].max() < 1e-14
@@ -81,10 +84,11 @@ def test_conservation(decide, merge):
         assert tout[4] < tin[4]
 
 
-def test_pair_geometry():
+@pytest.mark.parametrize("mass", [1.0, 0.0])
+def test_pair_geometry(mass):
     """Each pair: equal half weights, same position, P +- delta with delta orthogonal to P, and both
-    members carry the subset's mean energy."""
-    wl = _momentum_cloud(n_cells=5)
+    members carry the subset's mean energy (for photons, mass 0, the energy is |p|)."""
+    wl = _momentum_cloud(n_cells=5, mass=mass)
     r = oracle.run_workload(wl, decide=oracle.PAPER, merge_mode=oracle.PAIR)
     off = r.out_off
     for c in range(wl.n_cells):
@@ -97,7 +101,7 @@ def test_pair_geometry():
                 continue
             w = wl.w[s]; Wt = w.sum()
             P = np.array([np.average(getattr(wl, f)[s], weights=w) for f in ("px", "py", "pz")])
-            ebar = np.average(energy(wl.px[s], wl.py[s], wl.pz[s], 1.0), weights=w)
+            ebar = np.average(energy(wl.px[s], wl.py[s], wl.pz[s], mass), weights=w)
             a = np.array([r.out[f][o] for f in ("px", "py", "pz")])
             b = np.array([r.out[f][o + 1] for f in ("px", "py", "pz")])
             assert r.out["w"][o] == pytest.approx(Wt / 2, rel=1e-15)
@@ -106,7 +110,7 @@ def test_pair_geometry():
             d = (a - b) / 2
             assert abs(np.dot(d, P)) <= 1e-12 * np.linalg.norm(P) * max(np.linalg.norm(d), 1e-300)
             for v in (a, b):
-                assert energy(*v, 1.0) == pytest.approx(ebar, rel=1e-14)
+                assert energy(*v, mass) == pytest.approx(ebar, rel=1e-14)
             o += 2
 
 
