@@ -418,7 +418,8 @@ def main():
     # it processes (read 7 x FP32 per input particle, write 7 x FP32 per output particle) over its
     # average duration, timed with HIP events on the stream it runs on.
     counts = np.diff(wl32.cell_off)
-    out_counts = np.diff(out_off.cpu().numpy())
+    gpu_out_off = out_off.cpu().numpy()
+    out_counts = np.diff(gpu_out_off)
     in_a = (counts > prm["n_min_cell"]) & (counts <= tuning["bin_a_max"])
     bytes_dom = 28.0 * float(counts[in_a].sum() + out_counts[in_a].sum())
     dom = kernels[DOMINANT]
@@ -440,12 +441,32 @@ def main():
         import oracle
         cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "0") or 16))
         ta = time.perf_counter()
-        oracle.run_workload(wl32, decide=oracle.FIXED, n_threads=cores)
+        ref = oracle.run_workload(wl32, decide=oracle.FIXED, n_threads=cores)
         dt = time.perf_counter() - ta
         cpu = dict(value=n / dt, unit="particles/s", cores=cores, kind="oracle",
                    sample=f"all {n_cells} cells ({n} particles) of the same workload, fixed-point decisions, "
                           f"pair merge, {dt:.2f} s wall on {cores} threads")
         log(f"[bench] oracle: {dt:.2f} s on {cores} threads")
+        # The tree the method builds on this workload, from the same oracle run, and whether the GPU's
+        # per-cell output counts equal the oracle's over every cell.
+        st = ref.stats
+        done = st["n_nodes"] > 0
+        cpu["tree"] = dict(cells_processed=int(done.sum()),
+                           visited_subsets_per_cell=float(st["n_nodes"][done].mean()),
+                           mean_max_depth=float(st["max_depth"][done].mean()),
+                           max_depth=int(st["max_depth"].max()),
+                           particle_levels_per_particle=float(st["particle_levels"].sum()) / n,
+                           gpu_out_counts_equal=bool(np.array_equal(np.asarray(ref.out_off), gpu_out_off)))
+        del ref
+        # The same oracle on one thread, over every 16th cell.
+        part = wl32.cells(np.arange(0, n_cells, 16))
+        ta = time.perf_counter()
+        oracle.run_workload(part, decide=oracle.FIXED, n_threads=1)
+        d1 = time.perf_counter() - ta
+        cpu["single_thread"] = dict(value=part.n / d1, unit="particles/s",
+                                    sample=f"every 16th cell ({part.n} particles), {d1:.2f} s wall on 1 thread")
+        log(f"[bench] oracle: {d1:.2f} s on 1 thread for {part.n} particles; tree {cpu['tree']}")
+        del part
 
     extra = None
     if not args.no_extra:
