@@ -73,6 +73,11 @@ typedef enum { VPM_MERGE_PAIR = 0, VPM_MERGE_CENTROID = 1 } vpm_merge_mode;
 #define VPM_FLAG_BAD_OFFSETS    0x8u  /* cell_off decreasing, not starting at 0, or past n_particles */
 #define VPM_FLAG_BAD_PARTITION  0x10u /* vpm_merge: a cell's perm/subset_id/n_subsets is not a
                                          partition of that cell; the cell was copied unchanged     */
+#define VPM_FLAG_BAD_SPECIES    0x20u /* vpm_run_species: a cell's species index is not below
+                                         n_species; the cell was copied unchanged                  */
+
+/* Largest number of species in one vpm_run_species call. */
+#define VPM_MAX_SPECIES 8
 
 typedef struct {
     double  tol_x;        /* T_X >= 0: position tolerance (Step 3)                            */
@@ -120,6 +125,22 @@ vpm_status vpm_check_params(const vpm_params *p);
 vpm_status vpm_run(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, int64_t n_cells,
                    int64_t n_particles, const vpm_params *p, vpm_soa *out, int64_t *out_off,
                    int64_t *out_total, hipStream_t stream);
+
+/* Several particle species in one launch, e.g. the electrons, positrons and photons that the
+ * paper's shower simulation merges (Sec. "Simulation results", shower): every cell holds particles
+ * of one species, and only the energy sqrt(m^2 + |p|^2) of Step 7 depends on the mass.
+ *   cell_species  device uint8[n_cells]: species index s of each cell
+ *   species_mass  host double[n_species]: mass of each species in m_e units (finite, >= 0);
+ *                 read during the call only
+ *   n_species     1 ... VPM_MAX_SPECIES
+ * p->mass is not used.  The result equals vpm_run's on the cells of each species with
+ * p->mass = species_mass[s].  A cell with s >= n_species is copied unchanged and raises
+ * VPM_FLAG_BAD_SPECIES.  Other arguments, output and errors as vpm_run (FIXED and FP64
+ * decisions).                                                                                */
+vpm_status vpm_run_species(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, int64_t n_cells,
+                           int64_t n_particles, const vpm_params *p, const uint8_t *cell_species,
+                           const double *species_mass, int32_t n_species, vpm_soa *out,
+                           int64_t *out_off, int64_t *out_total, hipStream_t stream);
 
 /* Partition only (Steps 1-6).
  *   perm       device int32[n_particles]: for each slot of cell c's range, the global index of

@@ -20,7 +20,8 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
                                              int32_t n_min_cell, int32_t* counters, int32_t* q_untouched,
                                              int32_t* q_a, int32_t* q_b, int32_t* q_c, int32_t* q_big, int32_t* q_s,
                                              int64_t* out_count,
-                                             uint8_t* cell_mode, uint32_t* flags, BinLimits lim) {
+                                             uint8_t* cell_mode, uint32_t* flags, BinLimits lim,
+                                             const uint8_t* species, int n_species) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int cls = -1;
     if (c < n_cells) {
@@ -31,8 +32,10 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
         if (!range_ok) { f |= FLAG_BAD_OFFSETS; n = 0; }     // never read outside the arrays
         if (c == 0 && lo != 0) f |= FLAG_BAD_OFFSETS;
         if (n > NMAX_BIG) f |= FLAG_TOO_LARGE;
+        const bool species_ok = !species || species[c] < n_species;
+        if (!species_ok) f |= FLAG_BAD_SPECIES;
         if (f) atomicOr(flags, f);
-        if (n == 0 || n <= n_min_cell || n > NMAX_BIG || !range_ok) {
+        if (n == 0 || n <= n_min_cell || n > NMAX_BIG || !range_ok || !species_ok) {
             cls = Q_UNTOUCHED;
             out_count[c] = n;
             cell_mode[c] = CELL_UNTOUCHED;
@@ -207,7 +210,8 @@ __global__ __launch_bounds__(256) void k_identity(const int64_t* cell_off, int64
 }  // namespace
 
 hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off, int64_t n_cells,
-                      int64_t n_particles, int32_t n_min_cell, BinLimits lim) {
+                      int64_t n_particles, int32_t n_min_cell, BinLimits lim, const uint8_t* species,
+                      int n_species) {
     if (lc.pre) lc.pre(lc.prof, "reset", lc.stream);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, lc.stream, ws.counters);
     if (lc.post) lc.post(lc.prof, "reset", lc.stream);
@@ -216,7 +220,8 @@ hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* c
     const int64_t blocks = (n_cells + 255) / 256;
     hipLaunchKernelGGL(k_bin, dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells, n_particles,
                        n_min_cell, ws.counters, ws.queue[Q_UNTOUCHED], ws.queue[Q_A], ws.queue[Q_B],
-                       ws.queue[Q_C], ws.queue[Q_BIG], ws.queue[Q_S], ws.out_count, ws.cell_mode, ws.flags, lim);
+                       ws.queue[Q_C], ws.queue[Q_BIG], ws.queue[Q_S], ws.out_count, ws.cell_mode, ws.flags, lim,
+                       species, n_species);
     if (lc.post) lc.post(lc.prof, "bin", lc.stream);
     return hipGetLastError();
 }

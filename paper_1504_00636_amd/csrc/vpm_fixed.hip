@@ -52,6 +52,7 @@ struct Frame {
     int ext_e[3];        // frexp exponent of the cell's extent per position axis
     int eb;              // frexp exponent of a bound on |eps_i - eps_j| over the cell
     int amask;           // bit l: the codes of axis l are not all equal in the cell
+    double mass;         // the particle mass of the cell (Step 7 energies)
 };
 
 // ------------------------------------------------------------------------------------------
@@ -983,7 +984,7 @@ VPM_DEV void merge_subset(const FixedArgs& A, const Frame& F, IdxFn gidx, int le
     const int gx0 = 61 - eW - F.ext_e[0], gx1 = 61 - eW - F.ext_e[1], gx2 = 61 - eW - F.ext_e[2];
     const int gd0 = 61 - eW - F.ep[0] - 1, gd1 = 61 - eW - F.ep[1] - 1, gd2 = 61 - eW - F.ep[2] - 1;
     const int ge = 61 - eW - F.eb;
-    const float m = (float)A.P.mass;
+    const float m = (float)F.mass;
     const float m2 = m * m;
     const float e0f = sqrtf(m2 + (q0 * q0 + q1 * q1 + q2 * q2));
     int64_t sx0 = 0, sx1 = 0, sx2 = 0, sd0 = 0, sd1 = 0, sd2 = 0, se = 0;
@@ -1020,7 +1021,7 @@ VPM_DEV void merge_subset(const FixedArgs& A, const Frame& F, IdxFn gidx, int le
         A.tmp.px[o] = (float)Pm[0]; A.tmp.py[o] = (float)Pm[1]; A.tmp.pz[o] = (float)Pm[2];
         return;
     }
-    const double md = A.P.mass;
+    const double md = F.mass;
     const double et = sqrt(md * md + (pt[0] * pt[0] + pt[1] * pt[1] + pt[2] * pt[2]));
     const double P2 = Pm[0] * Pm[0] + Pm[1] * Pm[1] + Pm[2] * Pm[2];
     const double e0 = sqrt(md * md + P2);
@@ -1116,7 +1117,8 @@ VPM_DEV void facc_cell(FrameAcc& a, const Soa32& in, int64_t off, int first, int
 }
 
 // The frame from the cell maxima v (identical in every lane).
-VPM_DEV void frame_from(const float v[11], float mass, Frame& F) {
+VPM_DEV void frame_from(const float v[11], double mass, Frame& F) {
+    F.mass = mass;
     F.wmax = v[0];
     F.ew = frexp_exp(F.wmax);
     F.amask = 0;
@@ -1131,12 +1133,12 @@ VPM_DEV void frame_from(const float v[11], float mass, Frame& F) {
         if (!F.pzero[k]) F.amask |= 1 << (3 + k);          // else every momentum code is 0
     }
     // |eps_i - eps_j| <= m + |p|_1 for any two particles of the cell; 4x margin
-    F.eb = frexp_exp(4.0f * (mass + F.pmax[0] + F.pmax[1] + F.pmax[2]));
+    F.eb = frexp_exp(4.0f * ((float)mass + F.pmax[0] + F.pmax[1] + F.pmax[2]));
 }
 
 // The frame of a cell from the accumulators of a whole wavefront.  Returns false if some weight is
 // not positive or some value is not finite.
-VPM_DEV bool frame_of_wave(FrameAcc& acc, float mass, Frame& F) {
+VPM_DEV bool frame_of_wave(FrameAcc& acc, double mass, Frame& F) {
     if (__ballot(acc.bad) != 0) return false;
 #pragma unroll
     for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
@@ -1146,7 +1148,7 @@ VPM_DEV bool frame_of_wave(FrameAcc& acc, float mass, Frame& F) {
 }
 
 // Step 1 for one cell (whole wave): validate the values and build the cell frame.
-VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, float mass, Frame& F) {
+VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, double mass, Frame& F) {
     FrameAcc acc;
     facc_init(acc);
     facc_cell(acc, in, off, lane_id(), n, WAVE);
@@ -1155,7 +1157,7 @@ VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, float mass, Frame& 
 
 // The same for a cell shared by WPB wavefronts (all threads call; the result is the same in all).
 template <int WPB>
-VPM_DEV bool cell_frame_block(const Soa32& in, int64_t off, int n, float mass, Frame& F, BlockScratch<WPB>* bs) {
+VPM_DEV bool cell_frame_block(const Soa32& in, int64_t off, int n, double mass, Frame& F, BlockScratch<WPB>* bs) {
     if constexpr (WPB == 1) {
         return cell_frame(in, off, n, mass, F);
     } else {
@@ -1223,7 +1225,7 @@ __global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs G) {
         }
         const bool part_ok = __ballot(!ok) == 0;
         Frame F;
-        const bool vals_ok = part_ok && cell_frame(A.in, off, n, (float)A.P.mass, F);
+        const bool vals_ok = part_ok && cell_frame(A.in, off, n, cell_mass(A.P.mass, A.P.species, A.P.species_mass, c), F);
         if (!vals_ok) {
             if (lane == 0) {
                 if (part_ok || nsub >= 1) atomicOr(A.flags, part_ok ? FLAG_BAD_VALUE : FLAG_BAD_PARTITION);
@@ -1353,7 +1355,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
 
         // ---- Step 1: collect the cell, validate, frame ----
         Frame F;
-        const bool valid = cell_frame_block<WPB>(A.in, off, n, (float)A.P.mass, F, bs);
+        const bool valid = cell_frame_block<WPB>(A.in, off, n, cell_mass(A.P.mass, A.P.species, A.P.species_mass, c), F, bs);
         if (!valid) {
             if (tid == 0) {
                 atomicOr(A.flags, FLAG_BAD_VALUE);
@@ -1608,7 +1610,7 @@ VPM_DEV void small_root(const CellMem<uint16_t>& M, const FixedArgs& A, SmallSha
 #pragma unroll
     for (int r = 0; r < 11; ++r) acc.v[r] = group_max(acc.v[r], g);
     Frame F;
-    frame_from(acc.v, (float)A.P.mass, F);
+    frame_from(acc.v, cell_mass(A.P.mass, A.P.species, A.P.species_mass, ss.cell[j]), F);
     if (lid == 0) ss.frame[j] = F;
     FSums R;
     fsums_zero(R);

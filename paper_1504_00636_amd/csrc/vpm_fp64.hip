@@ -64,9 +64,9 @@ VPM_DEV double qval(const Soa64& in, int l, int64_t i) {
 // Replace a finished subset (Step 7) in FP64: the whole wave sums; lane 0 writes slot o (and o+1).
 // W and mean[6] are the subset's weight and centroid; gidx(j) is the global index of member j.
 template <typename IdxFn>
-VPM_DEV void fp64_merge_out(const Fp64Args& A, int64_t o, double W, const double mean[6], IdxFn gidx, int len) {
+VPM_DEV void fp64_merge_out(const Fp64Args& A, int64_t o, double W, const double mean[6], IdxFn gidx, int len,
+                            double m) {
     const int lane = threadIdx.x;
-    const double m = A.P.mass;
     const double P[3] = {mean[3], mean[4], mean[5]};
     const double P2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
     const double e0 = sqrt(m * m + P2);
@@ -122,6 +122,7 @@ __global__ __launch_bounds__(64) void k_fp64_cells(Fp64Args A) {
         const int c = A.queue[qi];
         const int64_t off = A.cell_off[c];
         const int n = (int)(A.cell_off[c + 1] - off);
+        const double mass = cell_mass(A.P.mass, A.P.species, A.P.species_mass, c);
 
         // validate the cell (w > 0, all values finite)
         bool ok = true;
@@ -238,7 +239,8 @@ __global__ __launch_bounds__(64) void k_fp64_cells(Fp64Args A) {
                 }
                 out_pos += len;
             } else {
-                fp64_merge_out(A, off + out_pos, W, mean, [&](int j) { return off + (int64_t)src[start + j]; }, len);
+                fp64_merge_out(A, off + out_pos, W, mean, [&](int j) { return off + (int64_t)src[start + j]; }, len,
+                               mass);
                 out_pos += npair;
             }
             ++nleaf;
@@ -271,6 +273,7 @@ __global__ __launch_bounds__(64) void k_fp64_merge(Fp64MergeArgs G) {
         const int c = A.queue[qi];
         const int64_t off = A.cell_off[c];
         const int n = (int)(A.cell_off[c + 1] - off);
+        const double mass = cell_mass(A.P.mass, A.P.species, A.P.species_mass, c);
         const int nsub = G.n_subsets[c];
         bool ok = nsub >= 1 && nsub <= n;
         for (int p = lane; p < n && ok; p += WAVE) {
@@ -325,7 +328,7 @@ __global__ __launch_bounds__(64) void k_fp64_merge(Fp64MergeArgs G) {
                 const double W = wsum(s[6]);
                 double mean[6];
                 for (int l = 0; l < 6; ++l) mean[l] = wsum(s[l]) / W;
-                fp64_merge_out(A, off + out_pos, W, mean, [&](int j) { return (int64_t)mem[j]; }, len);
+                fp64_merge_out(A, off + out_pos, W, mean, [&](int j) { return (int64_t)mem[j]; }, len, mass);
                 out_pos += npair;
             }
             b = e;

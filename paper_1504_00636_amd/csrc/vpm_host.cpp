@@ -163,6 +163,8 @@ FixedParams fixed_params(const vpm_params* p, const vpm_tuning& t) {
     f.merge_mode = p->merge_mode;
     f.ppl_shift = ilog2(t.ppl);
     f.mass = p->mass;
+    f.species = nullptr;
+    for (int k = 0; k < VPM_MAX_SPECIES; ++k) f.species_mass[k] = p->mass;
     return f;
 }
 
@@ -175,6 +177,8 @@ Fp64Params fp64_params(const vpm_params* p) {
     f.min_subset = p->min_subset;
     f.merge_mode = p->merge_mode;
     f.n_min_cell = p->n_min_cell;
+    f.species = nullptr;
+    for (int k = 0; k < VPM_MAX_SPECIES; ++k) f.species_mass[k] = p->mass;
     return f;
 }
 
@@ -186,6 +190,45 @@ Soa64 soa64(const vpm_soa* s) {
     return Soa64{(const double*)s->x, (const double*)s->y, (const double*)s->z, (const double*)s->px,
                  (const double*)s->py, (const double*)s->pz, (const double*)s->w};
 }
+
+// vpm_run and vpm_run_species: species (device, may be null) with its mass table (host).
+vpm_status run_impl(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int64_t n_cells,
+                    int64_t n_particles, const vpm_params* p, const uint8_t* species, const double* species_mass,
+                    int32_t n_species, vpm_soa* out, int64_t* out_off, int64_t* out_total, hipStream_t stream) {
+    vpm_status st = common_checks(ctx, in, cell_off, n_cells, n_particles, p);
+    if (st != VPM_OK) return st;
+    if (check_soa(out) != VPM_OK || !out_off || !out_total) return VPM_ERR_INVALID_ARG;
+    hipSetDevice(ctx->device);
+    LaunchCfg lc = make_cfg(ctx, stream);
+    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx),
+                              species, n_species);
+    if (e != hipSuccess) return hip_fail(ctx, e, "bin");
+    if (p->decide == VPM_DECIDE_FIXED) {
+        FixedParams fp = fixed_params(p, ctx->tune);
+        if (species) {
+            fp.species = species;
+            for (int k = 0; k < VPM_MAX_SPECIES; ++k) fp.species_mass[k] = species_mass[k < n_species ? k : 0];
+        }
+        e = launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fp, 0, nullptr, nullptr, nullptr);
+    } else {
+        Fp64Params fp = fp64_params(p);
+        if (species) {
+            fp.species = species;
+            for (int k = 0; k < VPM_MAX_SPECIES; ++k) fp.species_mass[k] = species_mass[k < n_species ? k : 0];
+        }
+        e = launch_fp64_cells(ctx->ws, lc, soa64(in), cell_off, n_cells, fp, 0, nullptr, nullptr, nullptr);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "cells");
+    e = launch_scan_offsets(ctx->ws, lc, n_cells, out_off, out_total);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scan");
+    const void* ins[7] = {in->x, in->y, in->z, in->px, in->py, in->pz, in->w};
+    void* outs[7] = {out->x, out->y, out->z, out->px, out->py, out->pz, out->w};
+    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs,
+                       p->dtype == VPM_F32 ? 4 : 8);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scatter");
+    return VPM_OK;
+}
+
 
 }  // namespace
 
@@ -324,26 +367,20 @@ vpm_status vpm_reserve(vpm_ctx* ctx, int64_t max_particles, int64_t max_cells) {
 vpm_status vpm_run(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int64_t n_cells,
                    int64_t n_particles, const vpm_params* p, vpm_soa* out, int64_t* out_off,
                    int64_t* out_total, hipStream_t stream) {
-    vpm_status st = common_checks(ctx, in, cell_off, n_cells, n_particles, p);
-    if (st != VPM_OK) return st;
-    if (check_soa(out) != VPM_OK || !out_off || !out_total) return VPM_ERR_INVALID_ARG;
-    hipSetDevice(ctx->device);
-    LaunchCfg lc = make_cfg(ctx, stream);
-    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx));
-    if (e != hipSuccess) return hip_fail(ctx, e, "bin");
-    if (p->decide == VPM_DECIDE_FIXED)
-        e = launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fixed_params(p, ctx->tune), 0, nullptr, nullptr, nullptr);
-    else
-        e = launch_fp64_cells(ctx->ws, lc, soa64(in), cell_off, n_cells, fp64_params(p), 0, nullptr, nullptr, nullptr);
-    if (e != hipSuccess) return hip_fail(ctx, e, "cells");
-    e = launch_scan_offsets(ctx->ws, lc, n_cells, out_off, out_total);
-    if (e != hipSuccess) return hip_fail(ctx, e, "scan");
-    const void* ins[7] = {in->x, in->y, in->z, in->px, in->py, in->pz, in->w};
-    void* outs[7] = {out->x, out->y, out->z, out->px, out->py, out->pz, out->w};
-    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs,
-                       p->dtype == VPM_F32 ? 4 : 8);
-    if (e != hipSuccess) return hip_fail(ctx, e, "scatter");
-    return VPM_OK;
+    return run_impl(ctx, in, cell_off, n_cells, n_particles, p, nullptr, nullptr, 0, out, out_off, out_total,
+                    stream);
+}
+
+vpm_status vpm_run_species(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int64_t n_cells,
+                           int64_t n_particles, const vpm_params* p, const uint8_t* cell_species,
+                           const double* species_mass, int32_t n_species, vpm_soa* out, int64_t* out_off,
+                           int64_t* out_total, hipStream_t stream) {
+    if (!species_mass || n_species < 1 || n_species > VPM_MAX_SPECIES) return VPM_ERR_INVALID_ARG;
+    if (!cell_species && n_cells > 0) return VPM_ERR_INVALID_ARG;
+    for (int k = 0; k < n_species; ++k)
+        if (!(std::isfinite(species_mass[k]) && species_mass[k] >= 0.0)) return VPM_ERR_INVALID_ARG;
+    return run_impl(ctx, in, cell_off, n_cells, n_particles, p, cell_species, species_mass, n_species, out,
+                    out_off, out_total, stream);
 }
 
 vpm_status vpm_partition(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int64_t n_cells,

@@ -26,6 +26,7 @@ constexpr uint32_t FLAG_OUT_OF_CELL = VPM_FLAG_OUT_OF_CELL;
 constexpr uint32_t FLAG_TOO_LARGE = VPM_FLAG_CELL_TOO_LARGE;
 constexpr uint32_t FLAG_BAD_OFFSETS = VPM_FLAG_BAD_OFFSETS;
 constexpr uint32_t FLAG_BAD_PARTITION = VPM_FLAG_BAD_PARTITION;
+constexpr uint32_t FLAG_BAD_SPECIES = VPM_FLAG_BAD_SPECIES;
 constexpr uint32_t FLAG_INTERNAL = 0x80000000u;  // a cut left one side empty (never expected)
 
 // Device workspace, allocated by vpm_reserve.
@@ -56,7 +57,19 @@ struct FixedParams {
     int32_t merge_mode;
     int32_t ppl_shift;              // log2 of the target particles per lane of a lane group
     double mass;
+    const uint8_t* species;         // per-cell species index (null: every cell has `mass`)
+    double species_mass[VPM_MAX_SPECIES];
 };
+
+// The particle mass of cell c (c wave-uniform).  The table is read with constant indices only.
+__host__ __device__ inline double cell_mass(double mass, const uint8_t* species, const double* table, int64_t c) {
+    if (!species) return mass;
+    const int s = species[c];
+    double m = table[0];
+#pragma unroll
+    for (int k = 1; k < VPM_MAX_SPECIES; ++k) if (s == k) m = table[k];
+    return m;
+}
 
 // Routing thresholds of the size bins: cells of up to `s` particles go to the small-cell batches,
 // up to `a` to bin A, up to `b` to B, up to `c` to C, larger ones to the global-memory bin.
@@ -81,8 +94,10 @@ struct Soa64 { const double *x, *y, *z, *px, *py, *pz, *w; };
 struct Soa64Out { double *x, *y, *z, *px, *py, *pz, *w; };
 
 // ---- launchers (vpm_common.hip) ----
+// species (may be null): cells whose species index is not below n_species are passed through.
 hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,
-                      int64_t n_cells, int64_t n_particles, int32_t n_min_cell, BinLimits lim);
+                      int64_t n_cells, int64_t n_particles, int32_t n_min_cell, BinLimits lim,
+                      const uint8_t* species = nullptr, int n_species = 0);
 hipError_t launch_scan_offsets(const Workspace& ws, const LaunchCfg& lc, int64_t n_cells,
                                int64_t* out_off, int64_t* out_total);
 hipError_t launch_scatter(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,
@@ -111,6 +126,8 @@ int64_t fixed_big_slab_bytes();            // one slab per workgroup of the big-
 struct Fp64Params {
     double tol_x, tol_p, L[3], mass;
     int32_t min_subset, merge_mode, n_min_cell;
+    const uint8_t* species;         // as in FixedParams
+    double species_mass[VPM_MAX_SPECIES];
 };
 hipError_t launch_fp64_cells(const Workspace& ws, const LaunchCfg& lc, const Soa64& in,
                              const int64_t* cell_off, int64_t n_cells, const Fp64Params& fp,

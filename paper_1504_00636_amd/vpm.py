@@ -22,8 +22,11 @@ VPM_DECIDE_FIXED, VPM_DECIDE_FP64 = 0, 1
 VPM_MERGE_PAIR, VPM_MERGE_CENTROID = 0, 1
 VPM_FLAG_BAD_VALUE, VPM_FLAG_OUT_OF_CELL, VPM_FLAG_CELL_TOO_LARGE, VPM_FLAG_BAD_OFFSETS = 1, 2, 4, 8
 VPM_FLAG_BAD_PARTITION = 16
+VPM_FLAG_BAD_SPECIES = 32
+VPM_MAX_SPECIES = 8
 
-EXPORTS = ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_partition",
+EXPORTS = ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_run_species",
+           "vpm_partition",
            "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read",
            "vpm_check_tuning", "vpm_get_tuning", "vpm_set_tuning", "vpm_autotune",
            "vpm_status_string", "vpm_last_error", "vpm_version")
@@ -80,6 +83,8 @@ def lib():
     L.vpm_reserve.argtypes = [vp, i64, i64]
     L.vpm_check_params.argtypes = [P(VpmParams)]
     L.vpm_run.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), P(VpmSoa), vp, vp, vp]
+    L.vpm_run_species.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, P(C.c_double), C.c_int32,
+                                  P(VpmSoa), vp, vp, vp]
     L.vpm_partition.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, vp]
     L.vpm_merge.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, P(VpmSoa), vp, vp, vp]
     L.vpm_device_status.argtypes = [vp, P(C.c_uint32), C.c_int]
@@ -94,8 +99,8 @@ def lib():
     L.vpm_last_error.argtypes = [vp]
     L.vpm_last_error.restype = C.c_char_p
     L.vpm_version.restype = C.c_char_p
-    for f in ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_partition",
-              "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read", "vpm_check_tuning",
+    for f in ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_run_species",
+              "vpm_partition", "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read", "vpm_check_tuning",
               "vpm_get_tuning", "vpm_set_tuning", "vpm_autotune"):
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -216,6 +221,25 @@ class Context:
                            _dev(out_total, torch.int64, 1, "out_total"), _stream(stream))
         self._check(st, "vpm_run")
 
+    def run_species(self, inp, cell_off, n_particles: int, p: VpmParams, cell_species, species_mass, out, out_off,
+                    out_total, stream=None):
+        """vpm_run_species: cell_species a device uint8 tensor (one entry per cell), species_mass a host
+        sequence of 1 ... VPM_MAX_SPECIES masses."""
+        import torch
+        n_cells = cell_off.numel() - 1
+        dt = _torch_dtype(p)
+        si = _soa(inp, dt, n_particles, "in")
+        so = _soa(out, dt, n_particles, "out")
+        masses = [float(m) for m in species_mass]
+        tab = (C.c_double * max(1, len(masses)))(*masses)
+        st = lib().vpm_run_species(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"),
+                                   n_cells, int(n_particles), C.byref(p),
+                                   _dev(cell_species, torch.uint8, n_cells, "cell_species") if n_cells else None,
+                                   tab, len(masses), C.byref(so),
+                                   _dev(out_off, torch.int64, n_cells + 1, "out_off"),
+                                   _dev(out_total, torch.int64, 1, "out_total"), _stream(stream))
+        self._check(st, "vpm_run_species")
+
     def partition(self, inp, cell_off, n_particles: int, p: VpmParams, perm, subset_id, n_subsets, stream=None):
         import torch
         n_cells = cell_off.numel() - 1
@@ -298,6 +322,10 @@ def vpm_reserve(ctx: Context, max_particles: int, max_cells: int):
 
 def vpm_run(ctx: Context, *a, **k):
     ctx.run(*a, **k)
+
+
+def vpm_run_species(ctx: Context, *a, **k):
+    ctx.run_species(*a, **k)
 
 
 def vpm_partition(ctx: Context, *a, **k):

@@ -88,6 +88,17 @@ def test_entry_points_reject_null_context():
     assert L.vpm_reserve(None, 1, 1) == vpm.VPM_ERR_INVALID_ARG
 
 
+@pytest.mark.parametrize("masses", [[1.0, 1.0, 0.0], [], [1.0] * 9, [1.0, -1.0], [float("nan")], [float("inf")]])
+def test_run_species_rejects_without_device(masses):
+    """Null context, or a bad species table (none, more than VPM_MAX_SPECIES, negative or non-finite
+    masses): rejected on the host before anything is enqueued."""
+    L = vpm.lib()
+    p = _p()
+    tab = (C.c_double * max(1, len(masses)))(*masses)
+    assert L.vpm_run_species(None, None, None, 0, 0, C.byref(p), None, tab, len(masses), None, None, None,
+                             None) == vpm.VPM_ERR_INVALID_ARG
+
+
 def _declared_arity():
     src = open(os.path.join(ROOT, "include", "vpm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
