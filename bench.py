@@ -46,17 +46,18 @@ def kernel_source_sha():
     return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
 
 
-def conservation_error(arrs_in, arrs_out, n_out, mass):
-    """Largest relative change of the totals W, Px, Py, Pz, E (momentum normalised by sum w|p|)."""
+def conservation_error(arrs_in, arrs_out, n_out, mass, mass_out=None):
+    """Largest relative change of the totals W, Px, Py, Pz, E (momentum normalised by sum w|p|).
+    mass: a number, or a per-particle tensor (then mass_out gives the output particles' masses)."""
     import torch
 
-    def totals(a, n):
+    def totals(a, n, mass):
         x, y, z, px, py, pz, w = [t[:n].double() for t in a]
         e = torch.sqrt(mass * mass + px * px + py * py + pz * pz)
         return torch.stack([w.sum(), (w * px).sum(), (w * py).sum(), (w * pz).sum(), (w * e).sum()]), \
             torch.stack([w.sum(), (w * px.abs()).sum(), (w * py.abs()).sum(), (w * pz.abs()).sum(), (w * e).sum()])
-    tin, scale = totals(arrs_in, arrs_in[0].numel())
-    tout, _ = totals(arrs_out, n_out)
+    tin, scale = totals(arrs_in, arrs_in[0].numel() if mass_out is None else mass.numel(), mass)
+    tout, _ = totals(arrs_out, n_out, mass if mass_out is None else mass_out)
     rel = ((tout - tin).abs() / scale).cpu().numpy()
     return dict(weight=float(rel[0]), momentum=float(rel[1:4].max()), energy=float(rel[4]))
 
@@ -240,6 +241,48 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps):
         rec["plain_fp64"] = pl
     log(f"[bench] {name}: {ms:.3f} ms/step ({rec['value']:.3g} particles/s), rho {rec['merge_ratio']:.4f}")
     return rec
+
+
+def species_shower(ctx, vpm, W, seed, steps=5, warmup=2):
+    """The shower population with three species (electrons, positrons and photons: masses 1, 1, 0),
+    one drawn per cell, merged in one launch by vpm_run_species with the batching tuned for the
+    shower."""
+    import torch
+    sh = W.shower_grid(nc=64, seed=seed)
+    prm = dict(sh.params)
+    masses = [1.0, 1.0, 0.0]
+    species = np.random.Generator(np.random.Philox(seed + 100)).integers(0, 3, sh.n_cells).astype(np.uint8)
+    n, n_cells = sh.n, sh.n_cells
+    arrs, off = vpm.upload(sh)
+    del sh
+    sp = torch.from_numpy(species).cuda()
+    p = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
+    out = [torch.empty_like(a) for a in arrs]
+    out_off = torch.empty(n_cells + 1, dtype=torch.int64, device="cuda")
+    out_total = torch.empty(1, dtype=torch.int64, device="cuda")
+    ctx.device_status(clear=True)
+    for _ in range(warmup):
+        ctx.run_species(arrs, off, n, p, sp, masses, out, out_off, out_total)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run_species(arrs, off, n, p, sp, masses, out, out_off, out_total)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    n_out = int(out_total.item())
+    m_cell = torch.tensor(masses, dtype=torch.float64, device="cuda")[sp.long()]
+    m_in = torch.repeat_interleave(m_cell, off[1:] - off[:-1], output_size=n)
+    m_out = torch.repeat_interleave(m_cell, out_off[1:] - out_off[:-1], output_size=n_out)
+    cons = conservation_error(arrs, out, n_out, m_in, m_out)
+    flags = ctx.device_status(clear=True)
+    del arrs, out, m_in, m_out
+    torch.cuda.empty_cache()
+    log(f"[bench] shower, three species: {ms:.3f} ms/step")
+    return dict(workload="shower_64cubed_three_species", n_particles=n, n_cells=n_cells, species_mass=masses,
+                cells_per_species=np.bincount(species, minlength=3).tolist(), ms_per_step=ms,
+                value=n / (ms * 1e-3), unit="particles/s", merge_ratio=n_out / n, conservation=cons,
+                device_flags=flags, tuning=ctx.get_tuning().as_dict(),
+                params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset")})
 
 
 def subset_labels(perm, sid, n_subsets_cell_off):
@@ -483,6 +526,7 @@ def main():
         extra["shower"] = extra_workload(ctx, vpm, "shower_64cubed_lognormal64", sh, sh64, dict(sh.params), 5,
                                          0 if args.no_fp64 else 1)
         del sh, sh64
+        extra["shower_three_species"] = species_shower(ctx, vpm, W, args.seed)
         if args.cascade_steps > 0:
             extra["cascade"] = cascade(ctx, vpm, W, args.cascade_steps, args.seed)
         if not args.no_fp64:
