@@ -36,6 +36,14 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_00636_amd", "csrc", "vpm_fixed.hi
 DOMINANT = "fixed_cells_576"          # the one-wavefront-per-cell bin: every two-stream cell but ~0.2 %
 DOMINANT_SYMBOL = "k_fixed_cells<576"  # how rocprofv3 names it
 COPY_BYTES = 1 << 30
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_fixed_cells_two_stream.json")
+# VALU issue peak: 256 CUs x 4 SIMDs, one 64-lane VALU instruction per SIMD every 4 cycles at 2.4 GHz
+VALU_PEAK_INSTS = 256 * 4 * 2.4e9 / 4
+# int32 lane operations: 256 CUs x 64 lanes x 2.4 GHz
+ALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# least lane operations per particle-level (moment sums of the smaller child, the cut and the
+# compaction), the algorithmic unit of the ALU figure
+LANE_OPS_PER_PARTICLE_LEVEL = 40
 
 
 def log(msg):
@@ -128,6 +136,39 @@ def traffic_summary(fetch_dir, write_dir, calib_fetch_dir, calib_write_dir):
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
+
+
+def valu_summary(pmc_dir):
+    """Instruction counts of the dominant kernel per launch (SQ_INSTS_VALU, SQ_INSTS_SALU,
+    SQ_INSTS_LDS, SQ_WAVES from one rocprofv3 --pmc pass), written under profiles/."""
+    is_dom = lambda k: DOMINANT_SYMBOL in k.replace(" ", "")
+    rec = {"kernel": DOMINANT, "workload": "two_stream_256x256_poisson512",
+           "kernel_source_sha256": kernel_source_sha()}
+    for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVES"):
+        v, k = _counter_means(pmc_dir, c, is_dom)
+        rec[c.lower() + "_per_launch"] = v
+        rec["launches"] = k
+    rec["command"] = ("rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVES --output-format csv "
+                      "-d <dir> -o run -- python3 bench.py --no-cpu --no-fp64 --no-extra --no-autotune "
+                      "--steps 3 --warmup 1; python3 bench.py --valu-summary <dir>")
+    os.makedirs(os.path.dirname(VALU_FILE), exist_ok=True)
+    with open(VALU_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def valu_from_profiles():
+    """VALU wave-instructions per launch of the dominant kernel from the committed counter run, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(VALU_FILE):
+        return None
+    try:
+        t = json.load(open(VALU_FILE))
+        if t.get("kernel_source_sha256") != kernel_source_sha():
+            return None
+        return float(t["sq_insts_valu_per_launch"])
+    except Exception:
+        return None
 
 
 def autotune(ctx, vpm, arrs, off, n, p):
@@ -416,12 +457,16 @@ def main():
     ap.add_argument("--cascade-steps", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default batching configuration (profiling runs: one kernel configuration only)")
+    ap.add_argument("--valu-summary", metavar="PMC_DIR")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the merge event captured in a HIP graph (checked against an eager call)")
     args = ap.parse_args()
 
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary)
+        return
+    if args.valu_summary:
+        valu_summary(args.valu_summary)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: a merge event is cell-local, and this benchmark times the "
@@ -480,6 +525,7 @@ def main():
         log(f"[bench] plain FP64: {plain['ms_per_step']:.3f} ms/step, speedup {plain['speedup_batched_over_plain']:.1f}x")
 
     cpu = None
+    pl_dom = None
     if not args.no_cpu:
         import oracle
         cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "0") or 16))
@@ -494,6 +540,7 @@ def main():
         # per-cell output counts equal the oracle's over every cell.
         st = ref.stats
         done = st["n_nodes"] > 0
+        pl_dom = float(st["particle_levels"][in_a].sum())
         cpu["tree"] = dict(cells_processed=int(done.sum()),
                            visited_subsets_per_cell=float(st["n_nodes"][done].mean()),
                            mean_max_depth=float(st["max_depth"][done].mean()),
@@ -532,6 +579,19 @@ def main():
         if not args.no_fp64:
             extra["precision_sweep"] = precision_sweep(ctx, vpm, W, [128, 512, 2048], args.seed)
 
+    # The ALU side of the dominant kernel: issued VALU instructions (committed counter run) against
+    # the VALU issue peak, and the algorithmic integer work (particle-levels of its cells, from the
+    # oracle run, times the least lane operations per particle-level) against the int32 lane peak.
+    t_dom = dom["avg_ms"] * 1e-3
+    valu = valu_from_profiles()
+    alu = {"issue": None if valu is None else
+           {"valu_insts_per_launch": valu, "achieved": valu / t_dom, "peak": VALU_PEAK_INSTS,
+            "unit": "VALU wave-instructions/s", "frac": valu / t_dom / VALU_PEAK_INSTS},
+           "algorithmic": None if pl_dom is None else
+           {"particle_levels_per_launch": pl_dom, "lane_ops_per_particle_level": LANE_OPS_PER_PARTICLE_LEVEL,
+            "achieved": pl_dom * LANE_OPS_PER_PARTICLE_LEVEL / t_dom, "peak": ALU_PEAK_LANE_OPS,
+            "unit": "int32 lane-ops/s", "frac": pl_dom * LANE_OPS_PER_PARTICLE_LEVEL / t_dom / ALU_PEAK_LANE_OPS}}
+
     line = {
         "metric": "input particles merged/sec + % HBM peak; batched-FP32 vs plain-FP64 at equal cons. err",
         "value": n / (ms_step * 1e-3),
@@ -551,6 +611,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": DOMINANT,
                      "kernel_avg_ms": dom["avg_ms"], "algorithmic_bytes_per_launch": bytes_dom},
+        "alu": alu,
         "cpu_baseline": cpu,
         "timing": dict(mode="HIP graph replay of the whole merge event" if args.graph else
                        "eager calls, no profiling events in the timed steps", **timing),
