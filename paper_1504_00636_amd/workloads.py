@@ -287,3 +287,60 @@ def cascade_split_device(arrs, cell_off, n: int, step: int, out_arrs, out_off, n
             dst[1:2 * n:2] = 0.0 if fresh[k] is None else fresh[k].to(dst.dtype)
     out_off.copy_(cell_off * 2)
     return 2 * n
+
+
+# --------------------------------------------------------------------------------------
+# Counter-propagating blocks (Sec. "Counter-propagating Plasma Blocks")
+# --------------------------------------------------------------------------------------
+
+BLOCKS_PARAMS = dict(tol_x=0.4, tol_p=0.01, n_min_cell=15, min_subset=4,
+                     cell_len=(1.0, 1.0, 1.0), mass=1.0)
+
+
+def counter_blocks(per_cell: int = 12, nx: int = 100, ny: int = 20, block_cells: int = 25, p0: float = 150.0,
+                   seed: int = 0, dtype=np.float32) -> Workload:
+    """Two blocks of non-interacting electrons over `block_cells` x `ny` unit cells each of an
+    nx x ny grid, `per_cell` particles in every cell of a block (uniform inside the cell, z uniform
+    in [0, 1)), with momenta (+p0, 0, 0) and (-p0, 0, 0) in m_e c and unit weights: 12,000
+    particles by default, 12 per cell, below the merge threshold N_min = 15 until the blocks
+    overlap.  The first block starts a quarter of the row in and moves to +x, the second ends a
+    quarter from the far end and moves to -x.  Box and grid are choices made here (the paper gives
+    neither)."""
+    r = _rng(seed)
+    a0 = nx // 4 - block_cells // 2
+    b0 = nx - nx // 4 - block_cells // 2
+    ix, iy = np.meshgrid(np.arange(block_cells), np.arange(ny), indexing="ij")
+    ix = np.repeat(ix.ravel(), per_cell)
+    iy = np.repeat(iy.ravel(), per_cell)
+    h = ix.size
+    x = np.concatenate([a0 + ix + r.random(h), b0 + ix + r.random(h)])
+    y = np.concatenate([iy + r.random(h), iy + r.random(h)])
+    px = np.concatenate([np.full(h, p0), np.full(h, -p0)])
+    n = 2 * h
+    wl = _sorted_grid(x, y, r.random(n), px, np.zeros(n), np.zeros(n), np.ones(n), nx, ny, dtype)
+    wl.params = dict(BLOCKS_PARAMS)
+    wl.name = "counter_blocks"
+    return wl
+
+
+def _sorted_grid(x, y, z, px, py, pz, w, nx, ny, dtype) -> Workload:
+    """Particles of an nx x ny grid of unit cells (x wraps around), stably sorted by cell
+    c = ix + nx * iy."""
+    x = np.mod(np.asarray(x, np.float64), nx)
+    y = np.asarray(y, np.float64)
+    cid = np.minimum(np.floor(x).astype(np.int64), nx - 1) + nx * np.minimum(np.floor(y).astype(np.int64), ny - 1)
+    order = np.argsort(cid, kind="stable")
+    cols = [np.asarray(a, np.float64)[order].astype(dtype) for a in (x, y, z, px, py, pz, w)]
+    counts = np.bincount(cid, minlength=nx * ny).astype(np.int64)
+    return Workload("grid", *cols, cell_off=_offsets(counts), cell_id=None, params={})
+
+
+def free_stream(wl: Workload, nx: int, ny: int, dt: float, dtype=np.float32) -> Workload:
+    """Move every particle by v dt along x (v = p / gamma, c = 1, mass 1), then sort by cell again."""
+    px, py, pz = (np.asarray(getattr(wl, f), np.float64) for f in ("px", "py", "pz"))
+    gamma = np.sqrt(1.0 + px * px + py * py + pz * pz)
+    out = _sorted_grid(np.asarray(wl.x, np.float64) + dt * px / gamma, wl.y, wl.z, px, py, pz, wl.w,
+                       nx, ny, dtype)
+    out.params = dict(wl.params)
+    out.name = wl.name
+    return out
