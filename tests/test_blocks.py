@@ -65,3 +65,37 @@ def test_gpu_passage_matches_oracle():
         assert tot == ref.out_total, ev
         check_merged_values(wl, params, vpm.VPM_MERGE_PAIR, got, got_off, ref)
         _check_blocks(got["w"], got["px"], got["py"], got["pz"], wl.w.sum() / 2, rel=1e-6)
+
+
+def _whole_box(wl):
+    """The population as one cell spanning the box (global merging: the paper's variant that merges
+    across cells and so gives up local charge conservation), with the position tolerance scaled to
+    the box so that subsets stay about as wide as a cell."""
+    params = dict(wl.params, cell_len=(float(NX), float(NY), 1.0), tol_x=0.02)   # 0.4 of a cell
+    box = W.Workload("box", *[getattr(wl, f) for f in W.FIELDS], cell_off=np.array([0, wl.n], np.int64),
+                     cell_id=None, params=params)
+    return box, params
+
+
+def test_oracle_whole_box_keeps_the_blocks_apart():
+    for ev, (wl, _) in enumerate(_passage()):
+        if ev in (0, 20, 30):
+            box, params = _whole_box(wl)
+            ref = oracle.run_workload(box, merge_mode=oracle.PAIR, **oracle_params(params))
+            assert ref.out_total < box.n
+            _check_blocks(ref.out["w"], ref.out["px"], ref.out["py"], ref.out["pz"], box.w.sum() / 2)
+
+
+@pytest.mark.gpu
+def test_gpu_whole_box_matches_oracle():
+    """12,000 particles in one cell: the global-memory bin of the library."""
+    pytest.importorskip("torch")
+    from paper_1504_00636_amd import vpm
+    from tests.gpu_common import check_merged_values, gpu_run
+    for ev, (wl, _) in enumerate(_passage()):
+        if ev in (0, 20, 30):
+            box, params = _whole_box(wl)
+            ref = oracle.run_workload(box, merge_mode=oracle.PAIR, **oracle_params(params))
+            got, got_off, tot = gpu_run(box, params, merge=vpm.VPM_MERGE_PAIR)
+            assert tot == ref.out_total
+            check_merged_values(box, params, vpm.VPM_MERGE_PAIR, got, got_off, ref)
