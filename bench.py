@@ -260,13 +260,17 @@ def time_plain(ctx, vpm, wl64, prm, steps):
     return dict(ms_per_step=ms, value=n / (ms * 1e-3), n_out=n_out, conservation=cons)
 
 
-def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps):
-    """One more population: FIXED FP32 timing and, unless fp64_steps == 0, the plain FP64 form."""
+def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True):
+    """One more population: FIXED FP32 timing and, unless fp64_steps == 0, the plain FP64 form.
+    tune = False keeps the context's batching configuration."""
     import torch
     n = wl32.n
     arrs, off = vpm.upload(wl32)
     p32 = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
-    tuning, tune_s = autotune(ctx, vpm, arrs, off, n, p32)
+    if tune:
+        tuning, tune_s = autotune(ctx, vpm, arrs, off, n, p32)
+    else:
+        tuning, tune_s = ctx.get_tuning().as_dict(), 0.0
     ms, out, _, n_out, kernels, _ = time_fixed(ctx, vpm, arrs, off, n, p32, steps, 2, True)
     rec = dict(workload=name, n_particles=n, n_cells=wl32.n_cells, ms_per_step=ms, value=n / (ms * 1e-3),
                tuning=tuning, autotune_s=tune_s,
@@ -458,6 +462,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default batching configuration (profiling runs: one kernel configuration only)")
     ap.add_argument("--valu-summary", metavar="PMC_DIR")
+    ap.add_argument("--shower-only", action="store_true",
+                    help="time only the shower population (every size bin) and print its record (profiling runs)")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the merge event captured in a HIP graph (checked against an eager call)")
     args = ap.parse_args()
@@ -478,6 +484,15 @@ def main():
 
     if args.copy_calib:
         copy_calibration()
+        return
+    if args.shower_only:
+        ctx = vpm.Context(0)
+        ctx.reserve(52_000_000, 64 ** 3)
+        sh = W.shower_grid(nc=64, seed=args.seed)
+        if args.no_autotune:        # the configuration the autotuner usually picks for this population
+            ctx.set_tuning(vpm.make_tuning(ppl=16, concurrent_bins=1))
+        print(json.dumps(extra_workload(ctx, vpm, "shower_64cubed_lognormal64", sh, None, dict(sh.params),
+                                        args.steps, 0, tune=not args.no_autotune)))
         return
 
     t0 = time.time()

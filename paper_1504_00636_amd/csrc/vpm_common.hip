@@ -11,8 +11,8 @@ constexpr int SCAN_PER_THREAD = 4;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_PER_THREAD;
 
 __global__ void k_reset(int32_t* counters) {
-    // queue lengths [0, 8) and work counters [8, 16)
-    if (threadIdx.x < 16) counters[threadIdx.x] = 0;
+    // queue lengths [0, 8), work counters [8, 16), size-class list lengths [BIGQ_LEN0, +4)
+    if (threadIdx.x < BIGQ_LEN0 + BIGQ_CLASSES) counters[threadIdx.x] = 0;
 }
 
 // Classify every cell by size and append it to its queue (wave-aggregated atomics).
@@ -21,9 +21,10 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
                                              int32_t* q_a, int32_t* q_b, int32_t* q_c, int32_t* q_big, int32_t* q_s,
                                              int64_t* out_count,
                                              uint8_t* cell_mode, uint32_t* flags, BinLimits lim,
-                                             const uint8_t* species, int n_species) {
+                                             const uint8_t* species, int n_species, int32_t* bq0,
+                                             int32_t* bq1, int32_t* bq2, int32_t* bq3) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int cls = -1;
+    int cls = -1, big = -1;
     if (c < n_cells) {
         const int64_t lo = cell_off[c], hi = cell_off[c + 1];
         int64_t n = hi - lo;
@@ -49,6 +50,7 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
             cls = Q_C;
         } else {
             cls = Q_BIG;
+            big = n <= 8192 ? 0 : n <= 16384 ? 1 : n <= 32768 ? 2 : 3;
         }
     }
     int32_t* qs[Q_COUNT] = {q_untouched, q_a, q_b, q_c, q_big, q_s};
@@ -61,6 +63,17 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
         if (lane_id() == leader) base = atomicAdd(&counters[q], __popcll(m));
         base = __shfl(base, leader);
         if (cls == q) qs[q][base + __popcll(m & lanes_below())] = (int32_t)c;
+    }
+    int32_t* bqs[BIGQ_CLASSES] = {bq0, bq1, bq2, bq3};
+#pragma unroll
+    for (int k = 0; k < BIGQ_CLASSES; ++k) {
+        const uint64_t m = __ballot(big == k);
+        if (m == 0) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(&counters[BIGQ_LEN0 + k], __popcll(m));
+        base = __shfl(base, leader);
+        if (big == k) bqs[k][base + __popcll(m & lanes_below())] = (int32_t)c;
     }
 }
 
@@ -221,7 +234,7 @@ hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* c
     hipLaunchKernelGGL(k_bin, dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells, n_particles,
                        n_min_cell, ws.counters, ws.queue[Q_UNTOUCHED], ws.queue[Q_A], ws.queue[Q_B],
                        ws.queue[Q_C], ws.queue[Q_BIG], ws.queue[Q_S], ws.out_count, ws.cell_mode, ws.flags, lim,
-                       species, n_species);
+                       species, n_species, ws.bigq[0], ws.bigq[1], ws.bigq[2], ws.bigq[3]);
     if (lc.post) lc.post(lc.prof, "bin", lc.stream);
     return hipGetLastError();
 }

@@ -443,6 +443,7 @@ struct FixedArgs {
     uint8_t* cell_mode;
     uint32_t* flags;
     int32_t *perm, *subset_id, *n_subsets;
+    const int32_t* bigq[BIGQ_CLASSES];   // the large-cell queue by size class (large-cell bin only)
     uint8_t* big;                  // global slabs for the large-cell path
     int64_t big_stride;            // bytes per slab
 };
@@ -1330,6 +1331,13 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
     // cell sizes here, and single claims keep the tail of the launch short.
     const int qlen = A.counters[A.qlen_index];
     if (qlen == 0) return;                         // an empty bin claims nothing
+    // the global-memory bin claims its cells largest size class first: its duration is set by its
+    // largest cells, which would otherwise be claimed in cell order, possibly last
+    int nbig[BIGQ_CLASSES] = {};
+    if constexpr (!IN_LDS) {
+#pragma unroll
+        for (int k = 0; k < BIGQ_CLASSES; ++k) nbig[k] = A.counters[BIGQ_LEN0 + k];
+    }
     for (;;) {
         int qi = 0;
         if constexpr (WPB == 1) {
@@ -1346,7 +1354,21 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             qi = __builtin_amdgcn_readfirstlane(sh.qi);
         }
         if (qi >= qlen) break;
-        const int c = A.queue[qi];
+        int c;
+        if constexpr (IN_LDS) {
+            c = A.queue[qi];
+        } else {
+            int v = qi;
+            const int32_t* qp = A.bigq[0];
+            bool found = false;
+#pragma unroll
+            for (int k = BIGQ_CLASSES - 1; k > 0; --k) {          // constant indices only
+                if (!found) {
+                    if (v < nbig[k]) { qp = A.bigq[k]; found = true; } else v -= nbig[k];
+                }
+            }
+            c = qp[v];
+        }
         const int64_t off = A.cell_off[c];
         const int n = (int)(A.cell_off[c + 1] - off);
         // the lane and thread indices as values formed anew for each cell (see opaque_lane)
@@ -1892,6 +1914,7 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
     A.flags = ws.flags;
     A.perm = nullptr; A.subset_id = nullptr; A.n_subsets = nullptr;
     A.big = nullptr; A.big_stride = 0;
+    for (int k = 0; k < BIGQ_CLASSES; ++k) A.bigq[k] = ws.bigq[k];
     G.perm = perm; G.subset_id = subset_id; G.n_subsets = n_subsets;
     G.starts = ws.perm2;
     const int qs[5] = {Q_BIG, Q_C, Q_B, Q_S, Q_A};
@@ -1925,6 +1948,7 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
     A.perm = perm; A.subset_id = subset_id; A.n_subsets = n_subsets;
     A.big = ws.big;
     A.big_stride = fixed_big_slab_bytes();
+    for (int k = 0; k < BIGQ_CLASSES; ++k) A.bigq[k] = ws.bigq[k];
 
     // The three bins touch disjoint cells, queues and counters, so they may run concurrently: the
     // large-cell and 2048 bins go first on the side streams (their cells are the longest), the

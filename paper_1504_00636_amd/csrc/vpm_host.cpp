@@ -108,6 +108,7 @@ void free_ws(Workspace& ws) {
     if (ws.out_count) hipFree(ws.out_count);
     if (ws.cell_mode) hipFree(ws.cell_mode);
     for (int q = 0; q < Q_COUNT; ++q) if (ws.queue[q]) hipFree(ws.queue[q]);
+    for (int k = 0; k < BIGQ_CLASSES; ++k) if (ws.bigq[k]) hipFree(ws.bigq[k]);
     if (ws.counters) hipFree(ws.counters);
     if (ws.flags) hipFree(ws.flags);
     if (ws.scan_blocks) hipFree(ws.scan_blocks);
@@ -343,6 +344,7 @@ vpm_status vpm_reserve(vpm_ctx* ctx, int64_t max_particles, int64_t max_cells) {
     alloc((void**)&ws.out_count, (size_t)nc * 8);
     alloc((void**)&ws.cell_mode, (size_t)nc);
     for (int q = 0; q < Q_COUNT; ++q) alloc((void**)&ws.queue[q], (size_t)nc * 4);
+    for (int k = 0; k < BIGQ_CLASSES; ++k) alloc((void**)&ws.bigq[k], (size_t)nc * 4);
     alloc((void**)&ws.counters, 4096);
     alloc((void**)&ws.flags, 256);
     alloc((void**)&ws.scan_blocks, (size_t)(nc / 4096 + 2) * 8);

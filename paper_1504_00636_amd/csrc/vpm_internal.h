@@ -19,6 +19,10 @@ constexpr int NMAX_BIG = 65536; // 8 wavefronts per cell, working set in a globa
 constexpr int NMAX_S = 512;     // batches of small cells: 1 wavefront, up to 512 particles in LDS
 constexpr int SMALL_MAX = 256;  // largest cell the small-cell bin may take
 enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_C = 3, Q_BIG = 4, Q_S = 5, Q_COUNT = 6 };
+// The cells of Q_BIG are also listed by size class (k: up to 8192 << k particles), so that the
+// global-memory bin can claim its largest cells first; the lists' lengths are counters
+// [BIGQ_LEN0, BIGQ_LEN0 + 4).
+constexpr int BIGQ_CLASSES = 4, BIGQ_LEN0 = 24;
 
 // Status bits (mirrors VPM_FLAG_* plus one internal bit).
 constexpr uint32_t FLAG_BAD_VALUE = VPM_FLAG_BAD_VALUE;
@@ -36,6 +40,7 @@ struct Workspace {
     int64_t* out_count = nullptr;   // [cap_cells]
     uint8_t* cell_mode = nullptr;   // [cap_cells]
     int32_t* queue[Q_COUNT] = {};   // [cap_cells] each
+    int32_t* bigq[BIGQ_CLASSES] = {};   // [cap_cells] each: Q_BIG's cells by size class
     int32_t* counters = nullptr;    // [64]: queue lengths, work counters
     uint32_t* flags = nullptr;      // sticky status
     int64_t* scan_blocks = nullptr; // block totals for the offset scan
