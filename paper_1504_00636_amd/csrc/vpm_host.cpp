@@ -497,31 +497,39 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
     vpm_tuning cur = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128};
     float cur_ms = 0.f;
     st = time_cfg(cur, cur_ms);
-    // coordinate search: each parameter in turn over its candidates, keeping the others
+    // coordinate search: each parameter in turn over its candidates, keeping the others; a second
+    // pass when the first changed something.  Concurrency goes first: it changes which bin limits
+    // are best more than the limits change whether concurrency pays.
     const int ppls[3] = {8, 16, 32};
     const int as[5] = {320, 384, 448, 512, NMAX_A};
     const int bs[3] = {1024, 1536, NMAX_B};
     const int cs[3] = {2560, 3456, NMAX_C};
     const int conc[2] = {0, 1};
     const int ss[5] = {0, 32, 64, 128, SMALL_MAX};
-    for (int dim = 0; dim < 6 && st == VPM_OK; ++dim) {
-        const int* cand = dim == 0 ? ppls : dim == 1 ? as : dim == 2 ? bs : dim == 3 ? cs : dim == 4 ? conc : ss;
-        const int nc = dim == 1 || dim == 5 ? 5 : dim == 4 ? 2 : 3;
-        for (int k = 0; k < nc && st == VPM_OK; ++k) {
-            vpm_tuning t = cur;
-            if (dim == 0) t.ppl = cand[k];
-            else if (dim == 1) t.bin_a_max = cand[k];
-            else if (dim == 2) t.bin_b_max = cand[k];
-            else if (dim == 3) t.bin_c_max = cand[k];
-            else if (dim == 4) t.concurrent_bins = cand[k];
-            else t.bin_s_max = cand[k];
-            if (vpm_check_tuning(&t) != VPM_OK) continue;
-            if (t.ppl == cur.ppl && t.bin_a_max == cur.bin_a_max && t.bin_b_max == cur.bin_b_max &&
-                t.bin_c_max == cur.bin_c_max && t.concurrent_bins == cur.concurrent_bins && t.bin_s_max == cur.bin_s_max)
-                continue;
-            float ms = 0.f;
-            st = time_cfg(t, ms);
-            if (st == VPM_OK && ms < cur_ms * 0.99f) { cur = t; cur_ms = ms; }
+    bool changed = true;
+    for (int pass = 0; pass < 2 && changed && st == VPM_OK; ++pass) {
+        changed = false;
+        const int order[6] = {4, 0, 1, 2, 3, 5};
+        for (int di = 0; di < 6 && st == VPM_OK; ++di) {
+            const int dim = order[di];
+            const int* cand = dim == 0 ? ppls : dim == 1 ? as : dim == 2 ? bs : dim == 3 ? cs : dim == 4 ? conc : ss;
+            const int nc = dim == 1 || dim == 5 ? 5 : dim == 4 ? 2 : 3;
+            for (int k = 0; k < nc && st == VPM_OK; ++k) {
+                vpm_tuning t = cur;
+                if (dim == 0) t.ppl = cand[k];
+                else if (dim == 1) t.bin_a_max = cand[k];
+                else if (dim == 2) t.bin_b_max = cand[k];
+                else if (dim == 3) t.bin_c_max = cand[k];
+                else if (dim == 4) t.concurrent_bins = cand[k];
+                else t.bin_s_max = cand[k];
+                if (vpm_check_tuning(&t) != VPM_OK) continue;
+                if (t.ppl == cur.ppl && t.bin_a_max == cur.bin_a_max && t.bin_b_max == cur.bin_b_max &&
+                    t.bin_c_max == cur.bin_c_max && t.concurrent_bins == cur.concurrent_bins && t.bin_s_max == cur.bin_s_max)
+                    continue;
+                float ms = 0.f;
+                st = time_cfg(t, ms);
+                if (st == VPM_OK && ms < cur_ms * 0.99f) { cur = t; cur_ms = ms; changed = true; }
+            }
         }
     }
     hipEventDestroy(e0);
