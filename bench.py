@@ -352,7 +352,8 @@ def subset_labels(perm, sid, n_subsets_cell_off):
 def precision_sweep(ctx, vpm, W, means, seed):
     """The two-stream population at several densities: the batched fixed-point FP32 form against the
     plain FP64 form on the same particles: time, conserved-total error of each against the exact
-    input totals, and the fraction of particles whose final subset is the same in both."""
+    input totals, the fraction of particles whose final subset is the same in both, and the
+    fraction of cells partitioned identically."""
     import torch
     recs = []
     for mean in means:
@@ -381,12 +382,18 @@ def precision_sweep(ctx, vpm, W, means, seed):
         del out64
         ctx.partition(arrs64, off64, n, p64, perm, sid, nsub)
         lab64 = subset_labels(perm, sid, off64)
-        agree = float((lab32 == lab64).double().mean().item())
-        del arrs64, lab32, lab64, perm, sid, nsub
+        same = lab32 == lab64
+        agree = float(same.double().mean().item())
+        cid = torch.repeat_interleave(torch.arange(wl64.n_cells, device="cuda"), off64[1:] - off64[:-1],
+                                      output_size=n)
+        differ = torch.zeros(wl64.n_cells, dtype=torch.int32, device="cuda").index_add_(0, cid, (~same).int())
+        cells_agree = float((differ == 0).double().mean().item())
+        del arrs64, lab32, lab64, perm, sid, nsub, same, cid, differ
         torch.cuda.empty_cache()
         recs.append(dict(mean_per_cell=mean, n_particles=n, fixed_fp32_ms=ms32, plain_fp64_ms=ms64,
                          speedup=ms64 / ms32, fixed_fp32_conservation=cons32, plain_fp64_conservation=cons64,
-                         merge_ratio_fp32=n_out32 / n, merge_ratio_fp64=n_out64 / n, partition_agreement=agree))
+                         merge_ratio_fp32=n_out32 / n, merge_ratio_fp64=n_out64 / n, partition_agreement=agree,
+                         identical_cells=cells_agree))
         log(f"[bench] precision sweep, mean {mean}: FP32 {ms32:.2f} ms, FP64 {ms64:.2f} ms, agreement {agree:.5f}")
     return dict(workload="two_stream_256x256_poisson_mean", tolerances=[0.1, 0.05], points=recs)
 
