@@ -276,6 +276,7 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True
                tuning=tuning, autotune_s=tune_s,
                unit="particles/s", merge_ratio=n_out / n,
                conservation=conservation_error(arrs, out, n_out, prm["mass"]),
+               merged_cv=merged_cv(ctx, vpm, arrs, off, n, p32, prm),
                kernels={k: round(v["avg_ms"], 4) for k, v in kernels.items()},
                params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset")})
     del arrs, out
@@ -328,6 +329,46 @@ def species_shower(ctx, vpm, W, seed, steps=5, warmup=2):
                 value=n / (ms * 1e-3), unit="particles/s", merge_ratio=n_out / n, conservation=cons,
                 device_flags=flags, tuning=ctx.get_tuning().as_dict(),
                 params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset")})
+
+
+def merged_cv(ctx, vpm, arrs, off, n, p, prm):
+    """Largest real-valued coefficients of variation (Eqs. cv_x and cv_p, in FP64 from the FP32
+    values) over the subsets that the fixed-point partition merges, per kind of axis, against the
+    tolerances: the fixed-point rule decides on the particles' codes, so a merged subset's CV may
+    exceed its tolerance by the codes' quantisation."""
+    import torch
+    n_cells = off.numel() - 1
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    sid = torch.empty(n, dtype=torch.int32, device="cuda")
+    nsub = torch.empty(n_cells, dtype=torch.int32, device="cuda")
+    ctx.partition(arrs, off, n, p, perm, sid, nsub)
+    cid = torch.repeat_interleave(torch.arange(n_cells, device="cuda"), off[1:] - off[:-1], output_size=n)
+    ok = sid >= 0
+    key = (cid * (1 << 20) + sid.long())[ok]
+    src = perm.long()[ok]
+    del cid, sid, nsub
+    _, inv = torch.unique_consecutive(key, return_inverse=True)
+    ns = int(inv.max().item()) + 1 if inv.numel() else 0
+    cnt = torch.bincount(inv, minlength=ns)
+    w = arrs[6][src].double()
+    W = torch.zeros(ns, dtype=torch.float64, device="cuda").index_add_(0, inv, w)
+    merged = cnt >= prm["min_subset"]
+    worst = []
+    for l in range(6):
+        v = arrs[l][src].double()
+        s1 = torch.zeros(ns, dtype=torch.float64, device="cuda").index_add_(0, inv, w * v)
+        mean = s1 / W
+        s2 = torch.zeros(ns, dtype=torch.float64, device="cuda").index_add_(0, inv, w * (v - mean[inv]) ** 2)
+        sigma = torch.sqrt(s2 / W)
+        if l < 3:
+            cv = sigma / prm["cell_len"][l]
+        else:
+            cv = torch.where(sigma == 0, torch.zeros_like(sigma), sigma / mean.abs())
+        worst.append(float(cv[merged].max().item()) if bool(merged.any()) else 0.0)
+    del perm, key, src, inv, w
+    torch.cuda.empty_cache()
+    return dict(merged_subsets=int(merged.sum().item()), max_cv_position=max(worst[:3]),
+                max_cv_momentum=max(worst[3:]), tol_x=prm["tol_x"], tol_p=prm["tol_p"])
 
 
 def subset_labels(perm, sid, n_subsets_cell_off):
@@ -537,6 +578,7 @@ def main():
     traffic = traffic_from_profiles()
     bytes_step = 28.0 * n * (1.0 + rho)
     cons32 = conservation_error(arrs32, out32, n_out, prm["mass"])
+    cv32 = merged_cv(ctx, vpm, arrs32, off, n, p32, prm)
     del out32
     torch.cuda.empty_cache()
 
@@ -643,6 +685,7 @@ def main():
         "pipeline_GBps": bytes_step / (ms_step * 1e-3) / 1e9,
         "kernels": kernels,
         "conservation": cons32,
+        "merged_cv": cv32,
         "plain_fp64": plain,
         "device_flags": flags,
         "workloads": extra,
