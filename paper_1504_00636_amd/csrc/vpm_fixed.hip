@@ -587,9 +587,9 @@ VPM_DEV int compact_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int lid
     const IdxT* sp = src + start;
     const int last = len - 1;
     if constexpr (sizeof(IdxT) == 4) {
-        // working set in global memory: the indices, then the codes, of four rounds are loaded
+        // working set in global memory: the indices, then the codes, of eight rounds are loaded
         // before any is placed, so that the loads' latencies overlap
-        constexpr int B = 4;
+        constexpr int B = 8;
         const int step = solo ? 1 : g;
         const int l0 = solo ? 0 : lid;
         int lb = 0, rb = 0;
@@ -687,12 +687,12 @@ VPM_DEV void record_final(const CellMem<IdxT>& M, const FixedArgs& A, const Deci
 }
 
 // Moments of the members src[0 .. cnt) over a lane group (lanes lid < g take part).  With the
-// working set in global memory (32-bit indices) four members' indices, then their codes, are loaded
-// before any is used, so that the loads' latencies overlap.
+// working set in global memory (32-bit indices) eight members' indices, then their codes, are
+// loaded before any is used, so that the loads' latencies overlap.
 template <typename IdxT>
 VPM_DEV void sum_members(const CellMem<IdxT>& M, FSums& S, const IdxT* src, int cnt, int lid, int g) {
     if constexpr (sizeof(IdxT) == 4) {
-        constexpr int B = 4;
+        constexpr int B = 8;
         for (int j0 = lid; j0 < cnt; j0 += B * g) {
             IdxT ix[B];
 #pragma unroll
