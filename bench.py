@@ -578,7 +578,9 @@ def main():
     traffic = traffic_from_profiles()
     bytes_step = 28.0 * n * (1.0 + rho)
     cons32 = conservation_error(arrs32, out32, n_out, prm["mass"])
-    cv32 = merged_cv(ctx, vpm, arrs32, off, n, p32, prm)
+    # (a vpm_partition launch of its own: left out of the counter and trace runs, which pass
+    # --no-extra, so that they see the timed form's launches only)
+    cv32 = None if args.no_extra else merged_cv(ctx, vpm, arrs32, off, n, p32, prm)
     del out32
     torch.cuda.empty_cache()
 
