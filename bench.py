@@ -260,9 +260,10 @@ def time_plain(ctx, vpm, wl64, prm, steps):
     return dict(ms_per_step=ms, value=n / (ms * 1e-3), n_out=n_out, conservation=cons)
 
 
-def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True):
+def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True, cv=True):
     """One more population: FIXED FP32 timing and, unless fp64_steps == 0, the plain FP64 form.
-    tune = False keeps the context's batching configuration."""
+    tune = False keeps the context's batching configuration; cv = False leaves out the
+    merged-subset CVs (a vpm_partition launch of their own)."""
     import torch
     n = wl32.n
     arrs, off = vpm.upload(wl32)
@@ -276,7 +277,7 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True
                tuning=tuning, autotune_s=tune_s,
                unit="particles/s", merge_ratio=n_out / n,
                conservation=conservation_error(arrs, out, n_out, prm["mass"]),
-               merged_cv=merged_cv(ctx, vpm, arrs, off, n, p32, prm),
+               merged_cv=merged_cv(ctx, vpm, arrs, off, n, p32, prm) if cv else None,
                kernels={k: round(v["avg_ms"], 4) for k, v in kernels.items()},
                params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset")})
     del arrs, out
@@ -540,7 +541,7 @@ def main():
         if args.no_autotune:        # the configuration the autotuner usually picks for this population
             ctx.set_tuning(vpm.make_tuning(ppl=16, concurrent_bins=1))
         print(json.dumps(extra_workload(ctx, vpm, "shower_64cubed_lognormal64", sh, None, dict(sh.params),
-                                        args.steps, 0, tune=not args.no_autotune)))
+                                        args.steps, 0, tune=not args.no_autotune, cv=False)))
         return
 
     t0 = time.time()
