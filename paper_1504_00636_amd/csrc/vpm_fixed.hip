@@ -584,48 +584,10 @@ VPM_DEV int compact_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int lid
         const int w = *(const int32_t*)(cbase + (uint32_t)i * cstride);
         return cshift < 0 ? w : ((w << cshift) >> 16);
     };
-    const IdxT* sp = src + start;
-    const int last = len - 1;
-    if constexpr (sizeof(IdxT) == 4) {
-        // working set in global memory: the indices, then the codes, of eight rounds are loaded
-        // before any is placed, so that the loads' latencies overlap
-        constexpr int B = 8;
-        const int step = solo ? 1 : g;
-        const int l0 = solo ? 0 : lid;
-        int lb = 0, rb = 0;
-        for (int j0 = 0; j0 < len; j0 += B * step) {
-            IdxT ix[B];
-            int cvs[B];
-#pragma unroll
-            for (int u = 0; u < B; ++u) ix[u] = sp[min(j0 + u * step + l0, last)];
-#pragma unroll
-            for (int u = 0; u < B; ++u) cvs[u] = code_of(ix[u]);
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const int jb = j0 + u * step;                  // the round's first position (group-uniform)
-                if (jb >= len) break;
-                const bool right = cvs[u] > thr;
-                if (solo) {
-                    dst[start + (right ? last - rb : lb)] = ix[u];
-                    rb += right ? 1 : 0;
-                    lb += right ? 0 : 1;
-                } else {
-                    const bool act = jb + lid < len;
-                    const uint64_t bra = __ballot(act && right) & gmask;
-                    const int rr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bra >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bra, 0u));
-                    if (act) dst[start + (right ? len - 1 - (rb + rr) : lb + (lid - rr))] = ix[u];
-                    const int nr = __popcll(bra);
-                    lb += min(g, len - jb) - nr;
-                    rb += nr;
-                }
-            }
-        }
-        wave_fence();
-        return lb;
-    }
     // software-pipelined: the code of the next position and the index of the one after it are loaded
     // while the current position is placed (reads past the subset's end repeat its last slot)
+    const IdxT* sp = src + start;
+    const int last = len - 1;
     IdxT i_nxt = sp[min(g + lid, last)];
     IdxT i_cur = sp[min(lid, last)];
     int cv_cur = code_of(i_cur);
@@ -667,6 +629,63 @@ VPM_DEV int compact_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int lid
 
 }
 
+// The global-memory bin's Step 6 with the children's moments: as compact_node, but each member's
+// whole record is loaded and added to the moments of the child it goes to while it is placed, so
+// the members are read from global memory once instead of twice.  Eight rounds of indices, then
+// records, are loaded before any is used.  Returns |V1|.
+template <typename IdxT>
+VPM_DEV int compact_sum_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int lid, int g, int gbase, bool solo,
+                             FSums& L, FSums& R) {
+    const int start = nd.start, len = nd.len;
+    const int k = nd.thr_axis & 7;
+    const int thr = nd.thr_axis >> 8;
+    const IdxT* sp = idx_buf(M, cur) + start;
+    IdxT* dst = idx_buf(M, cur ^ 1);
+    const uint64_t gmask = (g == 64 ? ~0ull : ((1ull << g) - 1ull)) << gbase;
+    const int last = len - 1;
+    constexpr int B = 8;
+    const int step = solo ? 1 : g;
+    const int l0 = solo ? 0 : lid;
+    int lb = 0, rb = 0;
+    for (int j0 = 0; j0 < len; j0 += B * step) {
+        IdxT ix[B];
+        int4 r[B];
+        int32_t v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) ix[u] = sp[min(j0 + u * step + l0, last)];
+#pragma unroll
+        for (int u = 0; u < B; ++u) { r[u] = M.rec[ix[u]]; v[u] = M.pyz[ix[u]]; }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int jb = j0 + u * step;                      // the round's first position (group-uniform)
+            if (jb >= len) break;
+            const int c0 = r[u].w >> 16, c1 = (v[u] << 16) >> 16, c2 = v[u] >> 16;
+            const int cv = k == 0 ? c0 : k == 1 ? c1 : k == 2 ? c2 : k == 3 ? r[u].x : k == 4 ? r[u].y : r[u].z;
+            const bool right = cv > thr;
+            bool act = true;
+            if (solo) {
+                dst[start + (right ? last - rb : lb)] = ix[u];
+                rb += right ? 1 : 0;
+                lb += right ? 0 : 1;
+            } else {
+                act = jb + lid < len;
+                const uint64_t bra = __ballot(act && right) & gmask;
+                const int rr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bra >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bra, 0u));
+                if (act) dst[start + (right ? len - 1 - (rb + rr) : lb + (lid - rr))] = ix[u];
+                const int nr = __popcll(bra);
+                lb += min(g, len - jb) - nr;
+                rb += nr;
+            }
+            const int om = act ? (r[u].w & 0xffff) : 0;            // weight 0 adds nothing
+            fsums_add(L, right ? 0 : om, c0, c1, c2, r[u].x, r[u].y, r[u].z);
+            fsums_add(R, right ? om : 0, c0, c1, c2, r[u].x, r[u].y, r[u].z);
+        }
+    }
+    wave_fence();
+    return lb;
+}
+
 // A final subset [cs, cs + cl) of the new slot order: its flags for the output, and its members put
 // back into increasing input order where that order is observable (copied particles, or the
 // partition output).  Lanes lid < g of its group take part.
@@ -686,34 +705,14 @@ VPM_DEV void record_final(const CellMem<IdxT>& M, const FixedArgs& A, const Deci
     for (int j = lid; j < cl; j += g) M.info[cs + j] = base | (j == 0 ? INF_HEAD : 0);
 }
 
-// Moments of the members src[0 .. cnt) over a lane group (lanes lid < g take part).  With the
-// working set in global memory (32-bit indices) eight members' indices, then their codes, are
-// loaded before any is used, so that the loads' latencies overlap.
+// Moments of the members src[0 .. cnt) over a lane group (lanes lid < g take part).
 template <typename IdxT>
 VPM_DEV void sum_members(const CellMem<IdxT>& M, FSums& S, const IdxT* src, int cnt, int lid, int g) {
-    if constexpr (sizeof(IdxT) == 4) {
-        constexpr int B = 8;
-        for (int j0 = lid; j0 < cnt; j0 += B * g) {
-            IdxT ix[B];
-#pragma unroll
-            for (int u = 0; u < B; ++u) ix[u] = src[min(j0 + u * g, cnt - 1)];
-            int4 r[B];
-            int32_t v[B];
-#pragma unroll
-            for (int u = 0; u < B; ++u) { r[u] = M.rec[ix[u]]; v[u] = M.pyz[ix[u]]; }
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                if (j0 + u * g >= cnt) continue;
-                fsums_add(S, r[u].w & 0xffff, r[u].w >> 16, (v[u] << 16) >> 16, v[u] >> 16, r[u].x, r[u].y, r[u].z);
-            }
-        }
-    } else {
 #pragma unroll 2
-        for (int j = lid; j < cnt; j += g) {
-            int c[6], om;
-            codes_of(M, src[j], c, om);
-            fsums_add(S, om, c[0], c[1], c[2], c[3], c[4], c[5]);
-        }
+    for (int j = lid; j < cnt; j += g) {
+        int c[6], om;
+        codes_of(M, src[j], c, om);
+        fsums_add(S, om, c[0], c[1], c[2], c[3], c[4], c[5]);
     }
 }
 
@@ -726,7 +725,11 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
     const int cell = (nd.thr_axis >> 4) & 15;
     const Frame& F = frames ? frames[cell] : F0;            // the frame of the subset's cell
     IdxT* dst = idx_buf(M, cur ^ 1);
-    const int nl = compact_node(M, nd, cur, lid, g, gbase, solo);
+    FSums L, R;
+    fsums_zero(L); fsums_zero(R);
+    int nl;
+    if constexpr (sizeof(IdxT) == 4) nl = compact_sum_node(M, nd, cur, lid, g, gbase, solo, L, R);
+    else nl = compact_node(M, nd, cur, lid, g, gbase, solo);
 
     const int n1 = nl, n2 = len - nl;
     int dv0, dv1;
@@ -737,12 +740,12 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
         dv0 = pack_decision(d);
         dv1 = -1;
     } else {
-        FSums L, R;
-        fsums_zero(L); fsums_zero(R);
-        // a child below min_subset is copied whatever its moments: skip its sums
-        const int e1 = n1 >= A.P.min_subset ? n1 : 0, e2 = n2 >= A.P.min_subset ? n2 : 0;
-        sum_members(M, L, dst + start, e1, lid, g);
-        sum_members(M, R, dst + start + n1, e2, lid, g);
+        if constexpr (sizeof(IdxT) != 4) {
+            // a child below min_subset is copied whatever its moments: skip its sums
+            const int e1 = n1 >= A.P.min_subset ? n1 : 0, e2 = n2 >= A.P.min_subset ? n2 : 0;
+            sum_members(M, L, dst + start, e1, lid, g);
+            sum_members(M, R, dst + start + n1, e2, lid, g);
+        }
         // lane 0 of the group decides V1 and lane 1 decides V2; a single lane decides both in turn
         if (g > 1) fsums_pair_reduce(L, R, lid, g);
         int mine0 = 0, mine1 = 0;
