@@ -121,3 +121,33 @@ def test_bad_offsets_flagged_and_skipped():
     c.run(arrs, past, wl.n, vpm.make_params(**PARAMS), out, out_off, out_total)
     torch.cuda.synchronize()
     assert c.device_status(clear=True) & vpm.VPM_FLAG_BAD_OFFSETS
+
+
+def test_two_contexts_on_two_streams():
+    """Two contexts (each with its own workspace) run at the same time on two streams of default
+    priority; each result equals the same population's eager run on the shared context."""
+    wl1 = population([300, 40, 3, 700, 2100, 64, 5000, 17], 21)
+    wl2 = population([20, 600, 1, 580, 900, 4400, 12, 64, 129], 22)
+    ref1 = eager(ctx(max(wl1.n, wl2.n), 16), wl1, vpm.VPM_MERGE_PAIR)
+    ref2 = eager(ctx(), wl2, vpm.VPM_MERGE_PAIR)
+    p = vpm.make_params(**PARAMS)
+    runs = []
+    for wl in (wl1, wl2):
+        c = vpm.Context(0)
+        c.reserve(wl.n, wl.n_cells)
+        arrs, off = vpm.upload(wl)
+        out = [torch.empty_like(a) for a in arrs]
+        out_off = torch.empty(wl.n_cells + 1, dtype=torch.int64, device="cuda")
+        out_total = torch.empty(1, dtype=torch.int64, device="cuda")
+        runs.append((c, arrs, off, wl.n, out, out_off, out_total, torch.cuda.Stream()))
+    torch.cuda.synchronize()
+    for c, arrs, off, n, out, out_off, out_total, s in runs:
+        with torch.cuda.stream(s):
+            c.run(arrs, off, n, p, out, out_off, out_total)
+    torch.cuda.synchronize()
+    for (c, arrs, off, n, out, out_off, out_total, s), (r_out, r_off, r_tot) in zip(runs, (ref1, ref2)):
+        tot = int(out_total.item())
+        assert tot == r_tot and torch.equal(out_off, r_off)
+        for a, b in zip(out, r_out):
+            assert torch.equal(a[:tot].view(torch.int32), b.view(torch.int32))
+        assert c.device_status(clear=True) == 0
