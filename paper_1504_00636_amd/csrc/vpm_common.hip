@@ -15,7 +15,7 @@ __global__ void k_reset(int32_t* counters) {
     if (threadIdx.x < BIGQ_LEN0 + BIGQ_CLASSES) counters[threadIdx.x] = 0;
 }
 
-// Classify every cell by size and append it to its queue (wave-aggregated atomics).
+// Classify every cell by size and append it to its queue (workgroup-aggregated atomics).
 __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_cells, int64_t n_particles,
                                              int32_t n_min_cell, int32_t* counters, int32_t* q_untouched,
                                              int32_t* q_a, int32_t* q_b, int32_t* q_c, int32_t* q_big, int32_t* q_s,
@@ -53,28 +53,43 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
             big = n <= 8192 ? 0 : n <= 16384 ? 1 : n <= 32768 ? 2 : 3;
         }
     }
-    int32_t* qs[Q_COUNT] = {q_untouched, q_a, q_b, q_c, q_big, q_s};
+    // Appends: each wave reserves its run within the workgroup's count of each list (LDS atomics),
+    // then one global atomic per list and workgroup reserves the workgroup's run in the list (one
+    // global atomic per wave and list queued up on the few shared counters otherwise).
+    constexpr int NL = Q_COUNT + BIGQ_CLASSES;   // the queues, then the large-cell size classes
+    __shared__ int s_cnt[NL], s_base[NL];
+    if (threadIdx.x < NL) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int pos_q = 0, pos_b = 0;
 #pragma unroll
-    for (int q = 0; q < Q_COUNT; ++q) {
-        const uint64_t m = __ballot(cls == q);
+    for (int L = 0; L < NL; ++L) {
+        const bool mine = L < Q_COUNT ? cls == L : big == L - Q_COUNT;
+        const uint64_t m = __ballot(mine);
         if (m == 0) continue;
         const int leader = __ffsll((unsigned long long)m) - 1;
-        int base = 0;
-        if (lane_id() == leader) base = atomicAdd(&counters[q], __popcll(m));
-        base = __shfl(base, leader);
-        if (cls == q) qs[q][base + __popcll(m & lanes_below())] = (int32_t)c;
+        int wbase = 0;
+        if (lane_id() == leader) wbase = atomicAdd(&s_cnt[L], __popcll(m));
+        wbase = __shfl(wbase, leader);
+        if (mine) {
+            const int r = wbase + __popcll(m & lanes_below());
+            if (L < Q_COUNT) pos_q = r; else pos_b = r;
+        }
     }
-    int32_t* bqs[BIGQ_CLASSES] = {bq0, bq1, bq2, bq3};
+    __syncthreads();
+    if (threadIdx.x < NL) {
+        const int k = s_cnt[threadIdx.x];
+        const int ci = threadIdx.x < Q_COUNT ? threadIdx.x : BIGQ_LEN0 + (threadIdx.x - Q_COUNT);
+        s_base[threadIdx.x] = k ? atomicAdd(&counters[ci], k) : 0;
+    }
+    __syncthreads();
+    int32_t* const qs[Q_COUNT] = {q_untouched, q_a, q_b, q_c, q_big, q_s};
+    int32_t* const bqs[BIGQ_CLASSES] = {bq0, bq1, bq2, bq3};
 #pragma unroll
-    for (int k = 0; k < BIGQ_CLASSES; ++k) {
-        const uint64_t m = __ballot(big == k);
-        if (m == 0) continue;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        int base = 0;
-        if (lane_id() == leader) base = atomicAdd(&counters[BIGQ_LEN0 + k], __popcll(m));
-        base = __shfl(base, leader);
-        if (big == k) bqs[k][base + __popcll(m & lanes_below())] = (int32_t)c;
-    }
+    for (int q = 0; q < Q_COUNT; ++q)
+        if (cls == q) qs[q][s_base[q] + pos_q] = (int32_t)c;
+#pragma unroll
+    for (int k = 0; k < BIGQ_CLASSES; ++k)
+        if (big == k) bqs[k][s_base[Q_COUNT + k] + pos_b] = (int32_t)c;
 }
 
 // Scan phase 1: per-tile totals of out_count.
