@@ -70,7 +70,11 @@ typedef enum { VPM_MERGE_PAIR = 0, VPM_MERGE_CENTROID = 1 } vpm_merge_mode;
 #define VPM_FLAG_OUT_OF_CELL    0x2u  /* a particle lay more than one cell length from the cell's
                                          lowest coordinate; its position code was clamped (FIXED)  */
 #define VPM_FLAG_CELL_TOO_LARGE 0x4u  /* a cell above 65,536 particles: passed through            */
-#define VPM_FLAG_BAD_OFFSETS    0x8u  /* cell_off decreasing, not starting at 0, or past n_particles */
+#define VPM_FLAG_BAD_OFFSETS    0x8u  /* cell_off decreasing, not starting at 0, or past n_particles;
+                                         a cell whose own range is invalid is passed through, but
+                                         cells whose ranges overlap make the whole output
+                                         unspecified (out_off and out_total are clamped to
+                                         n_particles and nothing is written past it)              */
 #define VPM_FLAG_BAD_PARTITION  0x10u /* vpm_merge: a cell's perm/subset_id/n_subsets is not a
                                          partition of that cell; the cell was copied unchanged     */
 #define VPM_FLAG_BAD_SPECIES    0x20u /* vpm_run_species: a cell's species index is not below
@@ -127,7 +131,7 @@ vpm_status vpm_run(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, int
                    int64_t *out_total, hipStream_t stream);
 
 /* Several particle species in one launch, e.g. the electrons, positrons and photons that the
- * paper's shower simulation merges (Sec. "Simulation results", shower): every cell holds particles
+ * paper's shower simulation merges (Sec. "Simulation", subsection "Magnetic Shower"): every cell holds particles
  * of one species, and only the energy sqrt(m^2 + |p|^2) of Step 7 depends on the mass.
  *   cell_species  device uint8[n_cells]: species index s of each cell
  *   species_mass  host double[n_species]: mass of each species in m_e units (finite, >= 0);

@@ -104,8 +104,11 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int64_t* cnt, i
     if (threadIdx.x == 0) tiles[blockIdx.x] = tot;
 }
 
-// Scan phase 2: exclusive scan of the tile totals (single workgroup, loops over chunks).
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tile_totals(int64_t* tiles, int64_t ntiles, int64_t* out_total) {
+// Scan phase 2: exclusive scan of the tile totals (single workgroup, loops over chunks).  The total
+// is clamped to n_particles: offsets that decrease somewhere (flagged by k_bin) can make cells
+// overlap, and their counts then add up to more than the output arrays hold.
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tile_totals(int64_t* tiles, int64_t ntiles, int64_t* out_total,
+                                                                 int64_t n_particles) {
     __shared__ int64_t red[SCAN_BLOCK / WAVE + 1];
     int64_t carry = 0;
     for (int64_t b = 0; b < ntiles; b += SCAN_BLOCK) {
@@ -117,12 +120,14 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tile_totals(int64_t* tiles,
         carry += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out_total = carry;
+    if (threadIdx.x == 0) *out_total = min(carry, n_particles);
 }
 
-// Scan phase 3: write the exclusive prefix (out_off) and out_off[n].
+// Scan phase 3: write the exclusive prefix (out_off, clamped to n_particles like the total; clamping
+// keeps it non-decreasing) and out_off[n].
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int64_t* cnt, int64_t n, const int64_t* tiles,
-                                                           int64_t* out_off, const int64_t* out_total) {
+                                                           int64_t* out_off, const int64_t* out_total,
+                                                           int64_t n_particles) {
     __shared__ int64_t red[SCAN_BLOCK / WAVE + 1];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
     int64_t v[SCAN_PER_THREAD];
@@ -133,7 +138,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int64_t* cnt, i
     int64_t pre = block_exclusive_scan<SCAN_BLOCK>(s, red, &tot) + tiles[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < SCAN_PER_THREAD; ++k) {
-        if (base + k < n) out_off[base + k] = pre;
+        if (base + k < n) out_off[base + k] = min(pre, n_particles);
         pre += v[k];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) out_off[n] = *out_total;
@@ -254,17 +259,17 @@ hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* c
     return hipGetLastError();
 }
 
-hipError_t launch_scan_offsets(const Workspace& ws, const LaunchCfg& lc, int64_t n_cells, int64_t* out_off,
-                               int64_t* out_total) {
+hipError_t launch_scan_offsets(const Workspace& ws, const LaunchCfg& lc, int64_t n_cells, int64_t n_particles,
+                               int64_t* out_off, int64_t* out_total) {
     const int64_t ntiles = (n_cells + SCAN_TILE - 1) / SCAN_TILE;
     if (lc.pre) lc.pre(lc.prof, "scan", lc.stream);
     if (ntiles > 0)
         hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(SCAN_BLOCK), 0, lc.stream, ws.out_count,
                            n_cells, ws.scan_blocks);
     hipLaunchKernelGGL(k_scan_tile_totals, dim3(1), dim3(SCAN_BLOCK), 0, lc.stream, ws.scan_blocks, ntiles,
-                       out_total);
+                       out_total, n_particles);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)(ntiles > 0 ? ntiles : 1)), dim3(SCAN_BLOCK), 0, lc.stream,
-                       ws.out_count, n_cells, ws.scan_blocks, out_off, out_total);
+                       ws.out_count, n_cells, ws.scan_blocks, out_off, out_total, n_particles);
     if (lc.post) lc.post(lc.prof, "scan", lc.stream);
     return hipGetLastError();
 }

@@ -1259,6 +1259,7 @@ struct MergeArgs {
     FixedArgs A;                   // in, params, tmp, out_count, cell_mode, flags
     const int32_t *perm, *subset_id, *n_subsets;
     int32_t* starts;               // scratch: first slot of every subset, indexed by input position
+    int32_t* marks;                // scratch: a slot holding each member, indexed by input position
 };
 
 __global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs G) {
@@ -1286,7 +1287,19 @@ __global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs G) {
             ok = m >= off && m < off + n && sd >= 0 && sd < nsub && (sd == prev || sd == prev + 1) &&
                  (p != n - 1 || sd == nsub - 1);
         }
-        const bool part_ok = __ballot(!ok) == 0;
+        bool part_ok = __ballot(!ok) == 0;
+        if (part_ok) {
+            // every member exactly once: each slot writes its position at its member's mark, then
+            // checks that the mark holds it (of two slots naming one member only one can pass, and
+            // n slots naming n distinct members of the cell's n form a permutation)
+            for (int p = lane; p < n; p += WAVE) G.marks[G.perm[off + p]] = (int32_t)(off + p);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            bool once = true;
+            for (int p = lane; p < n; p += WAVE) once = once && G.marks[G.perm[off + p]] == (int32_t)(off + p);
+            part_ok = __ballot(!once) == 0;
+        }
         Frame F;
         const bool vals_ok = part_ok && cell_frame(A.in, off, n, cell_mass(A.P.mass, A.P.species, A.P.species_mass, c), F);
         if (!vals_ok) {
@@ -1979,6 +1992,7 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
     for (int k = 0; k < BIGQ_CLASSES; ++k) A.bigq[k] = ws.bigq[k];
     G.perm = perm; G.subset_id = subset_id; G.n_subsets = n_subsets;
     G.starts = ws.perm2;
+    G.marks = ws.perm2 + (ws.cap_particles + 1);   // the second of the two buffers
     const int qs[5] = {Q_BIG, Q_C, Q_B, Q_S, Q_A};
     for (int q : qs) {
         A.queue = ws.queue[q];
@@ -2019,10 +2033,24 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
     bool forked = lc.fork != nullptr;
     for (int i = 0; i < 3; ++i) forked = forked && lc.side[i] && lc.join[i];
     hipError_t e = hipSuccess;
+    // The side streams that have waited on the fork are joined back to the caller's stream on
+    // every return, also after a failure, so that a stream capture in progress stays well formed.
+    int waited = 0;
+    auto join_back = [&](hipError_t err) {
+        for (int i = 0; i < waited; ++i) {
+            const hipError_t r = hipEventRecord(lc.join[i], lc.side[i]);
+            const hipError_t w = r == hipSuccess ? hipStreamWaitEvent(lc.stream, lc.join[i], 0) : r;
+            if (err == hipSuccess) err = w;
+        }
+        return err;
+    };
     if (forked) {
         e = hipEventRecord(lc.fork, lc.stream);
-        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(lc.side[i], lc.fork, 0);
-        if (e != hipSuccess) return e;
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+            e = hipStreamWaitEvent(lc.side[i], lc.fork, 0);
+            if (e == hipSuccess) waited = i + 1;
+        }
+        if (e != hipSuccess) return join_back(e);
     }
     struct Bin { int q; const char* name; hipStream_t s; };
     const Bin bins[5] = {{Q_BIG, "fixed_cells_big", forked ? lc.side[0] : lc.stream},
@@ -2050,14 +2078,10 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
             hipLaunchKernelGGL((k_fixed_cells<NMAX_BIG, uint32_t, false, WPB_BIG>), dim3(lc.grid_big),
                                dim3(WAVE * WPB_BIG), fixed_lds_bytes(3), b.s, A);
         e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess) return join_back(e);
         if (lc.post) lc.post(lc.prof, b.name, b.s);
     }
-    if (forked) {
-        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventRecord(lc.join[i], lc.side[i]);
-        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(lc.stream, lc.join[i], 0);
-    }
-    return e;
+    return join_back(e);
 }
 
 }  // namespace vpm

@@ -285,7 +285,17 @@ __global__ __launch_bounds__(64) void k_fp64_merge(Fp64MergeArgs G) {
                  (p != n - 1 || sd == nsub - 1) && wv > 0.0 && isfinite(wv);
             for (int l = 0; ok && l < 6; ++l) ok = isfinite(qval(A.in, l, mm));
         }
-        if (__ballot(!ok) != 0) {
+        bool part_ok = __ballot(!ok) == 0;
+        if (part_ok) {
+            // every member exactly once: each slot writes its position at its member's mark (the
+            // first permutation buffer serves as the marks), then checks that the mark holds it
+            for (int p = lane; p < n; p += WAVE) A.perm2[G.perm[off + p]] = (int32_t)(off + p);
+            fence_wave();
+            bool once = true;
+            for (int p = lane; p < n; p += WAVE) once = once && A.perm2[G.perm[off + p]] == (int32_t)(off + p);
+            part_ok = __ballot(!once) == 0;
+        }
+        if (!part_ok) {
             if (lane == 0) {
                 if (nsub >= 1) atomicOr(A.flags, FLAG_BAD_PARTITION);
                 A.out_count[c] = n;

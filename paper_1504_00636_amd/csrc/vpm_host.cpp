@@ -220,7 +220,7 @@ vpm_status run_impl(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, in
         e = launch_fp64_cells(ctx->ws, lc, soa64(in), cell_off, n_cells, fp, 0, nullptr, nullptr, nullptr);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "cells");
-    e = launch_scan_offsets(ctx->ws, lc, n_cells, out_off, out_total);
+    e = launch_scan_offsets(ctx->ws, lc, n_cells, n_particles, out_off, out_total);
     if (e != hipSuccess) return hip_fail(ctx, e, "scan");
     const void* ins[7] = {in->x, in->y, in->z, in->px, in->py, in->pz, in->w};
     void* outs[7] = {out->x, out->y, out->z, out->px, out->py, out->pz, out->w};
@@ -425,7 +425,7 @@ vpm_status vpm_merge(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, i
         e = launch_fp64_merge(ctx->ws, lc, soa64(in), cell_off, n_cells, fp64_params(p), perm, subset_id,
                               n_subsets);
     if (e != hipSuccess) return hip_fail(ctx, e, "merge");
-    e = launch_scan_offsets(ctx->ws, lc, n_cells, out_off, out_total);
+    e = launch_scan_offsets(ctx->ws, lc, n_cells, n_particles, out_off, out_total);
     if (e != hipSuccess) return hip_fail(ctx, e, "scan");
     const void* ins[7] = {in->x, in->y, in->z, in->px, in->py, in->pz, in->w};
     void* outs[7] = {out->x, out->y, out->z, out->px, out->py, out->pz, out->w};
@@ -469,6 +469,7 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
     if (check_soa(out) != VPM_OK || !out_off || !out_total) return VPM_ERR_INVALID_ARG;
     hipSetDevice(ctx->device);
     const bool was_profiling = ctx->profiling;
+    const vpm_tuning was_tuned = ctx->tune;        // restored if a trial fails
     ctx->profiling = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -535,7 +536,10 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     ctx->profiling = was_profiling;
-    if (st != VPM_OK) return st;
+    if (st != VPM_OK) {
+        ctx->tune = was_tuned;
+        return st;
+    }
     ctx->tune = cur;
     if (best) *best = cur;
     // leave the chosen configuration's result in the outputs

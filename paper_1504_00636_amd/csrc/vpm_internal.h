@@ -103,7 +103,8 @@ struct Soa64Out { double *x, *y, *z, *px, *py, *pz, *w; };
 hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,
                       int64_t n_cells, int64_t n_particles, int32_t n_min_cell, BinLimits lim,
                       const uint8_t* species = nullptr, int n_species = 0);
-hipError_t launch_scan_offsets(const Workspace& ws, const LaunchCfg& lc, int64_t n_cells,
+// out_off and out_total are clamped to n_particles (reached only with offsets flagged as bad).
+hipError_t launch_scan_offsets(const Workspace& ws, const LaunchCfg& lc, int64_t n_cells, int64_t n_particles,
                                int64_t* out_off, int64_t* out_total);
 hipError_t launch_scatter(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,
                           int64_t n_cells, int64_t n_particles, const int64_t* out_off,

@@ -151,3 +151,28 @@ def test_two_contexts_on_two_streams():
         for a, b in zip(out, r_out):
             assert torch.equal(a[:tot].view(torch.int32), b.view(torch.int32))
         assert c.device_status(clear=True) == 0
+
+
+def test_overlapping_offsets_write_nothing_past_n_particles():
+    """Offsets that decrease let later cells overlap earlier ones ([0, 80, 30, 100]: cells 0 and 2
+    share particles 30..79).  Their counts would add up past the arrays; out_total and out_off are
+    clamped to n_particles and canaries past it stay untouched."""
+    wl = population([80, 0, 70], 14)                  # 150 particles; only 100 are the call's
+    n = 100
+    c = ctx(n + 64, 3)
+    arrs, _ = vpm.upload(wl)
+    bad = torch.tensor([0, 80, 30, 100], dtype=torch.int64, device="cuda")
+    canary = 64
+    out = [torch.full((n + canary,), 7.0, dtype=torch.float32, device="cuda") for _ in range(7)]
+    out_off = torch.empty(4, dtype=torch.int64, device="cuda")
+    out_total = torch.empty(1, dtype=torch.int64, device="cuda")
+    p = vpm.make_params(**dict(PARAMS, n_min_cell=1000))     # every cell copied: counts 80 + 0 + 70
+    c.device_status(clear=True)
+    c.run([a[:n] for a in arrs], bad, n, p, [o[:n] for o in out], out_off, out_total)
+    torch.cuda.synchronize()
+    assert c.device_status(clear=True) & vpm.VPM_FLAG_BAD_OFFSETS
+    assert int(out_total.item()) <= n
+    oo = out_off.cpu().numpy()
+    assert np.all(np.diff(oo) >= 0) and oo[-1] <= n
+    for o in out:
+        assert torch.all(o[n:] == 7.0)

@@ -318,3 +318,26 @@ def test_merge_rejects_inconsistent_partition():
     assert ctx().device_status(clear=True) & vpm.VPM_FLAG_BAD_PARTITION
     assert got_off[1] - got_off[0] == 50          # copied unchanged
     np.testing.assert_array_equal(got["x"][:50], wl.x[:50].astype(np.float64))
+
+
+@pytest.mark.parametrize("decide", [vpm.VPM_DECIDE_FIXED, vpm.VPM_DECIDE_FP64])
+def test_merge_rejects_duplicated_member(decide):
+    """A perm that lists one member twice (and leaves another out) is not a partition of the cell:
+    the cell is copied unchanged and flagged, in both decision modes."""
+    from tests.gpu_common import ctx
+    dt = np.float32 if decide == vpm.VPM_DECIDE_FIXED else np.float64
+    wl = cloud_cells([60, 40], seed=12, dtype=dt)
+    perm, sid, nsub = gpu_partition(wl, CLOUD, decide=decide)
+    perm = perm.copy()
+    perm[5] = perm[17]                            # member perm[17] twice, old perm[5] missing
+    assert perm[5] >= 0 and perm[5] < 60
+    ctx().device_status(clear=True)
+    got, got_off, tot = _gpu_merge(wl, CLOUD, perm, sid, nsub, decide=decide)
+    assert ctx().device_status(clear=True) & vpm.VPM_FLAG_BAD_PARTITION
+    assert got_off[1] - got_off[0] == 60          # copied unchanged
+    for f in FIELDS:
+        np.testing.assert_array_equal(got[f][:60], getattr(wl, f)[:60].astype(np.float64))
+    # the other cell is merged as usual
+    ref = oracle.run_workload(wl.cells([1]), decide=oracle.FIXED if decide == vpm.VPM_DECIDE_FIXED else oracle.PAPER,
+                              **oracle_params(CLOUD))
+    assert tot - 60 == ref.out_total
