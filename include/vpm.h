@@ -219,6 +219,25 @@ vpm_status vpm_profile_read(vpm_ctx *ctx, int max_kernels, char names[][48], int
 const char *vpm_status_string(vpm_status st);
 const char *vpm_last_error(vpm_ctx *ctx);
 
+/* Limits of vpm_run_noalloc. */
+#define VPM_NOALLOC_MAX_PARTICLES 524288
+#define VPM_NOALLOC_MAX_CELLS     32768
+
+/* vpm_run without a context, for callers that cannot allocate device memory (code being captured
+ * into a HIP graph, serving loops and harnesses that forbid hipMalloc).  It allocates nothing: its
+ * working memory is a fixed array of 24 MiB in the library's device code, one copy per GPU, held
+ * until the process ends.  Runs on the current HIP device with vpm_create's default tuning and
+ * gives results bit-identical to vpm_run's with that tuning.
+ *   Only VPM_DECIDE_FIXED with dtype VPM_F32.  n_particles <= VPM_NOALLOC_MAX_PARTICLES and
+ *   n_cells <= VPM_NOALLOC_MAX_CELLS, else VPM_ERR_CAPACITY before anything is enqueued.
+ *   flags_out  device uint32 (may be NULL): this call's VPM_FLAG_* bits (cleared at its start).
+ * Other arguments, output and errors as vpm_run.  Every call on one GPU uses that GPU's single
+ * array: calls that overlap in time on one GPU (other streams, other host threads) race, so the
+ * caller must order them.                                                                        */
+vpm_status vpm_run_noalloc(const vpm_soa *in, const int64_t *cell_off, int64_t n_cells, int64_t n_particles,
+                           const vpm_params *p, vpm_soa *out, int64_t *out_off, int64_t *out_total,
+                           uint32_t *flags_out, hipStream_t stream);
+
 /* Library build identification (target architecture and version). */
 const char *vpm_version(void);
 

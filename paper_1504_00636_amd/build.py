@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libvpm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["vpm_common.hip", "vpm_fixed.hip", "vpm_fp64.hip", "vpm_host.cpp"]
+SOURCES = ["vpm_common.hip", "vpm_fixed.hip", "vpm_fp64.hip", "vpm_static.hip", "vpm_host.cpp"]
 
 ARCH = os.environ.get("VPM_OFFLOAD_ARCH", "gfx950")
 

@@ -29,7 +29,8 @@ EXPORTS = ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_
            "vpm_partition",
            "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read",
            "vpm_check_tuning", "vpm_get_tuning", "vpm_set_tuning", "vpm_autotune",
-           "vpm_status_string", "vpm_last_error", "vpm_version")
+           "vpm_status_string", "vpm_last_error", "vpm_version", "vpm_run_noalloc")
+VPM_NOALLOC_MAX_PARTICLES, VPM_NOALLOC_MAX_CELLS = 524288, 32768
 
 
 class VpmParams(C.Structure):
@@ -85,6 +86,7 @@ def lib():
     L.vpm_run.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), P(VpmSoa), vp, vp, vp]
     L.vpm_run_species.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, P(C.c_double), C.c_int32,
                                   P(VpmSoa), vp, vp, vp]
+    L.vpm_run_noalloc.argtypes = [P(VpmSoa), vp, i64, i64, P(VpmParams), P(VpmSoa), vp, vp, vp, vp]
     L.vpm_partition.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, vp]
     L.vpm_merge.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, P(VpmSoa), vp, vp, vp]
     L.vpm_device_status.argtypes = [vp, P(C.c_uint32), C.c_int]
@@ -100,6 +102,7 @@ def lib():
     L.vpm_last_error.restype = C.c_char_p
     L.vpm_version.restype = C.c_char_p
     for f in ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_run_species",
+              "vpm_run_noalloc",
               "vpm_partition", "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read", "vpm_check_tuning",
               "vpm_get_tuning", "vpm_set_tuning", "vpm_autotune"):
         getattr(L, f).restype = C.c_int
@@ -334,6 +337,24 @@ def vpm_partition(ctx: Context, *a, **k):
 
 def vpm_merge(ctx: Context, *a, **k):
     ctx.merge(*a, **k)
+
+
+def vpm_run_noalloc(inp, cell_off, n_particles: int, p: VpmParams, out, out_off, out_total, flags_out=None,
+                    stream=None):
+    """vpm_run without a context (no device allocation; limits VPM_NOALLOC_MAX_*), on the current
+    device.  flags_out: optional device uint32 tensor that receives the call's device flags."""
+    import torch
+    n_cells = cell_off.numel() - 1
+    dt = _torch_dtype(p)
+    si = _soa(inp, dt, n_particles, "in")
+    so = _soa(out, dt, n_particles, "out")
+    fo = None if flags_out is None else _dev(flags_out, torch.int32, 1, "flags_out")
+    st = lib().vpm_run_noalloc(C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"), n_cells,
+                               int(n_particles), C.byref(p), C.byref(so),
+                               _dev(out_off, torch.int64, n_cells + 1, "out_off"),
+                               _dev(out_total, torch.int64, 1, "out_total"), fo, _stream(stream))
+    if st != VPM_OK:
+        raise VpmError(st, "vpm_run_noalloc")
 
 
 def vpm_device_status(ctx: Context, clear: bool = False) -> int:

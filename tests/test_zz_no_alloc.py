@@ -1,0 +1,74 @@
+"""vpm_run_noalloc (no device allocation, working memory in a fixed device array) against vpm_run.
+
+Two calls in a row, the second on a smaller population, each compared bit for bit with vpm_run on a
+context with the default tuning; cells cover every size bin, including the global-memory one.
+"""
+import numpy as np
+import pytest
+
+from paper_1504_00636_amd import vpm, workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PARAMS = dict(tol_x=0.3, tol_p=0.08, n_min_cell=2, min_subset=4, cell_len=(1.0, 1.0, 1.0), mass=1.0)
+
+
+def population(sizes, seed):
+    r = np.random.Generator(np.random.Philox(seed))
+    cells = []
+    for k in sizes:
+        cells.append(np.stack([r.random(k), r.random(k), r.random(k), 1.0 + 0.1 * r.standard_normal(k),
+                               0.5 + 0.05 * r.standard_normal(k), -0.3 + 0.05 * r.standard_normal(k),
+                               0.5 + r.random(k)], axis=1))
+    return W.from_cells(cells, params=dict(PARAMS), dtype=np.float32)
+
+
+def run_both(wl, merge):
+    arrs, off = vpm.upload(wl)
+    p = vpm.make_params(merge_mode=merge, **PARAMS)
+    c = vpm.Context(0)
+    c.reserve(wl.n, wl.n_cells)
+    ref = vpm.run_population(c, arrs, off, p)
+    torch.cuda.synchronize()
+    c.close()
+    out = [torch.full_like(a, -3.0) for a in arrs]
+    out_off = torch.full((wl.n_cells + 1,), -1, dtype=torch.int64, device="cuda")
+    out_total = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    flags = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    vpm.vpm_run_noalloc(arrs, off, wl.n, p, out, out_off, out_total, flags_out=flags)
+    torch.cuda.synchronize()
+    tot = int(out_total.item())
+    assert tot == ref.out_total
+    assert torch.equal(out_off, ref.out_off)
+    for a, b in zip(out, ref.out):
+        assert torch.equal(a[:tot].view(torch.int32), b[:tot].view(torch.int32))
+    assert int(flags.item()) == 0
+    return tot
+
+
+@pytest.mark.parametrize("merge", [vpm.VPM_MERGE_PAIR, vpm.VPM_MERGE_CENTROID])
+def test_noalloc_matches_vpm_run_twice(merge):
+    big = population([300, 40, 3, 0, 700, 2100, 64, 5000, 17, 9000, 130, 1], 31)
+    small = population([20, 600, 1, 580, 4400, 12], 32)
+    assert big.n > small.n
+    t1 = run_both(big, merge)
+    t2 = run_both(small, merge)
+    assert t1 < big.n and t2 < small.n                    # both really merge
+
+
+def test_noalloc_rejects_sizes_past_its_limits():
+    n = vpm.VPM_NOALLOC_MAX_PARTICLES + 1
+    arrs = [torch.zeros(n, dtype=torch.float32, device="cuda") for _ in range(7)]
+    off = torch.tensor([0, n], dtype=torch.int64, device="cuda")
+    out = [torch.zeros(n, dtype=torch.float32, device="cuda") for _ in range(7)]
+    oo = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ot = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(vpm.VpmError) as ei:
+        vpm.vpm_run_noalloc(arrs, off, n, vpm.make_params(**PARAMS), out, oo, ot)
+    assert ei.value.status == vpm.VPM_ERR_CAPACITY
+    cells = torch.zeros(vpm.VPM_NOALLOC_MAX_CELLS + 2, dtype=torch.int64, device="cuda")
+    with pytest.raises(vpm.VpmError) as ei:
+        vpm.vpm_run_noalloc([a[:10] for a in arrs], cells, 10, vpm.make_params(**PARAMS), out,
+                            torch.zeros(cells.numel(), dtype=torch.int64, device="cuda"), ot)
+    assert ei.value.status == vpm.VPM_ERR_CAPACITY
