@@ -61,15 +61,25 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        lib = C.CDLL(_LIB)
-        dp = C.POINTER(C.c_double)
-        i64p = C.POINTER(C.c_int64)
-        i32p = C.POINTER(C.c_int32)
-        lib.orc_run.restype = C.c_int
-        lib.orc_run.argtypes = ([C.POINTER(_Params), C.c_int64, i64p] + [dp] * 7 +
-                                [i32p, i32p, i32p] + [dp] * 7 + [i64p, C.c_void_p, C.c_int])
-        _lib = lib
+        _lib = _bind(C.CDLL(_LIB))
     return _lib
+
+
+def _bind(lib):
+    dp = C.POINTER(C.c_double)
+    i64p = C.POINTER(C.c_int64)
+    i32p = C.POINTER(C.c_int32)
+    lib.orc_run.restype = C.c_int
+    lib.orc_run.argtypes = ([C.POINTER(_Params), C.c_int64, i64p] + [dp] * 7 +
+                            [i32p, i32p, i32p] + [dp] * 7 + [i64p, C.c_void_p, C.c_int])
+    return lib
+
+
+def runner(lib):
+    """`run` bound to another build of the oracle's source (the pin tests compile copies with planted
+    mistakes and check that the pins catch them)."""
+    lib = _bind(lib)
+    return lambda *a, **k: run(*a, lib=lib, **k)
 
 
 @dataclass
@@ -99,10 +109,10 @@ def make_params(tol_x, tol_p, n_min_cell=0, min_subset=4, cell_len=(1.0, 1.0, 1.
 
 
 def run(arrays, cell_off, tol_x, tol_p, n_min_cell=0, min_subset=4, cell_len=(1.0, 1.0, 1.0),
-        mass=1.0, merge_mode=PAIR, decide=FIXED, n_threads: int = 0) -> OracleResult:
+        mass=1.0, merge_mode=PAIR, decide=FIXED, n_threads: int = 0, lib=None) -> OracleResult:
     """Run the oracle.  ``arrays`` = (x, y, z, px, py, pz, w), any float dtype (FIXED mode rounds
     the values to FP32 first, as the GPU's fixed-point path does)."""
-    lib = _load()
+    lib = lib or _load()
     p = make_params(tol_x, tol_p, n_min_cell, min_subset, cell_len, mass, merge_mode, decide)
     cell_off = np.ascontiguousarray(cell_off, dtype=np.int64)
     n_cells = cell_off.shape[0] - 1

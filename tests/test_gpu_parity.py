@@ -248,21 +248,42 @@ def test_fp64_path_two_stream():
     assert _fp64_check(wl, wl.params) <= 2
 
 
-@pytest.mark.parametrize("fname", ["px_bisection_6.txt", "corners_tie_4.txt", "px_ladder_8.txt"])
-def test_golden_cells_on_gpu(fname):
+GOLDEN = ["px_bisection_6.txt", "corners_tie_4.txt", "px_ladder_8.txt", "pair_direction_2.txt",
+          "pair_two_clusters_4.txt"]
+
+
+@pytest.mark.parametrize("decide", [vpm.VPM_DECIDE_FIXED, vpm.VPM_DECIDE_FP64])
+@pytest.mark.parametrize("fname", GOLDEN)
+def test_golden_cells_on_gpu(fname, decide):
     """The hand-worked cells (one holds an exact CV tie, which the FP64 filter cannot settle and
-    hands to the exact integer rule) give the expected subsets on the GPU."""
+    hands to the exact integer rule; two derive pair momenta by hand) give the expected subsets and
+    particles on the GPU, on both decision paths."""
     from tests.helpers import load_golden, subsets_of
     arr, prm, merge, subsets, merged = load_golden(fname)
     params = dict(prm, cell_len=(1.0, 1.0, 1.0))
-    wl = W.from_cells([arr], params=params, dtype=np.float32)
+    fp64 = decide == vpm.VPM_DECIDE_FP64
+    wl = W.from_cells([arr], params=params, dtype=np.float64 if fp64 else np.float32)
     mm = vpm.VPM_MERGE_CENTROID if merge == "centroid" else vpm.VPM_MERGE_PAIR
-    perm, sid, nsub = gpu_partition(wl, params, merge=mm)
+    perm, sid, nsub = gpu_partition(wl, params, decide=decide, merge=mm)
     got = subsets_of(perm, sid, wl.cell_off, 0)
     assert [list(map(int, s)) for s in got] == subsets
-    out, out_off, tot = gpu_run(wl, params, merge=mm)
+    out, out_off, tot = gpu_run(wl, params, decide=decide, merge=mm)
     g = np.stack([out[f] for f in ("w", "x", "y", "z", "px", "py", "pz")], axis=1)
-    np.testing.assert_allclose(g, merged, rtol=1e-6, atol=1e-6)
+    tol = 1e-12 if fp64 else 1e-6
+    np.testing.assert_allclose(g, merged, rtol=tol, atol=tol)
+
+
+def test_exact_ties_on_gpu():
+    """Cells whose root holds an exact tie between a position CV and a momentum CV (built from the
+    fixed-point codes, so that the tie is exact): the FP64 filter cannot settle them, and the GPU's
+    exact 128/256-bit rule must give the oracle's partition (ties to the lowest axis)."""
+    from tests.test_oracle_exact_tiny import exact_tie
+    r = np.random.Generator(np.random.Philox(99))
+    cells = [exact_tie(r) for _ in range(300)]
+    params = dict(CLOUD, tol_x=0.01, tol_p=0.01, min_subset=2)
+    wl = W.from_cells(cells, params=params, dtype=np.float32)
+    full_check(wl, params)
+    full_check(wl, params, vpm.VPM_MERGE_CENTROID)
 
 
 def _gpu_merge(wl, params, perm, sid, nsub, decide=vpm.VPM_DECIDE_FIXED, merge=vpm.VPM_MERGE_PAIR):

@@ -22,7 +22,8 @@ from paper_1504_00636_amd import workloads as W
 from tests.helpers import (FIELDS, conserved_totals, energy, load_golden, partition_sets,
                            subsets_of)
 
-GOLDEN_FILES = ["px_bisection_6.txt", "corners_tie_4.txt", "px_ladder_8.txt"]
+GOLDEN_FILES = ["px_bisection_6.txt", "corners_tie_4.txt", "px_ladder_8.txt", "pair_direction_2.txt",
+                "pair_two_clusters_4.txt"]
 MODES = [oracle.FIXED, oracle.PAPER]
 
 
