@@ -166,6 +166,25 @@ vpm_status vpm_merge(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
                      const int32_t *subset_id, const int32_t *n_subsets, vpm_soa *out,
                      int64_t *out_off, int64_t *out_total, hipStream_t stream);
 
+/* The blind method, the paper's comparison method (Sec. "Simulation", described before the
+ * counter-propagating blocks; merging fraction alpha = 0.965 and 0.88 in Tables 1 and 2): in every
+ * cell of N > N_min particles with ceil(alpha N) < N, pairs of particles picked at random are merged
+ * until ceil(alpha N) remain.  A merge replaces two particles by one with their summed weight at
+ * their weighted centroid in position and momentum (weight and momentum kept, energy not).
+ *   Draws: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011), key (seed, 0), counter (t, c, 0, 0)
+ *   for the t-th merge of cell c.  With M = N - t particles left, outputs r0, r1 pick slots
+ *   i = r0 mod M and j = r1 mod (M - 1) (plus one if >= i): the group in slot j joins the group in
+ *   slot i, and the last slot moves into slot j.  Output k of the cell is the group left in slot
+ *   k: copied unchanged if it is one particle, else replaced by its centroid.
+ *   alpha     >= 0 (finite); alpha >= 1 merges nothing
+ *   group     device int32[n_particles] (may be NULL): the cell-local output ordinal of each input
+ *             particle (its own index in untouched cells)
+ * p: n_min_cell, mass and dtype (VPM_F32 only) are used; tolerances, min_subset, merge_mode and
+ * decide are not (p must still pass vpm_check_params).  Output and errors as vpm_run.           */
+vpm_status vpm_blind(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, int64_t n_cells,
+                     int64_t n_particles, const vpm_params *p, double alpha, uint64_t seed, vpm_soa *out,
+                     int64_t *out_off, int64_t *out_total, int32_t *group, hipStream_t stream);
+
 /* Launch configuration of the fixed-point path (batching, not arithmetic: every configuration gives
  * bit-identical results).  A cell of n particles (n > N_min) is processed
  *   in a batch with other small cells by one wavefront (up to 16 cells, 512 particles, in LDS)

@@ -148,3 +148,60 @@ def run_workload(wl, decide=FIXED, merge_mode=PAIR, n_threads: int = 0, **overri
     prm.update(override)
     return run(wl.arrays(), wl.cell_off, decide=decide, merge_mode=merge_mode,
                n_threads=n_threads, **prm)
+
+
+def _bind_blind(lib):
+    dp = C.POINTER(C.c_double)
+    lib.orc_blind.restype = C.c_int
+    lib.orc_blind.argtypes = ([C.c_double, C.c_uint64, C.c_int32, C.c_double, C.c_int, C.c_int64,
+                               C.POINTER(C.c_int64)] + [dp] * 7 + [C.POINTER(C.c_int32)] + [dp] * 7 +
+                              [C.POINTER(C.c_int64), C.c_int])
+    lib.orc_philox4x64_10.restype = None
+    lib.orc_philox4x64_10.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    return lib
+
+
+@dataclass
+class BlindResult:
+    group: np.ndarray       # int32[n]: cell-local output ordinal of each input particle
+    out: dict               # field -> float64[n_out]
+    out_off: np.ndarray     # int64[n_cells+1]
+
+    @property
+    def out_total(self) -> int:
+        return int(self.out_off[-1])
+
+
+def blind(arrays, cell_off, alpha, seed, n_min_cell=0, mass=1.0, f32=True, n_threads: int = 0,
+          lib=None) -> BlindResult:
+    """The paper's blind method: random pairs merged per cell until at most ceil(alpha N) remain
+    (Philox4x64-10 counter (t, cell, 0, 0), key (seed, 0)).  f32: round the inputs to FP32 first,
+    as the GPU's FP32 path works on them."""
+    lib = _bind_blind(lib or _load())
+    cell_off = np.ascontiguousarray(cell_off, dtype=np.int64)
+    n_cells = cell_off.shape[0] - 1
+    n = int(cell_off[-1])
+    ins = [np.ascontiguousarray(a, dtype=np.float64) for a in arrays]
+    group = np.empty(max(n, 1), np.int32)
+    outs = [np.empty(max(n, 1), np.float64) for _ in range(7)]
+    out_off = np.empty(n_cells + 1, np.int64)
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    rc = lib.orc_blind(float(alpha), int(seed) & (2 ** 64 - 1), int(n_min_cell), float(mass), int(bool(f32)),
+                       n_cells, cell_off.ctypes.data_as(C.POINTER(C.c_int64)), *[dp(a) for a in ins],
+                       group.ctypes.data_as(C.POINTER(C.c_int32)), *[dp(a) for a in outs],
+                       out_off.ctypes.data_as(C.POINTER(C.c_int64)), int(n_threads))
+    if rc != 0:
+        raise ValueError(f"oracle rejected its arguments (code {rc})")
+    nout = int(out_off[-1])
+    names = ("x", "y", "z", "px", "py", "pz", "w")
+    return BlindResult(group[:n], {k: outs[i][:nout] for i, k in enumerate(names)}, out_off)
+
+
+def philox4x64_10(counter, key):
+    """The oracle's Philox4x64-10 block for a 4-word counter and 2-word key (for its known-answer test)."""
+    lib = _bind_blind(_load())
+    c = (C.c_uint64 * 4)(*[int(v) for v in counter])
+    k = (C.c_uint64 * 2)(*[int(v) for v in key])
+    o = (C.c_uint64 * 4)()
+    lib.orc_philox4x64_10(c, k, o)
+    return [int(v) for v in o]

@@ -589,3 +589,147 @@ int orc_run(const orc_params *p, int64_t n_cells, const int64_t *cell_off,
     free(cnt_out);
     return 0;
 }
+
+/* ------------------------------------------------------- the blind method */
+
+/* The paper's comparison method (Sec. "Simulation", its description before the blocks test; Tables 1
+ * and 2 give the merging fraction alpha): in a cell of N particles, pairs of particles picked at
+ * random are merged until at most ceil(alpha N) remain.  A cell is merged only if ceil(alpha N) < N
+ * (and N > N_min).  Each merge replaces the two by one particle carrying their summed weight and
+ * their weighted centroid in position and momentum (weight and momentum kept, energy not).
+ *
+ * Random numbers: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC 2011) with key (seed, 0) and counter (t, c, 0, 0) for the t-th merge of cell c.
+ * With M = N - t particles left, outputs r0, r1 pick i = r0 mod M and j = r1 mod (M - 1), j
+ * shifted past i.  The survivors are kept in an array of slots; the particle in slot j joins the
+ * group of slot i and the last slot moves into slot j.  The output of a cell is its surviving slots
+ * in slot order: a group of one particle is copied, a larger group is replaced by its centroid,
+ * computed from its members (the same particle pairwise merges would give, in exact arithmetic).
+ * group[k] (cell-local) is the output ordinal of input particle k. */
+
+static void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        u128 p0 = (u128)M0 * c0, p1 = (u128)M1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0; c1 = lo1; c2 = hi0 ^ c3 ^ k1; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* exported for the generator's known-answer test */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    philox4x64_10(ctr, key, out);
+}
+
+static int blind_root(const int *parent, int i) {
+    while (parent[i] != i) i = parent[i];
+    return i;
+}
+
+/* Inputs as orc_run (rounded to FP32 first when f32 != 0).  Outputs: group[n] (may be NULL),
+ * out[7] compacted cell by cell, out_off[n_cells+1]. */
+int orc_blind(double alpha, uint64_t seed, int32_t n_min_cell, double mass, int f32, int64_t n_cells,
+              const int64_t *cell_off, const double *x, const double *y, const double *z,
+              const double *px, const double *py, const double *pz, const double *w, int32_t *group,
+              double *ox, double *oy, double *oz, double *opx, double *opy, double *opz, double *ow,
+              int64_t *out_off, int n_threads) {
+    if (n_cells < 0 || !cell_off || !(alpha >= 0) || !(alpha <= 1e9) || n_min_cell < 0 || !(mass >= 0)) return -1;
+    for (int64_t c = 0; c < n_cells; ++c) if (cell_off[c + 1] < cell_off[c]) return -2;
+    const int64_t N = cell_off[n_cells];
+    const double *in[7] = {x, y, z, px, py, pz, w};
+    double *outp[7] = {ox, oy, oz, opx, opy, opz, ow};
+    int32_t *cnt_out = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_cells + 1));
+    double *tmp[7];
+    for (int f = 0; f < 7; ++f) tmp[f] = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    orc_params prm;
+    memset(&prm, 0, sizeof prm);
+    prm.mass = mass;
+    prm.merge_mode = ORC_CENTROID;
+
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t c = 0; c < n_cells; ++c) {
+        const int64_t off = cell_off[c];
+        const int n = (int)(cell_off[c + 1] - off);
+        const int64_t T = (int64_t)ceil(alpha * (double)n);
+        int bad = 0;
+        for (int i = 0; i < n; ++i) {
+            for (int f = 0; f < 7; ++f) {
+                double v = f32 ? (double)(float)in[f][off + i] : in[f][off + i];
+                if (!isfinite(v) || (f == 6 && !(v > 0))) bad = 1;
+            }
+        }
+        const int untouched = n == 0 || n <= n_min_cell || T >= n || n > 65536 || bad;
+        double *buf = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 14);
+        cell_ctx cc;
+        memset(&cc, 0, sizeof cc);
+        cc.n = n; cc.p = &prm;
+        for (int a = 0; a < 6; ++a) cc.q[a] = buf + (size_t)a * n;
+        cc.w = buf + (size_t)6 * n;
+        for (int f = 0; f < 7; ++f) cc.out[f] = buf + (size_t)(7 + f) * n;
+        for (int i = 0; i < n; ++i) {
+            for (int a = 0; a < 6; ++a) cc.q[a][i] = f32 ? (double)(float)in[a][off + i] : in[a][off + i];
+            cc.w[i] = f32 ? (double)(float)w[off + i] : w[off + i];
+        }
+        if (untouched) {
+            for (int i = 0; i < n; ++i) {
+                for (int a = 0; a < 6; ++a) tmp[a][off + i] = cc.q[a][i];
+                tmp[6][off + i] = cc.w[i];
+                if (group) group[off + i] = i;
+            }
+            cnt_out[c] = n;
+            free(buf);
+            continue;
+        }
+        int *slot = (int *)malloc(sizeof(int) * (size_t)n * 5 + sizeof(int) * (size_t)(T + 1));
+        int *parent = slot + n, *mem = slot + 2 * n, *gid = slot + 3 * n, *ordk = slot + 4 * n;
+        int *start = slot + 5 * n;
+        for (int i = 0; i < n; ++i) { slot[i] = i; parent[i] = i; }
+        const uint64_t key[2] = {seed, 0};
+        for (int64_t t = 0; t < n - T; ++t) {
+            const uint64_t M = (uint64_t)(n - t);
+            const uint64_t ctr[4] = {(uint64_t)t, (uint64_t)c, 0, 0};
+            uint64_t r[4];
+            philox4x64_10(ctr, key, r);
+            uint64_t i = r[0] % M, j = r[1] % (M - 1);
+            if (j >= i) j += 1;
+            parent[slot[j]] = slot[i];            /* slot j's group joins slot i's */
+            slot[j] = slot[M - 1];                /* the last slot fills the gap   */
+        }
+        /* output k = 0 .. T-1: the group rooted at slot[k], members in input order */
+        for (int64_t k = 0; k < T; ++k) ordk[slot[k]] = (int)k;
+        for (int64_t k = 0; k <= T; ++k) start[k] = 0;
+        for (int i = 0; i < n; ++i) {
+            gid[i] = ordk[blind_root(parent, i)];
+            start[gid[i] + 1]++;
+            if (group) group[off + i] = gid[i];
+        }
+        for (int64_t k = 0; k < T; ++k) start[k + 1] += start[k];
+        for (int i = 0; i < n; ++i) mem[start[gid[i]]++] = i;      /* start[k] becomes start[k + 1] */
+        cc.n_out = 0;
+        for (int64_t k = 0; k < T; ++k) {
+            const int b = k == 0 ? 0 : start[k - 1], cntm = start[k] - b;
+            if (cntm == 1) passthrough_subset(&cc, mem + b, 1);
+            else merge_subset(&cc, mem + b, cntm, 0);
+        }
+        for (int o = 0; o < cc.n_out; ++o) for (int f = 0; f < 7; ++f) tmp[f][off + o] = cc.out[f][o];
+        cnt_out[c] = cc.n_out;
+        free(slot);
+        free(buf);
+    }
+    out_off[0] = 0;
+    for (int64_t c = 0; c < n_cells; ++c) out_off[c + 1] = out_off[c] + cnt_out[c];
+    for (int64_t c = 0; c < n_cells; ++c)
+        for (int64_t o = 0; o < cnt_out[c]; ++o)
+            for (int f = 0; f < 7; ++f) outp[f][out_off[c] + o] = tmp[f][cell_off[c] + o];
+    for (int f = 0; f < 7; ++f) free(tmp[f]);
+    free(cnt_out);
+    return 0;
+}

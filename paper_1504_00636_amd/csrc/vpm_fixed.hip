@@ -1940,6 +1940,137 @@ __global__ __launch_bounds__(WAVE, 2) void k_fixed_small(FixedArgs A) {
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// The blind method, the paper's comparison (Sec. "Simulation", before the blocks test): pairs of
+// particles picked at random are merged until at most ceil(alpha N) remain in a cell of N > N_min
+// particles.  Draws: Philox4x64-10 (Salmon et al., SC 2011), key (seed, 0), counter (t, c, 0, 0)
+// for the t-th merge of cell c; with M = N - t left, i = r0 mod M and j = r1 mod (M - 1), shifted
+// past i.  The particle in slot j joins slot i's group and the last slot fills slot j.  Output k
+// is the group of slot k: a single particle is copied, a larger group replaced by its centroid
+// (the fixed-point Step 7 sums, one particle: weight and momentum kept).
+// ------------------------------------------------------------------------------------------
+
+struct BlindArgs {
+    FixedArgs A;                   // in, cell_off, P (mass; CENTROID), tmp, out_count, cell_mode, flags
+    double alpha;
+    uint64_t seed;
+    int32_t n_min_cell;
+    int64_t n_cells, n_particles;
+    int32_t *slot, *parent, *aux;  // scratch indexed by input position
+    int32_t* group;                // optional: cell-local output ordinal of each input particle
+};
+
+VPM_DEV void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c3, uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+}
+
+__global__ __launch_bounds__(WAVE) void k_fixed_blind(BlindArgs B) {
+    const FixedArgs& A = B.A;
+    const int lane = lane_id();
+    for (int64_t c = blockIdx.x; c < B.n_cells; c += gridDim.x) {
+        const int64_t lo = A.cell_off[c], hi = A.cell_off[c + 1];
+        const bool range_ok = lo >= 0 && hi >= lo && hi <= B.n_particles && (c != 0 || lo == 0);
+        const int64_t n64 = range_ok ? hi - lo : 0;
+        const int n = (int)min<int64_t>(n64, (int64_t)NMAX_BIG + 1);
+        const int64_t T = (int64_t)ceil(B.alpha * (double)n64);
+        uint32_t fl = range_ok ? 0u : FLAG_BAD_OFFSETS;
+        if (n64 > NMAX_BIG) fl |= FLAG_TOO_LARGE;
+        bool touched = range_ok && n64 > 0 && n64 > B.n_min_cell && T < n64 && n64 <= NMAX_BIG;
+        Frame F;
+        if (touched && !cell_frame(A.in, lo, n, cell_mass(A.P.mass, nullptr, nullptr, c), F)) {
+            fl |= FLAG_BAD_VALUE;
+            touched = false;
+        }
+        if (fl && lane == 0) atomicOr(A.flags, fl);
+        if (!touched) {
+            if (lane == 0) { A.out_count[c] = n64; A.cell_mode[c] = CELL_UNTOUCHED; }
+            if (B.group && range_ok)
+                for (int64_t i = lane; i < n64; i += WAVE) B.group[lo + i] = (int32_t)i;
+            continue;
+        }
+        int32_t* const S = B.slot + lo;
+        int32_t* const Pa = B.parent + lo;
+        int32_t* const X = B.aux + lo;
+        for (int i = lane; i < n; i += WAVE) { S[i] = i; Pa[i] = i; }
+        wave_fence();
+        // the merges: 64 draws at a time in parallel, applied to the slots in order by lane 0
+        const int nm = n - (int)T;
+        for (int t0 = 0; t0 < nm; t0 += WAVE) {
+            const int t = t0 + lane;
+            int di = 0, dj = 0;
+            if (t < nm) {
+                uint64_t c0 = (uint64_t)t, c1 = (uint64_t)c, c2 = 0, c3 = 0;
+                philox4x64_10(c0, c1, c2, c3, B.seed, 0);
+                const uint32_t M = (uint32_t)(n - t);
+                di = (int)(c0 % M);
+                dj = (int)(c1 % (M - 1));
+                dj += dj >= di ? 1 : 0;
+            }
+            const int cnt = min(WAVE, nm - t0);
+            for (int u = 0; u < cnt; ++u) {
+                const int i = __shfl(di, u), j = __shfl(dj, u);
+                if (lane == 0) {
+                    const int M = n - (t0 + u);
+                    Pa[S[j]] = S[i];
+                    S[j] = S[M - 1];
+                }
+            }
+        }
+        wave_fence();
+        // output ordinal of each surviving group, then the group of every particle (into S)
+        for (int k = lane; k < (int)T; k += WAVE) X[S[k]] = k;
+        wave_fence();
+        for (int i = lane; i < n; i += WAVE) {
+            int r = i;
+            while (Pa[r] != r) r = Pa[r];
+            const int g = X[r];
+            if (B.group) B.group[lo + i] = g;
+            S[i] = g;                                  // S[k < T] was read above, before the fence
+        }
+        wave_fence();
+        // members of each group (counting sort into X; Pa holds the running starts)
+        for (int k = lane; k <= (int)T; k += WAVE) Pa[k] = 0;
+        wave_fence();
+        for (int i = lane; i < n; i += WAVE) atomicAdd(&Pa[S[i]], 1);
+        wave_fence();
+        int carry = 0;
+        for (int k0 = 0; k0 < (int)T; k0 += WAVE) {
+            const int k = k0 + lane;
+            const int v = k < (int)T ? Pa[k] : 0;
+            const int inc = wave_incl_scan(v, lane);
+            if (k < (int)T) Pa[k] = carry + inc - v;
+            carry += __shfl(inc, WAVE - 1);
+        }
+        wave_fence();
+        for (int i = lane; i < n; i += WAVE) X[atomicAdd(&Pa[S[i]], 1)] = i;
+        wave_fence();
+        // Pa[k] is now the end of group k; one lane per output
+        for (int k = lane; k < (int)T; k += WAVE) {
+            const int b = k == 0 ? 0 : Pa[k - 1], len = Pa[k] - b;
+            const int64_t o = lo + k;
+            if (len == 1) {
+                const int64_t i = lo + X[b];
+                A.tmp.x[o] = A.in.x[i]; A.tmp.y[o] = A.in.y[i]; A.tmp.z[o] = A.in.z[i];
+                A.tmp.px[o] = A.in.px[i]; A.tmp.py[o] = A.in.py[i]; A.tmp.pz[o] = A.in.pz[i];
+                A.tmp.w[o] = A.in.w[i];
+            } else {
+                merge_subset(A, F, [&](int j) { return lo + (int64_t)X[b + j]; }, len, 0, o, 0, 1);
+            }
+        }
+        if (lane == 0) { A.out_count[c] = T; A.cell_mode[c] = CELL_PROCESSED; }
+        wave_fence();
+    }
+}
+
 constexpr int WPB_A = 1, WPB_B = 4, WPB_C = 8, WPB_BIG = 8;
 
 }  // namespace
@@ -2082,6 +2213,48 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
         if (lc.post) lc.post(lc.prof, b.name, b.s);
     }
     return join_back(e);
+}
+
+}  // namespace vpm
+
+namespace vpm {
+
+hipError_t launch_fixed_blind(const Workspace& ws, const LaunchCfg& lc, const Soa32& in, const int64_t* cell_off,
+                              int64_t n_cells, int64_t n_particles, const FixedParams& fp, double alpha,
+                              uint64_t seed, int32_t n_min_cell, int32_t* group) {
+    BlindArgs B;
+    FixedArgs& A = B.A;
+    A.in = in;
+    A.cell_off = cell_off;
+    A.counters = ws.counters;
+    A.P = fp;
+    A.P.merge_mode = VPM_MERGE_CENTROID;
+    A.mode = 0;
+    A.tmp = Soa32Out{(float*)ws.tmp[0], (float*)ws.tmp[1], (float*)ws.tmp[2], (float*)ws.tmp[3],
+                     (float*)ws.tmp[4], (float*)ws.tmp[5], (float*)ws.tmp[6]};
+    A.out_count = ws.out_count;
+    A.cell_mode = ws.cell_mode;
+    A.flags = ws.flags;
+    A.perm = nullptr; A.subset_id = nullptr; A.n_subsets = nullptr;
+    A.big = nullptr; A.big_stride = 0;
+    for (int k = 0; k < BIGQ_CLASSES; ++k) A.bigq[k] = nullptr;
+    B.alpha = alpha;
+    B.seed = seed;
+    B.n_min_cell = n_min_cell;
+    B.n_cells = n_cells;
+    B.n_particles = n_particles;
+    B.slot = ws.perm2;
+    B.parent = ws.perm2 + (ws.cap_particles + 1);
+    B.aux = (int32_t*)ws.stack;
+    B.group = group;
+    if (n_cells == 0) return hipSuccess;
+    const int64_t cap = (int64_t)lc.grid_fp64 * 2;
+    const int64_t grid = n_cells < cap ? n_cells : cap;
+    if (lc.pre) lc.pre(lc.prof, "fixed_blind", lc.stream);
+    hipLaunchKernelGGL(k_fixed_blind, dim3((unsigned)grid), dim3(WAVE), 0, lc.stream, B);
+    const hipError_t e = hipGetLastError();
+    if (lc.post) lc.post(lc.prof, "fixed_blind", lc.stream);
+    return e;
 }
 
 }  // namespace vpm

@@ -435,6 +435,28 @@ vpm_status vpm_merge(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, i
     return VPM_OK;
 }
 
+vpm_status vpm_blind(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, int64_t n_cells,
+                     int64_t n_particles, const vpm_params* p, double alpha, uint64_t seed, vpm_soa* out,
+                     int64_t* out_off, int64_t* out_total, int32_t* group, hipStream_t stream) {
+    vpm_status st = common_checks(ctx, in, cell_off, n_cells, n_particles, p);
+    if (st != VPM_OK) return st;
+    if (p->dtype != VPM_F32) return VPM_ERR_UNSUPPORTED;
+    if (!(std::isfinite(alpha) && alpha >= 0.0)) return VPM_ERR_INVALID_ARG;
+    if (check_soa(out) != VPM_OK || !out_off || !out_total) return VPM_ERR_INVALID_ARG;
+    hipSetDevice(ctx->device);
+    LaunchCfg lc = make_cfg(ctx, stream);
+    hipError_t e = launch_fixed_blind(ctx->ws, lc, soa32(in), cell_off, n_cells, n_particles,
+                                      fixed_params(p, ctx->tune), alpha, seed, p->n_min_cell, group);
+    if (e != hipSuccess) return hip_fail(ctx, e, "blind");
+    e = launch_scan_offsets(ctx->ws, lc, n_cells, n_particles, out_off, out_total);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scan");
+    const void* ins[7] = {in->x, in->y, in->z, in->px, in->py, in->pz, in->w};
+    void* outs[7] = {out->x, out->y, out->z, out->px, out->py, out->pz, out->w};
+    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs, 4);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scatter");
+    return VPM_OK;
+}
+
 vpm_status vpm_check_tuning(const vpm_tuning* t) {
     if (!t) return VPM_ERR_INVALID_ARG;
     if (t->ppl != 8 && t->ppl != 16 && t->ppl != 32) return VPM_ERR_INVALID_ARG;

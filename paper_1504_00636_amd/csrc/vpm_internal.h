@@ -122,6 +122,11 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
                               const int64_t* cell_off, int64_t n_cells, int32_t n_min_cell,
                               const FixedParams& fp, const int32_t* perm,
                               const int32_t* subset_id, const int32_t* n_subsets);
+// The blind method (random pair merges down to ceil(alpha N) per cell) into ws.tmp, out_count and
+// cell_mode for every cell (validation included; no binning needed).
+hipError_t launch_fixed_blind(const Workspace& ws, const LaunchCfg& lc, const Soa32& in, const int64_t* cell_off,
+                              int64_t n_cells, int64_t n_particles, const FixedParams& fp, double alpha,
+                              uint64_t seed, int32_t n_min_cell, int32_t* group);
 // bins: 0 = A, 1 = B, 2 = C (LDS), 3 = big (global slabs), 4 = small-cell batches
 int fixed_lds_bytes(int which);            // dynamic LDS per workgroup
 const void* fixed_kernel_ptr(int which);   // for occupancy queries

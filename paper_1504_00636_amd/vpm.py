@@ -29,7 +29,7 @@ EXPORTS = ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_
            "vpm_partition",
            "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read",
            "vpm_check_tuning", "vpm_get_tuning", "vpm_set_tuning", "vpm_autotune",
-           "vpm_status_string", "vpm_last_error", "vpm_version", "vpm_run_noalloc")
+           "vpm_status_string", "vpm_last_error", "vpm_version", "vpm_run_noalloc", "vpm_blind")
 VPM_NOALLOC_MAX_PARTICLES, VPM_NOALLOC_MAX_CELLS = 524288, 32768
 
 
@@ -88,6 +88,8 @@ def lib():
                                   P(VpmSoa), vp, vp, vp]
     L.vpm_run_noalloc.argtypes = [P(VpmSoa), vp, i64, i64, P(VpmParams), P(VpmSoa), vp, vp, vp, vp]
     L.vpm_partition.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, vp]
+    L.vpm_blind.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), C.c_double, C.c_uint64, P(VpmSoa), vp, vp,
+                            vp, vp]
     L.vpm_merge.argtypes = [vp, P(VpmSoa), vp, i64, i64, P(VpmParams), vp, vp, vp, P(VpmSoa), vp, vp, vp]
     L.vpm_device_status.argtypes = [vp, P(C.c_uint32), C.c_int]
     L.vpm_check_tuning.argtypes = [P(VpmTuning)]
@@ -102,7 +104,7 @@ def lib():
     L.vpm_last_error.restype = C.c_char_p
     L.vpm_version.restype = C.c_char_p
     for f in ("vpm_create", "vpm_destroy", "vpm_reserve", "vpm_check_params", "vpm_run", "vpm_run_species",
-              "vpm_run_noalloc",
+              "vpm_run_noalloc", "vpm_blind",
               "vpm_partition", "vpm_merge", "vpm_device_status", "vpm_profile_enable", "vpm_profile_read", "vpm_check_tuning",
               "vpm_get_tuning", "vpm_set_tuning", "vpm_autotune"):
         getattr(L, f).restype = C.c_int
@@ -269,6 +271,22 @@ class Context:
                              _dev(out_total, torch.int64, 1, "out_total"), _stream(stream))
         self._check(st, "vpm_merge")
 
+    def blind(self, inp, cell_off, n_particles: int, p: VpmParams, alpha: float, seed: int, out, out_off,
+              out_total, group=None, stream=None):
+        """vpm_blind: random pair merges down to ceil(alpha N) per cell; group: optional device int32
+        tensor receiving each input particle's cell-local output ordinal."""
+        import torch
+        n_cells = cell_off.numel() - 1
+        dt = _torch_dtype(p)
+        si = _soa(inp, dt, n_particles, "in")
+        so = _soa(out, dt, n_particles, "out")
+        g = None if group is None else _dev(group, torch.int32, n_particles, "group")
+        st = lib().vpm_blind(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"), n_cells,
+                             int(n_particles), C.byref(p), float(alpha), int(seed) & (2 ** 64 - 1), C.byref(so),
+                             _dev(out_off, torch.int64, n_cells + 1, "out_off"),
+                             _dev(out_total, torch.int64, 1, "out_total"), g, _stream(stream))
+        self._check(st, "vpm_blind")
+
     def get_tuning(self) -> VpmTuning:
         t = VpmTuning()
         self._check(lib().vpm_get_tuning(self.h, C.byref(t)), "vpm_get_tuning")
@@ -329,6 +347,10 @@ def vpm_run(ctx: Context, *a, **k):
 
 def vpm_run_species(ctx: Context, *a, **k):
     ctx.run_species(*a, **k)
+
+
+def vpm_blind(ctx: Context, *a, **k):
+    ctx.blind(*a, **k)
 
 
 def vpm_partition(ctx: Context, *a, **k):

@@ -99,3 +99,61 @@ def test_gpu_whole_box_matches_oracle():
             got, got_off, tot = gpu_run(box, params, merge=vpm.VPM_MERGE_PAIR)
             assert tot == ref.out_total
             check_merged_values(box, params, vpm.VPM_MERGE_PAIR, got, got_off, ref)
+
+
+# ------------------------------------------------------------------------------------------
+# The blind method on the same passage (the paper's comparison): merging random pairs of the
+# overlapping blocks creates particles with momenta between the blocks' (near zero when two
+# counter-moving particles meet) and loses energy, while weight and momentum are kept.
+# ------------------------------------------------------------------------------------------
+
+ALPHA = 0.5
+
+
+def _blind_passage():
+    wl = W.counter_blocks(nx=NX, ny=NY, p0=P0, seed=3)
+    params = dict(wl.params)
+    for ev in range(EVENTS):
+        ref = oracle.blind(wl.arrays(), wl.cell_off, ALPHA, ev, n_min_cell=params["n_min_cell"])
+        yield ev, wl, ref
+        out = W.Workload(wl.name, *[ref.out[f] for f in W.FIELDS], cell_off=np.asarray(ref.out_off, np.int64),
+                         cell_id=None, params=dict(params)).astype(np.float32)
+        wl = W.free_stream(W.free_stream(out, NX, NY, 0.5), NX, NY, 0.5)
+
+
+def test_oracle_blind_mixes_the_blocks():
+    e0 = None
+    mixed = 0
+    for ev, wl, ref in _blind_passage():
+        px = np.asarray(ref.out["px"], np.float64)
+        w = np.asarray(ref.out["w"], np.float64)
+        e = np.sum(w * np.sqrt(1.0 + px ** 2))
+        if e0 is None:
+            e0 = np.sum(np.asarray(wl.w, np.float64) * np.sqrt(1.0 + np.asarray(wl.px, np.float64) ** 2))
+        np.testing.assert_allclose(w.sum(), np.asarray(wl.w, np.float64).sum(), rtol=1e-12)
+        np.testing.assert_allclose(np.sum(w * px), np.sum(np.asarray(wl.w, np.float64) * wl.px),
+                                   atol=1e-9 * P0 * w.sum())
+        mixed = max(mixed, int(np.sum(np.abs(np.abs(px) - P0) > 1e-3 * P0)))
+    assert mixed > 100                              # momenta off +-150 m_e c: the blocks were mixed
+    assert e < 0.95 * e0                            # and energy was lost
+
+
+@pytest.mark.gpu
+def test_gpu_blind_passage_matches_oracle():
+    torch = pytest.importorskip("torch")
+    from paper_1504_00636_amd import vpm
+    from tests.gpu_common import ctx
+    for ev, wl, ref in _blind_passage():
+        c = ctx(max(wl.n, 1), max(wl.n_cells, 1))
+        arrs, off = vpm.upload(wl)
+        out = [torch.empty_like(a) for a in arrs]
+        oo = torch.empty(wl.n_cells + 1, dtype=torch.int64, device="cuda")
+        ot = torch.empty(1, dtype=torch.int64, device="cuda")
+        g = torch.empty(max(wl.n, 1), dtype=torch.int32, device="cuda")
+        p = vpm.make_params(tol_x=0.4, tol_p=0.01, n_min_cell=wl.params["n_min_cell"])
+        c.blind(arrs, off, wl.n, p, ALPHA, ev, out, oo, ot, g)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(g.cpu().numpy()[:wl.n], ref.group, err_msg=str(ev))
+        np.testing.assert_array_equal(oo.cpu().numpy(), ref.out_off)
+        k = int(ot.item())
+        np.testing.assert_allclose(out[3][:k].cpu().numpy(), ref.out["px"], rtol=1e-6, atol=1e-6 * P0)
