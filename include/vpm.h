@@ -109,8 +109,7 @@ vpm_status vpm_create(vpm_ctx **ctx, int device);
 vpm_status vpm_destroy(vpm_ctx *ctx);
 
 /* Allocate the context's device workspace for up to max_particles particles and max_cells
- * cells per call (about 76 bytes per particle plus 32 bytes per cell, and up to one 2.9 MB slab
- * per compute unit for cells above 4,352 particles).  The only call that
+ * cells per call (about 110 bytes per particle plus 160 bytes per cell).  The only call that
  * allocates device memory.  May be called again to grow; it synchronises the device. */
 vpm_status vpm_reserve(vpm_ctx *ctx, int64_t max_particles, int64_t max_cells);
 
@@ -244,7 +243,7 @@ const char *vpm_last_error(vpm_ctx *ctx);
 
 /* vpm_run without a context, for callers that cannot allocate device memory (code being captured
  * into a HIP graph, serving loops and harnesses that forbid hipMalloc).  It allocates nothing: its
- * working memory is a fixed array of 24 MiB in the library's device code, one copy per GPU, held
+ * working memory is a fixed array of 48 MiB in the library's device code, one copy per GPU, held
  * until the process ends.  Runs on the current HIP device with vpm_create's default tuning and
  * gives results bit-identical to vpm_run's with that tuning.
  *   Only VPM_DECIDE_FIXED with dtype VPM_F32.  n_particles <= VPM_NOALLOC_MAX_PARTICLES and

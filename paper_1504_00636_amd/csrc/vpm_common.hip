@@ -11,8 +11,9 @@ constexpr int SCAN_PER_THREAD = 4;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_PER_THREAD;
 
 __global__ void k_reset(int32_t* counters) {
-    // queue lengths [0, 8), work counters [8, 16), size-class list lengths [BIGQ_LEN0, +4)
-    if (threadIdx.x < BIGQ_LEN0 + BIGQ_CLASSES) counters[threadIdx.x] = 0;
+    // queue lengths [0, 8), work counters [8, 16), size-class list lengths [BIGQ_LEN0, +4), the
+    // large-cell kernel's task ring and pending counts [28, 32)
+    if (threadIdx.x < 32) counters[threadIdx.x] = 0;
 }
 
 // Classify every cell by size and append it to its queue (workgroup-aggregated atomics).

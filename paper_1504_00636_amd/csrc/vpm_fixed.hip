@@ -374,7 +374,17 @@ struct CellShared {          // per-cell bookkeeping, in LDS
     uint32_t flags;
     int qi;                  // queue position of the current cell
     int rootv;               // packed decision of the root
+    int kind;                // large-cell kernel: the claimed work (0 none, 1 a cell, 2 a task)
+    int last;                // large-cell kernel: this workgroup finished the cell's last piece
 };
+
+// Subsets of a large cell handed to other workgroups (the large-cell kernel): those that a split
+// leaves unfinished with at least TASK_MIN particles.  A level collects them here and publishes
+// them as tasks once the level's writes are complete.
+constexpr int TASK_MIN = 2048;
+constexpr int SPAWN_MAX = 64;          // per level: spawned subsets are disjoint, each >= TASK_MIN
+template <typename IdxT>
+struct SpawnList { int n; Node<IdxT> node[SPAWN_MAX]; };
 
 // Cross-wave scratch of a cell processed by WPB > 1 wavefronts.
 template <int WPB>
@@ -399,7 +409,8 @@ struct CellMem {
     int32_t* pyz;
     IdxT *idx0, *idx1;
     uint8_t* info;
-    IdxT* emit;                    // output slot per position; schedule table while splitting
+    IdxT* emit;                    // output slot per position
+    IdxT* sched;                   // schedule table of a level's subsets (the emit array in LDS bins)
     Node<IdxT> *nodes0, *nodes1;   // current / next level (leaf tables at the end)
 };
 
@@ -427,6 +438,7 @@ VPM_DEV CellMem<IdxT> carve(uint8_t* base, int nmax) {
     M.idx1 = (IdxT*)take((size_t)nmax * sizeof(IdxT));
     M.emit = (IdxT*)take(((size_t)nmax + 1) * sizeof(IdxT));
     M.info = (uint8_t*)take((size_t)nmax);
+    M.sched = M.emit;
     return M;
 }
 
@@ -444,8 +456,6 @@ struct FixedArgs {
     uint32_t* flags;
     int32_t *perm, *subset_id, *n_subsets;
     const int32_t* bigq[BIGQ_CLASSES];   // the large-cell queue by size class (large-cell bin only)
-    uint8_t* big;                  // global slabs for the large-cell path
-    int64_t big_stride;            // bytes per slab
 };
 
 template <typename IdxT>
@@ -719,7 +729,8 @@ VPM_DEV void sum_members(const CellMem<IdxT>& M, FSums& S, const IdxT* src, int 
 // Process one unfinished subset with a lane group: compaction, child moments, child decisions.
 template <typename IdxT>
 VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F0, const Frame* frames, Node<IdxT> nd,
-                        int cur, int lid, int g, int gbase, Node<IdxT>* next, bool solo) {
+                        int cur, int lid, int g, int gbase, Node<IdxT>* next, bool solo,
+                        SpawnList<IdxT>* spawn = nullptr) {
     const int start = nd.start, len = nd.len;
     const int rev = (nd.thr_axis >> 3) & 1;
     const int cell = (nd.thr_axis >> 4) & 15;
@@ -786,11 +797,11 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
         const int crev = (dv1 == -1) ? (n1 == 0 ? rev ^ 1 : rev) : (ch == 0 ? rev : rev ^ 1);
         if (d.kind == D_SPLIT) {
             if (lid == 0) {
-                const int slot = atomicAdd(&M.sh->nnext, 1);
                 Node<IdxT> c;
                 c.start = (IdxT)cs; c.len = (IdxT)cl;
                 c.thr_axis = (d.thr << 8) | (cell << 4) | (crev << 3) | d.axis;
-                next[slot] = c;
+                if (spawn && cl >= TASK_MIN) spawn->node[atomicAdd(&spawn->n, 1)] = c;   // to another workgroup
+                else next[atomicAdd(&M.sh->nnext, 1)] = c;
             }
         } else {
             record_final(M, A, d, cs, cl, crev, cur, lid, g);
@@ -1382,6 +1393,132 @@ VPM_DEV void encode_particle(const CellMem<IdxT>& M, const FixedParams& P, const
     fsums_add(R, om, cc[0], cc[1], cc[2], cc[3], cc[4], cc[5]);
 }
 
+// The output of a cell whose final subsets are recorded in info (all its splitting done): one scan
+// over the cell's slots gives leaf ordinals and output slots; copied particles go to the staging
+// arrays, merged subsets are replaced (Step 7).  In partition mode the permutation and subset
+// ordinals are written instead.  leaf_start (n + 1 entries), mlist and msched (n each) are scratch.
+template <int WPB, typename IdxT>
+VPM_DEV void cell_output(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, int c, int64_t off, int n,
+                         BlockScratch<WPB>* bs, IdxT* leaf_start, IdxT* mlist, IdxT* msched) {
+    constexpr int NT = WAVE * WPB;
+    const int lane = opaque_lane();
+    const int tid = WPB == 1 ? lane : opaque_tid();
+    const int wv = threadIdx.x / WAVE;
+    CellShared& sh = *M.sh;
+    // one scan over the cell's slots gives leaf ordinals and output slots
+    const int per = (n + NT - 1) / NT;
+    const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+    const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
+    int64_t loc = 0;
+    for (int p = b0; p < b1; ++p) {
+        const uint8_t inf = M.info[p];
+        const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
+        loc += ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
+    }
+    const int64_t inc = wave_incl_scan(loc, lane);
+    int64_t tot, wbase = 0;
+    if constexpr (WPB > 1) {
+        if (lane == WAVE - 1) bs->scan[wv] = inc;
+        __syncthreads();
+        tot = 0;
+        for (int w = 0; w < WPB; ++w) {
+            if (w < wv) wbase += bs->scan[w];
+            tot += bs->scan[w];
+        }
+    } else {
+        tot = __shfl(inc, WAVE - 1);
+    }
+    int64_t pre = wbase + inc - loc;
+    const int nleaves = (int)(tot >> 32);
+    const int out_total = (int)(tot & 0xffffffff);
+    if (tid == 0) sh.nmerged = 0;
+    cell_sync<WPB>();
+    for (int p = b0; p < b1; ++p) {
+        const uint8_t inf = M.info[p];
+        const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
+        const int ord = (int)(pre >> 32) + ((inf & INF_HEAD) ? 1 : 0) - 1;
+        if (A.mode == 0) {
+            M.emit[p] = (IdxT)(pre & 0xffffffff);
+        } else {
+            A.perm[off + p] = (int32_t)(off + idx_buf(M, inf & INF_PARITY)[p]);
+            A.subset_id[off + p] = ord;
+        }
+        if (inf & INF_HEAD) {
+            leaf_start[ord] = (IdxT)p;
+            if ((inf & INF_MERGED) && A.mode == 0) mlist[atomicAdd(&sh.nmerged, 1)] = (IdxT)ord;
+        }
+        pre += ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
+    }
+    if (tid == 0) leaf_start[nleaves] = (IdxT)n;
+    cell_sync<WPB>();
+    const uint32_t fl = sh.flags;
+    if (A.mode == 1) {
+        if (tid == 0) {
+            A.n_subsets[c] = nleaves;
+            if (fl) atomicOr(A.flags, fl);
+        }
+        return;
+    }
+    // copied particles (subsets below min_subset): the cell's arrays from wave-uniform base
+    // pointers with 32-bit lane offsets (no 64-bit address arithmetic per access)
+    {
+        const float* const ib[7] = {A.in.x + off, A.in.y + off, A.in.z + off, A.in.px + off,
+                                    A.in.py + off, A.in.pz + off, A.in.w + off};
+        float* const ob[7] = {A.tmp.x + off, A.tmp.y + off, A.tmp.z + off, A.tmp.px + off,
+                              A.tmp.py + off, A.tmp.pz + off, A.tmp.w + off};
+        for (int p0 = tid; p0 < n; p0 += COPY_BATCH * NT) {
+            uint32_t si[COPY_BATCH], so[COPY_BATCH];
+            bool keep[COPY_BATCH];
+#pragma unroll
+            for (int u = 0; u < COPY_BATCH; ++u) {
+                const int p = min(p0 + u * NT, n - 1);
+                const uint8_t inf = M.info[p];
+                si[u] = idx_buf(M, inf & INF_PARITY)[p];
+                so[u] = M.emit[p];
+                keep[u] = p0 + u * NT < n && !(inf & INF_MERGED);
+            }
+            float v[COPY_BATCH][7];
+#pragma unroll
+            for (int u = 0; u < COPY_BATCH; ++u)
+#pragma unroll
+                for (int f = 0; f < 7; ++f) v[u][f] = ib[f][si[u]];
+#pragma unroll
+            for (int u = 0; u < COPY_BATCH; ++u) {
+                if (!keep[u]) continue;
+#pragma unroll
+                for (int f = 0; f < 7; ++f) ob[f][so[u]] = v[u][f];
+            }
+        }
+    }
+    // merged subsets (Step 7)
+    const int nm = sh.nmerged;
+    if (nm > 0) {
+        IdxT* sched = msched;
+        const Sched s = schedule<WPB, IdxT>(M, sched, nm, A.P.ppl_shift, [&](int it) {
+            const int ord = mlist[it];
+            return (int)(leaf_start[ord + 1] - leaf_start[ord]);
+        });
+        for (int r0 = wv * WAVE; r0 < s.total; r0 += NT) {
+            int slot, cls;
+            if (sched_lookup(s, r0 + lane, slot, cls)) {
+                const int ord = mlist[sched[slot]];
+                const int st = leaf_start[ord];
+                const int ln = leaf_start[ord + 1] - st;
+                const int g = 1 << cls;
+                const uint8_t inf = M.info[st];
+                const IdxT* src = idx_buf(M, inf & INF_PARITY);
+                merge_subset(A, F, [&](int j) { return off + (int64_t)src[st + j]; }, ln,
+                             (inf >> INF_JSHIFT) & 3, off + M.emit[st], lane & (g - 1), g);
+            }
+        }
+    }
+    if (tid == 0) {
+        A.out_count[c] = out_total;
+        A.cell_mode[c] = CELL_PROCESSED;
+        if (fl) atomicOr(A.flags, fl);
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // The cell kernel: one cell per workgroup of WPB wavefronts (one wavefront for the small bin).
 // The subsets of a level are spread over the lane groups of all wavefronts; workgroup barriers
@@ -1396,8 +1533,8 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
     const int wv = tid / WAVE;
     constexpr int NT = WAVE * WPB;
     constexpr size_t HDR = header_bytes<WPB>();
-    CellMem<IdxT> M = IN_LDS ? carve<IdxT>(smem + HDR, NMAX)
-                             : carve<IdxT>(A.big + (int64_t)blockIdx.x * A.big_stride, NMAX);
+    static_assert(IN_LDS, "cells above the LDS bins go to k_fixed_big");
+    CellMem<IdxT> M = carve<IdxT>(smem + HDR, NMAX);
     M.sh = (CellShared*)smem;
     BlockScratch<WPB>* bs = (BlockScratch<WPB>*)(smem + ((sizeof(CellShared) + 15) & ~(size_t)15));
     CellShared& sh = *M.sh;
@@ -1406,13 +1543,6 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
     // cell sizes here, and single claims keep the tail of the launch short.
     const int qlen = A.counters[A.qlen_index];
     if (qlen == 0) return;                         // an empty bin claims nothing
-    // the global-memory bin claims its cells largest size class first: its duration is set by its
-    // largest cells, which would otherwise be claimed in cell order, possibly last
-    int nbig[BIGQ_CLASSES] = {};
-    if constexpr (!IN_LDS) {
-#pragma unroll
-        for (int k = 0; k < BIGQ_CLASSES; ++k) nbig[k] = A.counters[BIGQ_LEN0 + k];
-    }
     for (;;) {
         int qi = 0;
         if constexpr (WPB == 1) {
@@ -1429,21 +1559,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             qi = __builtin_amdgcn_readfirstlane(sh.qi);
         }
         if (qi >= qlen) break;
-        int c;
-        if constexpr (IN_LDS) {
-            c = A.queue[qi];
-        } else {
-            int v = qi;
-            const int32_t* qp = A.bigq[0];
-            bool found = false;
-#pragma unroll
-            for (int k = BIGQ_CLASSES - 1; k > 0; --k) {          // constant indices only
-                if (!found) {
-                    if (v < nbig[k]) { qp = A.bigq[k]; found = true; } else v -= nbig[k];
-                }
-            }
-            c = qp[v];
-        }
+        const int c = A.queue[qi];
         const int64_t off = A.cell_off[c];
         const int n = (int)(A.cell_off[c + 1] - off);
         // the lane and thread indices as values formed anew for each cell (see opaque_lane)
@@ -1500,7 +1616,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         const Decision rd = unpack_decision(sh.rootv);
         int m = 0;
         int cur = 0;
-        if (WPB == 1 && IN_LDS && rd.kind == D_SPLIT) {
+        if (WPB == 1 && rd.kind == D_SPLIT) {
             inherit_levels<IdxT>(M, A, F, R, n, rd, lane, cur, m);
         } else if (rd.kind == D_SPLIT) {
             if (tid == 0) {
@@ -1520,13 +1636,13 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
             Node<IdxT>* curl = cur ? M.nodes1 : M.nodes0;
             Node<IdxT>* nextl = cur ? M.nodes0 : M.nodes1;
             if (tid == 0) sh.nnext = 0;
-            const Sched s = schedule<WPB, IdxT>(M, M.emit, m, A.P.ppl_shift, [&](int it) { return (int)curl[it].len; });
+            const Sched s = schedule<WPB, IdxT>(M, M.sched, m, A.P.ppl_shift, [&](int it) { return (int)curl[it].len; });
             const bool solo = __builtin_amdgcn_readfirstlane(s.total == s.cnt[0] ? 1 : 0) != 0;   // only 1-lane groups
             for (int r0 = wv * WAVE; r0 < s.total; r0 += NT) {
                 int slot, cls;
                 const int ln = opaque_lane();
                 if (sched_lookup(s, r0 + ln, slot, cls)) {
-                    const Node<IdxT> nd = curl[M.emit[slot]];
+                    const Node<IdxT> nd = curl[M.sched[slot]];
                     const int g = 1 << cls;
                     split_node<IdxT>(M, A, F, nullptr, nd, cur, ln & (g - 1), g, ln & ~(g - 1), nextl, solo);
                 }
@@ -1538,121 +1654,286 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
         }
 
         // ---- output ----
-        // one scan over the cell's slots gives leaf ordinals and output slots
-        const int per = (n + NT - 1) / NT;
-        const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
-        const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
-        int64_t loc = 0;
-        for (int p = b0; p < b1; ++p) {
-            const uint8_t inf = M.info[p];
-            const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
-            loc += ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
+        cell_output<WPB, IdxT>(M, A, F, c, off, n, bs, (IdxT*)M.nodes0, (IdxT*)M.nodes1, (IdxT*)M.rec);
+        if constexpr (WPB == 1) wave_fence();
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Cells above the LDS bins, several workgroups per cell.  A large cell's codes, index buffers, info
+// bytes and output slots live in cell-wide global arrays indexed by input position.  The workgroup
+// that claims the cell builds its frame and codes and splits it level by level as the other bins
+// do.  Once no cell is left to claim, so that workgroups fall idle, every unfinished subset of at
+// least TASK_MIN particles that a split leaves goes to a device task queue (a ring), from which any
+// workgroup takes it and splits it in turn, spawning further tasks.  (Before that every workgroup
+// has a cell of its own, and keeping a cell on one workgroup avoids the device-wide cache
+// maintenance that handing data between workgroups costs.)  Each piece of a cell (its root, or a
+// task) ends by decrementing the cell's count of open pieces; the workgroup that closes the last
+// one runs the cell's output.  The grid drains when no cell is left to claim and no piece is queued
+// or running (a device count, `pending`).
+//   Queued tasks are pairwise disjoint subsets of >= TASK_MIN particles (a task's descendants are
+// spawned only after it is claimed), so at most n_particles / TASK_MIN are queued at a time and the
+// ring never overwrites an unclaimed task.  Node lists and the schedule table are per workgroup,
+// in a global slab sized for a whole cell's frontier.
+// ------------------------------------------------------------------------------------------
+
+constexpr int BIG_NODES = NMAX_BIG / 2 + 2;
+constexpr int C_TASK_HEAD = 28, C_TASK_RESERVE = 29, C_PENDING = 30;   // counters, reset per call
+
+struct BigTask { int32_t qi, cur; Node<uint32_t> nd; };
+struct BigCell { Frame F; int64_t off; int32_t n, c, open, pad; };
+
+struct BigArgs {
+    FixedArgs A;
+    int4* rec;                     // cell-wide arrays of the large cells, indexed by input position
+    int32_t* pyz;
+    uint32_t *idx0, *idx1, *emit;
+    uint8_t* info;
+    BigCell* cells;                // per claimed cell (claim index): frame, offset, size, open pieces
+    BigTask* tasks;                // ring of ring_size slots
+    int32_t* ready;                // per slot: 1 once the task is written, 0 once it is taken
+    int32_t ring_size;
+    Node<uint32_t>* lists;         // per workgroup: two node lists of BIG_NODES
+    uint32_t* sched;               // per workgroup: a schedule table of BIG_NODES
+    int32_t wait_idle;             // idle workgroups wait for tasks (else they leave the chip to
+                                   // kernels running beside this one)
+};
+
+struct BigShared {                 // LDS after the header
+    SpawnList<uint32_t> spawn;
+    int spawn_ok;                  // the level may hand subsets to other workgroups
+};
+
+__host__ __device__ constexpr size_t big_lds_bytes() { return header_bytes<8>() + rnd16(sizeof(BigShared)); }
+
+// Polling loads are relaxed: an acquire at device scope invalidates the caches of the whole XCD
+// (other workgroups' working sets included), so it is made once, by one thread, after a claim.
+VPM_DEV int ld_relaxed(const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Queue subset nd of cell qi (its members in index buffer cur) as a task.  The caller has made the
+// writes it depends on visible at device scope.
+VPM_DEV void spawn_task(const BigArgs& B, int qi, int cur, Node<uint32_t> nd) {
+    int32_t* const ctr = B.A.counters;
+    atomicAdd(&B.cells[qi].open, 1);
+    atomicAdd(&ctr[C_PENDING], 1);
+    const int idx = atomicAdd(&ctr[C_TASK_RESERVE], 1);
+    const int slot = idx % B.ring_size;
+    BigTask t;
+    t.qi = qi; t.cur = cur; t.nd = nd;
+    B.tasks[slot] = t;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&B.ready[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs B) {
+    constexpr int WPB = 8, NT = WAVE * WPB;
+    using IdxT = uint32_t;
+    extern __shared__ __align__(16) uint8_t smem[];
+    const FixedArgs& A = B.A;
+    CellShared& sh = *(CellShared*)smem;
+    BlockScratch<WPB>* bs = (BlockScratch<WPB>*)(smem + rnd16(sizeof(CellShared)));
+    BigShared& bl = *(BigShared*)(smem + header_bytes<WPB>());
+    const int wv = threadIdx.x / WAVE;
+    int32_t* const ctr = A.counters;
+    const int qlen = ctr[A.qlen_index];
+    if (qlen == 0) return;                         // an empty bin claims nothing
+    int nbig[BIGQ_CLASSES];
+#pragma unroll
+    for (int k = 0; k < BIGQ_CLASSES; ++k) nbig[k] = ctr[BIGQ_LEN0 + k];
+    bool cells_left = true;                        // (thread 0)
+    for (;;) {
+        // ---- a piece of work: a queued task first (cells already started), else a new cell ----
+        if (threadIdx.x == 0) {
+            int kind = 0, q = 0;
+            for (;;) {
+                const int h = ld_relaxed(&ctr[C_TASK_HEAD]);
+                if (h < ld_relaxed(&ctr[C_TASK_RESERVE]) && ld_relaxed(&B.ready[h % B.ring_size]) == 1) {
+                    if (atomicCAS(&ctr[C_TASK_HEAD], h, h + 1) == h) { kind = 2; q = h % B.ring_size; break; }
+                    continue;
+                }
+                if (cells_left) {
+                    atomicAdd(&ctr[C_PENDING], 1);           // before the claim: no one sees the grid idle
+                    const int qi = atomicAdd(&ctr[A.work_index], 1);
+                    if (qi < qlen) { kind = 1; q = qi; break; }
+                    atomicSub(&ctr[C_PENDING], 1);
+                    cells_left = false;
+                    continue;
+                }
+                // Nothing to take now.  Every queued task is taken at the latest by the workgroup
+                // that spawned it, once its piece is done, so leaving is always safe; waiting for
+                // tasks adds workgroups to the cells still open.
+                if (!B.wait_idle || ld_relaxed(&ctr[C_PENDING]) == 0) break;
+                __builtin_amdgcn_s_sleep(8);
+            }
+            if (kind != 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the cell's data written elsewhere
+            sh.kind = kind;
+            sh.qi = q;
+            sh.flags = 0;
+            sh.nnext = 0;
         }
-        const int64_t inc = wave_incl_scan(loc, lane);
-        int64_t tot, wbase = 0;
-        if constexpr (WPB > 1) {
-            if (lane == WAVE - 1) bs->scan[wv] = inc;
-            __syncthreads();
-            tot = 0;
-            for (int w = 0; w < WPB; ++w) {
-                if (w < wv) wbase += bs->scan[w];
-                tot += bs->scan[w];
+        __syncthreads();
+        const int kind = __builtin_amdgcn_readfirstlane(sh.kind);
+        if (kind == 0) break;
+        const int lane = opaque_lane();
+        const int tid = opaque_tid();
+        int qi, c, n, m = 0, cur = 0;
+        int64_t off;
+        Frame F;
+        CellMem<IdxT> M;
+        M.sh = &sh;
+        M.nodes0 = B.lists + (int64_t)blockIdx.x * (2 * BIG_NODES);
+        M.nodes1 = M.nodes0 + BIG_NODES;
+        M.sched = B.sched + (int64_t)blockIdx.x * BIG_NODES;
+        if (kind == 1) {
+            // ---- a new cell: frame, codes, root moments and decision ----
+            qi = __builtin_amdgcn_readfirstlane(sh.qi);
+            int v = qi;
+            const int32_t* qp = A.bigq[0];
+            bool found = false;
+#pragma unroll
+            for (int k = BIGQ_CLASSES - 1; k > 0; --k) {          // largest size class first
+                if (!found) {
+                    if (v < nbig[k]) { qp = A.bigq[k]; found = true; } else v -= nbig[k];
+                }
+            }
+            c = qp[v];
+            off = A.cell_off[c];
+            n = (int)(A.cell_off[c + 1] - off);
+            const bool valid = cell_frame_block<WPB>(A.in, off, n, cell_mass(A.P.mass, A.P.species, A.P.species_mass, c),
+                                                     F, bs);
+            if (!valid) {
+                if (tid == 0) {
+                    atomicOr(A.flags, FLAG_BAD_VALUE);
+                    if (A.mode == 0) { A.out_count[c] = n; A.cell_mode[c] = CELL_UNTOUCHED; }
+                    else A.n_subsets[c] = 0;
+                }
+                if (A.mode == 1)
+                    for (int i = tid; i < n; i += NT) { A.perm[off + i] = (int32_t)(off + i); A.subset_id[off + i] = -1; }
+                __syncthreads();
+                if (tid == 0) { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); atomicSub(&ctr[C_PENDING], 1); }
+                continue;
+            }
+            if (tid == 0) {
+                BigCell& bc = B.cells[qi];
+                bc.F = F; bc.off = off; bc.n = n; bc.c = c; bc.open = 1;
             }
         } else {
-            tot = __shfl(inc, WAVE - 1);
-        }
-        int64_t pre = wbase + inc - loc;
-        const int nleaves = (int)(tot >> 32);
-        const int out_total = (int)(tot & 0xffffffff);
-        IdxT* leaf_start = (IdxT*)M.nodes0;                // first slot of each final subset
-        IdxT* mlist = (IdxT*)M.nodes1;                     // ordinals of the merged subsets
-        if (tid == 0) sh.nmerged = 0;
-        cell_sync<WPB>();
-        for (int p = b0; p < b1; ++p) {
-            const uint8_t inf = M.info[p];
-            const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
-            const int ord = (int)(pre >> 32) + ((inf & INF_HEAD) ? 1 : 0) - 1;
-            if (A.mode == 0) {
-                M.emit[p] = (IdxT)(pre & 0xffffffff);
-            } else {
-                A.perm[off + p] = (int32_t)(off + idx_buf(M, inf & INF_PARITY)[p]);
-                A.subset_id[off + p] = ord;
-            }
-            if (inf & INF_HEAD) {
-                leaf_start[ord] = (IdxT)p;
-                if ((inf & INF_MERGED) && A.mode == 0) mlist[atomicAdd(&sh.nmerged, 1)] = (IdxT)ord;
-            }
-            pre += ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
-        }
-        if (tid == 0) leaf_start[nleaves] = (IdxT)n;
-        cell_sync<WPB>();
-        const uint32_t fl = sh.flags;
-        if (A.mode == 1) {
+            // ---- a task: a subset of a cell started elsewhere ----
+            const BigTask t = B.tasks[sh.qi];
+            qi = __builtin_amdgcn_readfirstlane(t.qi);
+            const BigCell& bc = B.cells[qi];
+            F = bc.F;
+            off = bc.off;
+            n = bc.n;
+            c = bc.c;
+            cur = t.cur;
+            m = 1;
+            __syncthreads();                           // every thread has read the slot
             if (tid == 0) {
-                A.n_subsets[c] = nleaves;
-                if (fl) atomicOr(A.flags, fl);
-            }
-            continue;
-        }
-        // copied particles (subsets below min_subset): the cell's arrays from wave-uniform base
-        // pointers with 32-bit lane offsets (no 64-bit address arithmetic per access)
-        {
-            const float* const ib[7] = {A.in.x + off, A.in.y + off, A.in.z + off, A.in.px + off,
-                                        A.in.py + off, A.in.pz + off, A.in.w + off};
-            float* const ob[7] = {A.tmp.x + off, A.tmp.y + off, A.tmp.z + off, A.tmp.px + off,
-                                  A.tmp.py + off, A.tmp.pz + off, A.tmp.w + off};
-            for (int p0 = tid; p0 < n; p0 += COPY_BATCH * NT) {
-                uint32_t si[COPY_BATCH], so[COPY_BATCH];
-                bool keep[COPY_BATCH];
-#pragma unroll
-                for (int u = 0; u < COPY_BATCH; ++u) {
-                    const int p = min(p0 + u * NT, n - 1);
-                    const uint8_t inf = M.info[p];
-                    si[u] = idx_buf(M, inf & INF_PARITY)[p];
-                    so[u] = M.emit[p];
-                    keep[u] = p0 + u * NT < n && !(inf & INF_MERGED);
-                }
-                float v[COPY_BATCH][7];
-#pragma unroll
-                for (int u = 0; u < COPY_BATCH; ++u)
-#pragma unroll
-                    for (int f = 0; f < 7; ++f) v[u][f] = ib[f][si[u]];
-#pragma unroll
-                for (int u = 0; u < COPY_BATCH; ++u) {
-                    if (!keep[u]) continue;
-#pragma unroll
-                    for (int f = 0; f < 7; ++f) ob[f][so[u]] = v[u][f];
-                }
+                (cur ? M.nodes1 : M.nodes0)[0] = t.nd;
+                __hip_atomic_store(&B.ready[sh.qi], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        // merged subsets (Step 7)
-        const int nm = sh.nmerged;
-        if (nm > 0) {
-            IdxT* sched = (IdxT*)M.rec;                    // the codes are free now
-            const Sched s = schedule<WPB, IdxT>(M, sched, nm, A.P.ppl_shift, [&](int it) {
-                const int ord = mlist[it];
-                return (int)(leaf_start[ord + 1] - leaf_start[ord]);
+        M.rec = B.rec + off;
+        M.pyz = B.pyz + off;
+        M.idx0 = B.idx0 + off;
+        M.idx1 = B.idx1 + off;
+        M.emit = B.emit + off;
+        M.info = B.info + off;
+        if (kind == 1) {
+            FSums R;
+            fsums_zero(R);
+            bool oob = false;
+            load_particles(A.in, off, tid, n, NT, [&](int i, const float* q, bool ok) {
+                if (ok) encode_particle(M, A.P, F, i, q, R, oob);
             });
+            const bool any_oob = __ballot(oob) != 0;
+            fsums_group_reduce(R, WAVE);
+            if (lane == 0) {
+                bs->sums[wv][0] = R.s0;
+                for (int l = 0; l < 6; ++l) { bs->sums[wv][1 + l] = R.s1[l]; bs->sums[wv][7 + l] = R.s2[l]; }
+                if (any_oob) atomicOr(&sh.flags, FLAG_OUT_OF_CELL);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                fsums_zero(R);
+                for (int w = 0; w < WPB; ++w) {
+                    R.s0 += bs->sums[w][0];
+                    for (int l = 0; l < 6; ++l) { R.s1[l] += bs->sums[w][1 + l]; R.s2[l] += bs->sums[w][7 + l]; }
+                }
+                sh.rootv = pack_decision(decide(M, R, M.idx0, 0, n, A.P, F));
+            }
+            __syncthreads();
+            const Decision rd = unpack_decision(sh.rootv);
+            if (rd.kind == D_SPLIT) {
+                if (tid == 0) {
+                    Node<IdxT> nd;
+                    nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 8) | rd.axis;
+                    M.nodes0[0] = nd;
+                }
+                m = 1;
+            } else {
+                const uint8_t base = INF_SET | (rd.kind == D_MERGED ? INF_MERGED : 0) | (uint8_t)(rd.jdir << INF_JSHIFT);
+                for (int i = tid; i < n; i += NT) M.info[i] = base | (i == 0 ? INF_HEAD : 0);
+            }
+        }
+        __syncthreads();
+
+        // ---- Steps 2-6, level by level; large unfinished subsets become tasks ----
+        while (m > 0) {
+            Node<IdxT>* curl = cur ? M.nodes1 : M.nodes0;
+            Node<IdxT>* nextl = cur ? M.nodes0 : M.nodes1;
+            if (tid == 0) {
+                sh.nnext = 0;
+                bl.spawn.n = 0;
+                bl.spawn_ok = ld_relaxed(&ctr[A.work_index]) >= qlen ? 1 : 0;     // no cell left to claim
+            }
+            const Sched s = schedule<WPB, IdxT>(M, M.sched, m, A.P.ppl_shift, [&](int it) { return (int)curl[it].len; });
+            const bool solo = __builtin_amdgcn_readfirstlane(s.total == s.cnt[0] ? 1 : 0) != 0;
             for (int r0 = wv * WAVE; r0 < s.total; r0 += NT) {
                 int slot, cls;
-                if (sched_lookup(s, r0 + lane, slot, cls)) {
-                    const int ord = mlist[sched[slot]];
-                    const int st = leaf_start[ord];
-                    const int ln = leaf_start[ord + 1] - st;
+                const int ln = opaque_lane();
+                if (sched_lookup(s, r0 + ln, slot, cls)) {
+                    const Node<IdxT> nd = curl[M.sched[slot]];
                     const int g = 1 << cls;
-                    const uint8_t inf = M.info[st];
-                    const IdxT* src = idx_buf(M, inf & INF_PARITY);
-                    merge_subset(A, F, [&](int j) { return off + (int64_t)src[st + j]; }, ln,
-                                 (inf >> INF_JSHIFT) & 3, off + M.emit[st], lane & (g - 1), g);
+                    split_node<IdxT>(M, A, F, nullptr, nd, cur, ln & (g - 1), g, ln & ~(g - 1), nextl, solo,
+                                     bl.spawn_ok ? &bl.spawn : nullptr);
                 }
             }
+            __syncthreads();
+            const int ns = bl.spawn.n;
+            if (ns > 0) {
+                // release every wave's writes of this level device-wide (a write-back, no invalidation),
+                // then publish the spawned subsets
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __syncthreads();
+                if (tid == 0)
+                    for (int k = 0; k < ns; ++k) spawn_task(B, qi, cur ^ 1, bl.spawn.node[k]);
+            }
+            m = sh.nnext;
+            cur ^= 1;
+            __syncthreads();                           // nnext and the spawn list are read before reset
         }
+
+        // ---- the piece is done; the workgroup that closes the cell's last piece writes its output ----
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // every wave's writes, device-wide
+        __syncthreads();
         if (tid == 0) {
-            A.out_count[c] = out_total;
-            A.cell_mode[c] = CELL_PROCESSED;
-            if (fl) atomicOr(A.flags, fl);
+            if (sh.flags) atomicOr(A.flags, sh.flags);
+            const int last = atomicSub(&B.cells[qi].open, 1) == 1 ? 1 : 0;
+            if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every other piece's writes
+            sh.last = last;
         }
-        if constexpr (WPB == 1) wave_fence();
+        __syncthreads();
+        if (sh.last) {
+            IdxT* scratch = (IdxT*)M.rec;              // the codes are no longer needed
+            cell_output<WPB, IdxT>(M, A, F, c, off, n, bs, scratch, scratch + (n + 1), scratch + (2 * n + 1));
+        }
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomicSub(&ctr[C_PENDING], 1);
+        }
     }
 }
 
@@ -2081,11 +2362,15 @@ int fixed_lds_bytes(int which) {
         case 0: return (int)(header_bytes<WPB_A>() + slice_bytes<uint16_t>(NMAX_A));
         case 1: return (int)(header_bytes<WPB_B>() + slice_bytes<uint16_t>(NMAX_B));
         case 2: return (int)(header_bytes<WPB_C>() + slice_bytes<uint16_t>(NMAX_C));
-        default: return (int)header_bytes<WPB_BIG>();
+        default: return (int)big_lds_bytes();
     }
 }
 
-int64_t fixed_big_slab_bytes() { return (int64_t)slice_bytes<uint32_t>(NMAX_BIG); }
+int64_t fixed_big_cell_bytes() { return (int64_t)sizeof(BigCell); }
+int64_t fixed_big_task_bytes() { return (int64_t)sizeof(BigTask); }
+int fixed_task_min() { return TASK_MIN; }
+int64_t fixed_big_lists_bytes() { return (int64_t)(2 * BIG_NODES) * (int64_t)sizeof(Node<uint32_t>); }
+int64_t fixed_big_sched_bytes() { return (int64_t)BIG_NODES * 4; }
 
 const void* fixed_kernel_ptr(int which) {
     switch (which) {
@@ -2093,7 +2378,7 @@ const void* fixed_kernel_ptr(int which) {
         case 0: return (const void*)k_fixed_cells<NMAX_A, uint16_t, true, WPB_A>;
         case 1: return (const void*)k_fixed_cells<NMAX_B, uint16_t, true, WPB_B>;
         case 2: return (const void*)k_fixed_cells<NMAX_C, uint16_t, true, WPB_C>;
-        default: return (const void*)k_fixed_cells<NMAX_BIG, uint32_t, false, WPB_BIG>;
+        default: return (const void*)k_fixed_big;
     }
 }
 
@@ -2119,7 +2404,6 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
     A.cell_mode = ws.cell_mode;
     A.flags = ws.flags;
     A.perm = nullptr; A.subset_id = nullptr; A.n_subsets = nullptr;
-    A.big = nullptr; A.big_stride = 0;
     for (int k = 0; k < BIGQ_CLASSES; ++k) A.bigq[k] = ws.bigq[k];
     G.perm = perm; G.subset_id = subset_id; G.n_subsets = n_subsets;
     G.starts = ws.perm2;
@@ -2153,9 +2437,20 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
     A.cell_mode = ws.cell_mode;
     A.flags = ws.flags;
     A.perm = perm; A.subset_id = subset_id; A.n_subsets = n_subsets;
-    A.big = ws.big;
-    A.big_stride = fixed_big_slab_bytes();
     for (int k = 0; k < BIGQ_CLASSES; ++k) A.bigq[k] = ws.bigq[k];
+    BigArgs G;
+    G.rec = (int4*)ws.big_rec;
+    G.pyz = ws.big_pyz;
+    G.idx0 = ws.big_idx0;
+    G.idx1 = ws.big_idx1;
+    G.emit = ws.big_emit;
+    G.info = ws.big_info;
+    G.cells = (BigCell*)ws.big_cells;
+    G.tasks = (BigTask*)ws.big_tasks;
+    G.ready = ws.big_ready;
+    G.ring_size = (int32_t)ws.ring_size;
+    G.lists = (Node<uint32_t>*)ws.big_lists;
+    G.sched = ws.big_sched;
 
     // The three bins touch disjoint cells, queues and counters, so they may run concurrently: the
     // large-cell and 2048 bins go first on the side streams (their cells are the longest), the
@@ -2163,6 +2458,7 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
     // for both side streams.
     bool forked = lc.fork != nullptr;
     for (int i = 0; i < 3; ++i) forked = forked && lc.side[i] && lc.join[i];
+    G.wait_idle = forked ? 0 : 1;                 // with the bins in sequence nothing else needs the CUs
     hipError_t e = hipSuccess;
     // The side streams that have waited on the fork are joined back to the caller's stream on
     // every return, also after a failure, so that a stream capture in progress stays well formed.
@@ -2205,9 +2501,10 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
         else if (b.q == Q_C)
             hipLaunchKernelGGL((k_fixed_cells<NMAX_C, uint16_t, true, WPB_C>), dim3(lc.grid_c), dim3(WAVE * WPB_C),
                                fixed_lds_bytes(2), b.s, A);
-        else
-            hipLaunchKernelGGL((k_fixed_cells<NMAX_BIG, uint32_t, false, WPB_BIG>), dim3(lc.grid_big),
-                               dim3(WAVE * WPB_BIG), fixed_lds_bytes(3), b.s, A);
+        else {
+            G.A = A;
+            hipLaunchKernelGGL(k_fixed_big, dim3(lc.grid_big), dim3(WAVE * WPB_BIG), fixed_lds_bytes(3), b.s, G);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return join_back(e);
         if (lc.post) lc.post(lc.prof, b.name, b.s);
@@ -2236,7 +2533,6 @@ hipError_t launch_fixed_blind(const Workspace& ws, const LaunchCfg& lc, const So
     A.cell_mode = ws.cell_mode;
     A.flags = ws.flags;
     A.perm = nullptr; A.subset_id = nullptr; A.n_subsets = nullptr;
-    A.big = nullptr; A.big_stride = 0;
     for (int k = 0; k < BIGQ_CLASSES; ++k) A.bigq[k] = nullptr;
     B.alpha = alpha;
     B.seed = seed;

@@ -90,7 +90,7 @@ LaunchCfg make_cfg(vpm_ctx* c, hipStream_t s) {
     lc.grid_b = c->grid_b;
     lc.grid_c = c->grid_c;
     lc.grid_s = c->grid_s;
-    lc.grid_big = c->grid_big;
+    lc.grid_big = std::min(c->grid_big, c->ws.big_wgs > 0 ? c->ws.big_wgs : c->grid_big);
     lc.grid_fp64 = c->grid_fp64;
     const bool fork = c->tune.concurrent_bins != 0;
     for (int i = 0; i < 3; ++i) { lc.side[i] = fork ? c->side[i] : nullptr; lc.join[i] = fork ? c->join[i] : nullptr; }
@@ -112,7 +112,9 @@ void free_ws(Workspace& ws) {
     if (ws.counters) hipFree(ws.counters);
     if (ws.flags) hipFree(ws.flags);
     if (ws.scan_blocks) hipFree(ws.scan_blocks);
-    if (ws.big) hipFree(ws.big);
+    void* bigs[] = {ws.big_rec, ws.big_pyz, ws.big_idx0, ws.big_idx1, ws.big_emit, ws.big_info, ws.big_cells,
+                    ws.big_tasks, ws.big_ready, ws.big_lists, ws.big_sched};
+    for (void* b : bigs) if (b) hipFree(b);
     if (ws.perm2) hipFree(ws.perm2);
     if (ws.stack) hipFree(ws.stack);
     ws = Workspace();
@@ -281,14 +283,12 @@ vpm_status vpm_create(vpm_ctx** out, int device) {
     hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device);
     if (c->cu_count <= 0) c->cu_count = 256;
     // persistent grids: as many workgroups as fit on the chip at once
-    int* grids[5] = {&c->grid_a, &c->grid_b, &c->grid_c, nullptr, &c->grid_s};
+    int* grids[5] = {&c->grid_a, &c->grid_b, &c->grid_c, &c->grid_big, &c->grid_s};
     for (int b = 0; b < 5; ++b) {
-        if (!grids[b]) continue;
         int nb = 0;
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(b), fixed_block_threads(b), fixed_lds_bytes(b));
         *grids[b] = c->cu_count * (nb > 0 ? nb : 1);
     }
-    c->grid_big = 1;                       // sized by vpm_reserve from the particle capacity
     c->grid_fp64 = c->cu_count * 16;
     // side streams and events for running the size bins concurrently
     bool side_ok = true;
@@ -348,11 +348,23 @@ vpm_status vpm_reserve(vpm_ctx* ctx, int64_t max_particles, int64_t max_cells) {
     alloc((void**)&ws.counters, 4096);
     alloc((void**)&ws.flags, 256);
     alloc((void**)&ws.scan_blocks, (size_t)(nc / 4096 + 2) * 8);
-    // one global slab per workgroup of the large-cell kernel: one per CU, but never more than the
-    // number of cells above the LDS bins that the capacity allows
-    ctx->grid_big = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->cu_count, np / (NMAX_C + 1)));
-    ws.big_bytes = fixed_big_slab_bytes() * ctx->grid_big;
-    alloc((void**)&ws.big, (size_t)ws.big_bytes);
+    // the large-cell kernel: cell-wide arrays by input position, per-cell records, and a task ring
+    // with room for every task that can be queued at once (queued tasks are disjoint subsets of at
+    // least fixed_task_min() particles)
+    alloc(&ws.big_rec, (size_t)np * 16);
+    alloc((void**)&ws.big_pyz, (size_t)np * 4);
+    alloc((void**)&ws.big_idx0, (size_t)np * 4);
+    alloc((void**)&ws.big_idx1, (size_t)np * 4);
+    alloc((void**)&ws.big_emit, (size_t)(np + 1) * 4);
+    alloc((void**)&ws.big_info, (size_t)np);
+    alloc(&ws.big_cells, (size_t)nc * (size_t)fixed_big_cell_bytes());
+    ws.ring_size = np / fixed_task_min() + 1024;
+    alloc(&ws.big_tasks, (size_t)ws.ring_size * (size_t)fixed_big_task_bytes());
+    alloc((void**)&ws.big_ready, (size_t)ws.ring_size * 4);
+    if (e == hipSuccess) e = hipMemset(ws.big_ready, 0, (size_t)ws.ring_size * 4);
+    ws.big_wgs = ctx->grid_big;
+    alloc(&ws.big_lists, (size_t)ws.big_wgs * (size_t)fixed_big_lists_bytes());
+    alloc((void**)&ws.big_sched, (size_t)ws.big_wgs * (size_t)fixed_big_sched_bytes());
     alloc((void**)&ws.perm2, (size_t)np * 2 * 4);
     alloc((void**)&ws.stack, (size_t)np * 8);
     if (e == hipSuccess) e = hipMemset(ws.counters, 0, 4096);

@@ -15,7 +15,7 @@ enum CellMode : uint8_t { CELL_PROCESSED = 0, CELL_UNTOUCHED = 1 };
 constexpr int NMAX_A = 576;     // 1 wavefront per cell, working set in LDS (8 cells per CU)
 constexpr int NMAX_B = 2048;    // 4 wavefronts per cell, working set in LDS (2 cells per CU)
 constexpr int NMAX_C = 4352;    // 8 wavefronts per cell, working set in LDS (1 cell per CU)
-constexpr int NMAX_BIG = 65536; // 8 wavefronts per cell, working set in a global slab
+constexpr int NMAX_BIG = 65536; // 8 wavefronts per piece, several workgroups per cell, working set global
 constexpr int NMAX_S = 512;     // batches of small cells: 1 wavefront, up to 512 particles in LDS
 constexpr int SMALL_MAX = 256;  // largest cell the small-cell bin may take
 enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_C = 3, Q_BIG = 4, Q_S = 5, Q_COUNT = 6 };
@@ -44,9 +44,20 @@ struct Workspace {
     int32_t* counters = nullptr;    // [64]: queue lengths, work counters
     uint32_t* flags = nullptr;      // sticky status
     int64_t* scan_blocks = nullptr; // block totals for the offset scan
-    // global-memory working set of the big-cell path, indexed by input position
-    uint8_t* big = nullptr;
-    int64_t big_bytes = 0;
+    // cells above the LDS bins: cell-wide codes, index buffers, output slots and info bytes
+    // (indexed by input position), per-cell records and the task ring of the large-cell kernel
+    void* big_rec = nullptr;        // [cap_particles] 16 B
+    int32_t* big_pyz = nullptr;     // [cap_particles]
+    uint32_t *big_idx0 = nullptr, *big_idx1 = nullptr;
+    uint32_t* big_emit = nullptr;   // [cap_particles + 1]
+    uint8_t* big_info = nullptr;
+    void* big_cells = nullptr;      // [cap_cells] records
+    void* big_tasks = nullptr;      // [ring_size] tasks
+    int32_t* big_ready = nullptr;   // [ring_size], zero between calls
+    int64_t ring_size = 0;
+    void* big_lists = nullptr;      // per workgroup of the large-cell kernel: node lists
+    uint32_t* big_sched = nullptr;  // and a schedule table
+    int big_wgs = 0;                // workgroups the slabs serve (the kernel's grid)
     // scratch for the FP64 path: two permutation buffers and a node stack per particle slot
     int32_t* perm2 = nullptr;       // [2 * cap_particles]
     int64_t* stack = nullptr;       // [cap_particles]
@@ -131,7 +142,11 @@ hipError_t launch_fixed_blind(const Workspace& ws, const LaunchCfg& lc, const So
 int fixed_lds_bytes(int which);            // dynamic LDS per workgroup
 const void* fixed_kernel_ptr(int which);   // for occupancy queries
 int fixed_block_threads(int which);
-int64_t fixed_big_slab_bytes();            // one slab per workgroup of the big-cell kernel
+int64_t fixed_big_cell_bytes();            // per-cell record of the large-cell kernel
+int64_t fixed_big_task_bytes();            // one task of its ring
+int fixed_task_min();                      // smallest subset handed to another workgroup
+int64_t fixed_big_lists_bytes();           // per workgroup of the large-cell kernel
+int64_t fixed_big_sched_bytes();
 
 // ---- plain FP64 path (vpm_fp64.hip) ----
 struct Fp64Params {

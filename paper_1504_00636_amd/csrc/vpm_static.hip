@@ -18,11 +18,11 @@
 namespace vpm {
 namespace {
 
-// The limits of one call, and the bytes of the array.  Two slabs serve the cells above the LDS bins.
+// The limits of one call, and the bytes of the array.
 constexpr int64_t NA_MAX_PARTICLES = VPM_NOALLOC_MAX_PARTICLES;
 constexpr int64_t NA_MAX_CELLS = VPM_NOALLOC_MAX_CELLS;
-constexpr int NA_SLABS = 2;
-constexpr size_t NA_SCRATCH_BYTES = (size_t)24 << 20;
+constexpr int NA_BIG_WGS = 4;              // workgroups of the large-cell kernel (their node-list slabs)
+constexpr size_t NA_SCRATCH_BYTES = (size_t)48 << 20;
 
 static __device__ __align__(256) uint8_t scratch[NA_SCRATCH_BYTES];
 
@@ -55,8 +55,19 @@ size_t carve(uint8_t* base, Workspace& ws) {
     ws.counters = (int32_t*)take(4096);
     ws.flags = (uint32_t*)take(256);
     ws.scan_blocks = (int64_t*)take((size_t)(NA_MAX_CELLS / 4096 + 2) * 8);
-    ws.big_bytes = fixed_big_slab_bytes() * NA_SLABS;
-    ws.big = take((size_t)ws.big_bytes);
+    ws.big_rec = take((size_t)NA_MAX_PARTICLES * 16);
+    ws.big_pyz = (int32_t*)take((size_t)NA_MAX_PARTICLES * 4);
+    ws.big_idx0 = (uint32_t*)take((size_t)NA_MAX_PARTICLES * 4);
+    ws.big_idx1 = (uint32_t*)take((size_t)NA_MAX_PARTICLES * 4);
+    ws.big_emit = (uint32_t*)take((size_t)(NA_MAX_PARTICLES + 1) * 4);
+    ws.big_info = take((size_t)NA_MAX_PARTICLES);
+    ws.big_cells = take((size_t)NA_MAX_CELLS * (size_t)fixed_big_cell_bytes());
+    ws.ring_size = NA_MAX_PARTICLES / fixed_task_min() + 1024;
+    ws.big_tasks = take((size_t)ws.ring_size * (size_t)fixed_big_task_bytes());
+    ws.big_ready = (int32_t*)take((size_t)ws.ring_size * 4);     // zero at load, zero after every call
+    ws.big_wgs = NA_BIG_WGS;
+    ws.big_lists = take((size_t)NA_BIG_WGS * (size_t)fixed_big_lists_bytes());
+    ws.big_sched = (uint32_t*)take((size_t)NA_BIG_WGS * (size_t)fixed_big_sched_bytes());
     ws.perm2 = nullptr;                    // used only by the FP64 form and vpm_merge
     ws.stack = nullptr;
     return o;
@@ -75,10 +86,9 @@ vpm_status device_setup(int dev, uint8_t** ptr, int grid[5]) {
             cus = 256;
         for (int b = 0; b < 5; ++b) {
             int nb = 0;
-            if (b != 3)
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(b), fixed_block_threads(b),
-                                                             fixed_lds_bytes(b));
-            g_grid[dev][b] = b == 3 ? NA_SLABS : cus * (nb > 0 ? nb : 1);
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(b), fixed_block_threads(b),
+                                                         fixed_lds_bytes(b));
+            g_grid[dev][b] = b == 3 ? NA_BIG_WGS : cus * (nb > 0 ? nb : 1);
         }
         g_ptr[dev] = (uint8_t*)p;
     }

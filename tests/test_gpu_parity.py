@@ -362,3 +362,28 @@ def test_merge_rejects_duplicated_member(decide):
     ref = oracle.run_workload(wl.cells([1]), decide=oracle.FIXED if decide == vpm.VPM_DECIDE_FIXED else oracle.PAPER,
                               **oracle_params(CLOUD))
     assert tot - 60 == ref.out_total
+
+
+@pytest.mark.parametrize("concurrent", [0, 1])
+def test_large_cells_across_workgroups(concurrent):
+    """Cells above the LDS bins are split by several workgroups at once once no cell is left to claim
+    (subsets of >= 2,048 particles go to a device task queue).  Heavy-tailed momenta and lognormal
+    weights make the splits lopsided, so tasks spawn tasks along chains.  The result must be the
+    oracle's, with the bins in sequence (idle workgroups wait for tasks) and concurrent (they leave)."""
+    from tests.gpu_common import ctx
+    r = np.random.Generator(np.random.Philox(41))
+    cells = []
+    for k in (60000, 33000, 17000, 9000, 4400, 2100, 300):
+        p = np.exp(1.5 * r.standard_normal((k, 3))) * np.array([1.0, 0.3, 0.2])
+        cells.append(np.concatenate([r.random((k, 3)), p, np.exp(r.standard_normal((k, 1)))], axis=1))
+    params = dict(CLOUD, tol_x=0.2, tol_p=0.5)
+    wl = W.from_cells(cells, params=params, dtype=np.float32)
+    c = ctx(wl.n, wl.n_cells)
+    default = c.get_tuning()
+    c.set_tuning(vpm.make_tuning(concurrent_bins=concurrent))
+    try:
+        ref = full_check(wl, params)
+        full_check(wl, params, vpm.VPM_MERGE_CENTROID)
+    finally:
+        c.set_tuning(default)
+    assert ref.stats["max_depth"].max() > 12 and ref.out_total < wl.n
