@@ -64,6 +64,10 @@ typedef enum {
 typedef enum { VPM_F32 = 0, VPM_F64 = 1 } vpm_dtype;
 typedef enum { VPM_DECIDE_FIXED = 0, VPM_DECIDE_FP64 = 1 } vpm_decide;
 typedef enum { VPM_MERGE_PAIR = 0, VPM_MERGE_CENTROID = 1 } vpm_merge_mode;
+/* Step 4's axis: the largest raw CV (the paper's rule, default), or the largest CV over its own
+ * tolerance, Delta_l / T_l (a CV > 0 over a zero tolerance counts as infinite; ties still go to the
+ * lowest axis).  Step 3's test is the same under both. */
+typedef enum { VPM_AXIS_RAW = 0, VPM_AXIS_NORMALISED = 1 } vpm_axis_rule;
 
 /* Sticky device flags (vpm_device_status). */
 #define VPM_FLAG_BAD_VALUE      0x1u  /* w <= 0, NaN or Inf in a cell: that cell passed through     */
@@ -95,7 +99,7 @@ typedef struct {
     int32_t merge_mode;   /* vpm_merge_mode */
     int32_t decide;       /* vpm_decide */
     int32_t dtype;        /* vpm_dtype of every particle array */
-    int32_t reserved;     /* must be 0 */
+    int32_t axis_rule;    /* vpm_axis_rule */
 } vpm_params;
 
 typedef struct { void *x, *y, *z, *px, *py, *pz, *w; } vpm_soa;   /* device pointers */

@@ -39,7 +39,7 @@ class _Params(C.Structure):
     _fields_ = [("tol_x", C.c_double), ("tol_p", C.c_double),
                 ("n_min_cell", C.c_int32), ("min_subset", C.c_int32),
                 ("cell_len", C.c_double * 3), ("mass", C.c_double),
-                ("merge_mode", C.c_int32), ("decide", C.c_int32)]
+                ("merge_mode", C.c_int32), ("decide", C.c_int32), ("axis_rule", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -97,7 +97,7 @@ class OracleResult:
 
 
 def make_params(tol_x, tol_p, n_min_cell=0, min_subset=4, cell_len=(1.0, 1.0, 1.0), mass=1.0,
-                merge_mode=PAIR, decide=FIXED) -> _Params:
+                merge_mode=PAIR, decide=FIXED, axis_rule=0) -> _Params:
     p = _Params()
     p.tol_x, p.tol_p = float(tol_x), float(tol_p)
     p.n_min_cell, p.min_subset = int(n_min_cell), int(min_subset)
@@ -105,15 +105,17 @@ def make_params(tol_x, tol_p, n_min_cell=0, min_subset=4, cell_len=(1.0, 1.0, 1.
         p.cell_len[a] = float(cell_len[a])
     p.mass = float(mass)
     p.merge_mode, p.decide = int(merge_mode), int(decide)
+    p.axis_rule = int(axis_rule)
     return p
 
 
 def run(arrays, cell_off, tol_x, tol_p, n_min_cell=0, min_subset=4, cell_len=(1.0, 1.0, 1.0),
-        mass=1.0, merge_mode=PAIR, decide=FIXED, n_threads: int = 0, lib=None) -> OracleResult:
+        mass=1.0, merge_mode=PAIR, decide=FIXED, n_threads: int = 0, lib=None, axis_rule=0) -> OracleResult:
     """Run the oracle.  ``arrays`` = (x, y, z, px, py, pz, w), any float dtype (FIXED mode rounds
-    the values to FP32 first, as the GPU's fixed-point path does)."""
+    the values to FP32 first, as the GPU's fixed-point path does).  axis_rule 1: Step 4 on each CV
+    over its tolerance."""
     lib = lib or _load()
-    p = make_params(tol_x, tol_p, n_min_cell, min_subset, cell_len, mass, merge_mode, decide)
+    p = make_params(tol_x, tol_p, n_min_cell, min_subset, cell_len, mass, merge_mode, decide, axis_rule)
     cell_off = np.ascontiguousarray(cell_off, dtype=np.int64)
     n_cells = cell_off.shape[0] - 1
     n = int(cell_off[-1])

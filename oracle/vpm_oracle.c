@@ -32,7 +32,8 @@
  * Readings of the paper taken here (where it is silent or ambiguous):
  *   L in Delta_X is the simulation-cell side length, fixed for the cell;
  *   Delta_P divides by |P| (0/0 := 0; sigma > 0 with P = 0 gives +infinity);
- *   argmax over the six raw CVs, ties to the lowest axis (x,y,z,px,py,pz);
+ *   argmax over the six raw CVs, ties to the lowest axis (x,y,z,px,py,pz) -- or, as an option,
+ *   over each CV divided by its tolerance (a CV > 0 over a zero tolerance counts as infinite);
  *   subsets with fewer than min_subset particles are final and passed through;
  *   a cut that leaves one side empty (possible only through rounding) ends the
  *   subset as finished;  energy of a particle is sqrt(m^2 + |p|^2).
@@ -79,6 +80,7 @@ typedef struct {
     double mass;               /* particle mass in m_e units (0 for photons) */
     int32_t merge_mode;        /* ORC_PAIR or ORC_CENTROID */
     int32_t decide;            /* ORC_FIXED or ORC_PAPER */
+    int32_t axis_rule;         /* 0: Step 4 on the raw CVs; 1: on each CV over its tolerance */
 } orc_params;
 
 typedef struct {
@@ -120,6 +122,29 @@ static u256 u256_mul(u128 a, u128 b) {
 
 static int u256_cmp(u256 a, u256 b) {
     for (int i = 3; i >= 0; --i) {
+        if (a.v[i] < b.v[i]) return -1;
+        if (a.v[i] > b.v[i]) return 1;
+    }
+    return 0;
+}
+
+/* a 256-bit value times a 64-bit one (five limbs, enough for the normalised comparison) */
+typedef struct { uint64_t v[5]; } u320;
+
+static u320 u320_mul(u256 a, uint64_t b) {
+    u320 r;
+    u128 carry = 0;
+    for (int i = 0; i < 4; ++i) {
+        u128 t = (u128)a.v[i] * b + carry;
+        r.v[i] = (uint64_t)t;
+        carry = t >> 64;
+    }
+    r.v[4] = (uint64_t)carry;
+    return r;
+}
+
+static int u320_cmp(u320 a, u320 b) {
+    for (int i = 4; i >= 0; --i) {
         if (a.v[i] < b.v[i]) return -1;
         if (a.v[i] > b.v[i]) return 1;
     }
@@ -313,6 +338,19 @@ static int frac_gt(frac a, frac b) {          /* a > b ? */
     return u256_cmp(u256_mul(a.num, b.den), u256_mul(b.num, a.den)) > 0;
 }
 
+/* Step 4 with each CV over its tolerance: is Delta_a^2 / Ta^2 > Delta_b^2 / Tb^2 ?  With Delta^2 =
+ * V / D and T^2 = T2 / 2^48 this compares V_a D_b T2_b with V_b D_a T2_a (< 2^320).  A zero D or a
+ * zero T2 under V > 0 is infinite; V = 0 is 0. */
+static int frac_gt_norm(frac a, uint64_t t2a, frac b, uint64_t t2b) {
+    int az = a.num == 0, bz = b.num == 0;
+    if (az) return 0;
+    if (bz) return 1;
+    int ainf = a.den == 0 || t2a == 0, binf = b.den == 0 || t2b == 0;
+    if (ainf) return !binf;
+    if (binf) return 0;
+    return u320_cmp(u320_mul(u256_mul(a.num, b.den), t2b), u320_mul(u256_mul(b.num, a.den), t2a)) > 0;
+}
+
 /* Step 3 in integers: Delta^2 <= (T^2).  T = That / 2^24.
  *   position: V/(2^32 S0^2) <= That^2/2^48   <=>  V*2^16 <= That^2 S0^2
  *   momentum: V/S1^2        <= That^2/2^48   <=>  V*2^48 <= That^2 S1^2 */
@@ -375,9 +413,12 @@ static void run_cell(cell_ctx *cc) {
                 for (int l = 0; l < 6; ++l) done &= fixed_within(&S, l, l < 3 ? Tx : Tp);
                 if (!done) {
                     frac best = fixed_delta2(&S, 0);
+                    const uint64_t tx2 = (uint64_t)(Tx * Tx), tp2 = (uint64_t)(Tp * Tp);
                     for (int l = 1; l < 6; ++l) {
                         frac f = fixed_delta2(&S, l);
-                        if (frac_gt(f, best)) { best = f; k = l; }
+                        int gt = p->axis_rule ? frac_gt_norm(f, l < 3 ? tx2 : tp2, best, k < 3 ? tx2 : tp2)
+                                              : frac_gt(f, best);
+                        if (gt) { best = f; k = l; }
                     }
                     split = 1;
                     v1 = (int *)malloc(sizeof(int) * (size_t)cnt);
@@ -443,12 +484,19 @@ static void run_cell(cell_ctx *cc) {
                 if (isfinite(D[l])) margin_update(cc, T > 0 ? fabs(D[l] - T) / T : fabs(D[l]));
             }
             if (!done) {
+                /* Step 4 on the raw CVs, or on each CV over its tolerance (then a CV > 0 over a
+                 * zero tolerance is infinite) */
+                double R[6];
+                for (int l = 0; l < 6; ++l) {
+                    double T = l < 3 ? p->tol_x : p->tol_p;
+                    R[l] = !p->axis_rule ? D[l] : (T > 0 ? D[l] / T : (D[l] > 0 ? INFINITY : 0.0));
+                }
                 k = 0;
-                for (int l = 1; l < 6; ++l) if (D[l] > D[k]) k = l;
+                for (int l = 1; l < 6; ++l) if (R[l] > R[k]) k = l;
                 double second = -1;
-                for (int l = 0; l < 6; ++l) if (l != k && D[l] > second) second = D[l];
-                if (isinf(D[k])) margin_update(cc, isinf(second) ? 0.0 : 1.0);
-                else if (D[k] > 0) margin_update(cc, (D[k] - second) / D[k]);
+                for (int l = 0; l < 6; ++l) if (l != k && R[l] > second) second = R[l];
+                if (isinf(R[k])) margin_update(cc, isinf(second) ? 0.0 : 1.0);
+                else if (R[k] > 0) margin_update(cc, (R[k] - second) / R[k]);
                 split = 1;
                 v1 = (int *)malloc(sizeof(int) * (size_t)cnt);
                 v2 = (int *)malloc(sizeof(int) * (size_t)cnt);

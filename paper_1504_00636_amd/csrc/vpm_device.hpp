@@ -84,6 +84,31 @@ VPM_DEV int cmp256(U256 a, U256 b) {
     return 0;
 }
 
+struct U320 { uint64_t w[5]; };
+
+// a 256-bit value times a 64-bit one
+VPM_DEV U320 mul256x64(U256 a, uint64_t b) {
+    const uint64_t in[4] = {a.w0, a.w1, a.w2, a.w3};
+    U320 r;
+    uint64_t carry = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t lo = in[i] * b, hi = __umul64hi(in[i], b);
+        const uint64_t s = lo + carry;
+        r.w[i] = s;
+        carry = hi + (s < lo ? 1u : 0u);
+    }
+    r.w[4] = carry;
+    return r;
+}
+
+VPM_DEV int cmp320(const U320& a, const U320& b) {
+#pragma unroll
+    for (int i = 4; i >= 0; --i)
+        if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
+    return 0;
+}
+
 // ------------------------------------------------------------------------------------------
 // Lane groups: g lanes (g a power of two <= 64) starting at a lane multiple of g.
 // ------------------------------------------------------------------------------------------

@@ -189,6 +189,17 @@ VPM_DEV bool frac_gt(U128 Va, U128 Da, U128 Vb, U128 Db) {
     return cmp256(mul128(Va, Db), mul128(Vb, Da)) > 0;
 }
 
+// Is Delta_a^2 / Ta^2 > Delta_b^2 / Tb^2 (the normalised axis rule)?  With T^2 = T2 / 2^48 this
+// compares Va Db T2b with Vb Da T2a (< 2^320).  Zero D or zero T2 under V > 0 is +infinity.
+VPM_DEV bool frac_gt_norm(U128 Va, U128 Da, uint64_t T2a, U128 Vb, U128 Db, uint64_t T2b) {
+    if (is_zero128(Va)) return false;
+    if (is_zero128(Vb)) return true;
+    const bool ainf = is_zero128(Da) || T2a == 0, binf = is_zero128(Db) || T2b == 0;
+    if (ainf) return !binf;
+    if (binf) return false;
+    return cmp320(mul256x64(mul128(Va, Db), T2b), mul256x64(mul128(Vb, Da), T2a)) > 0;
+}
+
 // The exact rule on exact integer moments.
 VPM_DEV Decision decide_exact(const ISums& S, const FixedParams& P, const Frame& F) {
     Decision d;
@@ -239,8 +250,11 @@ VPM_DEV Decision decide_exact(const ISums& S, const FixedParams& P, const Frame&
     U128 bV = V[0], bD = D[0];
     double s1k = s1d[0];
 #pragma unroll
-    for (int l = 1; l < 6; ++l)
-        if (frac_gt(V[l], D[l], bV, bD)) { k = l; bV = V[l]; bD = D[l]; s1k = s1d[l]; }
+    for (int l = 1; l < 6; ++l) {
+        const bool gt = P.axis_rule ? frac_gt_norm(V[l], D[l], l < 3 ? P.tx2 : P.tp2, bV, bD, k < 3 ? P.tx2 : P.tp2)
+                                    : frac_gt(V[l], D[l], bV, bD);
+        if (gt) { k = l; bV = V[l]; bD = D[l]; s1k = s1d[l]; }
+    }
     d.kind = D_SPLIT;
     d.axis = k;
     d.thr = cut_threshold(s1k, (double)S.s0);
@@ -300,6 +314,22 @@ VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, cons
         d.kind = D_MERGED;
         d.jdir = pair_axis(S.s1, F);
         return d;
+    }
+    if (P.axis_rule) {
+        // Step 4 on Delta_l^2 / tau_l^2: the brackets times an outward FP32 bracket of 1 / tau^2
+        // (each product rounds by at most 2^-24, inside that bracket's 2^-22 margin); a zero
+        // tolerance makes any CV > 0 infinite
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+            const bool pos = l < 3;
+            if ((pos ? P.that_x : P.that_p) == 0) {
+                lo[l] = lo[l] > 0.0f ? INFINITY : 0.0f;
+                hi[l] = hi[l] > 0.0f ? INFINITY : 0.0f;
+            } else {
+                lo[l] = lo[l] * (pos ? P.it2x_lo : P.it2p_lo);
+                hi[l] = hi[l] * (pos ? P.it2x_hi : P.it2p_hi);
+            }
+        }
     }
     int k = 0;
     float best = lo[0];

@@ -189,6 +189,14 @@ __global__ __launch_bounds__(64) void k_fp64_cells(Fp64Args A) {
                     if (!(D[l] <= T)) done = false;
                 }
                 if (!done) {
+                    // Step 4: the largest CV, or with the normalised rule the largest CV over its
+                    // tolerance (> 0 over a zero tolerance: infinite); ties to the lowest axis
+                    if (A.P.axis_rule) {
+                        for (int l = 0; l < 6; ++l) {
+                            const double T = l < 3 ? A.P.tol_x : A.P.tol_p;
+                            D[l] = T > 0.0 ? D[l] / T : (D[l] > 0.0 ? INFINITY : 0.0);
+                        }
+                    }
                     int k = 0;
                     for (int l = 1; l < 6; ++l) if (D[l] > D[k]) k = l;
                     const double Q = mean[k];

@@ -161,6 +161,7 @@ FixedParams fixed_params(const vpm_params* p, const vpm_tuning& t) {
     };
     bracket(f.that_x, f.t2x_lo, f.t2x_hi);
     bracket(f.that_p, f.t2p_lo, f.t2p_hi);
+    fixed_axis_rule(f, p->axis_rule);
     for (int a = 0; a < 3; ++a) f.s[a] = (float)(65536.0 / p->cell_len[a]);
     f.min_subset = p->min_subset;
     f.merge_mode = p->merge_mode;
@@ -180,6 +181,7 @@ Fp64Params fp64_params(const vpm_params* p) {
     f.min_subset = p->min_subset;
     f.merge_mode = p->merge_mode;
     f.n_min_cell = p->n_min_cell;
+    f.axis_rule = p->axis_rule;
     f.species = nullptr;
     for (int k = 0; k < VPM_MAX_SPECIES; ++k) f.species_mass[k] = p->mass;
     return f;
@@ -266,7 +268,7 @@ vpm_status vpm_check_params(const vpm_params* p) {
     for (int a = 0; a < 3; ++a) if (!finite_pos(p->cell_len[a])) return VPM_ERR_INVALID_ARG;
     if (!(std::isfinite(p->mass) && p->mass >= 0.0)) return VPM_ERR_INVALID_ARG;
     if (p->dtype != VPM_F32 && p->dtype != VPM_F64) return VPM_ERR_INVALID_ARG;
-    if (p->reserved != 0) return VPM_ERR_INVALID_ARG;
+    if (p->axis_rule != VPM_AXIS_RAW && p->axis_rule != VPM_AXIS_NORMALISED) return VPM_ERR_INVALID_ARG;
     return VPM_OK;
 }
 

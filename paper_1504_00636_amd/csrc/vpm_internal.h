@@ -69,6 +69,10 @@ struct FixedParams {
     float t2x_lo, t2x_hi;           // FP32 bracket of (that_x / 2^24)^2
     float t2p_lo, t2p_hi;           // FP32 bracket of (that_p / 2^24)^2
     float s[3];                     // fl32(65536 / L_a)
+    int32_t axis_rule;              // vpm_axis_rule
+    uint64_t tx2, tp2;              // that_x^2, that_p^2 (< 2^62)
+    float it2x_lo, it2x_hi;         // FP32 bracket of 1 / (that_x / 2^24)^2 (0 if that_x = 0)
+    float it2p_lo, it2p_hi;
     int32_t min_subset;
     int32_t merge_mode;
     int32_t ppl_shift;              // log2 of the target particles per lane of a lane group
@@ -76,6 +80,21 @@ struct FixedParams {
     const uint8_t* species;         // per-cell species index (null: every cell has `mass`)
     double species_mass[VPM_MAX_SPECIES];
 };
+
+// Step 4's tolerance scale for the normalised axis rule, derived from that_x and that_p.
+inline void fixed_axis_rule(FixedParams& f, int rule) {
+    f.axis_rule = rule;
+    f.tx2 = f.that_x * f.that_x;
+    f.tp2 = f.that_p * f.that_p;
+    auto inv = [](uint64_t t, float& lo, float& hi) {      // 2^48 / t^2, bracketed 2^-22 each side
+        if (t == 0) { lo = hi = 0.0f; return; }
+        const float f = (float)(0x1p48 / ((double)t * (double)t));
+        lo = f * (1.0f - 0x1p-22f);
+        hi = f * (1.0f + 0x1p-22f);
+    };
+    inv(f.that_x, f.it2x_lo, f.it2x_hi);
+    inv(f.that_p, f.it2p_lo, f.it2p_hi);
+}
 
 // The particle mass of cell c (c wave-uniform).  The table is read with constant indices only.
 __host__ __device__ inline double cell_mass(double mass, const uint8_t* species, const double* table, int64_t c) {
@@ -151,7 +170,7 @@ int64_t fixed_big_sched_bytes();
 // ---- plain FP64 path (vpm_fp64.hip) ----
 struct Fp64Params {
     double tol_x, tol_p, L[3], mass;
-    int32_t min_subset, merge_mode, n_min_cell;
+    int32_t min_subset, merge_mode, n_min_cell, axis_rule;
     const uint8_t* species;         // as in FixedParams
     double species_mass[VPM_MAX_SPECIES];
 };

@@ -141,6 +141,7 @@ extern "C" vpm_status vpm_run_noalloc(const vpm_soa* in, const int64_t* cell_off
     };
     bracket(fp.that_x, fp.t2x_lo, fp.t2x_hi);
     bracket(fp.that_p, fp.t2p_lo, fp.t2p_hi);
+    fixed_axis_rule(fp, p->axis_rule);
     for (int a = 0; a < 3; ++a) fp.s[a] = (float)(65536.0 / p->cell_len[a]);
     fp.min_subset = p->min_subset;
     fp.merge_mode = p->merge_mode;

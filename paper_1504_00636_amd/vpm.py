@@ -20,6 +20,7 @@ VPM_OK, VPM_ERR_INVALID_ARG, VPM_ERR_UNSUPPORTED, VPM_ERR_CAPACITY, VPM_ERR_HIP,
 VPM_F32, VPM_F64 = 0, 1
 VPM_DECIDE_FIXED, VPM_DECIDE_FP64 = 0, 1
 VPM_MERGE_PAIR, VPM_MERGE_CENTROID = 0, 1
+VPM_AXIS_RAW, VPM_AXIS_NORMALISED = 0, 1
 VPM_FLAG_BAD_VALUE, VPM_FLAG_OUT_OF_CELL, VPM_FLAG_CELL_TOO_LARGE, VPM_FLAG_BAD_OFFSETS = 1, 2, 4, 8
 VPM_FLAG_BAD_PARTITION = 16
 VPM_FLAG_BAD_SPECIES = 32
@@ -38,7 +39,7 @@ class VpmParams(C.Structure):
                 ("n_min_cell", C.c_int32), ("min_subset", C.c_int32),
                 ("cell_len", C.c_double * 3), ("mass", C.c_double),
                 ("merge_mode", C.c_int32), ("decide", C.c_int32),
-                ("dtype", C.c_int32), ("reserved", C.c_int32)]
+                ("dtype", C.c_int32), ("axis_rule", C.c_int32)]
 
 
 class VpmTuning(C.Structure):
@@ -121,7 +122,7 @@ def vpm_version() -> str:
 
 
 def make_params(tol_x, tol_p, n_min_cell=0, min_subset=4, cell_len=(1.0, 1.0, 1.0), mass=1.0,
-                merge_mode=VPM_MERGE_PAIR, decide=VPM_DECIDE_FIXED, dtype=None) -> VpmParams:
+                merge_mode=VPM_MERGE_PAIR, decide=VPM_DECIDE_FIXED, dtype=None, axis_rule=VPM_AXIS_RAW) -> VpmParams:
     p = VpmParams()
     p.tol_x, p.tol_p = float(tol_x), float(tol_p)
     p.n_min_cell, p.min_subset = int(n_min_cell), int(min_subset)
@@ -132,7 +133,7 @@ def make_params(tol_x, tol_p, n_min_cell=0, min_subset=4, cell_len=(1.0, 1.0, 1.
     if dtype is None:
         dtype = VPM_F32 if decide == VPM_DECIDE_FIXED else VPM_F64
     p.dtype = int(dtype)
-    p.reserved = 0
+    p.axis_rule = int(axis_rule)
     return p
 
 

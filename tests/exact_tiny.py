@@ -14,7 +14,8 @@ paper (Sec. "Algorithm", Steps 1-7, and the two-particle merge of its remarks), 
   omega = rint(w 2^(15 - e_w)), position code rint(fl32(fl32(x - lo) * fl32(65536 / L))) - 32768
   (clamped to 65535 - 32768), momentum code rint(p 2^(22 - e_a)); moments S0, S1, S2; the tests
   V 2^16 <= T^2 S0^2 (positions) and V 2^48 <= T^2 S1^2 (momenta), T^ = rint(T 2^24); the argmax of
-  V / D as exact fractions; the cut c S0 <= S1.
+  V / D as exact fractions (or, with the tolerance-normalised axis rule, of V 2^48 / (D T^2)); the
+  cut c S0 <= S1.
 * Replacement with exact sums (Fractions); the pair's square roots in 50-digit decimals.  The pair
   direction: the momentum axis j with the smallest |sum w p_j| (on the codes in FIXED mode), ties
   to the lowest j; u = e_j - (e_j . P) P / |P|^2 (u = e_j when P = 0); delta = sqrt(r) u / |u| with
@@ -80,7 +81,7 @@ def fixed_codes(rows, L):
     return omega, codes, e_p, zero
 
 
-def _fixed_decide(members, omega, codes, e_p, that_x, that_p):
+def _fixed_decide(members, omega, codes, e_p, that_x, that_p, axis_rule=0):
     """(kind, axis, cut, jdir) for a subset in FIXED mode; kind is 'merge' or 'split'."""
     S0 = sum(omega[i] for i in members)
     S1 = [sum(omega[i] * codes[i][l] for i in members) for l in range(6)]
@@ -108,7 +109,12 @@ def _fixed_decide(members, omega, codes, e_p, that_x, that_p):
         if V[l] == 0:
             return Fraction(0)
         D = 2 ** 32 * S0 ** 2 if l < 3 else S1[l] ** 2
-        return INF if D == 0 else Fraction(V[l], D)
+        if axis_rule:                       # Delta^2 / T^2, T = T^ / 2^24
+            D *= (that_x if l < 3 else that_p) ** 2
+            V_l = V[l] * 2 ** 48
+        else:
+            V_l = V[l]
+        return INF if D == 0 else Fraction(V_l, D)
 
     k, best = 0, delta2(0)
     for l in range(1, 6):
@@ -120,7 +126,7 @@ def _fixed_decide(members, omega, codes, e_p, that_x, that_p):
     return "split", k, S1[k], S0, jdir
 
 
-def _paper_decide(members, q, w, L, tol_x, tol_p):
+def _paper_decide(members, q, w, L, tol_x, tol_p, axis_rule=0):
     W = sum(w[i] for i in members)
     mean = [sum(w[i] * q[l][i] for i in members) / W for l in range(6)]
     var = [sum(w[i] * (q[l][i] - mean[l]) ** 2 for i in members) / W for l in range(6)]
@@ -138,6 +144,8 @@ def _paper_decide(members, q, w, L, tol_x, tol_p):
     T2 = [tol_x ** 2] * 3 + [tol_p ** 2] * 3
     if all(d is not INF and d <= T2[l] for l, d in enumerate(d2)):
         return "merge", 0, mean, jdir
+    if axis_rule:                           # each CV over its tolerance (> 0 over 0: infinite)
+        d2 = [d if d is INF or d == 0 else (d / T2[l] if T2[l] > 0 else INF) for l, d in enumerate(d2)]
     k = 0
     for l in range(1, 6):
         if d2[k] is INF:
@@ -154,8 +162,9 @@ def _paper_decide(members, q, w, L, tol_x, tol_p):
 class Cell:
     """One cell: rows of 7 floats (x, y, z, px, py, pz, w) and the merge parameters."""
 
-    def __init__(self, rows, tol_x, tol_p, min_subset, L=(1.0, 1.0, 1.0), mass=1.0, mode=FIXED):
+    def __init__(self, rows, tol_x, tol_p, min_subset, L=(1.0, 1.0, 1.0), mass=1.0, mode=FIXED, axis_rule=0):
         self.mode = mode
+        self.axis_rule = int(axis_rule)
         if mode == FIXED:
             rows = [tuple(float(np.float32(v)) for v in r) for r in rows]
         self.rows = [tuple(float(v) for v in r) for r in rows]
@@ -176,13 +185,14 @@ class Cell:
         if len(members) < self.min_subset:
             return ("copy",)
         if self.mode == FIXED:
-            r = _fixed_decide(members, self.omega, self.codes, self.e_p, self.that_x, self.that_p)
+            r = _fixed_decide(members, self.omega, self.codes, self.e_p, self.that_x, self.that_p, self.axis_rule)
             if r[0] == "merge":
                 return ("merge", r[3])
             _, k, s1, s0, jdir = r
             v1 = [i for i in members if self.codes[i][k] * s0 <= s1]
         else:
-            r = _paper_decide(members, self.q, self.w, self.L, Fraction(self.tol_x), Fraction(self.tol_p))
+            r = _paper_decide(members, self.q, self.w, self.L, Fraction(self.tol_x), Fraction(self.tol_p),
+                              self.axis_rule)
             if r[0] == "merge":
                 return ("merge", r[3])
             _, k, cut, jdir = r

@@ -47,7 +47,8 @@ def gpu_run(wl, params: dict, decide=vpm.VPM_DECIDE_FIXED, merge=vpm.VPM_MERGE_P
 
 
 def oracle_params(params: dict):
-    return {k: params[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset", "cell_len", "mass")}
+    keys = ("tol_x", "tol_p", "n_min_cell", "min_subset", "cell_len", "mass", "axis_rule")
+    return {k: params[k] for k in keys if k in params}
 
 
 def check_partition_equal(wl, params, decide_gpu=vpm.VPM_DECIDE_FIXED, decide_orc=oracle.FIXED, ref=None,

@@ -32,7 +32,7 @@ def load_golden(name):
     arr = np.array(inputs, dtype=np.float64)
     prm = dict(tol_x=float(params["tol_x"]), tol_p=float(params["tol_p"]),
                min_subset=int(params["min_subset"]), n_min_cell=int(params["n_min_cell"]),
-               mass=float(params["mass"]))
+               mass=float(params["mass"]), axis_rule=int(params.get("axis_rule", 0)))
     return arr, prm, params.get("merge", "pair"), subsets, np.array(merged, dtype=np.float64)
 
 

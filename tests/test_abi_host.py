@@ -57,10 +57,12 @@ def test_fp64_mode_allows_large_tolerance():
     assert vpm.vpm_check_params(_p(decide=vpm.VPM_DECIDE_FP64, tol_x=1e6)) == vpm.VPM_OK
 
 
-def test_reserved_field_must_be_zero():
-    p = _p()
-    p.reserved = 1
-    assert vpm.vpm_check_params(p) == vpm.VPM_ERR_INVALID_ARG
+def test_axis_rule_field():
+    assert vpm.vpm_check_params(_p(axis_rule=vpm.VPM_AXIS_NORMALISED)) == vpm.VPM_OK
+    for bad in (2, -1):
+        p = _p()
+        p.axis_rule = bad
+        assert vpm.vpm_check_params(p) == vpm.VPM_ERR_INVALID_ARG
 
 
 def test_null_params_rejected():

@@ -249,7 +249,7 @@ def test_fp64_path_two_stream():
 
 
 GOLDEN = ["px_bisection_6.txt", "corners_tie_4.txt", "px_ladder_8.txt", "pair_direction_2.txt",
-          "pair_two_clusters_4.txt"]
+          "pair_two_clusters_4.txt", "axis_rule_normalised_4.txt", "axis_rule_raw_4.txt"]
 
 
 @pytest.mark.parametrize("decide", [vpm.VPM_DECIDE_FIXED, vpm.VPM_DECIDE_FP64])
@@ -387,3 +387,30 @@ def test_large_cells_across_workgroups(concurrent):
     finally:
         c.set_tuning(default)
     assert ref.stats["max_depth"].max() > 12 and ref.out_total < wl.n
+
+
+@pytest.mark.parametrize("merge", MERGES)
+def test_normalised_axis_rule(merge):
+    """Step 4 on each CV over its tolerance (VPM_AXIS_NORMALISED), with tolerances far apart so that
+    the rule changes the partitions: the fixed-point path against the FIXED oracle (bit-exact), the
+    FP64 form against the PAPER oracle (near-ties certified), and the result differs from the raw
+    rule's."""
+    wl = cloud_cells([300, 57, 1000, 5, 0, 3000, 9000, 2, 600], seed=15)
+    params = dict(CLOUD, tol_x=0.6, tol_p=0.02, axis_rule=1, min_subset=4 if merge == vpm.VPM_MERGE_PAIR else 2)
+    ref = full_check(wl, params, merge)
+    raw = oracle.run_workload(wl, merge_mode=merge, **oracle_params(dict(params, axis_rule=0)))
+    assert not np.array_equal(ref.subset_id, raw.subset_id)
+    wl64 = cloud_cells([300, 57, 1000, 5, 0, 3000, 2, 600], seed=16, dtype=np.float64)
+    assert _fp64_check(wl64, params, merge) <= 1
+
+
+def test_normalised_axis_rule_zero_tolerance_and_ties():
+    """A zero position tolerance makes every position CV > 0 infinite under the normalised rule (the
+    lowest such axis is cut); the exact-tie cells go through the GPU's exact 320-bit comparison."""
+    from tests.test_oracle_exact_tiny import exact_tie
+    wl = cloud_cells([200, 64, 33], seed=17)
+    full_check(wl, dict(CLOUD, tol_x=0.0, tol_p=0.05, axis_rule=1, min_subset=2))
+    r = np.random.Generator(np.random.Philox(98))
+    cells = [exact_tie(r) for _ in range(200)]
+    params = dict(CLOUD, tol_x=0.01, tol_p=0.01, min_subset=2, axis_rule=1)
+    full_check(W.from_cells(cells, params=params, dtype=np.float32), params)

@@ -131,14 +131,16 @@ def exact_tie(r):
 FAMILIES = {"generic": generic, "duplicates": duplicates, "zero_mean": zero_mean, "equal_cv": equal_cv,
             "scales": scales, "lattice": lattice, "one_axis": one_axis, "exact_tie": exact_tie}
 
-# (tol_x, tol_p, min_subset, L, mass, merge)
+# (tol_x, tol_p, min_subset, L, mass, merge, axis_rule)
 PARAM_SETS = [
-    (0.3, 0.08, 2, (1.0, 1.0, 1.0), 1.0, oracle.PAIR),
-    (0.1, 0.05, 4, (1.0, 1.0, 1.0), 1.0, oracle.PAIR),
-    (1.0, 0.3, 2, (0.5, 2.0, 1.0), 0.0, oracle.PAIR),
-    (0.0, 0.0, 1, (1.0, 1.0, 1.0), 1.0, oracle.CENTROID),
-    (5.0, 5.0, 2, (1.0, 1.0, 1.0), 1.0, oracle.CENTROID),
-    (0.05, 0.02, 1, (1.0, 1.0, 1.0), 1.0, oracle.CENTROID),
+    (0.3, 0.08, 2, (1.0, 1.0, 1.0), 1.0, oracle.PAIR, 0),
+    (0.1, 0.05, 4, (1.0, 1.0, 1.0), 1.0, oracle.PAIR, 0),
+    (1.0, 0.3, 2, (0.5, 2.0, 1.0), 0.0, oracle.PAIR, 0),
+    (0.0, 0.0, 1, (1.0, 1.0, 1.0), 1.0, oracle.CENTROID, 0),
+    (5.0, 5.0, 2, (1.0, 1.0, 1.0), 1.0, oracle.CENTROID, 0),
+    (0.05, 0.02, 1, (1.0, 1.0, 1.0), 1.0, oracle.CENTROID, 0),
+    (0.8, 0.03, 2, (1.0, 1.0, 1.0), 1.0, oracle.PAIR, 1),        # each CV over its tolerance
+    (0.02, 0.4, 1, (1.0, 0.5, 1.0), 1.0, oracle.CENTROID, 1),
 ]
 CELLS_PER_GROUP = {"generic": 70, "duplicates": 40, "zero_mean": 45, "equal_cv": 45, "scales": 45,
                    "lattice": 40, "one_axis": 30, "exact_tie": 50}
@@ -155,19 +157,19 @@ def groups():
 
 
 def _c_run(lib_run, cells, prm, decide):
-    tol_x, tol_p, ms, L, mass, merge = prm
+    tol_x, tol_p, ms, L, mass, merge, rule = prm
     counts = [c.shape[0] for c in cells]
     off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     data = np.concatenate(cells, 0)
     return lib_run([data[:, i] for i in range(7)], off, tol_x=tol_x, tol_p=tol_p, n_min_cell=0,
-                   min_subset=ms, cell_len=L, mass=mass, merge_mode=merge, decide=decide), off
+                   min_subset=ms, cell_len=L, mass=mass, merge_mode=merge, decide=decide, axis_rule=rule), off
 
 
 def _exact(cells, prm, mode):
-    tol_x, tol_p, ms, L, mass, merge = prm
+    tol_x, tol_p, ms, L, mass, merge, rule = prm
     res = []
     for rows in cells:
-        cell = X.Cell(rows, tol_x, tol_p, ms, L, mass, mode)
+        cell = X.Cell(rows, tol_x, tol_p, ms, L, mass, mode, rule)
         res.append((cell, *cell.run(X.PAIR if merge == oracle.PAIR else X.CENTROID)))
     return res
 
@@ -322,13 +324,16 @@ MUTATIONS = {
     # the inner carry of the 128 x 128-bit product dropped
     "u256_carry": ("carry = t >> 64;\n        }\n        int k = i + 2;", "carry = 0;\n        }\n        int k = i + 2;"),
     # Step 4 ties going to the highest axis in FIXED mode
-    "ties_high": ("if (frac_gt(f, best)) { best = f; k = l; }", "if (!frac_gt(best, f)) { best = f; k = l; }"),
+    "ties_high": (": frac_gt(f, best);", ": !frac_gt(best, f);"),
     # Step 5 in FIXED mode with a strict cut (c S0 < S1)
     "strict_cut": ("if ((i128)cc->c[k][i] * S.s0 <= (i128)S.s1[k])", "if ((i128)cc->c[k][i] * S.s0 < (i128)S.s1[k])"),
     # the pair direction's projection with the wrong sign
     "pair_sign": ("u[a] -= P[jdir] * P[a] / P2;", "u[a] += P[jdir] * P[a] / P2;"),
     # the momentum test's scale 2^48 off by one bit
     "mom_shift": ("(u128)1 << (l < 3 ? 16 : 48)", "(u128)1 << (l < 3 ? 16 : 47)"),
+    # the normalised axis rule dividing by the wrong tolerance
+    "norm_swap": ("frac_gt_norm(f, l < 3 ? tx2 : tp2, best, k < 3 ? tx2 : tp2)",
+                  "frac_gt_norm(f, l < 3 ? tp2 : tx2, best, k < 3 ? tp2 : tx2)"),
 }
 
 
@@ -346,7 +351,8 @@ def _mutant_runner(tmpdir, name):
 
 @pytest.mark.parametrize("name,decide", [("jdir_argmax", oracle.FIXED), ("u256_carry", oracle.FIXED),
                                          ("ties_high", oracle.FIXED), ("strict_cut", oracle.FIXED),
-                                         ("pair_sign", oracle.PAPER), ("mom_shift", oracle.FIXED)])
+                                         ("pair_sign", oracle.PAPER), ("mom_shift", oracle.FIXED),
+                                         ("norm_swap", oracle.FIXED)])
 def test_planted_mistake_is_caught(exact_results, name, decide):
     with tempfile.TemporaryDirectory() as d:
         run = _mutant_runner(d, name)

@@ -23,7 +23,7 @@ from tests.helpers import (FIELDS, conserved_totals, energy, load_golden, partit
                            subsets_of)
 
 GOLDEN_FILES = ["px_bisection_6.txt", "corners_tie_4.txt", "px_ladder_8.txt", "pair_direction_2.txt",
-                "pair_two_clusters_4.txt"]
+                "pair_two_clusters_4.txt", "axis_rule_normalised_4.txt", "axis_rule_raw_4.txt"]
 MODES = [oracle.FIXED, oracle.PAPER]
 
 
