@@ -38,7 +38,9 @@
  *                    the cell length, momenta 2^-22 of the cell's largest |p| per axis, all
  *                    taken from the FP32 values), so partitions are bit-reproducible across
  *                    launch shapes and runs.  Tolerances are used as round(T * 2^24) / 2^24 and
- *                    must be < 128.  Requires dtype VPM_F32.
+ *                    must be < 128.  dtype VPM_F32 or VPM_F64: FP64 particles are rounded to FP32
+ *                    (to nearest) as they are loaded, so both give identical results; the output
+ *                    particles are FP32 either way.
  *  VPM_DECIDE_FP64   the paper's statistics evaluated literally in IEEE double, one workgroup
  *                    per cell.  Requires dtype VPM_F64.
  */
@@ -126,7 +128,8 @@ vpm_status vpm_check_params(const vpm_params *p);
  * (CENTROID) or 2 (PAIR, the +delta one first); a subset below min_subset emits its particles
  * unchanged in input order; a cell with N <= N_min, or one flagged on the device, is copied
  * unchanged.
- *   out        7 device arrays of the same dtype with capacity >= n_particles
+ *   out        7 device arrays with capacity >= n_particles, FP32 with VPM_DECIDE_FIXED and FP64 with
+ *              VPM_DECIDE_FP64
  *   out_off    device int64[n_cells+1]: exclusive prefix of the per-cell output counts
  *   out_total  device int64 scalar: out_off[n_cells]                                         */
 vpm_status vpm_run(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, int64_t n_cells,

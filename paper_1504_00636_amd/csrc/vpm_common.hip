@@ -147,14 +147,14 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int64_t* cnt, i
 
 // Compaction: every output slot o finds its cell by binary search in out_off, then copies from the
 // cell's temporary output (processed cells) or from the input (untouched cells).
-template <typename T>
-struct Tables { const T* tmp[7]; const T* in[7]; T* out[7]; };
+template <typename TI, typename TO>
+struct Tables { const TO* tmp[7]; const TI* in[7]; TO* out[7]; };
 
 constexpr int SC_PER = 8, SC_CACHE = 256;
 
-template <typename T>
+template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_scatter(const int64_t* cell_off, int64_t n_cells, const int64_t* out_off,
-                                                 const uint8_t* cell_mode, Tables<T> tb) {
+                                                 const uint8_t* cell_mode, Tables<TI, TO> tb) {
     const int64_t total = out_off[n_cells];
     const int64_t per_block = (int64_t)blockDim.x * SC_PER;
     const int64_t o0 = (int64_t)blockIdx.x * per_block;
@@ -214,11 +214,17 @@ __global__ __launch_bounds__(256) void k_scatter(const int64_t* cell_off, int64_
             untouched[k] = cell_mode[lo] == CELL_UNTOUCHED;
         }
     }
-    T v[SC_PER][7];
+    TO v[SC_PER][7];
 #pragma unroll
     for (int k = 0; k < SC_PER; ++k)
 #pragma unroll
-        for (int f = 0; f < 7; ++f) v[k][f] = __builtin_nontemporal_load((untouched[k] ? tb.in[f] : tb.tmp[f]) + src[k]);
+        for (int f = 0; f < 7; ++f) {
+            if constexpr (sizeof(TI) == sizeof(TO))
+                v[k][f] = __builtin_nontemporal_load((untouched[k] ? (const TO*)tb.in[f] : tb.tmp[f]) + src[k]);
+            else                                               // FP64 input of the FP32 path: rounded
+                v[k][f] = untouched[k] ? (TO)__builtin_nontemporal_load(tb.in[f] + src[k])
+                                       : __builtin_nontemporal_load(tb.tmp[f] + src[k]);
+        }
 #pragma unroll
     for (int k = 0; k < SC_PER; ++k) {
         const int64_t o = o0 + (int64_t)k * blockDim.x + threadIdx.x;
@@ -275,23 +281,24 @@ hipError_t launch_scan_offsets(const Workspace& ws, const LaunchCfg& lc, int64_t
     return hipGetLastError();
 }
 
+template <typename TI, typename TO>
+void scatter_launch(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off, int64_t n_cells,
+                    const int64_t* out_off, const void* const in[7], void* const out[7], int64_t blocks) {
+    Tables<TI, TO> tb;
+    for (int f = 0; f < 7; ++f) { tb.tmp[f] = (const TO*)ws.tmp[f]; tb.in[f] = (const TI*)in[f]; tb.out[f] = (TO*)out[f]; }
+    hipLaunchKernelGGL((k_scatter<TI, TO>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells,
+                       out_off, ws.cell_mode, tb);
+}
+
 hipError_t launch_scatter(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off, int64_t n_cells,
                           int64_t n_particles, const int64_t* out_off, const void* const in[7], void* const out[7],
-                          int elem_size) {
+                          int in_size, int out_size) {
     if (n_cells == 0 || n_particles == 0) return hipSuccess;
     const int64_t blocks = (n_particles + 256 * SC_PER - 1) / (256 * SC_PER);   // out_total <= n_particles
     if (lc.pre) lc.pre(lc.prof, "scatter", lc.stream);
-    if (elem_size == 4) {
-        Tables<float> tb;
-        for (int f = 0; f < 7; ++f) { tb.tmp[f] = (const float*)ws.tmp[f]; tb.in[f] = (const float*)in[f]; tb.out[f] = (float*)out[f]; }
-        hipLaunchKernelGGL(k_scatter<float>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells,
-                           out_off, ws.cell_mode, tb);
-    } else {
-        Tables<double> tb;
-        for (int f = 0; f < 7; ++f) { tb.tmp[f] = (const double*)ws.tmp[f]; tb.in[f] = (const double*)in[f]; tb.out[f] = (double*)out[f]; }
-        hipLaunchKernelGGL(k_scatter<double>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells,
-                           out_off, ws.cell_mode, tb);
-    }
+    if (in_size == 4) scatter_launch<float, float>(ws, lc, cell_off, n_cells, out_off, in, out, blocks);
+    else if (out_size == 4) scatter_launch<double, float>(ws, lc, cell_off, n_cells, out_off, in, out, blocks);
+    else scatter_launch<double, double>(ws, lc, cell_off, n_cells, out_off, in, out, blocks);
     if (lc.post) lc.post(lc.prof, "scatter", lc.stream);
     return hipGetLastError();
 }

@@ -200,8 +200,34 @@ VPM_DEV bool frac_gt_norm(U128 Va, U128 Da, uint64_t T2a, U128 Vb, U128 Db, uint
     return cmp320(mul256x64(mul128(Va, Db), T2b), mul256x64(mul128(Vb, Da), T2a)) > 0;
 }
 
+// The decision rule's constants.  Each workgroup copies them from the kernel arguments into LDS
+// once and the decisions read them there: kernel-argument values live across a whole kernel hold
+// scalar registers, and their spills to vector lanes slow the particle loops.
+struct DecideConsts {
+    float t2x_lo, t2x_hi, t2p_lo, t2p_hi;   // Step 3: FP32 brackets of T_x^2, T_p^2
+    float wx_lo, wx_hi, wp_lo, wp_hi;       // Step 4: FP32 brackets of the axis weights (raw rule 1,
+                                            // normalised 1 / T^2, +infinity for T = 0)
+    uint64_t thx2, thp2;                    // That_x^2, That_p^2 (Step 3, exact)
+    uint64_t tx2, tp2;                      // Step 4 exact weights: 1, or That^2 (normalised rule)
+};
+
+VPM_DEV DecideConsts decide_consts(const FixedParams& P) {
+    DecideConsts K;
+    K.t2x_lo = P.t2x_lo; K.t2x_hi = P.t2x_hi; K.t2p_lo = P.t2p_lo; K.t2p_hi = P.t2p_hi;
+    const bool norm = P.axis_rule != 0;
+    K.wx_lo = !norm ? 1.0f : P.that_x == 0 ? INFINITY : P.it2x_lo;
+    K.wx_hi = !norm ? 1.0f : P.that_x == 0 ? INFINITY : P.it2x_hi;
+    K.wp_lo = !norm ? 1.0f : P.that_p == 0 ? INFINITY : P.it2p_lo;
+    K.wp_hi = !norm ? 1.0f : P.that_p == 0 ? INFINITY : P.it2p_hi;
+    K.thx2 = P.that_x * P.that_x;
+    K.thp2 = P.that_p * P.that_p;
+    K.tx2 = P.tx2;
+    K.tp2 = P.tp2;
+    return K;
+}
+
 // The exact rule on exact integer moments.
-VPM_DEV Decision decide_exact(const ISums& S, const FixedParams& P, const Frame& F) {
+VPM_DEV Decision decide_exact(const ISums& S, const DecideConsts& K, const Frame& F) {
     Decision d;
     d.axis = 0; d.thr = 0;
     double s1d[6];
@@ -228,11 +254,11 @@ VPM_DEV Decision decide_exact(const ISums& S, const FixedParams& P, const Frame&
     }
     bool done = true;
     {
-        const U128 rhs = mul64(P.that_x * P.that_x, s0sq.lo);     // That^2 S0^2
+        const U128 rhs = mul64(K.thx2, s0sq.lo);     // That^2 S0^2
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             if (!is_zero128(V[a]) && cmp128(shl128(V[a], 16), rhs) > 0) done = false;
-        const U128 tp2 = u128_make(P.that_p * P.that_p, 0);
+        const U128 tp2 = u128_make(K.thp2, 0);
 #pragma unroll
         for (int a = 3; a < 6; ++a) {
             if (is_zero128(V[a])) continue;
@@ -246,15 +272,29 @@ VPM_DEV Decision decide_exact(const ISums& S, const FixedParams& P, const Frame&
         }
     }
     if (done) { d.kind = D_MERGED; return d; }
-    int k = 0;
-    U128 bV = V[0], bD = D[0];
+    // Step 4 in two stages: the position axes share D, so their largest CV is their largest V; the
+    // momentum axes compare as fractions among themselves; then one comparison across the groups
+    // (raw, or each CV over its tolerance), which the momentum axis wins only when strictly larger
+    // (ties go to the lower axis, a position).  Under the normalised rule a zero tolerance makes every
+    // CV > 0 of its group infinite: the group's first such axis is its largest.
+    const bool xinf = K.tx2 == 0, pinf = K.tp2 == 0;
+    // (The running maxima are carried by value: indexing V and D with a variable would put them in
+    // private memory.)
+    int kx = 0;
+    U128 xV = V[0];
+#pragma unroll
+    for (int l = 1; l < 3; ++l)
+        if (xinf ? is_zero128(xV) && !is_zero128(V[l]) : cmp128(V[l], xV) > 0) { kx = l; xV = V[l]; }
+    int kp = 3;
+    U128 pV = V[3], pD = D[3];
+#pragma unroll
+    for (int l = 4; l < 6; ++l)
+        if (pinf ? is_zero128(pV) && !is_zero128(V[l]) : frac_gt(V[l], D[l], pV, pD)) { kp = l; pV = V[l]; pD = D[l]; }
+    const bool mom = frac_gt_norm(pV, pD, K.tp2, xV, D[0], K.tx2);      // raw rule: tx2 = tp2 = 1
+    const int k = mom ? kp : kx;
     double s1k = s1d[0];
 #pragma unroll
-    for (int l = 1; l < 6; ++l) {
-        const bool gt = P.axis_rule ? frac_gt_norm(V[l], D[l], l < 3 ? P.tx2 : P.tp2, bV, bD, k < 3 ? P.tx2 : P.tp2)
-                                    : frac_gt(V[l], D[l], bV, bD);
-        if (gt) { k = l; bV = V[l]; bD = D[l]; s1k = s1d[l]; }
-    }
+    for (int l = 1; l < 6; ++l) if (l == k) s1k = s1d[l];
     d.kind = D_SPLIT;
     d.axis = k;
     d.thr = cut_threshold(s1k, (double)S.s0);
@@ -274,7 +314,7 @@ VPM_DEV Decision decide_exact(const ISums& S, const FixedParams& P, const Frame&
 //   bracket is widened by 2^-19).  A subtraction of two floats has the sign of the exact difference,
 //   so the maxima below decide the comparisons exactly.
 // `amask` has bit l set for the axes whose codes vary in the cell; the others have V = 0.
-VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, const Frame& F, int amask, bool& ok,
+VPM_DEV Decision decide_fast(const FSums& S, int len, const DecideConsts& K, const Frame& F, int amask, bool& ok,
                              const double* e2 = nullptr) {
     Decision d;
     d.axis = 0; d.thr = 0; d.jdir = 0;
@@ -306,8 +346,8 @@ VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, cons
         const float lf = vlo > 0.0 ? (float)vlo * rlo : 0.0f;     // V > 0 certain
         const float hf = vhi < 1.0 ? 0.0f : (float)vhi * rhi;     // V is an integer: vhi < 1 gives V = 0
         lo[l] = lf; hi[l] = hf;
-        over = fmaxf(over, lf - (l < 3 ? P.t2x_hi : P.t2p_hi));
-        under = fmaxf(under, hf - (l < 3 ? P.t2x_lo : P.t2p_lo));
+        over = fmaxf(over, lf - (l < 3 ? K.t2x_hi : K.t2p_hi));
+        under = fmaxf(under, hf - (l < 3 ? K.t2x_lo : K.t2p_lo));
     }
     if (!(over > 0.0f)) {
         if (under > 0.0f) { ok = false; return d; }   // an axis too close to its tolerance
@@ -315,21 +355,14 @@ VPM_DEV Decision decide_fast(const FSums& S, int len, const FixedParams& P, cons
         d.jdir = pair_axis(S.s1, F);
         return d;
     }
-    if (P.axis_rule) {
-        // Step 4 on Delta_l^2 / tau_l^2: the brackets times an outward FP32 bracket of 1 / tau^2
-        // (each product rounds by at most 2^-24, inside that bracket's 2^-22 margin); a zero
-        // tolerance makes any CV > 0 infinite
+    // Step 4 on the weighted CVs: unit weights (raw rule, exact), or outward FP32 brackets of
+    // 1 / T^2 (normalised rule: each product rounds by at most 2^-24, inside the brackets' 2^-22
+    // margin); an infinite weight (zero tolerance) makes any CV > 0 infinite
 #pragma unroll
-        for (int l = 0; l < 6; ++l) {
-            const bool pos = l < 3;
-            if ((pos ? P.that_x : P.that_p) == 0) {
-                lo[l] = lo[l] > 0.0f ? INFINITY : 0.0f;
-                hi[l] = hi[l] > 0.0f ? INFINITY : 0.0f;
-            } else {
-                lo[l] = lo[l] * (pos ? P.it2x_lo : P.it2p_lo);
-                hi[l] = hi[l] * (pos ? P.it2x_hi : P.it2p_hi);
-            }
-        }
+    for (int l = 0; l < 6; ++l) {
+        const bool pos = l < 3;
+        lo[l] = lo[l] > 0.0f ? lo[l] * (pos ? K.wx_lo : K.wp_lo) : 0.0f;
+        hi[l] = hi[l] > 0.0f ? hi[l] * (pos ? K.wx_hi : K.wp_hi) : 0.0f;
     }
     int k = 0;
     float best = lo[0];
@@ -406,6 +439,7 @@ struct CellShared {          // per-cell bookkeeping, in LDS
     int rootv;               // packed decision of the root
     int kind;                // large-cell kernel: the claimed work (0 none, 1 a cell, 2 a task)
     int last;                // large-cell kernel: this workgroup finished the cell's last piece
+    DecideConsts dc;         // written once per workgroup at the start of a kernel
 };
 
 // Subsets of a large cell handed to other workgroups (the large-cell kernel): those that a split
@@ -472,8 +506,12 @@ VPM_DEV CellMem<IdxT> carve(uint8_t* base, int nmax) {
     return M;
 }
 
-struct FixedArgs {
-    Soa32 in;
+// The particle input is FP32 (InT = float) or FP64 (InT = double, rounded to FP32 as it is loaded:
+// the fixed-point path works on the FP32 values either way, so both give identical results).
+template <typename InT>
+struct FixedArgsT {
+    using In = InT;
+    SoaIn<InT> in;
     const int64_t* cell_off;
     const int32_t* queue;
     int32_t* counters;             // [qlen_index] = queue length, [work_index] = work counter
@@ -509,8 +547,9 @@ VPM_DEV Decision decide(const CellMem<IdxT>& M, const FSums& S, const IdxT* buf,
     Decision d;
     if (len < P.min_subset) { d.kind = D_COPY; d.axis = 0; d.thr = 0; d.jdir = 0; return d; }
     bool ok;
-    d = decide_fast(S, len, P, F, F.amask, ok, e2);
-    if (ok) return d;
+    const DecideConsts& K = M.sh->dc;
+    d = decide_fast(S, len, K, F, F.amask, ok, e2);
+    if (__builtin_expect(ok, 1)) return d;          // the exact path below is rare: laid out apart
     ISums E;
     E.s0 = 0;
 #pragma unroll
@@ -522,7 +561,7 @@ VPM_DEV Decision decide(const CellMem<IdxT>& M, const FSums& S, const IdxT* buf,
         codes_of(M, buf[start + j], c, om);
         isums_add(E, (uint32_t)om, c);
     }
-    return decide_exact(E, P, F);
+    return decide_exact(E, K, F);
 }
 
 // Make the cell's shared memory writes visible to all wavefronts working on the cell.
@@ -729,8 +768,8 @@ VPM_DEV int compact_sum_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int
 // A final subset [cs, cs + cl) of the new slot order: its flags for the output, and its members put
 // back into increasing input order where that order is observable (copied particles, or the
 // partition output).  Lanes lid < g of its group take part.
-template <typename IdxT>
-VPM_DEV void record_final(const CellMem<IdxT>& M, const FixedArgs& A, const Decision& d, int cs, int cl, int crev,
+template <typename IdxT, typename Args>
+VPM_DEV void record_final(const CellMem<IdxT>& M, const Args& A, const Decision& d, int cs, int cl, int crev,
                           int cur, int lid, int g) {
     IdxT* dst = idx_buf(M, cur ^ 1);
     if (crev && (d.kind == D_COPY || A.mode == 1)) {
@@ -757,8 +796,8 @@ VPM_DEV void sum_members(const CellMem<IdxT>& M, FSums& S, const IdxT* src, int 
 }
 
 // Process one unfinished subset with a lane group: compaction, child moments, child decisions.
-template <typename IdxT>
-VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F0, const Frame* frames, Node<IdxT> nd,
+template <typename IdxT, typename Args>
+VPM_DEV void split_node(const CellMem<IdxT>& M, const Args& A, const Frame& F0, const Frame* frames, Node<IdxT> nd,
                         int cur, int lid, int g, int gbase, Node<IdxT>* next, bool solo,
                         SpawnList<IdxT>* spawn = nullptr) {
     const int start = nd.start, len = nd.len;
@@ -844,8 +883,8 @@ VPM_DEV void split_node(const CellMem<IdxT>& M, const FixedArgs& A, const Frame&
 // goes to the lower half of the group and V2 to the upper half, which then hold its moments.  Only
 // the smaller child is summed; the other child's moments are the parent's minus these (S0 and S1
 // exactly, S2 with its error bound carried along).
-template <typename IdxT>
-VPM_DEV void split_inherit(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, Node<IdxT>& nd, bool& act,
+template <typename IdxT, typename Args>
+VPM_DEV void split_inherit(const CellMem<IdxT>& M, const Args& A, const Frame& F, Node<IdxT>& nd, bool& act,
                            FSums& P, double (&E2)[6], int cur, int lid, int g, int gbase) {
     const int start = nd.start, len = nd.len;
     const int rev = (nd.thr_axis >> 3) & 1;
@@ -918,8 +957,8 @@ VPM_DEV void split_inherit(const CellMem<IdxT>& M, const FixedArgs& A, const Fra
 
 // The last inherited level: one lane per subset, which decides both children in turn and hands the
 // unfinished ones to the scheduled levels (list `next`).
-template <typename IdxT>
-VPM_DEV void split_inherit_solo(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, Node<IdxT> nd,
+template <typename IdxT, typename Args>
+VPM_DEV void split_inherit_solo(const CellMem<IdxT>& M, const Args& A, const Frame& F, Node<IdxT> nd,
                                 const FSums& P, const double (&E2)[6], int cur, Node<IdxT>* next) {
     const int start = nd.start, len = nd.len;
     const int rev = (nd.thr_axis >> 3) & 1;
@@ -977,8 +1016,8 @@ VPM_DEV void split_inherit_solo(const CellMem<IdxT>& M, const FixedArgs& A, cons
 // the number of subsets in its list.
 constexpr int INHERIT_PPL = 32;
 
-template <typename IdxT>
-VPM_DEV void inherit_levels(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, const FSums& R, int n,
+template <typename IdxT, typename Args>
+VPM_DEV void inherit_levels(const CellMem<IdxT>& M, const Args& A, const Frame& F, const FSums& R, int n,
                             const Decision& rd, int lane, int& cur, int& m) {
     Node<IdxT> nd;
     nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 8) | rd.axis;
@@ -1021,8 +1060,8 @@ VPM_DEV void inherit_levels(const CellMem<IdxT>& M, const FixedArgs& A, const Fr
 // separates the loads of a batch.
 constexpr int COPY_BATCH = 4;          // particles per lane whose loads are in flight together
 
-template <int CB, typename SlotFn>
-VPM_DEV void copy_particles(const Soa32& in, const Soa32Out& out, int first, int end, int stride, SlotFn slot) {
+template <int CB, typename InT, typename SlotFn>
+VPM_DEV void copy_particles(const SoaIn<InT>& in, const Soa32Out& out, int first, int end, int stride, SlotFn slot) {
     for (int p0 = first; p0 < end; p0 += CB * stride) {
         int64_t si[CB], so[CB];
 #pragma unroll
@@ -1035,8 +1074,8 @@ VPM_DEV void copy_particles(const Soa32& in, const Soa32Out& out, int first, int
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
             const int64_t i = si[u];
-            v[u][0] = in.x[i]; v[u][1] = in.y[i]; v[u][2] = in.z[i];
-            v[u][3] = in.px[i]; v[u][4] = in.py[i]; v[u][5] = in.pz[i]; v[u][6] = in.w[i];
+            v[u][0] = (float)in.x[i]; v[u][1] = (float)in.y[i]; v[u][2] = (float)in.z[i];
+            v[u][3] = (float)in.px[i]; v[u][4] = (float)in.py[i]; v[u][5] = (float)in.pz[i]; v[u][6] = (float)in.w[i];
         }
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
@@ -1058,8 +1097,8 @@ VPM_DEV void copy_particles(const Soa32& in, const Soa32Out& out, int first, int
 // eps_i - eps(pt) is formed as (|d|^2 + 2 pt.d) / (eps_i + eps(pt)), d = p - pt, which does not
 // cancel; the FP64 solve then forms r = mean(eps)^2 - m^2 - |P|^2 from these differences.
 // gidx(j) gives the global index of the j-th member; the result goes to output slot `o` (and o+1).
-template <typename IdxFn>
-VPM_DEV void merge_subset(const FixedArgs& A, const Frame& F, IdxFn gidx, int len, int jdir, int64_t o,
+template <typename Args, typename IdxFn>
+VPM_DEV void merge_subset(const Args& A, const Frame& F, IdxFn gidx, int len, int jdir, int64_t o,
                           int lid, int g) {
     const int gb = 62 - ceil_log2(len);          // |term| < 2^gb keeps the sum below 2^62
 
@@ -1069,11 +1108,11 @@ VPM_DEV void merge_subset(const FixedArgs& A, const Frame& F, IdxFn gidx, int le
     int64_t sw = 0, s1x = 0, s1y = 0, s1z = 0;
     for (int j = lid; j < len; j += g) {
         const int64_t i = gidx(j);
-        const float w = A.in.w[i];
+        const float w = (float)A.in.w[i];
         sw += fixq(w, 1.0f, gw);
-        s1x += fixq(w, A.in.px[i], g1x);
-        s1y += fixq(w, A.in.py[i], g1y);
-        s1z += fixq(w, A.in.pz[i], g1z);
+        s1x += fixq(w, (float)A.in.px[i], g1x);
+        s1y += fixq(w, (float)A.in.py[i], g1y);
+        s1z += fixq(w, (float)A.in.pz[i], g1z);
     }
     sw = group_sum(sw, g);
     s1x = group_sum(s1x, g); s1y = group_sum(s1y, g); s1z = group_sum(s1z, g);
@@ -1094,9 +1133,9 @@ VPM_DEV void merge_subset(const FixedArgs& A, const Frame& F, IdxFn gidx, int le
     int64_t sx0 = 0, sx1 = 0, sx2 = 0, sd0 = 0, sd1 = 0, sd2 = 0, se = 0;
     for (int j = lid; j < len; j += g) {
         const int64_t i = gidx(j);
-        const float w = A.in.w[i];
-        const float x = A.in.x[i] - F.lo[0], y = A.in.y[i] - F.lo[1], z = A.in.z[i] - F.lo[2];
-        const float px = A.in.px[i], py = A.in.py[i], pz = A.in.pz[i];
+        const float w = (float)A.in.w[i];
+        const float x = (float)A.in.x[i] - F.lo[0], y = (float)A.in.y[i] - F.lo[1], z = (float)A.in.z[i] - F.lo[2];
+        const float px = (float)A.in.px[i], py = (float)A.in.py[i], pz = (float)A.in.pz[i];
         const float d0 = px - q0, d1 = py - q1, d2 = pz - q2;
         sx0 += fixq(w, x, gx0); sx1 += fixq(w, y, gx1); sx2 += fixq(w, z, gx2);
         sd0 += fixq(w, d0, gd0); sd1 += fixq(w, d1, gd1); sd2 += fixq(w, d2, gd2);
@@ -1199,24 +1238,26 @@ VPM_DEV void facc_add(FrameAcc& a, const float q[7]) {
 // again), so that a batch's loads are in flight together; fn(p, q, in_range) sees each of them.
 constexpr int LOAD_BATCH = 8;
 
-template <typename Fn>
-VPM_DEV void load_particles(const Soa32& in, int64_t off, int first, int n, int stride, Fn fn) {
-    const float* const b[7] = {in.x + off, in.y + off, in.z + off, in.px + off, in.py + off, in.pz + off, in.w + off};
-    for (int p0 = first; p0 < n; p0 += LOAD_BATCH * stride) {
-        float q[LOAD_BATCH][7];
+template <typename InT, typename Fn>
+VPM_DEV void load_particles(const SoaIn<InT>& in, int64_t off, int first, int n, int stride, Fn fn) {
+    constexpr int LB = sizeof(InT) == 4 ? LOAD_BATCH : LOAD_BATCH / 2;    // FP64: as many bytes in flight
+    const InT* const b[7] = {in.x + off, in.y + off, in.z + off, in.px + off, in.py + off, in.pz + off, in.w + off};
+    for (int p0 = first; p0 < n; p0 += LB * stride) {
+        float q[LB][7];
 #pragma unroll
-        for (int u = 0; u < LOAD_BATCH; ++u) {
+        for (int u = 0; u < LB; ++u) {
             const uint32_t i = (uint32_t)min(p0 + u * stride, n - 1);
 #pragma unroll
-            for (int f = 0; f < 7; ++f) q[u][f] = b[f][i];
+            for (int f = 0; f < 7; ++f) q[u][f] = (float)b[f][i];            // FP64: rounded to nearest
         }
 #pragma unroll
-        for (int u = 0; u < LOAD_BATCH; ++u) fn(p0 + u * stride, q[u], p0 + u * stride < n);
+        for (int u = 0; u < LB; ++u) fn(p0 + u * stride, q[u], p0 + u * stride < n);
     }
 }
 
 // Frame accumulation over positions first, first + stride, ... of a cell (duplicates change nothing).
-VPM_DEV void facc_cell(FrameAcc& a, const Soa32& in, int64_t off, int first, int n, int stride) {
+template <typename InT>
+VPM_DEV void facc_cell(FrameAcc& a, const SoaIn<InT>& in, int64_t off, int first, int n, int stride) {
     load_particles(in, off, first, n, stride, [&](int, const float* q, bool) { facc_add(a, q); });
 }
 
@@ -1252,7 +1293,8 @@ VPM_DEV bool frame_of_wave(FrameAcc& acc, double mass, Frame& F) {
 }
 
 // Step 1 for one cell (whole wave): validate the values and build the cell frame.
-VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, double mass, Frame& F) {
+template <typename InT>
+VPM_DEV bool cell_frame(const SoaIn<InT>& in, int64_t off, int n, double mass, Frame& F) {
     FrameAcc acc;
     facc_init(acc);
     facc_cell(acc, in, off, lane_id(), n, WAVE);
@@ -1260,8 +1302,8 @@ VPM_DEV bool cell_frame(const Soa32& in, int64_t off, int n, double mass, Frame&
 }
 
 // The same for a cell shared by WPB wavefronts (all threads call; the result is the same in all).
-template <int WPB>
-VPM_DEV bool cell_frame_block(const Soa32& in, int64_t off, int n, double mass, Frame& F, BlockScratch<WPB>* bs) {
+template <int WPB, typename InT>
+VPM_DEV bool cell_frame_block(const SoaIn<InT>& in, int64_t off, int n, double mass, Frame& F, BlockScratch<WPB>* bs) {
     if constexpr (WPB == 1) {
         return cell_frame(in, off, n, mass, F);
     } else {
@@ -1296,15 +1338,17 @@ VPM_DEV bool cell_frame_block(const Soa32& in, int64_t off, int n, double mass, 
 // Replacement from a given partition (vpm_merge): one wavefront per cell, one lane per subset.
 // ------------------------------------------------------------------------------------------
 
+template <typename InT>
 struct MergeArgs {
-    FixedArgs A;                   // in, params, tmp, out_count, cell_mode, flags
+    FixedArgsT<InT> A;                   // in, params, tmp, out_count, cell_mode, flags
     const int32_t *perm, *subset_id, *n_subsets;
     int32_t* starts;               // scratch: first slot of every subset, indexed by input position
     int32_t* marks;                // scratch: a slot holding each member, indexed by input position
 };
 
-__global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs G) {
-    const FixedArgs& A = G.A;
+template <typename InT>
+__global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs<InT> G) {
+    const auto& A = G.A;
     const int lane = lane_id();
     const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
     const int qlen = A.counters[A.qlen_index];
@@ -1386,8 +1430,8 @@ __global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs G) {
             double s1[6] = {0, 0, 0, 0, 0, 0};
             for (int j = 0; j < len; ++j) {
                 const int64_t i = mem[j];
-                const double om = rintf(ldexpf(A.in.w[i], 15 - F.ew));
-                const float pv[3] = {A.in.px[i], A.in.py[i], A.in.pz[i]};
+                const double om = rintf(ldexpf((float)A.in.w[i], 15 - F.ew));
+                const float pv[3] = {(float)A.in.px[i], (float)A.in.py[i], (float)A.in.pz[i]};
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
                     s1[3 + a] += om * (F.pzero[a] ? 0.0 : (double)rintf(ldexpf(pv[a], 22 - F.ep[a])));
@@ -1427,8 +1471,8 @@ VPM_DEV void encode_particle(const CellMem<IdxT>& M, const FixedParams& P, const
 // over the cell's slots gives leaf ordinals and output slots; copied particles go to the staging
 // arrays, merged subsets are replaced (Step 7).  In partition mode the permutation and subset
 // ordinals are written instead.  leaf_start (n + 1 entries), mlist and msched (n each) are scratch.
-template <int WPB, typename IdxT>
-VPM_DEV void cell_output(const CellMem<IdxT>& M, const FixedArgs& A, const Frame& F, int c, int64_t off, int n,
+template <int WPB, typename IdxT, typename Args>
+VPM_DEV void cell_output(const CellMem<IdxT>& M, const Args& A, const Frame& F, int c, int64_t off, int n,
                          BlockScratch<WPB>* bs, IdxT* leaf_start, IdxT* mlist, IdxT* msched) {
     constexpr int NT = WAVE * WPB;
     const int lane = opaque_lane();
@@ -1492,8 +1536,8 @@ VPM_DEV void cell_output(const CellMem<IdxT>& M, const FixedArgs& A, const Frame
     // copied particles (subsets below min_subset): the cell's arrays from wave-uniform base
     // pointers with 32-bit lane offsets (no 64-bit address arithmetic per access)
     {
-        const float* const ib[7] = {A.in.x + off, A.in.y + off, A.in.z + off, A.in.px + off,
-                                    A.in.py + off, A.in.pz + off, A.in.w + off};
+        const typename Args::In* const ib[7] = {A.in.x + off, A.in.y + off, A.in.z + off, A.in.px + off,
+                                                A.in.py + off, A.in.pz + off, A.in.w + off};
         float* const ob[7] = {A.tmp.x + off, A.tmp.y + off, A.tmp.z + off, A.tmp.px + off,
                               A.tmp.py + off, A.tmp.pz + off, A.tmp.w + off};
         for (int p0 = tid; p0 < n; p0 += COPY_BATCH * NT) {
@@ -1511,7 +1555,7 @@ VPM_DEV void cell_output(const CellMem<IdxT>& M, const FixedArgs& A, const Frame
 #pragma unroll
             for (int u = 0; u < COPY_BATCH; ++u)
 #pragma unroll
-                for (int f = 0; f < 7; ++f) v[u][f] = ib[f][si[u]];
+                for (int f = 0; f < 7; ++f) v[u][f] = (float)ib[f][si[u]];
 #pragma unroll
             for (int u = 0; u < COPY_BATCH; ++u) {
                 if (!keep[u]) continue;
@@ -1555,8 +1599,8 @@ VPM_DEV void cell_output(const CellMem<IdxT>& M, const FixedArgs& A, const Frame
 // separate the phases.
 // ------------------------------------------------------------------------------------------
 
-template <int NMAX, typename IdxT, bool IN_LDS, int WPB>
-__global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
+template <int NMAX, typename IdxT, bool IN_LDS, int WPB, typename InT>
+__global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgsT<InT> A) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int tid = threadIdx.x;
     const int lane = lane_id();
@@ -1573,6 +1617,8 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgs A) {
     // cell sizes here, and single claims keep the tail of the launch short.
     const int qlen = A.counters[A.qlen_index];
     if (qlen == 0) return;                         // an empty bin claims nothing
+    if (tid == 0) sh.dc = decide_consts(A.P);      // visible after the loop's first barrier
+    if constexpr (WPB == 1) wave_fence();
     for (;;) {
         int qi = 0;
         if constexpr (WPB == 1) {
@@ -1713,8 +1759,9 @@ constexpr int C_TASK_HEAD = 28, C_TASK_RESERVE = 29, C_PENDING = 30;   // counte
 struct BigTask { int32_t qi, cur; Node<uint32_t> nd; };
 struct BigCell { Frame F; int64_t off; int32_t n, c, open, pad; };
 
+template <typename InT>
 struct BigArgs {
-    FixedArgs A;
+    FixedArgsT<InT> A;
     int4* rec;                     // cell-wide arrays of the large cells, indexed by input position
     int32_t* pyz;
     uint32_t *idx0, *idx1, *emit;
@@ -1742,7 +1789,8 @@ VPM_DEV int ld_relaxed(const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_
 
 // Queue subset nd of cell qi (its members in index buffer cur) as a task.  The caller has made the
 // writes it depends on visible at device scope.
-VPM_DEV void spawn_task(const BigArgs& B, int qi, int cur, Node<uint32_t> nd) {
+template <typename InT>
+VPM_DEV void spawn_task(const BigArgs<InT>& B, int qi, int cur, Node<uint32_t> nd) {
     int32_t* const ctr = B.A.counters;
     atomicAdd(&B.cells[qi].open, 1);
     atomicAdd(&ctr[C_PENDING], 1);
@@ -1755,11 +1803,12 @@ VPM_DEV void spawn_task(const BigArgs& B, int qi, int cur, Node<uint32_t> nd) {
     __hip_atomic_store(&B.ready[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs B) {
+template <typename InT>
+__global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
     constexpr int WPB = 8, NT = WAVE * WPB;
     using IdxT = uint32_t;
     extern __shared__ __align__(16) uint8_t smem[];
-    const FixedArgs& A = B.A;
+    const auto& A = B.A;
     CellShared& sh = *(CellShared*)smem;
     BlockScratch<WPB>* bs = (BlockScratch<WPB>*)(smem + rnd16(sizeof(CellShared)));
     BigShared& bl = *(BigShared*)(smem + header_bytes<WPB>());
@@ -1767,6 +1816,7 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs B) {
     int32_t* const ctr = A.counters;
     const int qlen = ctr[A.qlen_index];
     if (qlen == 0) return;                         // an empty bin claims nothing
+    if (threadIdx.x == 0) sh.dc = decide_consts(A.P);   // visible after the loop's first barrier
     int nbig[BIGQ_CLASSES];
 #pragma unroll
     for (int k = 0; k < BIGQ_CLASSES; ++k) nbig[k] = ctr[BIGQ_LEN0 + k];
@@ -2002,7 +2052,8 @@ VPM_DEV int small_cell_of(const SmallShared& ss, int p) {
 }
 
 // Step 1 for batch cell j with a lane group: validity, frame, codes, root moments and decision.
-VPM_DEV void small_root(const CellMem<uint16_t>& M, const FixedArgs& A, SmallShared& ss, int j, int g, int lid,
+template <typename Args>
+VPM_DEV void small_root(const CellMem<uint16_t>& M, const Args& A, SmallShared& ss, int j, int g, int lid,
                         int gbase) {
     const int b = ss.base[j], n = ss.base[j + 1] - b;
     const int64_t off = ss.off[j];
@@ -2047,7 +2098,8 @@ VPM_DEV void small_root(const CellMem<uint16_t>& M, const FixedArgs& A, SmallSha
     }
 }
 
-__global__ __launch_bounds__(WAVE, 2) void k_fixed_small(FixedArgs A) {
+template <typename InT>
+__global__ __launch_bounds__(WAVE, 2) void k_fixed_small(FixedArgsT<InT> A) {
     extern __shared__ __align__(16) uint8_t smem[];
     using IdxT = uint16_t;
     const int lane = lane_id();
@@ -2057,6 +2109,8 @@ __global__ __launch_bounds__(WAVE, 2) void k_fixed_small(FixedArgs A) {
     M.sh = &sh;
     const int qlen = A.counters[A.qlen_index];
     if (qlen == 0) return;                         // an empty bin claims nothing
+    if (lane == 0) sh.dc = decide_consts(A.P);
+    wave_fence();
     const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
     int qnext = 0, qend = 0;
     for (;;) {
@@ -2261,8 +2315,9 @@ __global__ __launch_bounds__(WAVE, 2) void k_fixed_small(FixedArgs A) {
 // (the fixed-point Step 7 sums, one particle: weight and momentum kept).
 // ------------------------------------------------------------------------------------------
 
+template <typename InT>
 struct BlindArgs {
-    FixedArgs A;                   // in, cell_off, P (mass; CENTROID), tmp, out_count, cell_mode, flags
+    FixedArgsT<InT> A;                   // in, cell_off, P (mass; CENTROID), tmp, out_count, cell_mode, flags
     double alpha;
     uint64_t seed;
     int32_t n_min_cell;
@@ -2284,8 +2339,9 @@ VPM_DEV void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c
     }
 }
 
-__global__ __launch_bounds__(WAVE) void k_fixed_blind(BlindArgs B) {
-    const FixedArgs& A = B.A;
+template <typename InT>
+__global__ __launch_bounds__(WAVE) void k_fixed_blind(BlindArgs<InT> B) {
+    const auto& A = B.A;
     const int lane = lane_id();
     for (int64_t c = blockIdx.x; c < B.n_cells; c += gridDim.x) {
         const int64_t lo = A.cell_off[c], hi = A.cell_off[c + 1];
@@ -2370,9 +2426,9 @@ __global__ __launch_bounds__(WAVE) void k_fixed_blind(BlindArgs B) {
             const int64_t o = lo + k;
             if (len == 1) {
                 const int64_t i = lo + X[b];
-                A.tmp.x[o] = A.in.x[i]; A.tmp.y[o] = A.in.y[i]; A.tmp.z[o] = A.in.z[i];
-                A.tmp.px[o] = A.in.px[i]; A.tmp.py[o] = A.in.py[i]; A.tmp.pz[o] = A.in.pz[i];
-                A.tmp.w[o] = A.in.w[i];
+                A.tmp.x[o] = (float)A.in.x[i]; A.tmp.y[o] = (float)A.in.y[i]; A.tmp.z[o] = (float)A.in.z[i];
+                A.tmp.px[o] = (float)A.in.px[i]; A.tmp.py[o] = (float)A.in.py[i]; A.tmp.pz[o] = (float)A.in.pz[i];
+                A.tmp.w[o] = (float)A.in.w[i];
             } else {
                 merge_subset(A, F, [&](int j) { return lo + (int64_t)X[b + j]; }, len, 0, o, 0, 1);
             }
@@ -2404,11 +2460,11 @@ int64_t fixed_big_sched_bytes() { return (int64_t)BIG_NODES * 4; }
 
 const void* fixed_kernel_ptr(int which) {
     switch (which) {
-        case 4: return (const void*)k_fixed_small;
-        case 0: return (const void*)k_fixed_cells<NMAX_A, uint16_t, true, WPB_A>;
-        case 1: return (const void*)k_fixed_cells<NMAX_B, uint16_t, true, WPB_B>;
-        case 2: return (const void*)k_fixed_cells<NMAX_C, uint16_t, true, WPB_C>;
-        default: return (const void*)k_fixed_big;
+        case 4: return (const void*)k_fixed_small<float>;
+        case 0: return (const void*)k_fixed_cells<NMAX_A, uint16_t, true, WPB_A, float>;
+        case 1: return (const void*)k_fixed_cells<NMAX_B, uint16_t, true, WPB_B, float>;
+        case 2: return (const void*)k_fixed_cells<NMAX_C, uint16_t, true, WPB_C, float>;
+        default: return (const void*)k_fixed_big<float>;
     }
 }
 
@@ -2416,13 +2472,14 @@ int fixed_block_threads(int which) {
     return WAVE * (which == 0 || which == 4 ? 1 : which == 1 ? WPB_B : which == 2 ? WPB_C : WPB_BIG);
 }
 
-hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
-                              const int64_t* cell_off, int64_t n_cells, int32_t n_min_cell,
-                              const FixedParams& fp, const int32_t* perm,
-                              const int32_t* subset_id, const int32_t* n_subsets) {
-    (void)n_cells; (void)n_min_cell;
-    MergeArgs G;
-    FixedArgs& A = G.A;
+namespace {
+
+template <typename InT>
+hipError_t fixed_merge_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<InT>& in, const int64_t* cell_off,
+                         const FixedParams& fp, const int32_t* perm, const int32_t* subset_id,
+                         const int32_t* n_subsets) {
+    MergeArgs<InT> G;
+    auto& A = G.A;
     A.in = in;
     A.cell_off = cell_off;
     A.counters = ws.counters;
@@ -2444,7 +2501,7 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
         A.qlen_index = q;
         A.work_index = 8 + q;
         if (lc.pre) lc.pre(lc.prof, "fixed_merge", lc.stream);
-        hipLaunchKernelGGL(k_fixed_merge, dim3(lc.grid_fp64), dim3(WAVE), 0, lc.stream, G);
+        hipLaunchKernelGGL(k_fixed_merge<InT>, dim3(lc.grid_fp64), dim3(WAVE), 0, lc.stream, G);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (lc.post) lc.post(lc.prof, "fixed_merge", lc.stream);
@@ -2452,10 +2509,10 @@ hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const So
     return hipSuccess;
 }
 
-hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
-                              const int64_t* cell_off, const FixedParams& fp, int mode,
-                              int32_t* perm, int32_t* subset_id, int32_t* n_subsets) {
-    FixedArgs A;
+template <typename InT>
+hipError_t fixed_cells_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<InT>& in, const int64_t* cell_off,
+                         const FixedParams& fp, int mode, int32_t* perm, int32_t* subset_id, int32_t* n_subsets) {
+    FixedArgsT<InT> A;
     A.in = in;
     A.cell_off = cell_off;
     A.counters = ws.counters;
@@ -2468,7 +2525,7 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
     A.flags = ws.flags;
     A.perm = perm; A.subset_id = subset_id; A.n_subsets = n_subsets;
     for (int k = 0; k < BIGQ_CLASSES; ++k) A.bigq[k] = ws.bigq[k];
-    BigArgs G;
+    BigArgs<InT> G;
     G.rec = (int4*)ws.big_rec;
     G.pyz = ws.big_pyz;
     G.idx0 = ws.big_idx0;
@@ -2521,19 +2578,19 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
         A.work_index = 8 + b.q;
         if (lc.pre) lc.pre(lc.prof, b.name, b.s);
         if (b.q == Q_A)
-            hipLaunchKernelGGL((k_fixed_cells<NMAX_A, uint16_t, true, WPB_A>), dim3(lc.grid_a), dim3(WAVE * WPB_A),
+            hipLaunchKernelGGL((k_fixed_cells<NMAX_A, uint16_t, true, WPB_A, InT>), dim3(lc.grid_a), dim3(WAVE * WPB_A),
                                fixed_lds_bytes(0), b.s, A);
         else if (b.q == Q_B)
-            hipLaunchKernelGGL((k_fixed_cells<NMAX_B, uint16_t, true, WPB_B>), dim3(lc.grid_b), dim3(WAVE * WPB_B),
+            hipLaunchKernelGGL((k_fixed_cells<NMAX_B, uint16_t, true, WPB_B, InT>), dim3(lc.grid_b), dim3(WAVE * WPB_B),
                                fixed_lds_bytes(1), b.s, A);
         else if (b.q == Q_S)
-            hipLaunchKernelGGL(k_fixed_small, dim3(lc.grid_s), dim3(WAVE), fixed_lds_bytes(4), b.s, A);
+            hipLaunchKernelGGL(k_fixed_small<InT>, dim3(lc.grid_s), dim3(WAVE), fixed_lds_bytes(4), b.s, A);
         else if (b.q == Q_C)
-            hipLaunchKernelGGL((k_fixed_cells<NMAX_C, uint16_t, true, WPB_C>), dim3(lc.grid_c), dim3(WAVE * WPB_C),
+            hipLaunchKernelGGL((k_fixed_cells<NMAX_C, uint16_t, true, WPB_C, InT>), dim3(lc.grid_c), dim3(WAVE * WPB_C),
                                fixed_lds_bytes(2), b.s, A);
         else {
             G.A = A;
-            hipLaunchKernelGGL(k_fixed_big, dim3(lc.grid_big), dim3(WAVE * WPB_BIG), fixed_lds_bytes(3), b.s, G);
+            hipLaunchKernelGGL(k_fixed_big<InT>, dim3(lc.grid_big), dim3(WAVE * WPB_BIG), fixed_lds_bytes(3), b.s, G);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return join_back(e);
@@ -2542,15 +2599,12 @@ hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const So
     return join_back(e);
 }
 
-}  // namespace vpm
-
-namespace vpm {
-
-hipError_t launch_fixed_blind(const Workspace& ws, const LaunchCfg& lc, const Soa32& in, const int64_t* cell_off,
-                              int64_t n_cells, int64_t n_particles, const FixedParams& fp, double alpha,
-                              uint64_t seed, int32_t n_min_cell, int32_t* group) {
-    BlindArgs B;
-    FixedArgs& A = B.A;
+template <typename InT>
+hipError_t fixed_blind_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<InT>& in, const int64_t* cell_off,
+                         int64_t n_cells, int64_t n_particles, const FixedParams& fp, double alpha, uint64_t seed,
+                         int32_t n_min_cell, int32_t* group) {
+    BlindArgs<InT> B;
+    auto& A = B.A;
     A.in = in;
     A.cell_off = cell_off;
     A.counters = ws.counters;
@@ -2577,10 +2631,41 @@ hipError_t launch_fixed_blind(const Workspace& ws, const LaunchCfg& lc, const So
     const int64_t cap = (int64_t)lc.grid_fp64 * 2;
     const int64_t grid = n_cells < cap ? n_cells : cap;
     if (lc.pre) lc.pre(lc.prof, "fixed_blind", lc.stream);
-    hipLaunchKernelGGL(k_fixed_blind, dim3((unsigned)grid), dim3(WAVE), 0, lc.stream, B);
+    hipLaunchKernelGGL(k_fixed_blind<InT>, dim3((unsigned)grid), dim3(WAVE), 0, lc.stream, B);
     const hipError_t e = hipGetLastError();
     if (lc.post) lc.post(lc.prof, "fixed_blind", lc.stream);
     return e;
+}
+
+}  // namespace
+
+hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const Soa32& in, const int64_t* cell_off,
+                              const FixedParams& fp, int mode, int32_t* perm, int32_t* subset_id, int32_t* n_subsets) {
+    return fixed_cells_t(ws, lc, in, cell_off, fp, mode, perm, subset_id, n_subsets);
+}
+hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const Soa64& in, const int64_t* cell_off,
+                              const FixedParams& fp, int mode, int32_t* perm, int32_t* subset_id, int32_t* n_subsets) {
+    return fixed_cells_t(ws, lc, in, cell_off, fp, mode, perm, subset_id, n_subsets);
+}
+hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const Soa32& in, const int64_t* cell_off,
+                              const FixedParams& fp, const int32_t* perm, const int32_t* subset_id,
+                              const int32_t* n_subsets) {
+    return fixed_merge_t(ws, lc, in, cell_off, fp, perm, subset_id, n_subsets);
+}
+hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const Soa64& in, const int64_t* cell_off,
+                              const FixedParams& fp, const int32_t* perm, const int32_t* subset_id,
+                              const int32_t* n_subsets) {
+    return fixed_merge_t(ws, lc, in, cell_off, fp, perm, subset_id, n_subsets);
+}
+hipError_t launch_fixed_blind(const Workspace& ws, const LaunchCfg& lc, const Soa32& in, const int64_t* cell_off,
+                              int64_t n_cells, int64_t n_particles, const FixedParams& fp, double alpha, uint64_t seed,
+                              int32_t n_min_cell, int32_t* group) {
+    return fixed_blind_t(ws, lc, in, cell_off, n_cells, n_particles, fp, alpha, seed, n_min_cell, group);
+}
+hipError_t launch_fixed_blind(const Workspace& ws, const LaunchCfg& lc, const Soa64& in, const int64_t* cell_off,
+                              int64_t n_cells, int64_t n_particles, const FixedParams& fp, double alpha, uint64_t seed,
+                              int32_t n_min_cell, int32_t* group) {
+    return fixed_blind_t(ws, lc, in, cell_off, n_cells, n_particles, fp, alpha, seed, n_min_cell, group);
 }
 
 }  // namespace vpm

@@ -131,9 +131,7 @@ vpm_status common_checks(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_of
     vpm_status st = vpm_check_params(p);
     if (st != VPM_OK) return st;
     if (check_soa(in) != VPM_OK) return VPM_ERR_INVALID_ARG;
-    if (!((p->decide == VPM_DECIDE_FIXED && p->dtype == VPM_F32) ||
-          (p->decide == VPM_DECIDE_FP64 && p->dtype == VPM_F64)))
-        return VPM_ERR_UNSUPPORTED;
+    if (p->decide == VPM_DECIDE_FP64 && p->dtype != VPM_F64) return VPM_ERR_UNSUPPORTED;
     if (n_particles > ctx->ws.cap_particles || n_cells > ctx->ws.cap_cells) return VPM_ERR_CAPACITY;
     if (n_particles >= (int64_t)1 << 31) return VPM_ERR_CAPACITY;   // int32 permutation indices
     return VPM_OK;
@@ -187,6 +185,10 @@ Fp64Params fp64_params(const vpm_params* p) {
     return f;
 }
 
+// Element bytes of the input arrays and of the output arrays (the fixed-point path emits FP32).
+int elem_in(const vpm_params* p) { return p->dtype == VPM_F32 ? 4 : 8; }
+int elem_out(const vpm_params* p) { return p->decide == VPM_DECIDE_FIXED || p->dtype == VPM_F32 ? 4 : 8; }
+
 Soa32 soa32(const vpm_soa* s) {
     return Soa32{(const float*)s->x, (const float*)s->y, (const float*)s->z, (const float*)s->px,
                  (const float*)s->py, (const float*)s->pz, (const float*)s->w};
@@ -214,7 +216,8 @@ vpm_status run_impl(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, in
             fp.species = species;
             for (int k = 0; k < VPM_MAX_SPECIES; ++k) fp.species_mass[k] = species_mass[k < n_species ? k : 0];
         }
-        e = launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fp, 0, nullptr, nullptr, nullptr);
+        e = p->dtype == VPM_F32 ? launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fp, 0, nullptr, nullptr, nullptr)
+                                : launch_fixed_cells(ctx->ws, lc, soa64(in), cell_off, fp, 0, nullptr, nullptr, nullptr);
     } else {
         Fp64Params fp = fp64_params(p);
         if (species) {
@@ -228,8 +231,7 @@ vpm_status run_impl(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, in
     if (e != hipSuccess) return hip_fail(ctx, e, "scan");
     const void* ins[7] = {in->x, in->y, in->z, in->px, in->py, in->pz, in->w};
     void* outs[7] = {out->x, out->y, out->z, out->px, out->py, out->pz, out->w};
-    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs,
-                       p->dtype == VPM_F32 ? 4 : 8);
+    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs, elem_in(p), elem_out(p));
     if (e != hipSuccess) return hip_fail(ctx, e, "scatter");
     return VPM_OK;
 }
@@ -410,7 +412,9 @@ vpm_status vpm_partition(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_of
     hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx));
     if (e != hipSuccess) return hip_fail(ctx, e, "bin");
     if (p->decide == VPM_DECIDE_FIXED)
-        e = launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fixed_params(p, ctx->tune), 1, perm, subset_id, n_subsets);
+        e = p->dtype == VPM_F32
+                ? launch_fixed_cells(ctx->ws, lc, soa32(in), cell_off, fixed_params(p, ctx->tune), 1, perm, subset_id, n_subsets)
+                : launch_fixed_cells(ctx->ws, lc, soa64(in), cell_off, fixed_params(p, ctx->tune), 1, perm, subset_id, n_subsets);
     else
         e = launch_fp64_cells(ctx->ws, lc, soa64(in), cell_off, n_cells, fp64_params(p), 1, perm, subset_id,
                               n_subsets);
@@ -433,7 +437,9 @@ vpm_status vpm_merge(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, i
     hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx));
     if (e != hipSuccess) return hip_fail(ctx, e, "bin");
     if (p->decide == VPM_DECIDE_FIXED)
-        e = launch_fixed_merge(ctx->ws, lc, soa32(in), cell_off, n_cells, p->n_min_cell, fixed_params(p, ctx->tune), perm,
+        e = p->dtype == VPM_F32
+                ? launch_fixed_merge(ctx->ws, lc, soa32(in), cell_off, fixed_params(p, ctx->tune), perm, subset_id, n_subsets)
+                : launch_fixed_merge(ctx->ws, lc, soa64(in), cell_off, fixed_params(p, ctx->tune), perm,
                                subset_id, n_subsets);
     else
         e = launch_fp64_merge(ctx->ws, lc, soa64(in), cell_off, n_cells, fp64_params(p), perm, subset_id,
@@ -443,8 +449,7 @@ vpm_status vpm_merge(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, i
     if (e != hipSuccess) return hip_fail(ctx, e, "scan");
     const void* ins[7] = {in->x, in->y, in->z, in->px, in->py, in->pz, in->w};
     void* outs[7] = {out->x, out->y, out->z, out->px, out->py, out->pz, out->w};
-    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs,
-                       p->dtype == VPM_F32 ? 4 : 8);
+    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs, elem_in(p), elem_out(p));
     if (e != hipSuccess) return hip_fail(ctx, e, "scatter");
     return VPM_OK;
 }
@@ -454,19 +459,23 @@ vpm_status vpm_blind(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, i
                      int64_t* out_off, int64_t* out_total, int32_t* group, hipStream_t stream) {
     vpm_status st = common_checks(ctx, in, cell_off, n_cells, n_particles, p);
     if (st != VPM_OK) return st;
-    if (p->dtype != VPM_F32) return VPM_ERR_UNSUPPORTED;
+    if (p->decide != VPM_DECIDE_FIXED) return VPM_ERR_UNSUPPORTED;
     if (!(std::isfinite(alpha) && alpha >= 0.0)) return VPM_ERR_INVALID_ARG;
     if (check_soa(out) != VPM_OK || !out_off || !out_total) return VPM_ERR_INVALID_ARG;
     hipSetDevice(ctx->device);
     LaunchCfg lc = make_cfg(ctx, stream);
-    hipError_t e = launch_fixed_blind(ctx->ws, lc, soa32(in), cell_off, n_cells, n_particles,
-                                      fixed_params(p, ctx->tune), alpha, seed, p->n_min_cell, group);
+    const FixedParams fp = fixed_params(p, ctx->tune);
+    hipError_t e = p->dtype == VPM_F32
+                       ? launch_fixed_blind(ctx->ws, lc, soa32(in), cell_off, n_cells, n_particles, fp, alpha, seed,
+                                            p->n_min_cell, group)
+                       : launch_fixed_blind(ctx->ws, lc, soa64(in), cell_off, n_cells, n_particles, fp, alpha, seed,
+                                            p->n_min_cell, group);
     if (e != hipSuccess) return hip_fail(ctx, e, "blind");
     e = launch_scan_offsets(ctx->ws, lc, n_cells, n_particles, out_off, out_total);
     if (e != hipSuccess) return hip_fail(ctx, e, "scan");
     const void* ins[7] = {in->x, in->y, in->z, in->px, in->py, in->pz, in->w};
     void* outs[7] = {out->x, out->y, out->z, out->px, out->py, out->pz, out->w};
-    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs, 4);
+    e = launch_scatter(ctx->ws, lc, cell_off, n_cells, n_particles, out_off, ins, outs, elem_in(p), 4);
     if (e != hipSuccess) return hip_fail(ctx, e, "scatter");
     return VPM_OK;
 }

@@ -70,7 +70,7 @@ struct FixedParams {
     float t2p_lo, t2p_hi;           // FP32 bracket of (that_p / 2^24)^2
     float s[3];                     // fl32(65536 / L_a)
     int32_t axis_rule;              // vpm_axis_rule
-    uint64_t tx2, tp2;              // that_x^2, that_p^2 (< 2^62)
+    uint64_t tx2, tp2;              // normalised rule: that_x^2, that_p^2 (< 2^62); raw rule: 1, 1
     float it2x_lo, it2x_hi;         // FP32 bracket of 1 / (that_x / 2^24)^2 (0 if that_x = 0)
     float it2p_lo, it2p_hi;
     int32_t min_subset;
@@ -84,8 +84,8 @@ struct FixedParams {
 // Step 4's tolerance scale for the normalised axis rule, derived from that_x and that_p.
 inline void fixed_axis_rule(FixedParams& f, int rule) {
     f.axis_rule = rule;
-    f.tx2 = f.that_x * f.that_x;
-    f.tp2 = f.that_p * f.that_p;
+    f.tx2 = rule ? f.that_x * f.that_x : 1;      // the raw rule compares the CVs with unit weights
+    f.tp2 = rule ? f.that_p * f.that_p : 1;
     auto inv = [](uint64_t t, float& lo, float& hi) {      // 2^48 / t^2, bracketed 2^-22 each side
         if (t == 0) { lo = hi = 0.0f; return; }
         const float f = (float)(0x1p48 / ((double)t * (double)t));
@@ -123,9 +123,11 @@ struct LaunchCfg {
     void* prof;
 };
 
-struct Soa32 { const float *x, *y, *z, *px, *py, *pz, *w; };
+template <typename T>
+struct SoaIn { const T *x, *y, *z, *px, *py, *pz, *w; };
+using Soa32 = SoaIn<float>;
+using Soa64 = SoaIn<double>;
 struct Soa32Out { float *x, *y, *z, *px, *py, *pz, *w; };
-struct Soa64 { const double *x, *y, *z, *px, *py, *pz, *w; };
 struct Soa64Out { double *x, *y, *z, *px, *py, *pz, *w; };
 
 // ---- launchers (vpm_common.hip) ----
@@ -136,25 +138,34 @@ hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* c
 // out_off and out_total are clamped to n_particles (reached only with offsets flagged as bad).
 hipError_t launch_scan_offsets(const Workspace& ws, const LaunchCfg& lc, int64_t n_cells, int64_t n_particles,
                                int64_t* out_off, int64_t* out_total);
+// in_size, out_size: element bytes of the input and output arrays (4 or 8; FP64 input with FP32
+// output for the fixed-point path, rounded to nearest as untouched cells are copied).
 hipError_t launch_scatter(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,
                           int64_t n_cells, int64_t n_particles, const int64_t* out_off,
-                          const void* const in[7], void* const out[7], int elem_size);
+                          const void* const in[7], void* const out[7], int in_size, int out_size);
 hipError_t launch_identity(const Workspace& ws, const LaunchCfg& lc, const int64_t* cell_off,
                            int64_t n_particles, int32_t* perm, int32_t* subset_id,
                            int32_t* n_subsets);
 
 // ---- fixed-point path (vpm_fixed.hip) ----
-// mode 0: run (partition + merge into ws.tmp), mode 1: partition only
-hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
-                              const int64_t* cell_off, const FixedParams& fp, int mode,
-                              int32_t* perm, int32_t* subset_id, int32_t* n_subsets);
-hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const Soa32& in,
-                              const int64_t* cell_off, int64_t n_cells, int32_t n_min_cell,
-                              const FixedParams& fp, const int32_t* perm,
-                              const int32_t* subset_id, const int32_t* n_subsets);
+// mode 0: run (partition + merge into ws.tmp, FP32), mode 1: partition only.  FP64 particles are
+// rounded to FP32 as they are loaded (the fixed-point path works on FP32 values).
+hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const Soa32& in, const int64_t* cell_off,
+                              const FixedParams& fp, int mode, int32_t* perm, int32_t* subset_id, int32_t* n_subsets);
+hipError_t launch_fixed_cells(const Workspace& ws, const LaunchCfg& lc, const Soa64& in, const int64_t* cell_off,
+                              const FixedParams& fp, int mode, int32_t* perm, int32_t* subset_id, int32_t* n_subsets);
+hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const Soa32& in, const int64_t* cell_off,
+                              const FixedParams& fp, const int32_t* perm, const int32_t* subset_id,
+                              const int32_t* n_subsets);
+hipError_t launch_fixed_merge(const Workspace& ws, const LaunchCfg& lc, const Soa64& in, const int64_t* cell_off,
+                              const FixedParams& fp, const int32_t* perm, const int32_t* subset_id,
+                              const int32_t* n_subsets);
 // The blind method (random pair merges down to ceil(alpha N) per cell) into ws.tmp, out_count and
 // cell_mode for every cell (validation included; no binning needed).
 hipError_t launch_fixed_blind(const Workspace& ws, const LaunchCfg& lc, const Soa32& in, const int64_t* cell_off,
+                              int64_t n_cells, int64_t n_particles, const FixedParams& fp, double alpha,
+                              uint64_t seed, int32_t n_min_cell, int32_t* group);
+hipError_t launch_fixed_blind(const Workspace& ws, const LaunchCfg& lc, const Soa64& in, const int64_t* cell_off,
                               int64_t n_cells, int64_t n_particles, const FixedParams& fp, double alpha,
                               uint64_t seed, int32_t n_min_cell, int32_t* group);
 // bins: 0 = A, 1 = B, 2 = C (LDS), 3 = big (global slabs), 4 = small-cell batches

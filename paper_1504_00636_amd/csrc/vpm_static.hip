@@ -161,7 +161,7 @@ extern "C" vpm_status vpm_run_noalloc(const vpm_soa* in, const int64_t* cell_off
         e = launch_fixed_cells(ws, lc, s, cell_off, fp, 0, nullptr, nullptr, nullptr);
     }
     if (e == hipSuccess) e = launch_scan_offsets(ws, lc, n_cells, n_particles, out_off, out_total);
-    if (e == hipSuccess) e = launch_scatter(ws, lc, cell_off, n_cells, n_particles, out_off, ip, op, 4);
+    if (e == hipSuccess) e = launch_scatter(ws, lc, cell_off, n_cells, n_particles, out_off, ip, op, 4, 4);
     if (e == hipSuccess && flags_out) {
         hipLaunchKernelGGL(k_na_flags_out, dim3(1), dim3(64), 0, stream, ws.flags, flags_out);
         e = hipGetLastError();

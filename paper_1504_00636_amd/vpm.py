@@ -181,8 +181,16 @@ def _stream(stream) -> int:
 
 
 def _torch_dtype(p: VpmParams):
+    """Element type of the input arrays."""
     import torch
     return torch.float32 if p.dtype == VPM_F32 else torch.float64
+
+
+def _out_dtype(p: VpmParams):
+    """Element type of the output arrays: FP32 for fixed-point decisions (FP64 input is rounded to
+    FP32 as it is loaded), else the input's."""
+    import torch
+    return torch.float32 if p.decide == VPM_DECIDE_FIXED else _torch_dtype(p)
 
 
 class Context:
@@ -220,7 +228,7 @@ class Context:
         n_cells = cell_off.numel() - 1
         dt = _torch_dtype(p)
         si = _soa(inp, dt, n_particles, "in")
-        so = _soa(out, dt, n_particles, "out")
+        so = _soa(out, _out_dtype(p), n_particles, "out")
         st = lib().vpm_run(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"), n_cells,
                            int(n_particles), C.byref(p), C.byref(so),
                            _dev(out_off, torch.int64, n_cells + 1, "out_off"),
@@ -235,7 +243,7 @@ class Context:
         n_cells = cell_off.numel() - 1
         dt = _torch_dtype(p)
         si = _soa(inp, dt, n_particles, "in")
-        so = _soa(out, dt, n_particles, "out")
+        so = _soa(out, _out_dtype(p), n_particles, "out")
         masses = [float(m) for m in species_mass]
         tab = (C.c_double * max(1, len(masses)))(*masses)
         st = lib().vpm_run_species(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"),
@@ -263,7 +271,7 @@ class Context:
         n_cells = cell_off.numel() - 1
         dt = _torch_dtype(p)
         si = _soa(inp, dt, n_particles, "in")
-        so = _soa(out, dt, n_particles, "out")
+        so = _soa(out, _out_dtype(p), n_particles, "out")
         st = lib().vpm_merge(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"), n_cells,
                              int(n_particles), C.byref(p), _dev(perm, torch.int32, n_particles, "perm"),
                              _dev(subset_id, torch.int32, n_particles, "subset_id"),
@@ -280,7 +288,7 @@ class Context:
         n_cells = cell_off.numel() - 1
         dt = _torch_dtype(p)
         si = _soa(inp, dt, n_particles, "in")
-        so = _soa(out, dt, n_particles, "out")
+        so = _soa(out, _out_dtype(p), n_particles, "out")
         g = None if group is None else _dev(group, torch.int32, n_particles, "group")
         st = lib().vpm_blind(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"), n_cells,
                              int(n_particles), C.byref(p), float(alpha), int(seed) & (2 ** 64 - 1), C.byref(so),
@@ -302,7 +310,7 @@ class Context:
         n_cells = cell_off.numel() - 1
         dt = _torch_dtype(p)
         si = _soa(inp, dt, n_particles, "in")
-        so = _soa(out, dt, n_particles, "out")
+        so = _soa(out, _out_dtype(p), n_particles, "out")
         best = VpmTuning()
         st = lib().vpm_autotune(self.h, C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"), n_cells,
                                 int(n_particles), C.byref(p), C.byref(so),
@@ -370,7 +378,7 @@ def vpm_run_noalloc(inp, cell_off, n_particles: int, p: VpmParams, out, out_off,
     n_cells = cell_off.numel() - 1
     dt = _torch_dtype(p)
     si = _soa(inp, dt, n_particles, "in")
-    so = _soa(out, dt, n_particles, "out")
+    so = _soa(out, _out_dtype(p), n_particles, "out")
     fo = None if flags_out is None else _dev(flags_out, torch.int32, 1, "flags_out")
     st = lib().vpm_run_noalloc(C.byref(si), _dev(cell_off, torch.int64, n_cells + 1, "cell_off"), n_cells,
                                int(n_particles), C.byref(p), C.byref(so),
@@ -425,7 +433,7 @@ def run_population(ctx: Context, arrs, cell_off, p: VpmParams, stream=None) -> R
     import torch
     n = int(arrs[0].numel())
     n_cells = cell_off.numel() - 1
-    out = [torch.empty_like(a) for a in arrs]
+    out = [torch.empty_like(a, dtype=_out_dtype(p)) for a in arrs]
     out_off = torch.empty(n_cells + 1, dtype=torch.int64, device=arrs[0].device)
     out_total = torch.empty(1, dtype=torch.int64, device=arrs[0].device)
     ctx.run(arrs, cell_off, n, p, out, out_off, out_total, stream)

@@ -410,6 +410,8 @@ def test_normalised_axis_rule_zero_tolerance_and_ties():
     from tests.test_oracle_exact_tiny import exact_tie
     wl = cloud_cells([200, 64, 33], seed=17)
     full_check(wl, dict(CLOUD, tol_x=0.0, tol_p=0.05, axis_rule=1, min_subset=2))
+    full_check(wl, dict(CLOUD, tol_x=0.05, tol_p=0.0, axis_rule=1, min_subset=2))
+    full_check(wl, dict(CLOUD, tol_x=0.0, tol_p=0.0, axis_rule=1, min_subset=2))
     r = np.random.Generator(np.random.Philox(98))
     cells = [exact_tie(r) for _ in range(200)]
     params = dict(CLOUD, tol_x=0.01, tol_p=0.01, min_subset=2, axis_rule=1)
