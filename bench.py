@@ -3,12 +3,16 @@
 One step = one merge event (vpm_run: bin cells, partition every cell, merge, compact) over the whole
 synthetic two-stream population: 256 x 256 cells, Poisson(512) electrons per cell (33.5M particles),
 two drifting Maxwellians, tolerances T_X 0.1, T_P 0.05, minimum subset 4.  Inputs are resident in
-HBM before timing.  The batched fixed-point FP32 form is the measured line; the plain FP64 form
-(one wavefront per cell, FP64 statistics) is timed on the same population for the speedup, and both
-forms' conserved totals (weight, momentum, energy) are compared with their inputs.  Two more
-workloads are reported beside the headline: the shower-shaped 64^3 population (lognormal cell
-occupancy up to 32,768, gamma^-2 momenta) and the two-stream population at the paper's own
-two-stream tolerances.
+HBM before timing.  The batched fixed-point FP32 form is the measured line; the same event from the
+FP64 particle arrays (rounded as they are loaded) and the plain FP64 form (one wavefront per cell,
+FP64 statistics) are timed on the same population, and each form's conserved totals (weight,
+momentum, energy) are compared with its input.  More workloads are reported beside the headline,
+each with a roofline per size-bin kernel and the oracle timed on a sample of its cells: the
+two-stream population at the paper's own two-stream tolerances (with the paper's blind method
+beside the Voronoi merge), the shower-shaped 64^3 population (lognormal cell occupancy up to
+32,768, gamma^-2 momenta; with the fixed-point vs FP64 partition agreement), its three-species
+form, 50 graph-replayed events of the 512 x 512 cascade and the fixed-point vs FP64 comparison at
+five densities.
 
 Prints one JSON line.  Tooling modes: `--copy-calib` runs a plain device copy of known size (for
 scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes); `--traffic-summary` turns four
@@ -32,7 +36,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fixed_cells_two_stream.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1504_00636_amd", "csrc", "vpm_fixed.hip")
+# every source compiled into the kernels (a counter record taken on other sources is stale)
+KERNEL_SOURCES = sorted(f for f in glob.glob(os.path.join(ROOT, "paper_1504_00636_amd", "csrc", "*"))
+                        if f.endswith((".hip", ".h", ".hpp", ".cpp"))) + [os.path.join(ROOT, "include", "vpm.h")]
 DOMINANT = "fixed_cells_576"          # the one-wavefront-per-cell bin: every two-stream cell but ~0.2 %
 DOMINANT_SYMBOL = "k_fixed_cells<576"  # how rocprofv3 names it
 COPY_BYTES = 1 << 30
@@ -51,7 +57,29 @@ def log(msg):
 
 
 def kernel_source_sha():
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def host_cpu():
+    """The host's processor model, its logical CPU count and the CPUs this process may run on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return dict(model=model, logical_cpus=os.cpu_count(), usable_cpus=usable)
 
 
 def conservation_error(arrs_in, arrs_out, n_out, mass, mass_out=None):
@@ -171,19 +199,98 @@ def valu_from_profiles():
         return None
 
 
+# the size-bin kernels, in the order of their upper limits in the tuning (the last has none)
+BINS = [("fixed_cells_small", "bin_s_max"), ("fixed_cells_576", "bin_a_max"), ("fixed_cells_2048", "bin_b_max"),
+        ("fixed_cells_4352", "bin_c_max"), ("fixed_cells_big", None)]
+ORACLE_KEYS = ("tol_x", "tol_p", "n_min_cell", "min_subset", "cell_len", "mass")
+
+
+def bin_of_cells(counts, tuning, n_min_cell):
+    """The size bin of every cell as the library assigns it (-1: left untouched)."""
+    lims = [tuning[k] for _, k in BINS[:-1]]
+    b = np.searchsorted(np.asarray(lims), counts, side="left")      # first bin whose limit >= count
+    proc = (counts > n_min_cell) & (counts > 0) & (counts <= 65536)
+    return np.where(proc, b, -1)
+
+
+def oracle_threads():
+    """Threads for the oracle: the CPUs this process may use, capped by OMP_NUM_THREADS when set."""
+    usable = host_cpu()["usable_cpus"]
+    env = os.environ.get("OMP_NUM_THREADS")
+    return max(1, min(usable, int(env))) if env and env.isdigit() else usable
+
+
+def oracle_sample(wl, prm, bins, per_bin, seed):
+    """The CPU baseline of a workload on a bounded sample: the oracle (fixed-point decisions, pair
+    merge) on up to per_bin seeded cells of every size bin, timed; returns its rate and, per bin,
+    the particle-levels of the tree (particles times levels they pass through) per particle."""
+    import oracle
+    r = np.random.Generator(np.random.Philox(seed + 7))
+    counts = np.diff(wl.cell_off)
+    threads = oracle_threads()
+    pick = []
+    for i in range(len(BINS)):
+        cells = np.nonzero(bins == i)[0]
+        if cells.size:
+            pick.append(np.sort(r.choice(cells, min(per_bin, cells.size), replace=False)))
+    pick = np.concatenate(pick) if pick else np.zeros(0, np.int64)
+    sub = wl.cells(pick)
+    t0 = time.perf_counter()
+    ref = oracle.run(sub.arrays(), sub.cell_off, decide=oracle.FIXED, n_threads=threads,
+                     **{k: prm[k] for k in ORACLE_KEYS})
+    dt = time.perf_counter() - t0
+    per_bin_pl = {}
+    for i, (name, _) in enumerate(BINS):
+        m = bins[pick] == i
+        if m.any():
+            per_bin_pl[name] = float(ref.stats["particle_levels"][m].sum()) / float(counts[pick][m].sum())
+    return dict(value=sub.n / dt, unit="particles/s", cores=threads, kind="oracle",
+                sample=f"{pick.size} seeded cells (up to {per_bin} per size bin, {sub.n} particles), "
+                       f"{dt:.2f} s wall on {threads} threads"), per_bin_pl
+
+
+def bin_rooflines(counts, out_counts, bins, kernels, in_bytes=28.0, pl_per_particle=None):
+    """Per size-bin kernel: its cells' algorithmic bytes (in_bytes per input particle read, 28 per
+    output particle written) over the kernel's average duration against the HBM peak and, given the
+    particle-levels per particle of the bin, its algorithmic integer work against the int32 lane
+    peak.  Returns the per-bin records and the name of the longest-running kernel."""
+    rec = {}
+    for i, (name, _) in enumerate(BINS):
+        m = bins == i
+        if not m.any() or name not in kernels:
+            continue
+        ms = kernels[name]["avg_ms"]
+        byt = in_bytes * float(counts[m].sum()) + 28.0 * float(out_counts[m].sum())
+        r = dict(cells=int(m.sum()), particles=int(counts[m].sum()), avg_ms=ms, algorithmic_bytes=byt,
+                 roofline=dict(bound="hbm", achieved=byt / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                               frac=byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS))
+        if pl_per_particle and name in pl_per_particle:
+            pl = pl_per_particle[name] * float(counts[m].sum())
+            ops = pl * LANE_OPS_PER_PARTICLE_LEVEL / (ms * 1e-3)
+            r["alu"] = dict(particle_levels_per_launch=pl, lane_ops_per_particle_level=LANE_OPS_PER_PARTICLE_LEVEL,
+                            achieved=ops, peak=ALU_PEAK_LANE_OPS, unit="int32 lane-ops/s",
+                            frac=ops / ALU_PEAK_LANE_OPS, estimate="particle-levels per particle of the bin "
+                            "from the oracle's sample, times the bin's particles")
+        rec[name] = r
+    dominant = max(rec, key=lambda k: rec[k]["avg_ms"]) if rec else None
+    return rec, dominant
+
+
 def autotune(ctx, vpm, arrs, off, n, p):
-    """Let the library pick lane-group sizing and bin limits for this population (timed on the GPU);
-    returns (tuning dict, seconds spent)."""
+    """Let the library pick lane-group sizing and bin limits for this population (timed on the GPU),
+    through the persistent tuning cache (keyed by device, ROCm, dtype, sources and the population's
+    shape); returns (tuning dict, seconds spent).  The dict notes whether the cache held it."""
     import torch
-    out = [torch.empty_like(a) for a in arrs]
+    from paper_1504_00636_amd import tuning_cache
+    out = [torch.empty_like(a, dtype=torch.float32) for a in arrs]
     out_off = torch.empty(off.numel(), dtype=torch.int64, device="cuda")
     out_total = torch.empty(1, dtype=torch.int64, device="cuda")
     t0 = time.perf_counter()
-    best = ctx.autotune(arrs, off, n, p, out, out_off, out_total)
+    best, hit, _ = tuning_cache.autotune_cached(ctx, arrs, off, n, p, out, out_off, out_total)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     del out
-    return best.as_dict(), dt
+    return dict(best.as_dict(), from_cache=hit), dt
 
 
 def time_fixed(ctx, vpm, arrs, off, n, p, steps, warmup, profile, graph=False):
@@ -196,7 +303,8 @@ def time_fixed(ctx, vpm, arrs, off, n, p, steps, warmup, profile, graph=False):
     timed steps)."""
     import torch
     n_cells = off.numel() - 1
-    out = [torch.empty_like(a) for a in arrs]
+    odt = torch.float32 if p.decide == vpm.VPM_DECIDE_FIXED else arrs[0].dtype    # the fixed-point path writes FP32
+    out = [torch.empty_like(a, dtype=odt) for a in arrs]
     out_off = torch.empty(n_cells + 1, dtype=torch.int64, device="cuda")
     out_total = torch.empty(1, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -260,10 +368,14 @@ def time_plain(ctx, vpm, wl64, prm, steps):
     return dict(ms_per_step=ms, value=n / (ms * 1e-3), n_out=n_out, conservation=cons)
 
 
-def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True, cv=True):
-    """One more population: FIXED FP32 timing and, unless fp64_steps == 0, the plain FP64 form.
-    tune = False keeps the context's batching configuration; cv = False leaves out the
-    merged-subset CVs (a vpm_partition launch of their own)."""
+def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True, cv=True, cpu=True,
+                   agreement=False, seed=0):
+    """One more population: FIXED FP32 timing with a roofline per size-bin kernel and, unless
+    fp64_steps == 0, the plain FP64 form.  tune = False keeps the context's batching configuration;
+    cv = False leaves out the merged-subset CVs (a vpm_partition launch of their own); cpu: the
+    oracle timed on a bounded sample of the workload's cells (its CPU baseline, whose tree also
+    gives each bin's particle-levels for the ALU figure); agreement: the fraction of particles whose
+    final subset is the same under the fixed-point and the FP64 decisions (on the same FP32 values)."""
     import torch
     n = wl32.n
     arrs, off = vpm.upload(wl32)
@@ -272,15 +384,45 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True
         tuning, tune_s = autotune(ctx, vpm, arrs, off, n, p32)
     else:
         tuning, tune_s = ctx.get_tuning().as_dict(), 0.0
-    ms, out, _, n_out, kernels, _ = time_fixed(ctx, vpm, arrs, off, n, p32, steps, 2, True)
+    ms, out, out_off, n_out, kernels, _ = time_fixed(ctx, vpm, arrs, off, n, p32, steps, 2, True)
+    counts = np.diff(wl32.cell_off)
+    bins = bin_of_cells(counts, tuning, prm["n_min_cell"])
+    out_counts = np.diff(out_off.cpu().numpy())
+    cpu_rec, pl = (oracle_sample(wl32, prm, bins, 2048, seed) if cpu else (None, None))
+    per_bin, dominant = bin_rooflines(counts, out_counts, bins, kernels, 28.0, pl)
     rec = dict(workload=name, n_particles=n, n_cells=wl32.n_cells, ms_per_step=ms, value=n / (ms * 1e-3),
                tuning=tuning, autotune_s=tune_s,
                unit="particles/s", merge_ratio=n_out / n,
+               pipeline_GBps=28.0 * (n + n_out) / (ms * 1e-3) / 1e9,
+               roofline=dict(per_bin[dominant]["roofline"], kernel=dominant) if dominant else None,
+               alu=dict(per_bin[dominant]["alu"], kernel=dominant) if dominant and "alu" in per_bin[dominant] else None,
+               bins=per_bin, cpu_baseline=cpu_rec,
                conservation=conservation_error(arrs, out, n_out, prm["mass"]),
                merged_cv=merged_cv(ctx, vpm, arrs, off, n, p32, prm) if cv else None,
                kernels={k: round(v["avg_ms"], 4) for k, v in kernels.items()},
                params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset")})
-    del arrs, out
+    del out
+    if agreement:
+        perm = torch.empty(n, dtype=torch.int32, device="cuda")
+        sid = torch.empty(n, dtype=torch.int32, device="cuda")
+        nsub = torch.empty(wl32.n_cells, dtype=torch.int32, device="cuda")
+        ctx.partition(arrs, off, n, p32, perm, sid, nsub)
+        lab32 = subset_labels(perm, sid, off)
+        del arrs
+        torch.cuda.empty_cache()
+        arrs64, off64 = vpm.upload(wl32, dtype=torch.float64)
+        p64 = vpm.make_params(decide=vpm.VPM_DECIDE_FP64, **prm)
+        ctx.partition(arrs64, off64, n, p64, perm, sid, nsub)
+        lab64 = subset_labels(perm, sid, off64)
+        same = lab32 == lab64
+        cid = torch.repeat_interleave(torch.arange(wl32.n_cells, device="cuda"), off64[1:] - off64[:-1],
+                                      output_size=n)
+        differ = torch.zeros(wl32.n_cells, dtype=torch.int32, device="cuda").index_add_(0, cid, (~same).int())
+        rec["fixed_vs_fp64_partition"] = dict(particle_agreement=float(same.double().mean().item()),
+                                              identical_cells=float((differ == 0).double().mean().item()))
+        del arrs64, perm, sid, nsub, lab32, lab64, same, cid, differ
+    else:
+        del arrs
     torch.cuda.empty_cache()
     if fp64_steps > 0 and wl64 is not None:
         pl = time_plain(ctx, vpm, wl64, prm, fp64_steps)
@@ -288,6 +430,48 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True
         rec["plain_fp64"] = pl
     log(f"[bench] {name}: {ms:.3f} ms/step ({rec['value']:.3g} particles/s), rho {rec['merge_ratio']:.4f}")
     return rec
+
+
+def blind_vs_voronoi(ctx, vpm, wl32, prm, alphas, seed, steps=5):
+    """The paper's comparison on one population: the Voronoi merge (vpm_run) against the blind method
+    (vpm_blind: random pairs merged until at most ceil(alpha N) particles remain per cell), each
+    with its particle count, time and conserved-total errors; the blind method runs at the paper's
+    fraction(s) and at the Voronoi merge's own output fraction (the same particle count)."""
+    import torch
+    n = wl32.n
+    arrs, off = vpm.upload(wl32)
+    p = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
+    out = [torch.empty_like(a) for a in arrs]
+    oo = torch.empty(off.numel(), dtype=torch.int64, device="cuda")
+    ot = torch.empty(1, dtype=torch.int64, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    ms = timed(lambda: ctx.run(arrs, off, n, p, out, oo, ot))
+    n_v = int(ot.item())
+    recs = {"voronoi": dict(n_out=n_v, merge_ratio=n_v / n, ms_per_step=ms,
+                            conservation=conservation_error(arrs, out, n_v, prm["mass"]))}
+    for a in list(alphas) + [n_v / n]:
+        ms = timed(lambda: ctx.blind(arrs, off, n, p, a, seed, out, oo, ot))
+        k = int(ot.item())
+        recs[f"blind_alpha_{a:.6g}"] = dict(alpha=a, n_out=k, merge_ratio=k / n, ms_per_step=ms,
+                                          conservation=conservation_error(arrs, out, k, prm["mass"]))
+    flags = ctx.device_status(clear=True)
+    del arrs, out
+    torch.cuda.empty_cache()
+    log(f"[bench] blind vs Voronoi: " + ", ".join(f"{k}: {v['n_out']} out, dE {v['conservation']['energy']:.2e}"
+                                                   for k, v in recs.items()))
+    return dict(workload="two_stream_256x256_poisson512_T0.8_0.15_Nmin200", seed=seed, device_flags=flags,
+                params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset")}, methods=recs,
+                note="energy: relative change of the total energy; the blind method conserves weight and "
+                     "momentum and loses energy, the Voronoi pair merge conserves all three")
 
 
 def species_shower(ctx, vpm, W, seed, steps=5, warmup=2):
@@ -440,14 +624,18 @@ def precision_sweep(ctx, vpm, W, means, seed):
     return dict(workload="two_stream_256x256_poisson_mean", tolerances=[0.1, 0.05], points=recs)
 
 
+CASCADE_TOL_P = 0.6   # merged cells fall to a few hundred particles and grow back: cells stay near N_min
+
+
 def cascade(ctx, vpm, W, steps, seed):
     """Repeated merge events: the 512 x 512 cascade (256 particles per cell at the start, every particle
-    split in two between events, cells above 1,024 particles merged).  The merge event is captured
-    once in a HIP graph and replayed for every step; the population size is read on the device."""
+    split in two between events, cells above 1,024 particles merged) at T_P 0.6, which holds the
+    cells near 1,024 particles.  The merge event is captured once in a HIP graph and replayed for
+    every step; the population size is read on the device."""
     import torch
     cap = 540_000_000
     wl = W.cascade_initial(seed=seed)
-    prm = dict(wl.params)
+    prm = dict(wl.params, tol_p=CASCADE_TOL_P)
     n_cells = wl.n_cells
     ctx.reserve(cap, n_cells)
     ctx.set_tuning(vpm.make_tuning())       # default batching (the early steps merge nothing to tune on)
@@ -488,11 +676,14 @@ def cascade(ctx, vpm, W, steps, seed):
     flags = ctx.device_status(clear=True)
     del P, Q
     torch.cuda.empty_cache()
+    tot_ms = sum(r["ms"] for r in recs)
+    tot_in = sum(r["n_in"] for r in recs)
     return dict(workload="cascade_512x512_from256", params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset")},
-                capacity=cap, graph_replayed=True, steps=recs, device_flags=flags,
-                note="the population doubles between events; merged cells keep nearly all particles under "
-                     "the per-component momentum CV, so the run stops when the next split would exceed "
-                     "the capacity")
+                capacity=cap, graph_replayed=True, steps_run=len(recs), total_merge_ms=tot_ms,
+                value=tot_in / (tot_ms * 1e-3) if tot_ms > 0 else None, unit="input particles/s over all events",
+                max_population=max((r["n_in"] for r in recs), default=0), steps=recs, device_flags=flags,
+                note="every particle is split in two between events; each event merges the cells above "
+                     "N_min, and the run stops early only if the next split would exceed the capacity")
 
 
 def main():
@@ -507,7 +698,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CALIB_FETCH", "CALIB_WRITE"))
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cascade-steps", type=int, default=3)
+    ap.add_argument("--cascade-steps", type=int, default=50)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default batching configuration (profiling runs: one kernel configuration only)")
     ap.add_argument("--valu-summary", metavar="PMC_DIR")
@@ -572,7 +763,7 @@ def main():
     counts = np.diff(wl32.cell_off)
     gpu_out_off = out_off.cpu().numpy()
     out_counts = np.diff(gpu_out_off)
-    in_a = (counts > prm["n_min_cell"]) & (counts <= tuning["bin_a_max"])
+    in_a = bin_of_cells(counts, tuning, prm["n_min_cell"]) == 1
     bytes_dom = 28.0 * float(counts[in_a].sum() + out_counts[in_a].sum())
     dom = kernels[DOMINANT]
     achieved = bytes_dom / (dom["avg_ms"] * 1e-3) / 1e9
@@ -582,6 +773,29 @@ def main():
     # (a vpm_partition launch of its own: left out of the counter and trace runs, which pass
     # --no-extra, so that they see the timed form's launches only)
     cv32 = None if args.no_extra else merged_cv(ctx, vpm, arrs32, off, n, p32, prm)
+
+    # The same event from the FP64 particle arrays (the fixed-point kernels round each value to FP32
+    # as they load it; FP32 output): its time, its roofline on 56 bytes read per input particle, and
+    # whether its output equals the FP32 run's bit for bit.
+    fp64_in = None
+    if not args.no_fp64:
+        arrs64, off64 = vpm.upload(wl64)
+        p64in = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, dtype=vpm.VPM_F64, **prm)
+        ms64i, out64i, oo64i, n64i, k64i, _ = time_fixed(ctx, vpm, arrs64, off64, n, p64in, args.steps,
+                                                         args.warmup, True)
+        same = n64i == n_out and torch.equal(oo64i, out_off) and all(
+            torch.equal(a[:n_out].view(torch.int32), b[:n_out].view(torch.int32)) for a, b in zip(out64i, out32))
+        b64 = 56.0 * float(counts[in_a].sum()) + 28.0 * float(out_counts[in_a].sum())
+        d64 = k64i[DOMINANT]["avg_ms"]
+        fp64_in = dict(ms_per_step=ms64i, value=n / (ms64i * 1e-3), unit="particles/s", dtype_in="f64",
+                       output_equals_fp32_input=bool(same),
+                       pipeline_GBps=(56.0 * n + 28.0 * n64i) / (ms64i * 1e-3) / 1e9,
+                       roofline=dict(bound="hbm", achieved=b64 / (d64 * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                                     frac=b64 / (d64 * 1e-3) / 1e9 / HBM_PEAK_GBS, kernel=DOMINANT,
+                                     kernel_avg_ms=d64, algorithmic_bytes_per_launch=b64),
+                       kernels={k: round(v["avg_ms"], 4) for k, v in k64i.items()})
+        log(f"[bench] fixed-point from FP64 input: {ms64i:.3f} ms/step, output equal to the FP32 run: {same}")
+        del arrs64, out64i
     del out32
     torch.cuda.empty_cache()
 
@@ -595,13 +809,14 @@ def main():
     pl_dom = None
     if not args.no_cpu:
         import oracle
-        cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "0") or 16))
+        cores = oracle_threads()
         ta = time.perf_counter()
         ref = oracle.run_workload(wl32, decide=oracle.FIXED, n_threads=cores)
         dt = time.perf_counter() - ta
-        cpu = dict(value=n / dt, unit="particles/s", cores=cores, kind="oracle",
+        cpu = dict(value=n / dt, unit="particles/s", cores=cores, kind="oracle", host=host_cpu(),
                    sample=f"all {n_cells} cells ({n} particles) of the same workload, fixed-point decisions, "
-                          f"pair merge, {dt:.2f} s wall on {cores} threads")
+                          f"pair merge, {dt:.2f} s wall on {cores} threads (every CPU the process may use, "
+                          f"capped by OMP_NUM_THREADS when set)")
         log(f"[bench] oracle: {dt:.2f} s on {cores} threads")
         # The tree the method builds on this workload, from the same oracle run, and whether the GPU's
         # per-cell output counts equal the oracle's over every cell.
@@ -633,18 +848,21 @@ def main():
         ts_paper = W.two_stream_grid(nx=256, ny=256, mean=512, seed=args.seed, params=W.TWO_STREAM_PAPER_PARAMS)
         extra["two_stream_paper_tolerances"] = extra_workload(
             ctx, vpm, "two_stream_256x256_poisson512_T0.8_0.15_Nmin200", ts_paper.astype(np.float32), None,
-            dict(ts_paper.params), 10, 0)
+            dict(ts_paper.params), 10, 0, cpu=not args.no_cpu, seed=args.seed)
+        extra["blind_vs_voronoi"] = blind_vs_voronoi(ctx, vpm, ts_paper.astype(np.float32), dict(ts_paper.params),
+                                                     [0.965, 0.88], args.seed)
         del ts_paper
         sh = W.shower_grid(nc=64, seed=args.seed)
         sh64 = sh.astype(np.float64) if not args.no_fp64 else None
         extra["shower"] = extra_workload(ctx, vpm, "shower_64cubed_lognormal64", sh, sh64, dict(sh.params), 5,
-                                         0 if args.no_fp64 else 1)
+                                         0 if args.no_fp64 else 1, cpu=not args.no_cpu,
+                                         agreement=not args.no_fp64, seed=args.seed)
         del sh, sh64
         extra["shower_three_species"] = species_shower(ctx, vpm, W, args.seed)
         if args.cascade_steps > 0:
             extra["cascade"] = cascade(ctx, vpm, W, args.cascade_steps, args.seed)
         if not args.no_fp64:
-            extra["precision_sweep"] = precision_sweep(ctx, vpm, W, [128, 512, 2048], args.seed)
+            extra["precision_sweep"] = precision_sweep(ctx, vpm, W, [128, 256, 512, 1024, 2048], args.seed)
 
     # The ALU side of the dominant kernel: issued VALU instructions (committed counter run) against
     # the VALU issue peak, and the algorithmic integer work (particle-levels of its cells, from the
@@ -690,6 +908,7 @@ def main():
         "conservation": cons32,
         "merged_cv": cv32,
         "plain_fp64": plain,
+        "fp64_input": fp64_in,
         "device_flags": flags,
         "workloads": extra,
     }

@@ -663,45 +663,54 @@ VPM_DEV int compact_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int lid
         const int w = *(const int32_t*)(cbase + (uint32_t)i * cstride);
         return cshift < 0 ? w : ((w << cshift) >> 16);
     };
-    // software-pipelined: the code of the next position and the index of the one after it are loaded
-    // while the current position is placed (reads past the subset's end repeat its last slot)
+    // Batches of CB rounds: the indices of a batch are loaded together, then their codes, before
+    // any is used (two LDS round trips per batch instead of a dependent pair per round; positions
+    // past the subset's end repeat its last slot and store nothing).
+    constexpr int CB = 4;
     const IdxT* sp = src + start;
     const int last = len - 1;
-    IdxT i_nxt = sp[min(g + lid, last)];
-    IdxT i_cur = sp[min(lid, last)];
-    int cv_cur = code_of(i_cur);
     int lb = 0, rb = 0;
     if (solo) {
         // every group of the round is a single lane (a wave-uniform fact): no ranks to exchange
-        for (int j = 0; j < len; ++j) {
-            const IdxT i = i_cur;
-            const int cv = cv_cur;
-            i_cur = i_nxt;
-            cv_cur = code_of(i_nxt);
-            i_nxt = sp[min(j + 2, last)];
-            const bool right = cv > thr;
-            dst[start + (right ? last - rb : lb)] = i;
-            rb += right ? 1 : 0;
-            lb += right ? 0 : 1;
+        for (int j0 = 0; j0 < len; j0 += CB) {
+            IdxT ix[CB];
+            int cv[CB];
+#pragma unroll
+            for (int u = 0; u < CB; ++u) ix[u] = sp[min(j0 + u, last)];
+#pragma unroll
+            for (int u = 0; u < CB; ++u) cv[u] = code_of(ix[u]);
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                if (j0 + u >= len) break;
+                const bool right = cv[u] > thr;
+                dst[start + (right ? last - rb : lb)] = ix[u];
+                rb += right ? 1 : 0;
+                lb += right ? 0 : 1;
+            }
         }
     } else
-    for (int j0 = 0; j0 < len; j0 += g) {
-        const int j = j0 + lid;
-        const bool act = j < len;
-        const IdxT i = i_cur;
-        const int cv = cv_cur;
-        i_cur = i_nxt;
-        cv_cur = code_of(i_nxt);
-        i_nxt = sp[min(j + 2 * g, last)];
-        // the active lanes of a group are a prefix of it: an active lane has lid active lanes
-        // below it in the group, and the group has min(g, len - j0) active lanes
-        const bool right = cv > thr;
-        const uint64_t bra = __ballot(act && right) & gmask;            // this group's lanes only
-        const int rr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bra >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bra, 0u));
-        if (act) dst[start + (right ? len - 1 - (rb + rr) : lb + (lid - rr))] = i;
-        const int nr = __popcll(bra);
-        lb += min(g, len - j0) - nr;
-        rb += nr;
+    for (int j0 = 0; j0 < len; j0 += CB * g) {
+        IdxT ix[CB];
+        int cv[CB];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) ix[u] = sp[min(j0 + u * g + lid, last)];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) cv[u] = code_of(ix[u]);
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            const int jb = j0 + u * g;                          // the round's first position (group-uniform)
+            if (jb >= len) break;
+            // the active lanes of a group are a prefix of it: an active lane has lid active lanes
+            // below it in the group, and the group has min(g, len - jb) active lanes
+            const bool act = jb + lid < len;
+            const bool right = cv[u] > thr;
+            const uint64_t bra = __ballot(act && right) & gmask;            // this group's lanes only
+            const int rr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bra >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bra, 0u));
+            if (act) dst[start + (right ? len - 1 - (rb + rr) : lb + (lid - rr))] = ix[u];
+            const int nr = __popcll(bra);
+            lb += min(g, len - jb) - nr;
+            rb += nr;
+        }
     }
     wave_fence();
     return lb;
@@ -1334,6 +1343,56 @@ VPM_DEV bool cell_frame_block(const SoaIn<InT>& in, int64_t off, int n, double m
     }
 }
 
+// The whole cell in registers: thread t holds positions t, t + NT, ..., t + (RP - 1) NT (clamped to
+// the last one past the end).  All the loads are issued before any is used, so that the cell costs
+// one memory round trip; the frame and the codes are then formed from the registers.
+template <int RP, int NT, typename InT>
+VPM_DEV void load_cell_regs(const SoaIn<InT>& in, int64_t off, int n, int t, float (&q)[RP][7]) {
+    const InT* const b[7] = {in.x + off, in.y + off, in.z + off, in.px + off, in.py + off, in.pz + off, in.w + off};
+#pragma unroll
+    for (int u = 0; u < RP; ++u) {
+        const uint32_t i = (uint32_t)min(t + u * NT, n - 1);
+#pragma unroll
+        for (int f = 0; f < 7; ++f) q[u][f] = (float)b[f][i];            // FP64: rounded to nearest
+    }
+}
+
+// Step 1 from a cell held in registers (load_cell_regs); all threads of the cell call.
+template <int WPB, int RP>
+VPM_DEV bool cell_frame_regs(const float (&q)[RP][7], int n, int t, double mass, Frame& F, BlockScratch<WPB>* bs) {
+    constexpr int NT = WAVE * WPB;
+    FrameAcc acc;
+    facc_init(acc);
+#pragma unroll
+    for (int u = 0; u < RP; ++u)
+        if (t + u * NT < n) facc_add(acc, q[u]);
+    if constexpr (WPB == 1) {
+        return frame_of_wave(acc, mass, F);
+    } else {
+        const int wv = threadIdx.x / WAVE;
+        const bool bad = __ballot(acc.bad) != 0;
+#pragma unroll
+        for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
+        if (lane_id() == 0) {
+            bs->bad[wv] = bad;
+            for (int r = 0; r < 11; ++r) bs->fmax[wv][r] = acc.v[r];
+        }
+        __syncthreads();
+        bool any_bad = false;
+        float v[11];
+        for (int r = 0; r < 11; ++r) v[r] = bs->fmax[0][r];
+        for (int w = 0; w < WPB; ++w) {
+            any_bad |= bs->bad[w] != 0;
+            for (int r = 0; r < 11; ++r) v[r] = fmaxf(v[r], bs->fmax[w][r]);
+        }
+        __syncthreads();                                   // the scratch is reused below
+        if (any_bad) return false;
+        frame_from(v, mass, F);
+        F.amask = __builtin_amdgcn_readfirstlane(F.amask);
+        return true;
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Replacement from a given partition (vpm_merge): one wavefront per cell, one lane per subset.
 // ------------------------------------------------------------------------------------------
@@ -1471,7 +1530,7 @@ VPM_DEV void encode_particle(const CellMem<IdxT>& M, const FixedParams& P, const
 // over the cell's slots gives leaf ordinals and output slots; copied particles go to the staging
 // arrays, merged subsets are replaced (Step 7).  In partition mode the permutation and subset
 // ordinals are written instead.  leaf_start (n + 1 entries), mlist and msched (n each) are scratch.
-template <int WPB, typename IdxT, typename Args>
+template <int WPB, typename IdxT, typename Args, int RP = 0>
 VPM_DEV void cell_output(const CellMem<IdxT>& M, const Args& A, const Frame& F, int c, int64_t off, int n,
                          BlockScratch<WPB>* bs, IdxT* leaf_start, IdxT* mlist, IdxT* msched) {
     constexpr int NT = WAVE * WPB;
@@ -1535,11 +1594,38 @@ VPM_DEV void cell_output(const CellMem<IdxT>& M, const Args& A, const Frame& F, 
     }
     // copied particles (subsets below min_subset): the cell's arrays from wave-uniform base
     // pointers with 32-bit lane offsets (no 64-bit address arithmetic per access)
-    {
-        const typename Args::In* const ib[7] = {A.in.x + off, A.in.y + off, A.in.z + off, A.in.px + off,
-                                                A.in.py + off, A.in.pz + off, A.in.w + off};
-        float* const ob[7] = {A.tmp.x + off, A.tmp.y + off, A.tmp.z + off, A.tmp.px + off,
-                              A.tmp.py + off, A.tmp.pz + off, A.tmp.w + off};
+    const typename Args::In* const ib[7] = {A.in.x + off, A.in.y + off, A.in.z + off, A.in.px + off,
+                                            A.in.py + off, A.in.pz + off, A.in.w + off};
+    float* const ob[7] = {A.tmp.x + off, A.tmp.y + off, A.tmp.z + off, A.tmp.px + off,
+                          A.tmp.py + off, A.tmp.pz + off, A.tmp.w + off};
+    if constexpr (RP > 0) {
+        // An LDS cell (at most RP positions per thread): every input particle is read once, in
+        // input order (coalesced, the whole cell's loads in flight together), and stored to its
+        // output slot.  inv maps an input position to that slot (0xffff: merged); the codes' pyz
+        // array is free by now.
+        static_assert(sizeof(IdxT) == 2, "slots of an LDS cell are 16-bit");
+        uint16_t* inv = (uint16_t*)M.pyz;
+        for (int p = tid; p < n; p += NT) {
+            const uint8_t inf = M.info[p];
+            inv[idx_buf(M, inf & INF_PARITY)[p]] = (inf & INF_MERGED) ? (uint16_t)0xffff : (uint16_t)M.emit[p];
+        }
+        cell_sync<WPB>();
+        float v[RP][7];
+#pragma unroll
+        for (int u = 0; u < RP; ++u) {
+            const uint32_t i = (uint32_t)min(tid + u * NT, n - 1);
+#pragma unroll
+            for (int f = 0; f < 7; ++f) v[u][f] = (float)ib[f][i];
+        }
+#pragma unroll
+        for (int u = 0; u < RP; ++u) {
+            const int i = tid + u * NT;
+            const uint32_t so = i < n ? inv[i] : 0xffffu;
+            if (so == 0xffffu) continue;
+#pragma unroll
+            for (int f = 0; f < 7; ++f) ob[f][so] = v[u][f];
+        }
+    } else {
         for (int p0 = tid; p0 < n; p0 += COPY_BATCH * NT) {
             uint32_t si[COPY_BATCH], so[COPY_BATCH];
             bool keep[COPY_BATCH];
@@ -1607,6 +1693,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgsT<InT> A
     const int wv = tid / WAVE;
     constexpr int NT = WAVE * WPB;
     constexpr size_t HDR = header_bytes<WPB>();
+    constexpr int RP = (NMAX + NT - 1) / NT;       // positions per thread of a whole cell
     static_assert(IN_LDS, "cells above the LDS bins go to k_fixed_big");
     CellMem<IdxT> M = carve<IdxT>(smem + HDR, NMAX);
     M.sh = (CellShared*)smem;
@@ -1642,9 +1729,11 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgsT<InT> A
         const int lane = opaque_lane();
         const int tid = WPB == 1 ? lane : opaque_tid();
 
-        // ---- Step 1: collect the cell, validate, frame ----
+        // ---- Step 1: collect the cell (into registers: RP positions per thread), validate, frame ----
         Frame F;
-        const bool valid = cell_frame_block<WPB>(A.in, off, n, cell_mass(A.P.mass, A.P.species, A.P.species_mass, c), F, bs);
+        float q[RP][7];
+        load_cell_regs<RP, NT>(A.in, off, n, tid, q);
+        const bool valid = cell_frame_regs<WPB, RP>(q, n, tid, cell_mass(A.P.mass, A.P.species, A.P.species_mass, c), F, bs);
         if (!valid) {
             if (tid == 0) {
                 atomicOr(A.flags, FLAG_BAD_VALUE);
@@ -1663,8 +1752,9 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgsT<InT> A
         FSums R;
         fsums_zero(R);
         bool oob = false;
-        auto encode = [&](int i, const float* q) { encode_particle(M, A.P, F, i, q, R, oob); };
-        load_particles(A.in, off, tid, n, NT, [&](int i, const float* q, bool ok) { if (ok) encode(i, q); });
+#pragma unroll
+        for (int u = 0; u < RP; ++u)
+            if (tid + u * NT < n) encode_particle(M, A.P, F, tid + u * NT, q[u], R, oob);
         const bool any_oob = __ballot(oob) != 0;
         fsums_group_reduce(R, WAVE);
         if constexpr (WPB > 1) {
@@ -1730,7 +1820,8 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgsT<InT> A
         }
 
         // ---- output ----
-        cell_output<WPB, IdxT>(M, A, F, c, off, n, bs, (IdxT*)M.nodes0, (IdxT*)M.nodes1, (IdxT*)M.rec);
+        cell_output<WPB, IdxT, FixedArgsT<InT>, RP>(M, A, F, c, off, n, bs, (IdxT*)M.nodes0, (IdxT*)M.nodes1,
+                                                    (IdxT*)M.rec);
         if constexpr (WPB == 1) wave_fence();
     }
 }

@@ -22,11 +22,13 @@ def _next_input(wl, ref, params):
                       params=dict(params)).astype(np.float32)
 
 
-@pytest.mark.parametrize("tol_p,steps", [(0.02, 6), (0.3, 5)])
+@pytest.mark.parametrize("tol_p,steps", [(0.02, 6), (0.3, 5), (0.6, 50)])
 def test_cascade_graph_replays(tol_p, steps):
     """tol_p 0.02 (the shower's tolerance) splits almost every subset down to single particles, so
     the population doubles up to cells of 16,384 (the global-slab bin); tol_p 0.3 merges, so the
-    population size and the cell sizes (1,800 to 2,500 particles) change between replays."""
+    population size and the cell sizes (1,800 to 2,500 particles) change between replays; tol_p 0.6
+    (the benchmark's cascade) holds the cells near N_min = 1,024 over 50 events (merged cells fall
+    to a few hundred particles and grow back), every event checked on every cell."""
     wl = W.cascade_initial(nx=NX, ny=NX, seed=4)
     params = dict(wl.params, tol_p=tol_p)
     n_cells = wl.n_cells

@@ -248,6 +248,40 @@ def test_fp64_path_two_stream():
     assert _fp64_check(wl, wl.params) <= 2
 
 
+def test_fp64_path_two_stream_full_size_sampled():
+    """The plain FP64 form on the whole 256 x 256 Poisson(512) two-stream population (33.5M particles,
+    FP64, the population the benchmark times it on), 300 sampled cells against the PAPER oracle run
+    on those cells alone: subset membership identical except in cells with a certified near-tie
+    (oracle margin below 1e-9), merged particles to 1e-12."""
+    wl = W.two_stream_grid(seed=0)
+    params = dict(wl.params)
+    r = np.random.Generator(np.random.Philox(13))
+    sample = np.sort(r.choice(wl.n_cells, 300, replace=False))
+    perm, sid, nsub = gpu_partition(wl, params, decide=vpm.VPM_DECIDE_FP64)
+    got, got_off, _ = gpu_run(wl, params, decide=vpm.VPM_DECIDE_FP64)
+    sub = wl.cells(sample)
+    ref = oracle.run_workload(sub, decide=oracle.PAPER, **oracle_params(params))
+    good, near = [], 0
+    for k, c in enumerate(sample):
+        lo, hi = int(wl.cell_off[c]), int(wl.cell_off[c + 1])
+        slo = int(sub.cell_off[k])
+        same = (nsub[c] == ref.n_subsets[k] and
+                np.array_equal(perm[lo:hi] - lo, ref.perm[slo:slo + hi - lo] - slo) and
+                np.array_equal(sid[lo:hi], ref.subset_id[slo:slo + hi - lo]))
+        if not same:
+            assert ref.stats["min_margin"][k] < 1e-9, f"cell {c} differs without a near-tie"
+            near += 1
+            continue
+        assert got_off[c + 1] - got_off[c] == ref.out_off[k + 1] - ref.out_off[k]
+        good.append(k)
+    assert near <= 3
+    cells = sample[good]
+    rsub = oracle.run_workload(sub.cells(good), decide=oracle.PAPER, **oracle_params(params))
+    sel = np.concatenate([np.arange(got_off[c], got_off[c + 1]) for c in cells])
+    check_merged_values(sub.cells(good), params, vpm.VPM_MERGE_PAIR, {f: got[f][sel] for f in FIELDS},
+                        rsub.out_off, rsub, rel=1e-12)
+
+
 GOLDEN = ["px_bisection_6.txt", "corners_tie_4.txt", "px_ladder_8.txt", "pair_direction_2.txt",
           "pair_two_clusters_4.txt", "axis_rule_normalised_4.txt", "axis_rule_raw_4.txt"]
 
