@@ -658,10 +658,12 @@ VPM_DEV int compact_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int lid
     const bool kpyz = k == 1 || k == 2;
     const uint8_t* cbase = kpyz ? (const uint8_t*)M.pyz : (const uint8_t*)M.rec + (k == 0 ? 12 : 4 * (k - 3));
     const uint32_t cstride = kpyz ? 4u : 16u;
-    const int cshift = k == 1 ? 16 : (k == 0 || k == 2) ? 0 : -1;   // left shift before >> 16; -1: whole
+    // one signed bit-field extract: bits [16, 32) for x and z, [0, 16) for y, [0, 24) for a momentum
+    // code (|code| <= 2^22)
+    const uint32_t boff = (k == 0 || k == 2) ? 16u : 0u, bwid = k < 3 ? 16u : 24u;
     auto code_of = [&](IdxT i) {
         const int w = *(const int32_t*)(cbase + (uint32_t)i * cstride);
-        return cshift < 0 ? w : ((w << cshift) >> 16);
+        return __builtin_amdgcn_sbfe(w, boff, bwid);
     };
     // Batches of CB rounds: the indices of a batch are loaded together, then their codes, before
     // any is used (two LDS round trips per batch instead of a dependent pair per round; positions
