@@ -139,12 +139,14 @@ VPM_DEV int opaque_tid() {
 // one of the other half of its 8- or 16-lane block (equivalent to xor for a sum, because after the
 // earlier steps every lane of a half holds the same partial); step 16 is a swizzle with xor 16;
 // step 32 a cross-half permute.  Every partner lies in the caller's group, so it is active.
+// (mov_dpp rather than update_dpp: every lane's source is valid, so no "old" value has to be
+// materialised in the destination first, one VALU move less per exchange.)
 template <int M>
 VPM_DEV int xchg32(int v) {
-    if constexpr (M == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
-    else if constexpr (M == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
-    else if constexpr (M == 4) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
-    else if constexpr (M == 8) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+    if constexpr (M == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (M == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (M == 4) return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);
+    else if constexpr (M == 8) return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);
     else if constexpr (M == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);
     else return __shfl_xor(v, 32);
 }

@@ -209,6 +209,8 @@ struct DecideConsts {
                                             // normalised 1 / T^2, +infinity for T = 0)
     uint64_t thx2, thp2;                    // That_x^2, That_p^2 (Step 3, exact)
     uint64_t tx2, tp2;                      // Step 4 exact weights: 1, or That^2 (normalised rule)
+    int32_t norm;                           // the normalised rule (else the weights are 1)
+    int32_t pad;
 };
 
 VPM_DEV DecideConsts decide_consts(const FixedParams& P) {
@@ -223,6 +225,8 @@ VPM_DEV DecideConsts decide_consts(const FixedParams& P) {
     K.thp2 = P.that_p * P.that_p;
     K.tx2 = P.tx2;
     K.tp2 = P.tp2;
+    K.norm = norm ? 1 : 0;
+    K.pad = 0;
     return K;
 }
 
@@ -355,14 +359,16 @@ VPM_DEV Decision decide_fast(const FSums& S, int len, const DecideConsts& K, con
         d.jdir = pair_axis(S.s1, F);
         return d;
     }
-    // Step 4 on the weighted CVs: unit weights (raw rule, exact), or outward FP32 brackets of
-    // 1 / T^2 (normalised rule: each product rounds by at most 2^-24, inside the brackets' 2^-22
-    // margin); an infinite weight (zero tolerance) makes any CV > 0 infinite
+    // Step 4 on the weighted CVs: under the normalised rule, outward FP32 brackets of 1 / T^2 (each
+    // product rounds by at most 2^-24, inside the brackets' 2^-22 margin); an infinite weight (zero
+    // tolerance) makes any CV > 0 infinite.  The raw rule's weights are 1.
+    if (__builtin_amdgcn_readfirstlane(K.norm)) {
 #pragma unroll
-    for (int l = 0; l < 6; ++l) {
-        const bool pos = l < 3;
-        lo[l] = lo[l] > 0.0f ? lo[l] * (pos ? K.wx_lo : K.wp_lo) : 0.0f;
-        hi[l] = hi[l] > 0.0f ? hi[l] * (pos ? K.wx_hi : K.wp_hi) : 0.0f;
+        for (int l = 0; l < 6; ++l) {
+            const bool pos = l < 3;
+            lo[l] = lo[l] > 0.0f ? lo[l] * (pos ? K.wx_lo : K.wp_lo) : 0.0f;
+            hi[l] = hi[l] > 0.0f ? hi[l] * (pos ? K.wx_hi : K.wp_hi) : 0.0f;
+        }
     }
     int k = 0;
     float best = lo[0];
