@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
 #pragma unroll
     for (int L = 0; L < NL; ++L) {
         const bool mine = L < Q_COUNT ? cls == L : big == L - Q_COUNT;
-        const uint64_t m = __ballot(mine);
+        const uint64_t m = ballot(mine);
         if (m == 0) continue;
         const int leader = __ffsll((unsigned long long)m) - 1;
         int wbase = 0;

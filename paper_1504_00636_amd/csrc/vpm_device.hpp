@@ -115,6 +115,11 @@ VPM_DEV int cmp320(const U320& a, const U320& b) {
 
 VPM_DEV int lane_id() { return __lane_id(); }
 
+// Wave ballot of a boolean.  (HIP's __ballot takes an int, and the int -> bool test it adds is
+// compiled as a move of the condition into a vector register and a compare back: two VALU
+// instructions per ballot that the boolean form does not need.)
+VPM_DEV uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 VPM_DEV uint64_t lanes_below_of(int l) {         // bit mask of the lanes below lane l
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }

@@ -688,12 +688,12 @@ VPM_DEV int compact_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int lid
 #pragma unroll
             for (int u = 0; u < CB; ++u) cv[u] = code_of(ix[u]);
 #pragma unroll
-            for (int u = 0; u < CB; ++u) {
-                if (j0 + u >= len) break;
+            for (int u = 0; u < CB; ++u) {                      // predicated: no branch per round
+                const bool act = j0 + u < len;
                 const bool right = cv[u] > thr;
-                dst[start + (right ? last - rb : lb)] = ix[u];
-                rb += right ? 1 : 0;
-                lb += right ? 0 : 1;
+                if (act) dst[start + (right ? last - rb : lb)] = ix[u];
+                rb += (act && right) ? 1 : 0;
+                lb += (act && !right) ? 1 : 0;
             }
         }
     } else
@@ -707,16 +707,16 @@ VPM_DEV int compact_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int lid
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
             const int jb = j0 + u * g;                          // the round's first position (group-uniform)
-            if (jb >= len) break;
             // the active lanes of a group are a prefix of it: an active lane has lid active lanes
-            // below it in the group, and the group has min(g, len - jb) active lanes
+            // below it in the group, and the group has max(0, min(g, len - jb)) active lanes
+            // (rounds past the end are predicated off rather than left by a branch)
             const bool act = jb + lid < len;
             const bool right = cv[u] > thr;
-            const uint64_t bra = __ballot(act && right) & gmask;            // this group's lanes only
+            const uint64_t bra = ballot(right) & ballot(act) & gmask;            // this group's lanes only
             const int rr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bra >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bra, 0u));
             if (act) dst[start + (right ? len - 1 - (rb + rr) : lb + (lid - rr))] = ix[u];
             const int nr = __popcll(bra);
-            lb += min(g, len - jb) - nr;
+            lb += max(0, min(g, len - jb)) - nr;
             rb += nr;
         }
     }
@@ -765,7 +765,7 @@ VPM_DEV int compact_sum_node(const CellMem<IdxT>& M, Node<IdxT> nd, int cur, int
                 lb += right ? 0 : 1;
             } else {
                 act = jb + lid < len;
-                const uint64_t bra = __ballot(act && right) & gmask;
+                const uint64_t bra = ballot(right) & ballot(act) & gmask;
                 const int rr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bra >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bra, 0u));
                 if (act) dst[start + (right ? len - 1 - (rb + rr) : lb + (lid - rr))] = ix[u];
@@ -1045,12 +1045,12 @@ VPM_DEV void inherit_levels(const CellMem<IdxT>& M, const Args& A, const Frame& 
     for (int l = 0; l < 6; ++l) E2[l] = R.s2[l] * ((double)(n + 16) * 0x1p-51);
     int g = WAVE;
     for (; g >= 2; g >>= 1) {
-        if (__ballot(act && (int)nd.len > INHERIT_PPL * g) != 0) break;
+        if (ballot(act && (int)nd.len > INHERIT_PPL * g) != 0) break;
         if (act) split_inherit(M, A, F, nd, act, P, E2, cur, lane & (g - 1), g, lane & ~(g - 1));
         wave_fence();
         cur ^= 1;
     }
-    if (g == 1 && __ballot(act && (int)nd.len > INHERIT_PPL) == 0) {
+    if (g == 1 && ballot(act && (int)nd.len > INHERIT_PPL) == 0) {
         if (lane == 0) M.sh->nnext = 0;
         wave_fence();
         if (act) split_inherit_solo(M, A, F, nd, P, E2, cur, cur ? M.nodes0 : M.nodes1);
@@ -1062,7 +1062,7 @@ VPM_DEV void inherit_levels(const CellMem<IdxT>& M, const Args& A, const Frame& 
     // the unfinished subsets, one per group of g lanes, to the scheduled levels
     Node<IdxT>* list = cur ? M.nodes1 : M.nodes0;
     const bool lead = act && (lane & (g - 1)) == 0;
-    const uint64_t b = __ballot(lead);
+    const uint64_t b = ballot(lead);
     if (lead) list[__popcll(b & lanes_below_of(lane))] = nd;
     m = __popcll(b);
     wave_fence();
@@ -1301,7 +1301,7 @@ VPM_DEV void frame_from(const float v[11], double mass, Frame& F) {
 // The frame of a cell from the accumulators of a whole wavefront.  Returns false if some weight is
 // not positive or some value is not finite.
 VPM_DEV bool frame_of_wave(FrameAcc& acc, double mass, Frame& F) {
-    if (__ballot(acc.bad) != 0) return false;
+    if (ballot(acc.bad) != 0) return false;
 #pragma unroll
     for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
     frame_from(acc.v, mass, F);
@@ -1328,7 +1328,7 @@ VPM_DEV bool cell_frame_block(const SoaIn<InT>& in, int64_t off, int n, double m
         FrameAcc acc;
         facc_init(acc);
         facc_cell(acc, in, off, threadIdx.x, n, WAVE * WPB);
-        const bool bad = __ballot(acc.bad) != 0;
+        const bool bad = ballot(acc.bad) != 0;
 #pragma unroll
         for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
         if (lane_id() == 0) {
@@ -1378,7 +1378,7 @@ VPM_DEV bool cell_frame_regs(const float (&q)[RP][7], int n, int t, double mass,
         return frame_of_wave(acc, mass, F);
     } else {
         const int wv = threadIdx.x / WAVE;
-        const bool bad = __ballot(acc.bad) != 0;
+        const bool bad = ballot(acc.bad) != 0;
 #pragma unroll
         for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
         if (lane_id() == 0) {
@@ -1439,7 +1439,7 @@ __global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs<InT> G) {
             ok = m >= off && m < off + n && sd >= 0 && sd < nsub && (sd == prev || sd == prev + 1) &&
                  (p != n - 1 || sd == nsub - 1);
         }
-        bool part_ok = __ballot(!ok) == 0;
+        bool part_ok = ballot(!ok) == 0;
         if (part_ok) {
             // every member exactly once: each slot writes its position at its member's mark, then
             // checks that the mark holds it (of two slots naming one member only one can pass, and
@@ -1450,7 +1450,7 @@ __global__ __launch_bounds__(WAVE) void k_fixed_merge(MergeArgs<InT> G) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             bool once = true;
             for (int p = lane; p < n; p += WAVE) once = once && G.marks[G.perm[off + p]] == (int32_t)(off + p);
-            part_ok = __ballot(!once) == 0;
+            part_ok = ballot(!once) == 0;
         }
         Frame F;
         const bool vals_ok = part_ok && cell_frame(A.in, off, n, cell_mass(A.P.mass, A.P.species, A.P.species_mass, c), F);
@@ -1763,7 +1763,7 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgsT<InT> A
 #pragma unroll
         for (int u = 0; u < RP; ++u)
             if (tid + u * NT < n) encode_particle(M, A.P, F, tid + u * NT, q[u], R, oob);
-        const bool any_oob = __ballot(oob) != 0;
+        const bool any_oob = ballot(oob) != 0;
         fsums_group_reduce(R, WAVE);
         if constexpr (WPB > 1) {
             if (lane == 0) {
@@ -2026,7 +2026,7 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
             load_particles(A.in, off, tid, n, NT, [&](int i, const float* q, bool ok) {
                 if (ok) encode_particle(M, A.P, F, i, q, R, oob);
             });
-            const bool any_oob = __ballot(oob) != 0;
+            const bool any_oob = ballot(oob) != 0;
             fsums_group_reduce(R, WAVE);
             if (lane == 0) {
                 bs->sums[wv][0] = R.s0;
@@ -2160,7 +2160,7 @@ VPM_DEV void small_root(const CellMem<uint16_t>& M, const Args& A, SmallShared& 
     FrameAcc acc;
     facc_init(acc);
     facc_cell(acc, A.in, off, lid, n, g);
-    if ((__ballot(acc.bad) & gm) != 0) {
+    if ((ballot(acc.bad) & gm) != 0) {
         if (lid == 0) ss.cflags[j] = FLAG_BAD_VALUE;
         for (int p = lid; p < n; p += g) M.info[b + p] = INF_SKIP;
         return;
@@ -2177,7 +2177,7 @@ VPM_DEV void small_root(const CellMem<uint16_t>& M, const Args& A, SmallShared& 
         if (ok) encode_particle(M, A.P, F, b + p, q, R, oob);
     });
     fsums_group_reduce(R, g);
-    if ((__ballot(oob) & gm) != 0 && lid == 0) atomicOr(&ss.cflags[j], FLAG_OUT_OF_CELL);
+    if ((ballot(oob) & gm) != 0 && lid == 0) atomicOr(&ss.cflags[j], FLAG_OUT_OF_CELL);
     wave_fence();
     int dv = 0;
     if (lid == 0) {

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(64) void k_fp64_cells(Fp64Args A) {
             ok = ok && w > 0.0 && isfinite(w);
             for (int l = 0; l < 6; ++l) ok = ok && isfinite(qval(A.in, l, off + i));
         }
-        if (__ballot(!ok) != 0) {
+        if (ballot(!ok) != 0) {
             if (lane == 0) {
                 atomicOr(A.flags, FLAG_BAD_VALUE);
                 if (A.mode == 0) { A.out_count[c] = n; A.cell_mode[c] = CELL_UNTOUCHED; }
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(64) void k_fp64_cells(Fp64Args A) {
                             int32_t li = 0;
                             bool right = false;
                             if (act) { li = src[start + j]; right = !(qval(A.in, k, off + li) <= Q); }
-                            const uint64_t bl = __ballot(act && !right), br = __ballot(act && right);
+                            const uint64_t bl = ballot(act && !right), br = ballot(act && right);
                             if (act) {
                                 const int d = right ? n1 + rb + __popcll(br & lanes_below()) : lb + __popcll(bl & lanes_below());
                                 dst[start + d] = li;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(64) void k_fp64_merge(Fp64MergeArgs G) {
                  (p != n - 1 || sd == nsub - 1) && wv > 0.0 && isfinite(wv);
             for (int l = 0; ok && l < 6; ++l) ok = isfinite(qval(A.in, l, mm));
         }
-        bool part_ok = __ballot(!ok) == 0;
+        bool part_ok = ballot(!ok) == 0;
         if (part_ok) {
             // every member exactly once: each slot writes its position at its member's mark (the
             // first permutation buffer serves as the marks), then checks that the mark holds it
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(64) void k_fp64_merge(Fp64MergeArgs G) {
             fence_wave();
             bool once = true;
             for (int p = lane; p < n; p += WAVE) once = once && A.perm2[G.perm[off + p]] == (int32_t)(off + p);
-            part_ok = __ballot(!once) == 0;
+            part_ok = ballot(!once) == 0;
         }
         if (!part_ok) {
             if (lane == 0) {
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(64) void k_fp64_merge(Fp64MergeArgs G) {
             while (e < n) {
                 const int j = e + lane;
                 const bool same = j < n && G.subset_id[off + j] == sd;
-                const uint64_t notsame = __ballot(!same);
+                const uint64_t notsame = ballot(!same);
                 if (notsame != 0) { e += __ffsll((unsigned long long)notsame) - 1; break; }
                 e += WAVE;
             }
