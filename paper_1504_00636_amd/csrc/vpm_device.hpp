@@ -167,7 +167,7 @@ template <int M>
 VPM_DEV double xor_dbl(double v) {
     const int64_t u = __double_as_longlong(v);
     auto x = [](int w) {
-        if constexpr (M >= 32) return xchg32<M>(w);
+        if constexpr (M >= 32 || M <= 2) return xchg32<M>(w);         // xor 1, 2: DPP quad permutes, exact
         else return xor32<M>(w);
     };
     const int lo = x((int)(uint32_t)u), hi = x((int)((uint64_t)u >> 32));
