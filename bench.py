@@ -796,6 +796,23 @@ def main():
                        kernels={k: round(v["avg_ms"], 4) for k, v in k64i.items()})
         log(f"[bench] fixed-point from FP64 input: {ms64i:.3f} ms/step, output equal to the FP32 run: {same}")
         del arrs64, out64i
+    # The same event with every decision taken by the exact integer rule (the certified FP64
+    # evaluation skipped): its output must equal the fast form's bit for bit.
+    exact_check = None
+    if not args.no_extra:
+        saved = ctx.get_tuning()
+        t = vpm.make_tuning(**{k: v for k, v in saved.as_dict().items() if k != "exact_decisions"}, exact_decisions=1)
+        ctx.set_tuning(t)
+        try:
+            msx, outx, oox, nx, _, _ = time_fixed(ctx, vpm, arrs32, off, n, p32, 2, 1, False)
+        finally:
+            ctx.set_tuning(saved)
+        same = nx == n_out and torch.equal(oox, out_off) and all(
+            torch.equal(a[:n_out].view(torch.int32), b[:n_out].view(torch.int32)) for a, b in zip(outx, out32))
+        exact_check = dict(ms_per_step=msx, output_equals_fast_form=bool(same),
+                           note="every Step 3-5 decision by the exact 128/256/320-bit rule")
+        log(f"[bench] exact decisions everywhere: {msx:.3f} ms/step, output equal: {same}")
+        del outx
     del out32
     torch.cuda.empty_cache()
 
@@ -909,6 +926,7 @@ def main():
         "merged_cv": cv32,
         "plain_fp64": plain,
         "fp64_input": fp64_in,
+        "exact_decisions_check": exact_check,
         "device_flags": flags,
         "workloads": extra,
     }

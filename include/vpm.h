@@ -202,7 +202,12 @@ vpm_status vpm_blind(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
  * a subset of len particles is handled by a group of about len / ppl lanes (ppl = 8, 16 or 32;
  * at most 64 lanes).  Limits must satisfy 1 <= bin_a_max <= bin_b_max <= bin_c_max.
  * concurrent_bins = 1 runs the four bins at once on the context's side streams (forked from and
- * joined back to the caller's stream), 0 runs them one after another on the caller's stream.    */
+ * joined back to the caller's stream), 0 runs them one after another on the caller's stream.
+ * exact_decisions = 1 takes every Step 3-5 decision of the fixed-point path by the exact integer
+ * rule (Sec. "Algorithm", Steps 3-5, on 128/256/320-bit moments recomputed from the codes) instead
+ * of first trying the certified FP64 evaluation: slower, and by construction the same result; it
+ * exists to cross-check that evaluation on whole populations.  0 (the default) is the fast form.
+ * The autotuner keeps the value it finds in the context.                                         */
 typedef struct {
     int32_t ppl;
     int32_t bin_a_max;
@@ -210,6 +215,7 @@ typedef struct {
     int32_t bin_c_max;
     int32_t concurrent_bins;
     int32_t bin_s_max;
+    int32_t exact_decisions;
 } vpm_tuning;
 
 /* Host-only validation of a tuning block (no device needed). */

@@ -210,7 +210,7 @@ struct DecideConsts {
     uint64_t thx2, thp2;                    // That_x^2, That_p^2 (Step 3, exact)
     uint64_t tx2, tp2;                      // Step 4 exact weights: 1, or That^2 (normalised rule)
     int32_t norm;                           // the normalised rule (else the weights are 1)
-    int32_t pad;
+    int32_t force_exact;                    // skip the FP64 evaluation: every decision exactly
 };
 
 VPM_DEV DecideConsts decide_consts(const FixedParams& P) {
@@ -226,7 +226,7 @@ VPM_DEV DecideConsts decide_consts(const FixedParams& P) {
     K.tx2 = P.tx2;
     K.tp2 = P.tp2;
     K.norm = norm ? 1 : 0;
-    K.pad = 0;
+    K.force_exact = P.force_exact ? 1 : 0;
     return K;
 }
 
@@ -555,7 +555,7 @@ VPM_DEV Decision decide(const CellMem<IdxT>& M, const FSums& S, const IdxT* buf,
     bool ok;
     const DecideConsts& K = M.sh->dc;
     d = decide_fast(S, len, K, F, F.amask, ok, e2);
-    if (__builtin_expect(ok, 1)) return d;          // the exact path below is rare: laid out apart
+    if (__builtin_expect(ok && !K.force_exact, 1)) return d;   // the exact path below is rare: laid out apart
     ISums E;
     E.s0 = 0;
 #pragma unroll

@@ -19,7 +19,7 @@ struct vpm_ctx {
     int cu_count = 0;
     Workspace ws;
     int grid_a = 0, grid_b = 0, grid_c = 0, grid_big = 0, grid_s = 0, grid_fp64 = 0;
-    vpm_tuning tune = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128};
+    vpm_tuning tune = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128, 0};
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     std::string last_error;
@@ -164,6 +164,7 @@ FixedParams fixed_params(const vpm_params* p, const vpm_tuning& t) {
     f.min_subset = p->min_subset;
     f.merge_mode = p->merge_mode;
     f.ppl_shift = ilog2(t.ppl);
+    f.force_exact = t.exact_decisions;
     f.mass = p->mass;
     f.species = nullptr;
     for (int k = 0; k < VPM_MAX_SPECIES; ++k) f.species_mass[k] = p->mass;
@@ -488,6 +489,7 @@ vpm_status vpm_check_tuning(const vpm_tuning* t) {
     if (t->bin_c_max < t->bin_b_max || t->bin_c_max > NMAX_C) return VPM_ERR_INVALID_ARG;
     if (t->concurrent_bins != 0 && t->concurrent_bins != 1) return VPM_ERR_INVALID_ARG;
     if (t->bin_s_max < 0 || t->bin_s_max > SMALL_MAX) return VPM_ERR_INVALID_ARG;
+    if (t->exact_decisions != 0 && t->exact_decisions != 1) return VPM_ERR_INVALID_ARG;
     return VPM_OK;
 }
 
@@ -540,7 +542,7 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
         ms = bestms;
         return VPM_OK;
     };
-    vpm_tuning cur = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128};
+    vpm_tuning cur = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128, was_tuned.exact_decisions};
     float cur_ms = 0.f;
     st = time_cfg(cur, cur_ms);
     // coordinate search: each parameter in turn over its candidates, keeping the others; a second

@@ -76,6 +76,7 @@ struct FixedParams {
     int32_t min_subset;
     int32_t merge_mode;
     int32_t ppl_shift;              // log2 of the target particles per lane of a lane group
+    int32_t force_exact;            // every decision by the exact integer rule (cross-checking)
     double mass;
     const uint8_t* species;         // per-cell species index (null: every cell has `mass`)
     double species_mass[VPM_MAX_SPECIES];

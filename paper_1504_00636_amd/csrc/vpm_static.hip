@@ -146,6 +146,7 @@ extern "C" vpm_status vpm_run_noalloc(const vpm_soa* in, const int64_t* cell_off
     fp.min_subset = p->min_subset;
     fp.merge_mode = p->merge_mode;
     fp.ppl_shift = 4;
+    fp.force_exact = 0;
     fp.mass = p->mass;
     fp.species = nullptr;
     for (int k = 0; k < VPM_MAX_SPECIES; ++k) fp.species_mass[k] = p->mass;

@@ -128,7 +128,45 @@ def test_binding_argument_counts_match_header():
     ((16, 576, 2048, 2047), False), ((16, 576, 2048, 4353), False),
     ((16, 576, 2048, 4352, 1), True), ((16, 576, 2048, 4352, 2), False), ((16, 576, 2048, 4352, -1), False),
     ((16, 576, 2048, 4352, 0, 0), True), ((16, 576, 2048, 4352, 0, 256), True), ((16, 576, 2048, 4352, 0, 257), False),
-    ((16, 576, 2048, 4352, 0, -1), False)])
+    ((16, 576, 2048, 4352, 0, -1), False), ((16, 576, 2048, 4352, 0, 128, 1), True),
+    ((16, 576, 2048, 4352, 0, 128, 2), False), ((16, 576, 2048, 4352, 0, 128, -1), False)])
 def test_check_tuning(t, ok):
     st = vpm.vpm_check_tuning(vpm.make_tuning(*t))
     assert (st == vpm.VPM_OK) == ok, (t, st)
+
+
+def _header_structs():
+    """Field lists of the header's typedef'd structs: name -> [(c type, field, array length)]."""
+    import re
+    text = open(os.path.join(ROOT, "include", "vpm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(\w+)\s*;", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.replace("const", " ").strip()
+            if not decl:
+                continue
+            base, first = re.match(r"(\w+)\s+(.*)$", decl).groups()
+            for item in first.split(","):               # "void *x, *y" declares several
+                m = re.match(r"\s*(\*?)\s*(\w+)\s*(?:\[(\w+)\])?\s*$", item)
+                assert m, decl
+                fields.append((base + (" *" if m.group(1) else ""), m.group(2), m.group(3)))
+        out[name] = fields
+    return out
+
+
+@pytest.mark.parametrize("cname,pyclass", [("vpm_params", "VpmParams"), ("vpm_tuning", "VpmTuning"),
+                                           ("vpm_soa", "VpmSoa")])
+def test_binding_structs_match_header(cname, pyclass):
+    """The ctypes structures have the header's fields, in its order, with matching types and sizes."""
+    hdr = _header_structs()[cname]
+    py = getattr(vpm, pyclass)._fields_
+    assert [f for _, f, _ in hdr] == [f for f, _ in py]
+    ctype = {"int32_t": C.c_int32, "double": C.c_double, "void *": C.c_void_p, "void*": C.c_void_p}
+    for (t, f, n), (pf, pt) in zip(hdr, py):
+        want = ctype[t]
+        if n is not None:
+            assert issubclass(pt, C.Array) and pt._type_ is want and pt._length_ == int(n), f
+        else:
+            assert pt is want, f

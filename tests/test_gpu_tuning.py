@@ -16,7 +16,8 @@ SIZES = [1, 2, 5, 17, 64, 200, 575, 577, 900, 2047, 2049, 3000, 4353, 6000, 300,
          3, 4, 9, 33, 90, 110, 7, 40, 60]
 TUNINGS = [(16, 576, 2048, 4352), (8, 64, 512, 1024, 1), (32, 320, 1024, 2560), (8, 1, 1, 1, 0, 0),
            (32, 576, 576, 576, 1), (16, 100, 2048, 2048), (16, 576, 2048, 4352, 1), (16, 576, 2048, 4352, 0, 0),
-           (8, 576, 2048, 4352, 0, 256), (32, 576, 2048, 4352, 1, 17)]
+           (8, 576, 2048, 4352, 0, 256), (32, 576, 2048, 4352, 1, 17), (16, 576, 2048, 4352, 0, 128, 1),
+           (8, 320, 1024, 2560, 1, 64, 1)]
 
 
 def _run(c, arrs, off, n, p):
@@ -89,3 +90,30 @@ def test_autotune_choice_is_valid_and_exact():
         _same(_run(c, arrs, off, wl.n, p), base)
     finally:
         c.set_tuning(default)
+
+
+@pytest.mark.parametrize("axis_rule", [0, 1])
+def test_exact_rule_everywhere_gives_identical_results(axis_rule):
+    """Every decision taken by the exact integer rule (exact_decisions = 1, the certified FP64
+    evaluation skipped) on populations where the FP64 filter decides nearly everything: the
+    two-stream grid (64 x 64 cells, Poisson(512)) and the shower shape (16^3 cells, every size bin),
+    each at its own tolerances.  Partition and output must equal the fast form's bit for bit."""
+    from paper_1504_00636_amd import workloads as W
+    pops = [W.two_stream_grid(nx=64, ny=64, seed=5).astype(np.float32), W.shower_grid(nc=16, seed=6)]
+    for wl in pops:
+        c = ctx(wl.n, wl.n_cells)
+        default = c.get_tuning()
+        prm = dict(wl.params, axis_rule=axis_rule)
+        p = vpm.make_params(**prm)
+        arrs, off = vpm.upload(wl)
+        try:
+            c.set_tuning(vpm.make_tuning())
+            fast = _run(c, arrs, off, wl.n, p), _partition(c, arrs, off, wl.n, wl.n_cells, p)
+            c.set_tuning(vpm.make_tuning(exact_decisions=1))
+            exact = _run(c, arrs, off, wl.n, p), _partition(c, arrs, off, wl.n, wl.n_cells, p)
+        finally:
+            c.set_tuning(default)
+        _same(exact[0], fast[0])
+        for a, b in zip(exact[1], fast[1]):
+            np.testing.assert_array_equal(a, b)
+        assert c.device_status(clear=True) == 0
