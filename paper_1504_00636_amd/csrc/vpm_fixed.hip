@@ -456,6 +456,14 @@ constexpr int SPAWN_MAX = 64;          // per level: spawned subsets are disjoin
 template <typename IdxT>
 struct SpawnList { int n; Node<IdxT> node[SPAWN_MAX]; };
 
+// A subset handed from one wavefront to another in the inherited top levels of a cell shared by
+// several wavefronts: its node, its moments and their S2 error bound.
+struct Handoff {
+    double P[13];            // S0, S1[6], S2[6]
+    double E2[6];
+    int32_t start, len, thr_axis, act;
+};
+
 // Cross-wave scratch of a cell processed by WPB > 1 wavefronts.
 template <int WPB>
 struct BlockScratch {
@@ -463,6 +471,8 @@ struct BlockScratch {
     int bad[WPB];
     double sums[WPB][13];    // per-wave root moments
     int64_t scan[WPB];       // per-wave totals of the output scan
+    Handoff ho[WPB];         // inherited levels: the subset each wavefront takes over
+    int vote[2][WPB];        // inherited levels: per-wave votes, alternating between levels
 };
 
 template <int WPB>
@@ -1068,7 +1078,173 @@ VPM_DEV void inherit_levels(const CellMem<IdxT>& M, const Args& A, const Frame& 
     wave_fence();
 }
 
-// Copy particles unchanged from the input to the staging arrays.  For positions p = first,
+// A top level of a cell shared by several wavefronts: the wavefront that owns subset nd splits it with
+// all its lanes (compaction, the smaller child's moments, the other's as the parent's minus these, the
+// two children's decisions), keeps V1 and hands V2 to another wavefront through `out` (written by
+// lane 0; out->act stays 0 when V2 is final).  Finished children are recorded by the whole wavefront.
+template <typename IdxT, typename Args>
+VPM_DEV void split_handoff(const CellMem<IdxT>& M, const Args& A, const Frame& F, Node<IdxT>& nd, bool& act,
+                           FSums& P, double (&E2)[6], int cur, Handoff* out) {
+    const int lane = opaque_lane();
+    const int start = nd.start, len = nd.len;
+    const int rev = (nd.thr_axis >> 3) & 1;
+    IdxT* dst = idx_buf(M, cur ^ 1);
+    const int n1 = compact_node(M, nd, cur, lane, WAVE, 0, false);
+    const int n2 = len - n1;
+    act = false;
+    if (n1 == 0 || n2 == 0) {
+        // impossible under the exact rule (the chosen axis has V > 0); end the subset
+        if (lane == 0) atomicOr(&M.sh->flags, FLAG_INTERNAL);
+        Decision d; d.kind = D_MERGED; d.axis = 0; d.thr = 0; d.jdir = 0;
+        record_final(M, A, d, start, len, n1 == 0 ? rev ^ 1 : rev, cur, lane, WAVE);
+        return;
+    }
+    const bool s_first = n1 <= n2;
+    const int ss = s_first ? start : start + n1, sl = s_first ? n1 : n2, ol = len - sl;
+    FSums S;
+    fsums_zero(S);
+    if (ol >= A.P.min_subset) {                           // else both children are copied
+#pragma unroll 2
+        for (int j = lane; j < sl; j += WAVE) {
+            int c[6], om;
+            codes_of(M, dst[ss + j], c, om);
+            fsums_add(S, om, c[0], c[1], c[2], c[3], c[4], c[5]);
+        }
+        fsums_group_reduce(S, WAVE);
+    }
+    double eS[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) eS[l] = S.s2[l] * ((double)(sl + 16) * 0x1p-51);
+    FSums O;
+    double eO[6];
+    O.s0 = P.s0 - S.s0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        O.s1[l] = P.s1[l] - S.s1[l];
+        O.s2[l] = P.s2[l] - S.s2[l];
+        eO[l] = (E2[l] + eS[l] + fabs(O.s2[l]) * 0x1p-52) * (1.0 + 0x1p-40);
+    }
+    // lane 0 decides V1 and lane 1 decides V2
+    const bool second = lane == 1;
+    const bool mine_s = second != s_first;
+    FSums C;
+    double eC[6];
+    C.s0 = mine_s ? S.s0 : O.s0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        C.s1[l] = mine_s ? S.s1[l] : O.s1[l];
+        C.s2[l] = mine_s ? S.s2[l] : O.s2[l];
+        eC[l] = mine_s ? eS[l] : eO[l];
+    }
+    int mine = 0;
+    if (lane < 2) mine = pack_decision(decide(M, C, dst, second ? start + n1 : start, second ? n2 : n1, A.P, F, eC));
+    const Decision d1 = unpack_decision(__shfl(mine, 0)), d2 = unpack_decision(__shfl(mine, 1));
+    if (d2.kind == D_SPLIT) {
+        if (second) {                                      // lane 1 holds V2's moments in C
+            out->start = start + n1;
+            out->len = n2;
+            out->thr_axis = (d2.thr << 8) | ((rev ^ 1) << 3) | d2.axis;
+            out->act = 1;
+            out->P[0] = C.s0;
+#pragma unroll
+            for (int l = 0; l < 6; ++l) { out->P[1 + l] = C.s1[l]; out->P[7 + l] = C.s2[l]; out->E2[l] = eC[l]; }
+        }
+    } else {
+        record_final(M, A, d2, start + n1, n2, rev ^ 1, cur, lane, WAVE);
+    }
+    if (d1.kind == D_SPLIT) {
+        nd.start = (IdxT)start; nd.len = (IdxT)n1;
+        nd.thr_axis = (d1.thr << 8) | (rev << 3) | d1.axis;
+        act = true;
+        const bool v1s = s_first;                          // V1's moments: S if V1 is the smaller child
+        P.s0 = v1s ? S.s0 : O.s0;
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+            P.s1[l] = v1s ? S.s1[l] : O.s1[l];
+            P.s2[l] = v1s ? S.s2[l] : O.s2[l];
+            E2[l] = v1s ? eS[l] : eO[l];
+        }
+    } else {
+        record_final(M, A, d1, start, n1, rev, cur, lane, WAVE);
+    }
+}
+
+// Block-wide vote: whether pred holds in any thread of the workgroup (every thread calls; one
+// barrier; the vote slots alternate between calls so that a slot is rewritten only after the
+// barrier of the next call).
+template <int WPB>
+VPM_DEV bool block_any(BlockScratch<WPB>* bs, bool pred, int& parity) {
+    const int wv = threadIdx.x / WAVE;
+    if (lane_id() == 0) bs->vote[parity][wv] = ballot(pred) != 0;
+    __syncthreads();
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < WPB; ++w) any |= bs->vote[parity][w] != 0;
+    parity ^= 1;
+    return any;
+}
+
+// The inherited levels of a cell shared by WPB > 1 wavefronts.  The root (a split; its moments and
+// node in bs->ho[0], written by the thread that decided it) belongs to wavefront 0.  For the first
+// log2(WPB) levels every wavefront that owns a subset splits it with all its lanes, keeps V1 and
+// hands V2 to wavefront wv + step; from then on each wavefront continues alone with the
+// one-wavefront inherited levels (lane groups halving down to one lane).  All wavefronts take the
+// same number of levels (block-wide votes), so that all open subsets sit in the same index buffer
+// when they go to the scheduled levels.  Leaves in cur / m the level and the length of its list.
+template <int WPB, typename IdxT, typename Args>
+VPM_DEV void inherit_block(const CellMem<IdxT>& M, const Args& A, const Frame& F, BlockScratch<WPB>* bs, int& cur,
+                           int& m) {
+    const int wv = threadIdx.x / WAVE;
+    const int lane = opaque_lane();
+    Node<IdxT> nd;
+    bool act;
+    FSums P;
+    double E2[6];
+    auto take = [&](int w) {
+        const Handoff& h = bs->ho[w];
+        act = h.act != 0;
+        nd.start = (IdxT)h.start; nd.len = (IdxT)h.len; nd.thr_axis = h.thr_axis;
+        P.s0 = h.P[0];
+#pragma unroll
+        for (int l = 0; l < 6; ++l) { P.s1[l] = h.P[1 + l]; P.s2[l] = h.P[7 + l]; E2[l] = h.E2[l]; }
+    };
+    take(wv);                                           // wavefront 0: the root; the others: nothing yet
+    for (int step = 1; step < WPB; step <<= 1) {
+        if (wv < step && act) split_handoff(M, A, F, nd, act, P, E2, cur, &bs->ho[wv + step]);
+        cur ^= 1;
+        __syncthreads();
+        if (wv >= step && wv < 2 * step) take(wv);
+    }
+    int parity = 0;
+    int g = WAVE;
+    for (; g >= 2; g >>= 1) {
+        if (block_any<WPB>(bs, act && (int)nd.len > INHERIT_PPL * g, parity)) break;
+        if (act) split_inherit(M, A, F, nd, act, P, E2, cur, lane & (g - 1), g, lane & ~(g - 1));
+        wave_fence();
+        cur ^= 1;
+    }
+    const bool solo = g == 1 && !block_any<WPB>(bs, act && (int)nd.len > INHERIT_PPL, parity);
+    if (threadIdx.x == 0) M.sh->nnext = 0;
+    __syncthreads();
+    if (solo) {
+        if (act) split_inherit_solo(M, A, F, nd, P, E2, cur, cur ? M.nodes0 : M.nodes1);
+        cur ^= 1;
+    } else {
+        // the open subsets, one per group of g lanes, to the scheduled levels
+        Node<IdxT>* list = cur ? M.nodes1 : M.nodes0;
+        const bool lead = act && (lane & (g - 1)) == 0;
+        const uint64_t b = ballot(lead);
+        int base = 0;
+        if (lane == 0 && b != 0) base = atomicAdd(&M.sh->nnext, __popcll(b));
+        base = __shfl(base, 0);
+        if (lead) list[base + __popcll(b & lanes_below_of(lane))] = nd;
+    }
+    __syncthreads();
+    m = M.sh->nnext;
+    __syncthreads();                                    // nnext is read before the levels reset it
+}
+
+// Copy particles unchanged from the input to the staging arrays.// Copy particles unchanged from the input to the staging arrays.  For positions p = first,
 // first + stride, ... below end, slot(p, src, dst) gives the input index and the staging slot, or
 // dst < 0 for nothing (src must then still be a valid input index).  The loads of CB positions are
 // all issued before their stores: the two arrays never overlap, but the compiler cannot know that
@@ -1778,7 +1954,18 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgsT<InT> A
                     R.s0 += bs->sums[w][0];
                     for (int l = 0; l < 6; ++l) { R.s1[l] += bs->sums[w][1 + l]; R.s2[l] += bs->sums[w][7 + l]; }
                 }
-                sh.rootv = pack_decision(decide(M, R, M.idx0, 0, n, A.P, F));
+                const Decision d = decide(M, R, M.idx0, 0, n, A.P, F);
+                sh.rootv = pack_decision(d);
+                // the root as the first wavefront's subset for the inherited levels
+                Handoff& h = bs->ho[0];
+                h.start = 0; h.len = n; h.thr_axis = (d.thr << 8) | d.axis; h.act = 1;
+                h.P[0] = R.s0;
+                for (int l = 0; l < 6; ++l) {
+                    h.P[1 + l] = R.s1[l];
+                    h.P[7 + l] = R.s2[l];
+                    h.E2[l] = R.s2[l] * ((double)(n + 16) * 0x1p-51);
+                }
+                for (int w = 1; w < WPB; ++w) bs->ho[w].act = 0;
             }
             __syncthreads();
         } else {
@@ -1790,15 +1977,9 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgsT<InT> A
         const Decision rd = unpack_decision(sh.rootv);
         int m = 0;
         int cur = 0;
-        if (WPB == 1 && rd.kind == D_SPLIT) {
-            inherit_levels<IdxT>(M, A, F, R, n, rd, lane, cur, m);
-        } else if (rd.kind == D_SPLIT) {
-            if (tid == 0) {
-                Node<IdxT> nd;
-                nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 8) | rd.axis;
-                M.nodes0[0] = nd;
-            }
-            m = 1;
+        if (rd.kind == D_SPLIT) {
+            if constexpr (WPB == 1) inherit_levels<IdxT>(M, A, F, R, n, rd, lane, cur, m);
+            else inherit_block<WPB, IdxT>(M, A, F, bs, cur, m);
         } else {
             const uint8_t base = INF_SET | (rd.kind == D_MERGED ? INF_MERGED : 0) | (uint8_t)(rd.jdir << INF_JSHIFT);
             for (int i = tid; i < n; i += NT) M.info[i] = base | (i == 0 ? INF_HEAD : 0);
