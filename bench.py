@@ -704,6 +704,8 @@ def main():
     ap.add_argument("--valu-summary", metavar="PMC_DIR")
     ap.add_argument("--shower-only", action="store_true",
                     help="time only the shower population (every size bin) and print its record (profiling runs)")
+    ap.add_argument("--bins-in-sequence", action="store_true",
+                    help="with --shower-only --no-autotune: run the size bins one after another (per-bin times)")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the merge event captured in a HIP graph (checked against an eager call)")
     args = ap.parse_args()
@@ -730,7 +732,7 @@ def main():
         ctx.reserve(52_000_000, 64 ** 3)
         sh = W.shower_grid(nc=64, seed=args.seed)
         if args.no_autotune:        # the configuration the autotuner usually picks for this population
-            ctx.set_tuning(vpm.make_tuning(ppl=16, concurrent_bins=1))
+            ctx.set_tuning(vpm.make_tuning(ppl=16, concurrent_bins=0 if args.bins_in_sequence else 1))
         print(json.dumps(extra_workload(ctx, vpm, "shower_64cubed_lognormal64", sh, None, dict(sh.params),
                                         args.steps, 0, tune=not args.no_autotune, cv=False)))
         return
