@@ -866,8 +866,9 @@ def main():
         extra = {}
         ts_paper = W.two_stream_grid(nx=256, ny=256, mean=512, seed=args.seed, params=W.TWO_STREAM_PAPER_PARAMS)
         extra["two_stream_paper_tolerances"] = extra_workload(
-            ctx, vpm, "two_stream_256x256_poisson512_T0.8_0.15_Nmin200", ts_paper.astype(np.float32), None,
-            dict(ts_paper.params), 10, 0, cpu=not args.no_cpu, seed=args.seed)
+            ctx, vpm, "two_stream_256x256_poisson512_T0.8_0.15_Nmin200", ts_paper.astype(np.float32),
+            None if args.no_fp64 else ts_paper, dict(ts_paper.params), 10, 0 if args.no_fp64 else 2,
+            cpu=not args.no_cpu, agreement=not args.no_fp64, seed=args.seed)
         extra["blind_vs_voronoi"] = blind_vs_voronoi(ctx, vpm, ts_paper.astype(np.float32), dict(ts_paper.params),
                                                      [0.965, 0.88], args.seed)
         del ts_paper
