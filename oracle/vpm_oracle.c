@@ -69,8 +69,16 @@ enum { ORC_FIXED = 0, ORC_PAPER = 1 };
 enum {
     ORC_FLAG_BAD_VALUE = 1u << 0,   /* w <= 0, NaN or Inf in the cell: cell untouched */
     ORC_FLAG_OUT_OF_CELL = 1u << 1, /* a position code had to be clamped (FIXED)       */
-    ORC_FLAG_TOO_LARGE = 1u << 2,   /* more than 65536 particles: cell untouched        */
+    ORC_FLAG_TOO_LARGE = 1u << 2,   /* more particles than the mode's largest cell: untouched */
 };
+
+/* Largest cell processed.  The method's first subset V0 may be the whole simulation box (the
+ * paper's remark after the algorithm on merging globally), so FIXED mode takes cells of up to
+ * 2^24 particles: its integer moments stay exact there (S0 <= 2^39, |S1| <= 2^61, S2 <= 2^83; V
+ * below 2^123 in 128 bits, the products of Steps 3-4 below 2^256 and 2^320).  PAPER mode, checked against the plain FP64
+ * GPU form, keeps that form's limit of 2^16. */
+#define ORC_NMAX_FIXED (1 << 24)
+#define ORC_NMAX_PAPER 65536
 
 typedef struct {
     double tol_x, tol_p;       /* T_X, T_P */
@@ -575,7 +583,8 @@ int orc_run(const orc_params *p, int64_t n_cells, const int64_t *cell_off,
             double wv = p->decide == ORC_FIXED ? (double)(float)w[off + i] : w[off + i];
             if (!(wv > 0)) bad |= ORC_FLAG_BAD_VALUE;
         }
-        if (cell_off[c + 1] - off > 65536) bad |= ORC_FLAG_TOO_LARGE;
+        if (cell_off[c + 1] - off > (p->decide == ORC_FIXED ? ORC_NMAX_FIXED : ORC_NMAX_PAPER))
+            bad |= ORC_FLAG_TOO_LARGE;
 
         if (n <= p->n_min_cell || bad || n == 0) {
             /* untouched: identity order, inputs copied (rounded to FP32 in FIXED mode) */
