@@ -29,7 +29,7 @@
  *  - A context may be used by one host thread and one stream at a time.
  *  - Host-checkable argument errors are returned immediately and nothing is enqueued.
  *    Data-dependent problems found on the device (bad values, offsets that decrease,
- *    cells above 65,536 particles) set sticky flags read by vpm_device_status; the
+ *    cells above the largest size, below) set sticky flags read by vpm_device_status; the
  *    affected cells are passed through unchanged.
  *
  * Decision modes (vpm_params.decide)
@@ -40,9 +40,9 @@
  *                    launch shapes and runs.  Tolerances are used as round(T * 2^24) / 2^24 and
  *                    must be < 128.  dtype VPM_F32 or VPM_F64: FP64 particles are rounded to FP32
  *                    (to nearest) as they are loaded, so both give identical results; the output
- *                    particles are FP32 either way.
+ *                    particles are FP32 either way.  Cells of up to 2^24 particles (a whole box).
  *  VPM_DECIDE_FP64   the paper's statistics evaluated literally in IEEE double, one workgroup
- *                    per cell.  Requires dtype VPM_F64.
+ *                    per cell.  Requires dtype VPM_F64.  Cells of up to 65,536 particles.
  */
 #ifndef VPM_H
 #define VPM_H
@@ -75,7 +75,10 @@ typedef enum { VPM_AXIS_RAW = 0, VPM_AXIS_NORMALISED = 1 } vpm_axis_rule;
 #define VPM_FLAG_BAD_VALUE      0x1u  /* w <= 0, NaN or Inf in a cell: that cell passed through     */
 #define VPM_FLAG_OUT_OF_CELL    0x2u  /* a particle lay more than one cell length from the cell's
                                          lowest coordinate; its position code was clamped (FIXED)  */
-#define VPM_FLAG_CELL_TOO_LARGE 0x4u  /* a cell above 65,536 particles: passed through            */
+#define VPM_FLAG_CELL_TOO_LARGE 0x4u  /* a cell above the largest size: passed through (2^24 =
+                                         16,777,216 particles for vpm_run, vpm_run_species and
+                                         vpm_partition with fixed-point decisions; 65,536 for
+                                         the FP64 form and vpm_merge)                           */
 #define VPM_FLAG_BAD_OFFSETS    0x8u  /* cell_off decreasing, not starting at 0, or past n_particles;
                                          a cell whose own range is invalid is passed through, but
                                          cells whose ranges overlap make the whole output
@@ -198,7 +201,10 @@ vpm_status vpm_blind(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
  *   by one wavefront, working set in LDS          if n <= bin_a_max  (bin_a_max <= 576)
  *   four wavefronts, working set in LDS           if n <= bin_b_max  (bin_b_max <= 2048)
  *   eight wavefronts, working set in LDS          if n <= bin_c_max  (bin_c_max <= 4352)
- *   eight wavefronts, working set in global memory otherwise (n <= 65,536);
+ *   eight wavefronts, working set in global memory otherwise (n <= 2^24: a whole box may be one
+ *     cell, the method's first subset (Sec. "Algorithm", the remark on merging globally); a
+ *     subset above 65,536 particles is split by one workgroup on exact integer moments and its
+ *     unfinished children are handed to other workgroups);
  * a subset of len particles is handled by a group of about len / ppl lanes (ppl = 8, 16 or 32;
  * at most 64 lanes).  Limits must satisfy 1 <= bin_a_max <= bin_b_max <= bin_c_max.
  * concurrent_bins = 1 runs the four bins at once on the context's side streams (forked from and

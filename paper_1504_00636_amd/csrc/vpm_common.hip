@@ -33,11 +33,11 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
         const bool range_ok = lo >= 0 && hi >= lo && hi <= n_particles;
         if (!range_ok) { f |= FLAG_BAD_OFFSETS; n = 0; }     // never read outside the arrays
         if (c == 0 && lo != 0) f |= FLAG_BAD_OFFSETS;
-        if (n > NMAX_BIG) f |= FLAG_TOO_LARGE;
+        if (n > lim.big) f |= FLAG_TOO_LARGE;
         const bool species_ok = !species || species[c] < n_species;
         if (!species_ok) f |= FLAG_BAD_SPECIES;
         if (f) atomicOr(flags, f);
-        if (n == 0 || n <= n_min_cell || n > NMAX_BIG || !range_ok || !species_ok) {
+        if (n == 0 || n <= n_min_cell || n > lim.big || !range_ok || !species_ok) {
             cls = Q_UNTOUCHED;
             out_count[c] = n;
             cell_mode[c] = CELL_UNTOUCHED;

@@ -305,6 +305,142 @@ VPM_DEV Decision decide_exact(const ISums& S, const DecideConsts& K, const Frame
     return d;
 }
 
+// ------------------------------------------------------------------------------------------
+// Subsets above 2^16 particles (a whole simulation box merged as one cell: the method's first
+// subset may be the box itself).  With up to 2^24 particles |S1| reaches 2^61, past the 2^53 that
+// FP64 holds exactly, so these subsets are decided by the exact rule only, on integer moments
+// summed exactly: S0 <= 2^39, |S1| <= 2^61, S2 <= 2^83 (128 bits).  The products of Steps 3-4 stay
+// below 2^256 (2^320 under the normalised axis rule).
+// ------------------------------------------------------------------------------------------
+
+constexpr int NMAX_NARROW = 65536;     // largest subset decided through the FP64 filter
+
+struct WSums { uint64_t s0; int64_t s1[6]; U128 s2[6]; };
+
+VPM_DEV void wsums_zero(WSums& S) {
+    S.s0 = 0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) { S.s1[l] = 0; S.s2[l] = u128_make(0, 0); }
+}
+
+VPM_DEV void wsums_add(WSums& S, int om, const int c[6]) {
+    S.s0 += (uint64_t)om;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        const int64_t t = (int64_t)om * c[l];                  // |t| <= 2^37
+        S.s1[l] += t;
+        S.s2[l] = add128(S.s2[l], u128_make((uint64_t)(t * c[l]), 0));   // omega c^2 < 2^60
+    }
+}
+
+VPM_DEV void wsums_acc(WSums& S, const WSums& T) {
+    S.s0 += T.s0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) { S.s1[l] += T.s1[l]; S.s2[l] = add128(S.s2[l], T.s2[l]); }
+}
+
+// Sum over the wavefront (every lane receives the total).
+VPM_DEV void wsums_wave_reduce(WSums& S) {
+#pragma unroll
+    for (int m = 1; m < WAVE; m <<= 1) {
+        WSums T;
+        T.s0 = __shfl_xor(S.s0, m);
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+            T.s1[l] = __shfl_xor(S.s1[l], m);
+            T.s2[l] = u128_make(__shfl_xor(S.s2[l].lo, m), __shfl_xor(S.s2[l].hi, m));
+        }
+        wsums_acc(S, T);
+    }
+}
+
+// Pair-direction axis from exact S1: argmin over the momentum axes of |S1_a| 2^e_a, ties to the
+// lowest axis (compared exactly: first by magnitude, bit length plus exponent, then the aligned
+// values).
+VPM_DEV int pair_axis_exact(const int64_t s1[6], const Frame& F) {
+    int best = 0;
+    uint64_t bm = 0;
+    int be = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint64_t m = F.pzero[a] ? 0 : uabs64(s1[3 + a]);
+        const int e = F.ep[a];
+        bool less = false;
+        if (a > 0) {
+            if (m == 0 || bm == 0) {
+                less = m == 0 && bm != 0;
+            } else {
+                const int lm = 64 - __clzll((long long)m) + e, lb = 64 - __clzll((long long)bm) + be;
+                if (lm != lb) less = lm < lb;
+                else less = e >= be ? (m << (e - be)) < bm : m < (bm << (be - e));
+            }
+        }
+        if (a == 0 || less) { best = a; bm = m; be = e; }
+    }
+    return best;
+}
+
+// The exact rule on exact wide moments (the same comparisons as decide_exact, in wider integers).
+VPM_DEV Decision decide_exact_wide(const WSums& S, const DecideConsts& K, const Frame& F) {
+    Decision d;
+    d.axis = 0; d.thr = 0;
+    d.jdir = pair_axis_exact(S.s1, F);
+    if (S.s0 == 0) { d.kind = D_MERGED; return d; }
+    const uint64_t s0 = S.s0;
+    const U128 s0sq = mul64(s0, s0);                 // <= 2^78
+    auto times_s0 = [&](U128 v) {                    // s0 v < 2^128
+        U128 r = mul64(s0, v.lo);
+        r.hi += s0 * v.hi;
+        return r;
+    };
+    U128 V[6], D[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        const uint64_t s1 = uabs64(S.s1[l]);
+        const U128 sq = mul64(s1, s1);
+        V[l] = sub128(times_s0(S.s2[l]), sq);
+        D[l] = l < 3 ? shl128(s0sq, 32) : sq;
+    }
+    bool done = true;
+    {
+        const U256 rhs = mul128(u128_make(K.thx2, 0), s0sq);      // That^2 S0^2
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (!is_zero128(V[a]) && cmp256(mul128(V[a], u128_make(1ull << 16, 0)), rhs) > 0) done = false;
+        const U128 tp2 = u128_make(K.thp2, 0);
+#pragma unroll
+        for (int a = 3; a < 6; ++a) {
+            if (is_zero128(V[a])) continue;
+            if (is_zero128(D[a])) { done = false; continue; }
+            if (cmp256(mul128(V[a], u128_make(1ull << 48, 0)), mul128(tp2, D[a])) > 0) done = false;
+        }
+    }
+    if (done) { d.kind = D_MERGED; return d; }
+    const bool xinf = K.tx2 == 0, pinf = K.tp2 == 0;
+    int kx = 0;
+    U128 xV = V[0];
+#pragma unroll
+    for (int l = 1; l < 3; ++l)
+        if (xinf ? is_zero128(xV) && !is_zero128(V[l]) : cmp128(V[l], xV) > 0) { kx = l; xV = V[l]; }
+    int kp = 3;
+    U128 pV = V[3], pD = D[3];
+#pragma unroll
+    for (int l = 4; l < 6; ++l)
+        if (pinf ? is_zero128(pV) && !is_zero128(V[l]) : frac_gt(V[l], D[l], pV, pD)) { kp = l; pV = V[l]; pD = D[l]; }
+    const int k = frac_gt_norm(pV, pD, K.tp2, xV, D[0], K.tx2) ? kp : kx;
+    int64_t s1k = S.s1[0];
+#pragma unroll
+    for (int l = 1; l < 6; ++l) if (l == k) s1k = S.s1[l];
+    // Step 5: floor(S1 / S0) in integers (|S1 / S0| <= 2^22)
+    const int64_t den = (int64_t)s0;
+    int64_t t = s1k / den;
+    if (t * den > s1k) t -= 1;
+    d.kind = D_SPLIT;
+    d.axis = k;
+    d.thr = (int)t;
+    return d;
+}
+
 // The same rule evaluated in floating point with error bounds.  Sets ok = false when a comparison
 // cannot be certified (the caller then applies the exact rule).
 //   V = S0 S2 - S1^2 in FP64 (S0, S1 exact): S2 is rounded over at most len + 6 operations, the FMA
@@ -2083,6 +2219,178 @@ VPM_DEV void spawn_task(const BigArgs<InT>& B, int qi, int cur, Node<uint32_t> n
     __hip_atomic_store(&B.ready[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Exact wide moments of the whole workgroup: each wavefront's total goes to the workgroup's
+// slab (`part`, WPB records of 19 words), then thread 0 adds them up.  All threads call; the result
+// is valid in thread 0.
+template <int WPB>
+VPM_DEV void wsums_block_reduce(WSums& S, uint64_t* part) {
+    wsums_wave_reduce(S);
+    constexpr int W = 19;
+    if (lane_id() == 0) {
+        uint64_t* q = part + (size_t)(threadIdx.x / WAVE) * W;
+        q[0] = S.s0;
+        for (int l = 0; l < 6; ++l) {
+            q[1 + l] = (uint64_t)S.s1[l];
+            q[7 + 2 * l] = S.s2[l].lo;
+            q[8 + 2 * l] = S.s2[l].hi;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        wsums_zero(S);
+        for (int w = 0; w < WPB; ++w) {
+            const uint64_t* q = part + (size_t)w * W;
+            WSums T;
+            T.s0 = q[0];
+            for (int l = 0; l < 6; ++l) {
+                T.s1[l] = (int64_t)q[1 + l];
+                T.s2[l] = u128_make(q[7 + 2 * l], q[8 + 2 * l]);
+            }
+            wsums_acc(S, T);
+        }
+    }
+    __syncthreads();
+}
+
+// Steps 5-6 for one subset of more than NMAX_NARROW particles, by the whole workgroup: the stable
+// cut into the other index buffer (V1 = {c <= thr} from the front in slot order, V2 from the back
+// in reverse slot order, as compact_node lays them out), the exact moments of both children while
+// they are placed, and their exact decisions (Steps 3-4).  Unfinished children of at least TASK_MIN
+// particles become tasks; smaller ones go to `kept` (the node list of the other buffer).  Returns
+// the number kept.
+// The root decision of a cell above NMAX_NARROW (into sh.rootv): its moments summed exactly over
+// the whole workgroup, then the exact rule.
+VPM_DEV void wide_root(const CellMem<uint32_t>& M, const Frame& F, int n, int min_subset) {
+    WSums W0;
+    wsums_zero(W0);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int cc[6], om;
+        codes_of(M, i, cc, om);
+        wsums_add(W0, om, cc);
+    }
+    wsums_block_reduce<8>(W0, (uint64_t*)M.sched);
+    if (threadIdx.x == 0) {
+        Decision cp; cp.kind = D_COPY; cp.axis = 0; cp.thr = 0; cp.jdir = 0;
+        M.sh->rootv = pack_decision(n < min_subset ? cp : decide_exact_wide(W0, M.sh->dc, F));
+    }
+}
+
+template <typename InT>
+VPM_DEV int wide_split(const BigArgs<InT>& B, const CellMem<uint32_t>& M, const Frame& F, BlockScratch<8>* bs,
+                       Node<uint32_t> nd, int cur, int qi, Node<uint32_t>* kept) {
+    constexpr int WPB = 8, NT = WAVE * WPB;
+    const auto& A = B.A;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    const int start = nd.start, len = nd.len;
+    const int k = nd.thr_axis & 7, thr = nd.thr_axis >> 8, rev = (nd.thr_axis >> 3) & 1;
+    const uint32_t* src = idx_buf(M, cur) + start;
+    uint32_t* dst = idx_buf(M, cur ^ 1);
+    // each wavefront takes one contiguous segment of the subset's slots
+    const int seg = (len + WPB - 1) / WPB;
+    const int s0 = min(len, wv * seg), s1 = min(len, s0 + seg);
+    // pass 1: the lower side's count per wavefront and the subset's moments
+    WSums P;
+    wsums_zero(P);
+    int cnt = 0;
+    for (int j = s0 + lane; j < s1; j += WAVE) {
+        int c[6], om;
+        codes_of(M, (int)src[j], c, om);
+        int ck = c[0];
+#pragma unroll
+        for (int l = 1; l < 6; ++l) if (l == k) ck = c[l];
+        cnt += ck <= thr ? 1 : 0;
+        wsums_add(P, om, c);
+    }
+    cnt = group_sum(cnt, WAVE);
+    if (lane == 0) bs->scan[wv] = cnt;
+    __syncthreads();
+    int lb = 0, n1 = 0;
+    for (int w = 0; w < WPB; ++w) {
+        if (w < wv) lb += (int)bs->scan[w];
+        n1 += (int)bs->scan[w];
+    }
+    int rb = s0 - lb;                                   // V2 members before this segment
+    wsums_block_reduce<WPB>(P, (uint64_t*)M.sched);
+    // pass 2: the cut, with V1's moments (V2's are the subset's minus V1's, exactly)
+    WSums L;
+    wsums_zero(L);
+    for (int j0 = s0; j0 < s1; j0 += WAVE) {
+        const int j = j0 + lane;
+        const bool act = j < s1;
+        const uint32_t ix = src[act ? j : s1 - 1];
+        int c[6], om;
+        codes_of(M, (int)ix, c, om);
+        int ck = c[0];
+#pragma unroll
+        for (int l = 1; l < 6; ++l) if (l == k) ck = c[l];
+        const bool right = ck > thr;
+        const uint64_t br = ballot(act && right), bl = ballot(act && !right);
+        const uint64_t below = lanes_below();
+        if (act) {
+            if (right) dst[start + len - 1 - (rb + __popcll(br & below))] = ix;
+            else {
+                dst[start + lb + __popcll(bl & below)] = ix;
+                wsums_add(L, om, c);
+            }
+        }
+        lb += __popcll(bl);
+        rb += __popcll(br);
+    }
+    wsums_block_reduce<WPB>(L, (uint64_t*)M.sched);
+    const int n2 = len - n1;
+    int* const dv = bs->vote[0];
+    if (tid == 0) {
+        if (n1 == 0 || n2 == 0) {
+            // impossible under the exact rule (the chosen axis has V > 0); end the subset
+            atomicOr(&M.sh->flags, FLAG_INTERNAL);
+            Decision d; d.kind = D_MERGED; d.axis = 0; d.thr = 0; d.jdir = 0;
+            dv[0] = pack_decision(d);
+            dv[1] = -1;
+        } else {
+            const DecideConsts& K = M.sh->dc;
+            Decision cp; cp.kind = D_COPY; cp.axis = 0; cp.thr = 0; cp.jdir = 0;
+            WSums R;
+            R.s0 = P.s0 - L.s0;
+#pragma unroll
+            for (int l = 0; l < 6; ++l) { R.s1[l] = P.s1[l] - L.s1[l]; R.s2[l] = sub128(P.s2[l], L.s2[l]); }
+            dv[0] = pack_decision(n1 < A.P.min_subset ? cp : decide_exact_wide(L, K, F));
+            dv[1] = pack_decision(n2 < A.P.min_subset ? cp : decide_exact_wide(R, K, F));
+        }
+        dv[2] = 0;                                      // children kept
+        dv[3] = 0;                                      // children to hand out
+    }
+    __syncthreads();
+    Node<uint32_t>* const hand = (Node<uint32_t>*)(dv + 4);   // bs->vote[1] and past: two nodes
+    const int d0 = dv[0], d1 = dv[1];
+    for (int ch = 0; ch < 2; ++ch) {
+        const int dvv = ch == 0 ? d0 : d1;
+        if (dvv == -1) continue;
+        const Decision d = unpack_decision(dvv);
+        const int cs = d1 == -1 ? start : (ch == 0 ? start : start + n1);
+        const int cl = d1 == -1 ? len : (ch == 0 ? n1 : n2);
+        const int crev = d1 == -1 ? (n1 == 0 ? rev ^ 1 : rev) : (ch == 0 ? rev : rev ^ 1);
+        if (d.kind == D_SPLIT) {
+            if (tid == 0) {
+                Node<uint32_t> c;
+                c.start = (uint32_t)cs; c.len = (uint32_t)cl;
+                c.thr_axis = (d.thr << 8) | (crev << 3) | d.axis;
+                if (cl >= TASK_MIN) hand[dv[3]++] = c;
+                else kept[dv[2]++] = c;
+            }
+        } else {
+            record_final(M, A, d, cs, cl, crev, cur, tid, NT);
+        }
+    }
+    // the cut and the info bytes, device-wide, before another workgroup may take a child
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    const int nk = dv[2], nh = dv[3];
+    if (tid == 0)
+        for (int h = 0; h < nh; ++h) spawn_task(B, qi, cur ^ 1, hand[h]);
+    __syncthreads();                                    // dv is read before it is reused
+    return nk;
+}
+
 template <typename InT>
 __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
     constexpr int WPB = 8, NT = WAVE * WPB;
@@ -2137,6 +2445,8 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
         const int lane = opaque_lane();
         const int tid = opaque_tid();
         int qi, c, n, m = 0, cur = 0;
+        bool wide = false;                     // the piece starts with a subset above NMAX_NARROW
+        Node<IdxT> wnode;
         int64_t off;
         Frame F;
         CellMem<IdxT> M;
@@ -2187,10 +2497,12 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
             n = bc.n;
             c = bc.c;
             cur = t.cur;
-            m = 1;
+            wide = t.nd.len > (uint32_t)NMAX_NARROW;
+            wnode = t.nd;
+            m = wide ? 0 : 1;
             __syncthreads();                           // every thread has read the slot
             if (tid == 0) {
-                (cur ? M.nodes1 : M.nodes0)[0] = t.nd;
+                if (!wide) (cur ? M.nodes1 : M.nodes0)[0] = t.nd;
                 __hip_atomic_store(&B.ready[sh.qi], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
@@ -2215,7 +2527,10 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
                 if (any_oob) atomicOr(&sh.flags, FLAG_OUT_OF_CELL);
             }
             __syncthreads();
-            if (tid == 0) {
+            if (n > NMAX_NARROW) {
+                // a cell above NMAX_NARROW: the root's moments summed exactly, the exact rule
+                wide_root(M, F, n, A.P.min_subset);
+            } else if (tid == 0) {
                 fsums_zero(R);
                 for (int w = 0; w < WPB; ++w) {
                     R.s0 += bs->sums[w][0];
@@ -2225,7 +2540,10 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
             }
             __syncthreads();
             const Decision rd = unpack_decision(sh.rootv);
-            if (rd.kind == D_SPLIT) {
+            if (rd.kind == D_SPLIT && n > NMAX_NARROW) {
+                wide = true;
+                wnode.start = 0; wnode.len = (IdxT)n; wnode.thr_axis = (rd.thr << 8) | rd.axis;
+            } else if (rd.kind == D_SPLIT) {
                 if (tid == 0) {
                     Node<IdxT> nd;
                     nd.start = 0; nd.len = (IdxT)n; nd.thr_axis = (rd.thr << 8) | rd.axis;
@@ -2238,6 +2556,12 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
             }
         }
         __syncthreads();
+        if (wide) {
+            // a subset above NMAX_NARROW: split by the whole workgroup; its unfinished children of
+            // at least TASK_MIN particles become tasks, the smaller ones continue here
+            m = wide_split(B, M, F, bs, wnode, cur, qi, cur ? M.nodes0 : M.nodes1);
+            cur ^= 1;
+        }
 
         // ---- Steps 2-6, level by level; large unfinished subsets become tasks ----
         while (m > 0) {

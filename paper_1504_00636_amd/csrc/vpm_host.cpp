@@ -143,8 +143,10 @@ int ilog2(int v) {
     return s;
 }
 
-BinLimits bin_limits(const vpm_ctx* c) {
-    return BinLimits{c->tune.bin_a_max, c->tune.bin_b_max, c->tune.bin_c_max, c->tune.bin_s_max};
+// big: the largest cell processed (the fixed-point partition takes whole boxes; the FP64 form and
+// vpm_merge keep to NMAX_BIG)
+BinLimits bin_limits(const vpm_ctx* c, int32_t big) {
+    return BinLimits{c->tune.bin_a_max, c->tune.bin_b_max, c->tune.bin_c_max, c->tune.bin_s_max, big};
 }
 
 FixedParams fixed_params(const vpm_params* p, const vpm_tuning& t) {
@@ -208,8 +210,9 @@ vpm_status run_impl(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, in
     if (check_soa(out) != VPM_OK || !out_off || !out_total) return VPM_ERR_INVALID_ARG;
     hipSetDevice(ctx->device);
     LaunchCfg lc = make_cfg(ctx, stream);
-    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx),
-                              species, n_species);
+    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell,
+                              bin_limits(ctx, p->decide == VPM_DECIDE_FIXED ? NMAX_WIDE : NMAX_BIG), species,
+                              n_species);
     if (e != hipSuccess) return hip_fail(ctx, e, "bin");
     if (p->decide == VPM_DECIDE_FIXED) {
         FixedParams fp = fixed_params(p, ctx->tune);
@@ -410,7 +413,8 @@ vpm_status vpm_partition(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_of
     if (!perm || !subset_id || !n_subsets) return VPM_ERR_INVALID_ARG;
     hipSetDevice(ctx->device);
     LaunchCfg lc = make_cfg(ctx, stream);
-    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx));
+    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell,
+                              bin_limits(ctx, p->decide == VPM_DECIDE_FIXED ? NMAX_WIDE : NMAX_BIG));
     if (e != hipSuccess) return hip_fail(ctx, e, "bin");
     if (p->decide == VPM_DECIDE_FIXED)
         e = p->dtype == VPM_F32
@@ -435,7 +439,7 @@ vpm_status vpm_merge(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off, i
         return VPM_ERR_INVALID_ARG;
     hipSetDevice(ctx->device);
     LaunchCfg lc = make_cfg(ctx, stream);
-    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx));
+    hipError_t e = launch_bin(ctx->ws, lc, cell_off, n_cells, n_particles, p->n_min_cell, bin_limits(ctx, NMAX_BIG));
     if (e != hipSuccess) return hip_fail(ctx, e, "bin");
     if (p->decide == VPM_DECIDE_FIXED)
         e = p->dtype == VPM_F32

@@ -16,6 +16,8 @@ constexpr int NMAX_A = 576;     // 1 wavefront per cell, working set in LDS (8 c
 constexpr int NMAX_B = 2048;    // 4 wavefronts per cell, working set in LDS (2 cells per CU)
 constexpr int NMAX_C = 4352;    // 8 wavefronts per cell, working set in LDS (1 cell per CU)
 constexpr int NMAX_BIG = 65536; // 8 wavefronts per piece, several workgroups per cell, working set global
+constexpr int NMAX_WIDE = 1 << 24;  // largest cell of the fixed-point vpm_run / vpm_partition (a whole box;
+                                    // subsets above NMAX_BIG are split by one workgroup each, exactly)
 constexpr int NMAX_S = 512;     // batches of small cells: 1 wavefront, up to 512 particles in LDS
 constexpr int SMALL_MAX = 256;  // largest cell the small-cell bin may take
 enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_C = 3, Q_BIG = 4, Q_S = 5, Q_COUNT = 6 };
@@ -109,7 +111,7 @@ __host__ __device__ inline double cell_mass(double mass, const uint8_t* species,
 
 // Routing thresholds of the size bins: cells of up to `s` particles go to the small-cell batches,
 // up to `a` to bin A, up to `b` to B, up to `c` to C, larger ones to the global-memory bin.
-struct BinLimits { int32_t a, b, c, s; };
+struct BinLimits { int32_t a, b, c, s, big; };   // big: the largest cell processed
 
 struct LaunchCfg {
     hipStream_t stream;

@@ -150,7 +150,7 @@ extern "C" vpm_status vpm_run_noalloc(const vpm_soa* in, const int64_t* cell_off
     fp.mass = p->mass;
     fp.species = nullptr;
     for (int k = 0; k < VPM_MAX_SPECIES; ++k) fp.species_mass[k] = p->mass;
-    const BinLimits lim{NMAX_A, NMAX_B, NMAX_C, 128};
+    const BinLimits lim{NMAX_A, NMAX_B, NMAX_C, 128, NMAX_WIDE};
 
     // the flags start at zero for every call (a kernel, not a memset: the call may be captured)
     hipLaunchKernelGGL(k_na_clear, dim3(1), dim3(64), 0, stream, ws.flags);
