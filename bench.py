@@ -432,6 +432,59 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True
     return rec
 
 
+def whole_box(ctx, vpm, W, seed, steps=3, cpu=True):
+    """Global merging: a whole simulation box passed as one cell (the method's first subset is the
+    box), in two populations: the counter-propagating blocks at 4,000 electrons per unit cell (4 M
+    particles in a 100 x 20 box) and a 64 x 64 patch of the two-stream population (2.1 M particles).
+    Each is timed per merge event; the oracle is timed on the same box (its CPU baseline), and that
+    run's partition is compared with the GPU's (bit-exact)."""
+    import torch
+    import oracle
+    recs = {}
+    blocks = W.counter_blocks(per_cell=4000, seed=seed)
+    ts = W.two_stream_grid(nx=64, ny=64, mean=512, seed=seed)
+    cases = [("counter_blocks_4M", blocks, dict(blocks.params, cell_len=(100.0, 20.0, 1.0), tol_x=0.02)),
+             ("two_stream_64x64", ts, dict(ts.params, cell_len=(64.0, 64.0, 1.0), tol_x=0.02))]
+    for name, wl, prm in cases:
+        box = W.Workload(name, *[getattr(wl, f).astype(np.float32) for f in W.FIELDS],
+                         cell_off=np.array([0, wl.n], np.int64), cell_id=None, params=prm)
+        n = box.n
+        arrs, off = vpm.upload(box)
+        p32 = vpm.make_params(decide=vpm.VPM_DECIDE_FIXED, **prm)
+        ctx.device_status(clear=True)
+        ms, out, out_off, n_out, kernels, _ = time_fixed(ctx, vpm, arrs, off, n, p32, steps, 1, True)
+        rec = dict(workload=f"{name}_as_one_cell", n_particles=n, ms_per_step=ms, value=n / (ms * 1e-3),
+                   unit="particles/s", n_out=n_out, device_flags=ctx.device_status(clear=True),
+                   conservation=conservation_error(arrs, out, n_out, prm["mass"]),
+                   kernels={k: round(v["avg_ms"], 4) for k, v in kernels.items()},
+                   params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset", "cell_len")})
+        del out
+        perm = torch.empty(n, dtype=torch.int32, device="cuda")
+        sid = torch.empty(n, dtype=torch.int32, device="cuda")
+        nsub = torch.empty(1, dtype=torch.int32, device="cuda")
+        ctx.partition(arrs, off, n, p32, perm, sid, nsub)
+        torch.cuda.synchronize()
+        rec["subsets"] = int(nsub.item())
+        if cpu:
+            keys = ("tol_x", "tol_p", "n_min_cell", "min_subset", "cell_len", "mass")
+            t0 = time.perf_counter()
+            ref = oracle.run_workload(box, decide=oracle.FIXED, merge_mode=oracle.PAIR,
+                                      **{k: prm[k] for k in keys})
+            t_orc = time.perf_counter() - t0
+            same = bool(int(ref.n_subsets[0]) == rec["subsets"] and ref.out_total == n_out and
+                        np.array_equal(perm.cpu().numpy(), ref.perm) and
+                        np.array_equal(sid.cpu().numpy(), ref.subset_id))
+            rec["cpu_baseline"] = dict(value=n / t_orc, unit="particles/s", cores=1, kind="oracle",
+                                       sample=f"the whole box ({n} particles), {t_orc:.2f} s wall (one cell: one thread)",
+                                       gpu_partition_equal=same)
+        del arrs, perm, sid, nsub
+        torch.cuda.empty_cache()
+        log(f"[bench] whole box {name}: {n} particles, {ms:.2f} ms/event, {rec['subsets']} subsets, "
+            f"oracle equal: {(rec.get('cpu_baseline') or {}).get('gpu_partition_equal')}")
+        recs[name] = rec
+    return recs
+
+
 def blind_vs_voronoi(ctx, vpm, wl32, prm, alphas, seed, steps=5):
     """The paper's comparison on one population: the Voronoi merge (vpm_run) against the blind method
     (vpm_blind: random pairs merged until at most ceil(alpha N) particles remain per cell), each
@@ -879,6 +932,7 @@ def main():
                                          agreement=not args.no_fp64, seed=args.seed)
         del sh, sh64
         extra["shower_three_species"] = species_shower(ctx, vpm, W, args.seed)
+        extra["whole_box"] = whole_box(ctx, vpm, W, args.seed, cpu=not args.no_cpu)
         if args.cascade_steps > 0:
             extra["cascade"] = cascade(ctx, vpm, W, args.cascade_steps, args.seed)
         if not args.no_fp64:

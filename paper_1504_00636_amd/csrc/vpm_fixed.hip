@@ -2263,10 +2263,14 @@ VPM_DEV void wsums_block_reduce(WSums& S, uint64_t* part) {
 VPM_DEV void wide_root(const CellMem<uint32_t>& M, const Frame& F, int n, int min_subset) {
     WSums W0;
     wsums_zero(W0);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        int cc[6], om;
-        codes_of(M, i, cc, om);
-        wsums_add(W0, om, cc);
+    constexpr int WB = 4;                           // rounds whose codes are loaded together
+    for (int i0 = 0; i0 < n; i0 += WB * (int)blockDim.x) {
+        int cc[WB][6], om[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) codes_of(M, min(i0 + u * (int)blockDim.x + (int)threadIdx.x, n - 1), cc[u], om[u]);
+#pragma unroll
+        for (int u = 0; u < WB; ++u)
+            if (i0 + u * (int)blockDim.x + (int)threadIdx.x < n) wsums_add(W0, om[u], cc[u]);
     }
     wsums_block_reduce<8>(W0, (uint64_t*)M.sched);
     if (threadIdx.x == 0) {
@@ -2288,18 +2292,29 @@ VPM_DEV int wide_split(const BigArgs<InT>& B, const CellMem<uint32_t>& M, const 
     // each wavefront takes one contiguous segment of the subset's slots
     const int seg = (len + WPB - 1) / WPB;
     const int s0 = min(len, wv * seg), s1 = min(len, s0 + seg);
+    // Both passes take WB rounds of 64 slots at a time: their indices, then their codes, are loaded
+    // before any is used, so that a wavefront keeps several gathers in flight.
+    constexpr int WB = 4;
     // pass 1: the lower side's count per wavefront and the subset's moments
     WSums P;
     wsums_zero(P);
     int cnt = 0;
-    for (int j = s0 + lane; j < s1; j += WAVE) {
-        int c[6], om;
-        codes_of(M, (int)src[j], c, om);
-        int ck = c[0];
+    for (int j0 = s0; j0 < s1; j0 += WB * WAVE) {
+        uint32_t ix[WB];
 #pragma unroll
-        for (int l = 1; l < 6; ++l) if (l == k) ck = c[l];
-        cnt += ck <= thr ? 1 : 0;
-        wsums_add(P, om, c);
+        for (int u = 0; u < WB; ++u) ix[u] = src[min(j0 + u * WAVE + lane, s1 - 1)];
+        int c[WB][6], om[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) codes_of(M, (int)ix[u], c[u], om[u]);
+#pragma unroll
+        for (int u = 0; u < WB; ++u) {
+            if (j0 + u * WAVE + lane >= s1) continue;
+            int ck = c[u][0];
+#pragma unroll
+            for (int l = 1; l < 6; ++l) if (l == k) ck = c[u][l];
+            cnt += ck <= thr ? 1 : 0;
+            wsums_add(P, om[u], c[u]);
+        }
     }
     cnt = group_sum(cnt, WAVE);
     if (lane == 0) bs->scan[wv] = cnt;
@@ -2314,27 +2329,32 @@ VPM_DEV int wide_split(const BigArgs<InT>& B, const CellMem<uint32_t>& M, const 
     // pass 2: the cut, with V1's moments (V2's are the subset's minus V1's, exactly)
     WSums L;
     wsums_zero(L);
-    for (int j0 = s0; j0 < s1; j0 += WAVE) {
-        const int j = j0 + lane;
-        const bool act = j < s1;
-        const uint32_t ix = src[act ? j : s1 - 1];
-        int c[6], om;
-        codes_of(M, (int)ix, c, om);
-        int ck = c[0];
+    const uint64_t below = lanes_below();
+    for (int j0 = s0; j0 < s1; j0 += WB * WAVE) {
+        uint32_t ix[WB];
 #pragma unroll
-        for (int l = 1; l < 6; ++l) if (l == k) ck = c[l];
-        const bool right = ck > thr;
-        const uint64_t br = ballot(act && right), bl = ballot(act && !right);
-        const uint64_t below = lanes_below();
-        if (act) {
-            if (right) dst[start + len - 1 - (rb + __popcll(br & below))] = ix;
-            else {
-                dst[start + lb + __popcll(bl & below)] = ix;
-                wsums_add(L, om, c);
+        for (int u = 0; u < WB; ++u) ix[u] = src[min(j0 + u * WAVE + lane, s1 - 1)];
+        int c[WB][6], om[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) codes_of(M, (int)ix[u], c[u], om[u]);
+#pragma unroll
+        for (int u = 0; u < WB; ++u) {
+            const bool act = j0 + u * WAVE + lane < s1;
+            int ck = c[u][0];
+#pragma unroll
+            for (int l = 1; l < 6; ++l) if (l == k) ck = c[u][l];
+            const bool right = ck > thr;
+            const uint64_t br = ballot(act && right), bl = ballot(act && !right);
+            if (act) {
+                if (right) dst[start + len - 1 - (rb + __popcll(br & below))] = ix[u];
+                else {
+                    dst[start + lb + __popcll(bl & below)] = ix[u];
+                    wsums_add(L, om[u], c[u]);
+                }
             }
+            lb += __popcll(bl);
+            rb += __popcll(br);
         }
-        lb += __popcll(bl);
-        rb += __popcll(br);
     }
     wsums_block_reduce<WPB>(L, (uint64_t*)M.sched);
     const int n2 = len - n1;
