@@ -441,6 +441,10 @@ def whole_box(ctx, vpm, W, seed, steps=3, cpu=True):
     import torch
     import oracle
     recs = {}
+    # the default batching (bins in sequence): a lone large cell needs every workgroup of the
+    # large-cell kernel to wait for its subsets, which the concurrent-bin mode does not do
+    saved = ctx.get_tuning()
+    ctx.set_tuning(vpm.make_tuning())
     blocks = W.counter_blocks(per_cell=4000, seed=seed)
     ts = W.two_stream_grid(nx=64, ny=64, mean=512, seed=seed)
     cases = [("counter_blocks_4M", blocks, dict(blocks.params, cell_len=(100.0, 20.0, 1.0), tol_x=0.02)),
@@ -455,6 +459,7 @@ def whole_box(ctx, vpm, W, seed, steps=3, cpu=True):
         ms, out, out_off, n_out, kernels, _ = time_fixed(ctx, vpm, arrs, off, n, p32, steps, 1, True)
         rec = dict(workload=f"{name}_as_one_cell", n_particles=n, ms_per_step=ms, value=n / (ms * 1e-3),
                    unit="particles/s", n_out=n_out, device_flags=ctx.device_status(clear=True),
+                   tuning=ctx.get_tuning().as_dict(),
                    conservation=conservation_error(arrs, out, n_out, prm["mass"]),
                    kernels={k: round(v["avg_ms"], 4) for k, v in kernels.items()},
                    params={k: prm[k] for k in ("tol_x", "tol_p", "n_min_cell", "min_subset", "cell_len")})
@@ -482,6 +487,7 @@ def whole_box(ctx, vpm, W, seed, steps=3, cpu=True):
         log(f"[bench] whole box {name}: {n} particles, {ms:.2f} ms/event, {rec['subsets']} subsets, "
             f"oracle equal: {(rec.get('cpu_baseline') or {}).get('gpu_partition_equal')}")
         recs[name] = rec
+    ctx.set_tuning(saved)
     return recs
 
 
