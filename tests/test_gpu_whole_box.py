@@ -90,3 +90,32 @@ def test_largest_cell_limits():
     perm, sid, nsub = gpu_partition(wl2, CLOUD, decide=vpm.VPM_DECIDE_FP64)
     assert c.device_status(clear=True) & vpm.VPM_FLAG_CELL_TOO_LARGE
     assert nsub[0] == 0 and nsub[1] > 0
+
+
+def test_wide_lattice_zero_tolerance():
+    """T = 0 on a 90,000-particle cell drawn from a small lattice: the final subsets are the
+    duplicate classes, reached through exact ties between axes (ties go to the lowest axis) and
+    zero-variance axes, all decided on the exact wide moments at the top."""
+    r = np.random.Generator(np.random.Philox(25))
+    k = 90000
+    base = r.integers(0, 3, size=(k, 6)).astype(np.float64)
+    base[:, :3] *= 1000.0
+    base[:, 3:] -= 1.0
+    w = r.integers(1, 4, size=(k, 1)).astype(np.float64)
+    params = dict(tol_x=0.0, tol_p=0.0, n_min_cell=0, min_subset=1, cell_len=(65536.0,) * 3, mass=1.0)
+    wl = W.from_cells([np.concatenate([base, w], axis=1), np.concatenate([base[:500], w[:500]], axis=1)],
+                      params=params, dtype=np.float32)
+    ref = full_check(wl, params, vpm.VPM_MERGE_CENTROID)
+    assert ref.n_subsets[0] == len({tuple(v) for v in base.tolist()})
+
+
+@pytest.mark.parametrize("axis_rule", [0, 1])
+def test_wide_normalised_rule_and_photons(axis_rule):
+    """The tolerance-normalised axis rule and massless particles with one momentum axis all zero,
+    on cells above 2^16 (the exact wide decisions weigh each CV by its tolerance)."""
+    rows = heavy_cell(200000, seed=26)
+    ph = heavy_cell(80000, seed=27)
+    ph[:, 5] = 0.0                                   # pz = 0 throughout: a zero momentum axis
+    prm = dict(HEAVY, tol_p=0.03, axis_rule=axis_rule, mass=0.0)
+    wl = W.from_cells([rows, ph], params=dict(prm), dtype=np.float32)
+    full_check(wl, prm)
