@@ -1850,45 +1850,25 @@ VPM_DEV void encode_particle(const CellMem<IdxT>& M, const FixedParams& P, const
 // over the cell's slots gives leaf ordinals and output slots; copied particles go to the staging
 // arrays, merged subsets are replaced (Step 7).  In partition mode the permutation and subset
 // ordinals are written instead.  leaf_start (n + 1 entries), mlist and msched (n each) are scratch.
+// defer: only the slots, leaf starts and the merged list are formed (and the counts recorded); the
+// copies and merges are left to the caller (a cell above NMAX_NARROW hands them to other workgroups).
 template <int WPB, typename IdxT, typename Args, int RP = 0>
 VPM_DEV void cell_output(const CellMem<IdxT>& M, const Args& A, const Frame& F, int c, int64_t off, int n,
-                         BlockScratch<WPB>* bs, IdxT* leaf_start, IdxT* mlist, IdxT* msched) {
+                         BlockScratch<WPB>* bs, IdxT* leaf_start, IdxT* mlist, IdxT* msched, bool defer = false) {
     constexpr int NT = WAVE * WPB;
     const int lane = opaque_lane();
     const int tid = WPB == 1 ? lane : opaque_tid();
     const int wv = threadIdx.x / WAVE;
     CellShared& sh = *M.sh;
     // one scan over the cell's slots gives leaf ordinals and output slots
-    const int per = (n + NT - 1) / NT;
-    const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
     const int npair = A.P.merge_mode == VPM_MERGE_PAIR ? 2 : 1;
-    int64_t loc = 0;
-    for (int p = b0; p < b1; ++p) {
-        const uint8_t inf = M.info[p];
+    // a slot's contribution: (1 if it heads a subset) << 32 | (its outputs)
+    auto slot_val = [&](uint8_t inf) -> int64_t {
         const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
-        loc += ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
-    }
-    const int64_t inc = wave_incl_scan(loc, lane);
-    int64_t tot, wbase = 0;
-    if constexpr (WPB > 1) {
-        if (lane == WAVE - 1) bs->scan[wv] = inc;
-        __syncthreads();
-        tot = 0;
-        for (int w = 0; w < WPB; ++w) {
-            if (w < wv) wbase += bs->scan[w];
-            tot += bs->scan[w];
-        }
-    } else {
-        tot = __shfl(inc, WAVE - 1);
-    }
-    int64_t pre = wbase + inc - loc;
-    const int nleaves = (int)(tot >> 32);
-    const int out_total = (int)(tot & 0xffffffff);
-    if (tid == 0) sh.nmerged = 0;
-    cell_sync<WPB>();
-    for (int p = b0; p < b1; ++p) {
-        const uint8_t inf = M.info[p];
-        const int e = (inf & INF_MERGED) ? ((inf & INF_HEAD) ? npair : 0) : 1;
+        return ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
+    };
+    // what a slot records once its prefix `pre` (over the slots before it) is known
+    auto record_slot = [&](int p, uint8_t inf, int64_t pre) {
         const int ord = (int)(pre >> 32) + ((inf & INF_HEAD) ? 1 : 0) - 1;
         if (A.mode == 0) {
             M.emit[p] = (IdxT)(pre & 0xffffffff);
@@ -1900,7 +1880,78 @@ VPM_DEV void cell_output(const CellMem<IdxT>& M, const Args& A, const Frame& F, 
             leaf_start[ord] = (IdxT)p;
             if ((inf & INF_MERGED) && A.mode == 0) mlist[atomicAdd(&sh.nmerged, 1)] = (IdxT)ord;
         }
-        pre += ((int64_t)((inf & INF_HEAD) ? 1 : 0) << 32) | (int64_t)e;
+    };
+    int nleaves, out_total;
+    bool seg_scan = false;
+    if constexpr (WPB > 1 && RP == 0) seg_scan = n > NMAX_NARROW;   // global-memory cells only
+    if (seg_scan) {
+        // A cell above NMAX_NARROW: each wavefront scans one contiguous segment in rounds of 64
+        // consecutive slots (coalesced, RB rounds' loads in flight together), after a first pass
+        // that totals the segments.
+        constexpr int RB = 8;
+        const int seg = (n + WPB - 1) / WPB;
+        const int s0 = min(n, wv * seg), s1 = min(n, s0 + seg);
+        int64_t acc = 0;
+        for (int j0 = s0; j0 < s1; j0 += RB * WAVE) {
+            uint8_t b[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) b[u] = M.info[min(j0 + u * WAVE + lane, s1 - 1)];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) acc += j0 + u * WAVE + lane < s1 ? slot_val(b[u]) : 0;
+        }
+        const int64_t wtot = __shfl(wave_incl_scan(acc, lane), WAVE - 1);
+        if (lane == 0) bs->scan[wv] = wtot;
+        __syncthreads();
+        int64_t run = 0, tot = 0;
+        for (int w = 0; w < WPB; ++w) {
+            if (w < wv) run += bs->scan[w];
+            tot += bs->scan[w];
+        }
+        nleaves = (int)(tot >> 32);
+        out_total = (int)(tot & 0xffffffff);
+        if (tid == 0) sh.nmerged = 0;
+        __syncthreads();
+        for (int j0 = s0; j0 < s1; j0 += RB * WAVE) {
+            uint8_t b[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) b[u] = M.info[min(j0 + u * WAVE + lane, s1 - 1)];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const int p = j0 + u * WAVE + lane;
+                const int64_t v = p < s1 ? slot_val(b[u]) : 0;
+                const int64_t inc = wave_incl_scan(v, lane);
+                if (p < s1) record_slot(p, b[u], run + inc - v);
+                run += __shfl(inc, WAVE - 1);
+            }
+        }
+    } else {
+        const int per = (n + NT - 1) / NT;
+        const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+        int64_t loc = 0;
+        for (int p = b0; p < b1; ++p) loc += slot_val(M.info[p]);
+        const int64_t inc = wave_incl_scan(loc, lane);
+        int64_t tot, wbase = 0;
+        if constexpr (WPB > 1) {
+            if (lane == WAVE - 1) bs->scan[wv] = inc;
+            __syncthreads();
+            tot = 0;
+            for (int w = 0; w < WPB; ++w) {
+                if (w < wv) wbase += bs->scan[w];
+                tot += bs->scan[w];
+            }
+        } else {
+            tot = __shfl(inc, WAVE - 1);
+        }
+        int64_t pre = wbase + inc - loc;
+        nleaves = (int)(tot >> 32);
+        out_total = (int)(tot & 0xffffffff);
+        if (tid == 0) sh.nmerged = 0;
+        cell_sync<WPB>();
+        for (int p = b0; p < b1; ++p) {
+            const uint8_t inf = M.info[p];
+            record_slot(p, inf, pre);
+            pre += slot_val(inf);
+        }
     }
     if (tid == 0) leaf_start[nleaves] = (IdxT)n;
     cell_sync<WPB>();
@@ -1908,6 +1959,14 @@ VPM_DEV void cell_output(const CellMem<IdxT>& M, const Args& A, const Frame& F, 
     if (A.mode == 1) {
         if (tid == 0) {
             A.n_subsets[c] = nleaves;
+            if (fl) atomicOr(A.flags, fl);
+        }
+        return;
+    }
+    if (defer) {
+        if (tid == 0) {
+            A.out_count[c] = out_total;
+            A.cell_mode[c] = CELL_PROCESSED;
             if (fl) atomicOr(A.flags, fl);
         }
         return;
@@ -2172,8 +2231,12 @@ __global__ __launch_bounds__(WAVE * WPB, 2) void k_fixed_cells(FixedArgsT<InT> A
 constexpr int BIG_NODES = NMAX_BIG / 2 + 2;
 constexpr int C_TASK_HEAD = 28, C_TASK_RESERVE = 29, C_PENDING = 30;   // counters, reset per call
 
-struct BigTask { int32_t qi, cur; Node<uint32_t> nd; };
-struct BigCell { Frame F; int64_t off; int32_t n, c, open, pad; };
+// A task: a subset to split (TASK_NODE), or part of the output of a cell above NMAX_NARROW once its
+// partition is complete: the copies of slots nd.start .. nd.start + nd.len - 1 (TASK_COPY), or the
+// merged subsets nd.start, nd.start + nd.len, nd.start + 2 nd.len, ... of its list (TASK_MERGE).
+enum { TASK_NODE = 0, TASK_COPY = 1, TASK_MERGE = 2 };
+struct BigTask { int32_t qi, cur; Node<uint32_t> nd; int32_t kind; };
+struct BigCell { Frame F; int64_t off; int32_t n, c, open, nmerged; };
 
 template <typename InT>
 struct BigArgs {
@@ -2206,14 +2269,14 @@ VPM_DEV int ld_relaxed(const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_
 // Queue subset nd of cell qi (its members in index buffer cur) as a task.  The caller has made the
 // writes it depends on visible at device scope.
 template <typename InT>
-VPM_DEV void spawn_task(const BigArgs<InT>& B, int qi, int cur, Node<uint32_t> nd) {
+VPM_DEV void spawn_task(const BigArgs<InT>& B, int qi, int cur, Node<uint32_t> nd, int kind = TASK_NODE) {
     int32_t* const ctr = B.A.counters;
-    atomicAdd(&B.cells[qi].open, 1);
+    if (kind == TASK_NODE) atomicAdd(&B.cells[qi].open, 1);     // output tasks are not pieces of the partition
     atomicAdd(&ctr[C_PENDING], 1);
     const int idx = atomicAdd(&ctr[C_TASK_RESERVE], 1);
     const int slot = idx % B.ring_size;
     BigTask t;
-    t.qi = qi; t.cur = cur; t.nd = nd;
+    t.qi = qi; t.cur = cur; t.nd = nd; t.kind = kind;
     B.tasks[slot] = t;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(&B.ready[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2411,6 +2474,59 @@ VPM_DEV int wide_split(const BigArgs<InT>& B, const CellMem<uint32_t>& M, const 
     return nk;
 }
 
+// One output task of a cell above NMAX_NARROW (its slots, leaf starts and merged list are complete):
+// TASK_COPY copies the unmerged particles of slots a .. a + cnt - 1 to their output slots; TASK_MERGE
+// merges the subsets a, a + cnt, a + 2 cnt, ... of the merged list (Step 7), one wavefront each.
+template <typename InT>
+VPM_DEV void output_task(const BigArgs<InT>& B, const CellMem<uint32_t>& M, const Frame& F, int64_t off, int n,
+                         int kind, int a, int cnt, int nm) {
+    constexpr int NT = WAVE * 8;
+    const auto& A = B.A;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    if (kind == TASK_COPY) {
+        const InT* const ib[7] = {A.in.x + off, A.in.y + off, A.in.z + off, A.in.px + off,
+                                  A.in.py + off, A.in.pz + off, A.in.w + off};
+        float* const ob[7] = {A.tmp.x + off, A.tmp.y + off, A.tmp.z + off, A.tmp.px + off,
+                              A.tmp.py + off, A.tmp.pz + off, A.tmp.w + off};
+        const int end = a + cnt;
+        for (int p0 = a + tid; p0 < end; p0 += COPY_BATCH * NT) {
+            uint32_t si[COPY_BATCH], so[COPY_BATCH];
+            bool keep[COPY_BATCH];
+#pragma unroll
+            for (int u = 0; u < COPY_BATCH; ++u) {
+                const int p = min(p0 + u * NT, end - 1);
+                const uint8_t inf = M.info[p];
+                si[u] = idx_buf(M, inf & INF_PARITY)[p];
+                so[u] = M.emit[p];
+                keep[u] = p0 + u * NT < end && !(inf & INF_MERGED);
+            }
+            float v[COPY_BATCH][7];
+#pragma unroll
+            for (int u = 0; u < COPY_BATCH; ++u)
+                if (keep[u])
+#pragma unroll
+                    for (int f = 0; f < 7; ++f) v[u][f] = (float)ib[f][si[u]];
+#pragma unroll
+            for (int u = 0; u < COPY_BATCH; ++u)
+                if (keep[u])
+#pragma unroll
+                    for (int f = 0; f < 7; ++f) ob[f][so[u]] = v[u][f];
+        }
+    } else {
+        const uint32_t* leaf_start = (const uint32_t*)M.rec;
+        const uint32_t* mlist = leaf_start + (n + 1);
+        for (int k = a + wv * cnt; k < nm; k += 8 * cnt) {
+            const int ord = (int)mlist[k];
+            const int st = (int)leaf_start[ord];
+            const int ln = (int)leaf_start[ord + 1] - st;
+            const uint8_t inf = M.info[st];
+            const uint32_t* src = idx_buf(M, inf & INF_PARITY);
+            merge_subset(A, F, [&](int j) { return off + (int64_t)src[st + j]; }, ln, (inf >> INF_JSHIFT) & 3,
+                         off + M.emit[st], lane, WAVE);
+        }
+    }
+}
+
 template <typename InT>
 __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
     constexpr int WPB = 8, NT = WAVE * WPB;
@@ -2467,6 +2583,7 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
         int qi, c, n, m = 0, cur = 0;
         bool wide = false;                     // the piece starts with a subset above NMAX_NARROW
         Node<IdxT> wnode;
+        int tkind = TASK_NODE, nmerged = 0;
         int64_t off;
         Frame F;
         CellMem<IdxT> M;
@@ -2517,12 +2634,14 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
             n = bc.n;
             c = bc.c;
             cur = t.cur;
-            wide = t.nd.len > (uint32_t)NMAX_NARROW;
+            tkind = t.kind;
+            wide = tkind == TASK_NODE && t.nd.len > (uint32_t)NMAX_NARROW;
             wnode = t.nd;
-            m = wide ? 0 : 1;
+            m = wide || tkind != TASK_NODE ? 0 : 1;
+            nmerged = bc.nmerged;
             __syncthreads();                           // every thread has read the slot
             if (tid == 0) {
-                if (!wide) (cur ? M.nodes1 : M.nodes0)[0] = t.nd;
+                if (tkind == TASK_NODE && !wide) (cur ? M.nodes1 : M.nodes0)[0] = t.nd;
                 __hip_atomic_store(&B.ready[sh.qi], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
@@ -2532,6 +2651,14 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
         M.idx1 = B.idx1 + off;
         M.emit = B.emit + off;
         M.info = B.info + off;
+        if (tkind != TASK_NODE) {
+            // part of the output of a cell above NMAX_NARROW (not a piece of its partition)
+            output_task(B, M, F, off, n, tkind, (int)wnode.start, (int)wnode.len, nmerged);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (tid == 0) atomicSub(&ctr[C_PENDING], 1);
+            continue;
+        }
         if (kind == 1) {
             FSums R;
             fsums_zero(R);
@@ -2631,7 +2758,33 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
         __syncthreads();
         if (sh.last) {
             IdxT* scratch = (IdxT*)M.rec;              // the codes are no longer needed
-            cell_output<WPB, IdxT>(M, A, F, c, off, n, bs, scratch, scratch + (n + 1), scratch + (2 * n + 1));
+            // a cell above NMAX_NARROW: its copies and merges go to other workgroups as tasks
+            const bool defer = n > NMAX_NARROW && A.mode == 0;
+            cell_output<WPB, IdxT>(M, A, F, c, off, n, bs, scratch, scratch + (n + 1), scratch + (2 * n + 1),
+                                   defer);
+            if (defer) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // slots, leaf starts, merged list
+                __syncthreads();
+                if (tid == 0) {
+                    const int nm = sh.nmerged;
+                    B.cells[qi].nmerged = nm;
+                    // at most n / NMAX_NARROW tasks of each kind (the ring holds n / TASK_MIN)
+                    const int kc = (n + NMAX_NARROW - 1) / NMAX_NARROW, span = (n + kc - 1) / kc;
+                    Node<IdxT> r;
+                    r.thr_axis = 0;
+                    for (int k = 0; k < kc; ++k) {
+                        r.start = (IdxT)(k * span);
+                        r.len = (IdxT)min(span, n - k * span);
+                        spawn_task(B, qi, 0, r, TASK_COPY);
+                    }
+                    const int km = min(nm, kc);
+                    for (int k = 0; k < km; ++k) {
+                        r.start = (IdxT)k;
+                        r.len = (IdxT)km;
+                        spawn_task(B, qi, 0, r, TASK_MERGE);
+                    }
+                }
+            }
         }
         __syncthreads();
         if (tid == 0) {
