@@ -2234,8 +2234,18 @@ constexpr int C_TASK_HEAD = 28, C_TASK_RESERVE = 29, C_PENDING = 30;   // counte
 // A task: a subset to split (TASK_NODE), or part of the output of a cell above NMAX_NARROW once its
 // partition is complete: the copies of slots nd.start .. nd.start + nd.len - 1 (TASK_COPY), or the
 // merged subsets nd.start, nd.start + nd.len, nd.start + 2 nd.len, ... of its list (TASK_MERGE).
-enum { TASK_NODE = 0, TASK_COPY = 1, TASK_MERGE = 2 };
+// TASK_WCOUNT and TASK_WPLACE are the two passes of one chunk of a subset above NMAX_NARROW split by
+// several workgroups (nd.start: the job, nd.len: the chunk).
+enum { TASK_NODE = 0, TASK_COPY = 1, TASK_MERGE = 2, TASK_WCOUNT = 3, TASK_WPLACE = 4 };
+VPM_DEV bool task_is_piece(int kind) { return kind != TASK_COPY && kind != TASK_MERGE; }
 struct BigTask { int32_t qi, cur; Node<uint32_t> nd; int32_t kind; };
+// A subset above NMAX_NARROW split by several workgroups: its slots fall into `nchunks` chunks of at
+// least NMAX_NARROW (records chunk0 ..); `left` counts the chunks still to finish the current pass.
+struct WideJob { Node<uint32_t> nd; int32_t cur, qi, nchunks, chunk0, left, n1, d0, d1; };
+// One chunk: the lower side's count per wavefront segment, the chunk's first V1 position, and (after
+// the counting pass) the exact moments of the subset's and V1's members in the chunk.
+struct WideChunk { int32_t cnt[8]; int32_t lb, pad; uint64_t P[19], L[19]; };
+constexpr int C_JOBS = 16, C_CHUNKS = 17;     // allocation counters of jobs and chunks, reset per call
 struct BigCell { Frame F; int64_t off; int32_t n, c, open, nmerged; };
 
 template <typename InT>
@@ -2251,6 +2261,9 @@ struct BigArgs {
     int32_t ring_size;
     Node<uint32_t>* lists;         // per workgroup: two node lists of BIG_NODES
     uint32_t* sched;               // per workgroup: a schedule table of BIG_NODES
+    WideJob* jobs;                 // subsets above NMAX_NARROW split by several workgroups (capacities:
+    WideChunk* chunks;             // 0 splits every such subset with one workgroup)
+    int32_t jobs_cap, chunks_cap;
     int32_t wait_idle;             // idle workgroups wait for tasks (else they leave the chip to
                                    // kernels running beside this one)
 };
@@ -2271,7 +2284,7 @@ VPM_DEV int ld_relaxed(const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_
 template <typename InT>
 VPM_DEV void spawn_task(const BigArgs<InT>& B, int qi, int cur, Node<uint32_t> nd, int kind = TASK_NODE) {
     int32_t* const ctr = B.A.counters;
-    if (kind == TASK_NODE) atomicAdd(&B.cells[qi].open, 1);     // output tasks are not pieces of the partition
+    if (task_is_piece(kind)) atomicAdd(&B.cells[qi].open, 1);    // output tasks are not pieces of the partition
     atomicAdd(&ctr[C_PENDING], 1);
     const int idx = atomicAdd(&ctr[C_TASK_RESERVE], 1);
     const int slot = idx % B.ring_size;
@@ -2313,6 +2326,75 @@ VPM_DEV void wsums_block_reduce(WSums& S, uint64_t* part) {
         }
     }
     __syncthreads();
+}
+
+// Thread 0: the decisions of the two children of a subset of len particles above NMAX_NARROW whose
+// lower side V1 holds n1, from the subset's exact moments P and V1's L (V2's are P - L), into dv[0]
+// and dv[1] (dv[1] = -1: the cut left a side empty, which the exact rule never does; the subset ends).
+template <typename Args>
+VPM_DEV void decide_children(const Args& A, const CellMem<uint32_t>& M, const Frame& F, const WSums& P,
+                             const WSums& L, int len, int n1, int* dv) {
+    const int n2 = len - n1;
+    if (n1 == 0 || n2 == 0) {
+        atomicOr(&M.sh->flags, FLAG_INTERNAL);
+        Decision d; d.kind = D_MERGED; d.axis = 0; d.thr = 0; d.jdir = 0;
+        dv[0] = pack_decision(d);
+        dv[1] = -1;
+        return;
+    }
+    const DecideConsts& K = M.sh->dc;
+    Decision cp; cp.kind = D_COPY; cp.axis = 0; cp.thr = 0; cp.jdir = 0;
+    WSums R;
+    R.s0 = P.s0 - L.s0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) { R.s1[l] = P.s1[l] - L.s1[l]; R.s2[l] = sub128(P.s2[l], L.s2[l]); }
+    dv[0] = pack_decision(n1 < A.P.min_subset ? cp : decide_exact_wide(L, K, F));
+    dv[1] = pack_decision(n2 < A.P.min_subset ? cp : decide_exact_wide(R, K, F));
+}
+
+// The children of a subset above NMAX_NARROW once it is cut (its members placed in the other index
+// buffer) and decided (d0, d1): finished children are recorded, unfinished ones of TASK_MIN or more
+// become tasks, smaller ones go to `kept` (the node list of the other buffer).  All threads call;
+// returns the number kept.
+template <typename InT>
+VPM_DEV int wide_children(const BigArgs<InT>& B, const CellMem<uint32_t>& M, BlockScratch<8>* bs,
+                          Node<uint32_t> nd, int cur, int qi, int n1, int d0, int d1, Node<uint32_t>* kept) {
+    constexpr int NT = WAVE * 8;
+    const int tid = threadIdx.x;
+    const int start = nd.start, len = nd.len, n2 = len - n1;
+    const int rev = (nd.thr_axis >> 3) & 1;
+    int* const dv = bs->vote[0];
+    __syncthreads();                                    // dv may still be read
+    if (tid == 0) { dv[2] = 0; dv[3] = 0; }             // children kept, children handed out
+    __syncthreads();
+    Node<uint32_t>* const hand = (Node<uint32_t>*)(dv + 4);   // bs->vote[0][4] on: two nodes
+    for (int ch = 0; ch < 2; ++ch) {
+        const int dvv = ch == 0 ? d0 : d1;
+        if (dvv == -1) continue;
+        const Decision d = unpack_decision(dvv);
+        const int cs = d1 == -1 ? start : (ch == 0 ? start : start + n1);
+        const int cl = d1 == -1 ? len : (ch == 0 ? n1 : n2);
+        const int crev = d1 == -1 ? (n1 == 0 ? rev ^ 1 : rev) : (ch == 0 ? rev : rev ^ 1);
+        if (d.kind == D_SPLIT) {
+            if (tid == 0) {
+                Node<uint32_t> c;
+                c.start = (uint32_t)cs; c.len = (uint32_t)cl;
+                c.thr_axis = (d.thr << 8) | (crev << 3) | d.axis;
+                if (cl >= TASK_MIN) hand[dv[3]++] = c;
+                else kept[dv[2]++] = c;
+            }
+        } else {
+            record_final(M, B.A, d, cs, cl, crev, cur, tid, NT);
+        }
+    }
+    // the cut and the info bytes, device-wide, before another workgroup may take a child
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    const int nk = dv[2], nh = dv[3];
+    if (tid == 0)
+        for (int h = 0; h < nh; ++h) spawn_task(B, qi, cur ^ 1, hand[h]);
+    __syncthreads();                                    // dv is read before it is reused
+    return nk;
 }
 
 // Steps 5-6 for one subset of more than NMAX_NARROW particles, by the whole workgroup: the stable
@@ -2420,58 +2502,205 @@ VPM_DEV int wide_split(const BigArgs<InT>& B, const CellMem<uint32_t>& M, const 
         }
     }
     wsums_block_reduce<WPB>(L, (uint64_t*)M.sched);
-    const int n2 = len - n1;
     int* const dv = bs->vote[0];
-    if (tid == 0) {
-        if (n1 == 0 || n2 == 0) {
-            // impossible under the exact rule (the chosen axis has V > 0); end the subset
-            atomicOr(&M.sh->flags, FLAG_INTERNAL);
-            Decision d; d.kind = D_MERGED; d.axis = 0; d.thr = 0; d.jdir = 0;
-            dv[0] = pack_decision(d);
-            dv[1] = -1;
-        } else {
-            const DecideConsts& K = M.sh->dc;
-            Decision cp; cp.kind = D_COPY; cp.axis = 0; cp.thr = 0; cp.jdir = 0;
-            WSums R;
-            R.s0 = P.s0 - L.s0;
-#pragma unroll
-            for (int l = 0; l < 6; ++l) { R.s1[l] = P.s1[l] - L.s1[l]; R.s2[l] = sub128(P.s2[l], L.s2[l]); }
-            dv[0] = pack_decision(n1 < A.P.min_subset ? cp : decide_exact_wide(L, K, F));
-            dv[1] = pack_decision(n2 < A.P.min_subset ? cp : decide_exact_wide(R, K, F));
+    if (tid == 0) decide_children(A, M, F, P, L, len, n1, dv);
+    __syncthreads();
+    return wide_children(B, M, bs, nd, cur, qi, n1, dv[0], dv[1], kept);
+}
+
+VPM_DEV void wsums_store(uint64_t* q, const WSums& S) {
+    q[0] = S.s0;
+    for (int l = 0; l < 6; ++l) {
+        q[1 + l] = (uint64_t)S.s1[l];
+        q[7 + 2 * l] = S.s2[l].lo;
+        q[8 + 2 * l] = S.s2[l].hi;
+    }
+}
+
+VPM_DEV WSums wsums_load(const uint64_t* q) {
+    WSums S;
+    S.s0 = q[0];
+    for (int l = 0; l < 6; ++l) {
+        S.s1[l] = (int64_t)q[1 + l];
+        S.s2[l] = u128_make(q[7 + 2 * l], q[8 + 2 * l]);
+    }
+    return S;
+}
+
+// ------------------------------------------------------------------------------------------
+// A subset above NMAX_NARROW split by several workgroups.  Its slots fall into K = len / NMAX_NARROW
+// chunks; each chunk is a task in two passes.  Counting: the chunk's lower side per wavefront segment
+// and the exact moments of its members and of its V1 members.  The workgroup that finishes the last
+// count adds the chunks up in chunk order (integer sums: the result does not depend on which
+// workgroup does what), decides both children by the exact rule and gives every chunk its first V1
+// position.  Placing: each chunk puts its members at their positions in the other index buffer, V1
+// from the front in slot order and V2 from the back in reverse order, as one workgroup would.  The
+// workgroup that finishes the last placement records the children.
+// ------------------------------------------------------------------------------------------
+
+// Hand subset nd of cell qi (members in index buffer cur) to the chunk tasks of a new job.  All
+// threads call, after the subset's members are visible device-wide; false when the job and chunk
+// records are used up (the caller then splits the subset itself).
+template <typename InT>
+VPM_DEV bool start_wide_job(const BigArgs<InT>& B, BlockScratch<8>* bs, Node<uint32_t> nd, int cur, int qi) {
+    int* const flag = &bs->vote[1][7];
+    if (threadIdx.x == 0) {
+        int ok = 0;
+        const int K = (int)(nd.len / (uint32_t)NMAX_NARROW);          // >= 1
+        if (B.jobs_cap > 0) {
+            const int j = atomicAdd(&B.A.counters[C_JOBS], 1);
+            const int c0 = atomicAdd(&B.A.counters[C_CHUNKS], K);
+            if (j < B.jobs_cap && c0 <= B.chunks_cap - K) {
+                WideJob& J = B.jobs[j];
+                J.nd = nd; J.cur = cur; J.qi = qi; J.nchunks = K; J.chunk0 = c0; J.left = K;
+                Node<uint32_t> r;
+                r.start = (uint32_t)j; r.thr_axis = 0;
+                for (int k = 0; k < K; ++k) { r.len = (uint32_t)k; spawn_task(B, qi, cur, r, TASK_WCOUNT); }
+                ok = 1;
+            }
         }
-        dv[2] = 0;                                      // children kept
-        dv[3] = 0;                                      // children to hand out
+        *flag = ok;
     }
     __syncthreads();
-    Node<uint32_t>* const hand = (Node<uint32_t>*)(dv + 4);   // bs->vote[1] and past: two nodes
-    const int d0 = dv[0], d1 = dv[1];
-    for (int ch = 0; ch < 2; ++ch) {
-        const int dvv = ch == 0 ? d0 : d1;
-        if (dvv == -1) continue;
-        const Decision d = unpack_decision(dvv);
-        const int cs = d1 == -1 ? start : (ch == 0 ? start : start + n1);
-        const int cl = d1 == -1 ? len : (ch == 0 ? n1 : n2);
-        const int crev = d1 == -1 ? (n1 == 0 ? rev ^ 1 : rev) : (ch == 0 ? rev : rev ^ 1);
-        if (d.kind == D_SPLIT) {
-            if (tid == 0) {
-                Node<uint32_t> c;
-                c.start = (uint32_t)cs; c.len = (uint32_t)cl;
-                c.thr_axis = (d.thr << 8) | (crev << 3) | d.axis;
-                if (cl >= TASK_MIN) hand[dv[3]++] = c;
-                else kept[dv[2]++] = c;
+    const bool ok = *flag != 0;
+    __syncthreads();
+    return ok;
+}
+
+// The slots of chunk k of a job, relative to its subset: [a, b), and wavefront wv's segment of it.
+VPM_DEV void chunk_range(int len, int K, int k, int wv, int& s0, int& s1) {
+    const int span = (len + K - 1) / K;
+    const int a = min(len, k * span), b = min(len, a + span);
+    const int seg = (b - a + 7) / 8;
+    s0 = min(b, a + wv * seg);
+    s1 = min(b, s0 + seg);
+}
+
+// The counting pass of chunk k of job j (all threads).
+template <typename InT>
+VPM_DEV void wide_count_task(const BigArgs<InT>& B, const CellMem<uint32_t>& M, const Frame& F,
+                             BlockScratch<8>* bs, int j, int k) {
+    constexpr int WPB = 8;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    WideJob& J = B.jobs[j];
+    const Node<uint32_t> nd = J.nd;
+    const int cur = J.cur, K = J.nchunks, len = nd.len;
+    const int ax = nd.thr_axis & 7, thr = nd.thr_axis >> 8;
+    WideChunk& ck = B.chunks[J.chunk0 + k];
+    const uint32_t* src = idx_buf(M, cur) + nd.start;
+    int s0, s1;
+    chunk_range(len, K, k, wv, s0, s1);
+    constexpr int WB = 4;
+    // two passes over the chunk (the subset's members, then V1's), so that one set of wide sums is
+    // live at a time
+    int cnt = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        WSums S;
+        wsums_zero(S);
+        for (int j0 = s0; j0 < s1; j0 += WB * WAVE) {
+            uint32_t ix[WB];
+#pragma unroll
+            for (int u = 0; u < WB; ++u) ix[u] = src[min(j0 + u * WAVE + lane, s1 - 1)];
+            int c[WB][6], om[WB];
+#pragma unroll
+            for (int u = 0; u < WB; ++u) codes_of(M, (int)ix[u], c[u], om[u]);
+#pragma unroll
+            for (int u = 0; u < WB; ++u) {
+                if (j0 + u * WAVE + lane >= s1) continue;
+                int cv = c[u][0];
+#pragma unroll
+                for (int l = 1; l < 6; ++l) if (l == ax) cv = c[u][l];
+                if (pass == 0 || cv <= thr) wsums_add(S, om[u], c[u]);
+                if (pass == 1 && cv <= thr) ++cnt;
             }
-        } else {
-            record_final(M, A, d, cs, cl, crev, cur, tid, NT);
         }
+        wsums_block_reduce<WPB>(S, (uint64_t*)M.sched);
+        if (tid == 0) wsums_store(pass == 0 ? ck.P : ck.L, S);
     }
-    // the cut and the info bytes, device-wide, before another workgroup may take a child
+    cnt = group_sum(cnt, WAVE);
+    if (lane == 0) ck.cnt[wv] = cnt;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    const int nk = dv[2], nh = dv[3];
-    if (tid == 0)
-        for (int h = 0; h < nh; ++h) spawn_task(B, qi, cur ^ 1, hand[h]);
-    __syncthreads();                                    // dv is read before it is reused
-    return nk;
+    if (tid == 0 && atomicSub(&J.left, 1) == 1) {
+        // the last count: the chunks in order, the children's decisions, each chunk's first V1 slot
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        WSums Pt, Lt;
+        wsums_zero(Pt); wsums_zero(Lt);
+        int n1 = 0;
+        for (int q = 0; q < K; ++q) {
+            WideChunk& cq = B.chunks[J.chunk0 + q];
+            cq.lb = n1;
+            for (int w = 0; w < 8; ++w) n1 += cq.cnt[w];
+            wsums_acc(Pt, wsums_load(cq.P));
+            wsums_acc(Lt, wsums_load(cq.L));
+        }
+        int dv[2];
+        decide_children(B.A, M, F, Pt, Lt, len, n1, dv);
+        J.n1 = n1; J.d0 = dv[0]; J.d1 = dv[1];
+        J.left = K;
+        Node<uint32_t> r;
+        r.start = (uint32_t)j; r.thr_axis = 0;
+        for (int q = 0; q < K; ++q) { r.len = (uint32_t)q; spawn_task(B, J.qi, cur, r, TASK_WPLACE); }
+    }
+}
+
+// The placing pass of chunk k of job j (all threads).  The workgroup that places the last chunk
+// records the children; it returns the number of children it keeps in `kept` (else 0).
+template <typename InT>
+VPM_DEV int wide_place_task(const BigArgs<InT>& B, const CellMem<uint32_t>& M, BlockScratch<8>* bs, int j, int k,
+                            Node<uint32_t>* kept) {
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    WideJob& J = B.jobs[j];
+    const Node<uint32_t> nd = J.nd;
+    const int cur = J.cur, K = J.nchunks, len = nd.len, start = nd.start;
+    const int ax = nd.thr_axis & 7, thr = nd.thr_axis >> 8;
+    const WideChunk& ck = B.chunks[J.chunk0 + k];
+    const uint32_t* src = idx_buf(M, cur) + start;
+    uint32_t* dst = idx_buf(M, cur ^ 1);
+    int s0, s1;
+    chunk_range(len, K, k, wv, s0, s1);
+    int lb = ck.lb;
+    for (int w = 0; w < wv; ++w) lb += ck.cnt[w];
+    int rb = s0 - lb;                                   // V2 members before this segment
+    const uint64_t below = lanes_below();
+    constexpr int WB = 4;
+    for (int j0 = s0; j0 < s1; j0 += WB * WAVE) {
+        uint32_t ix[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) ix[u] = src[min(j0 + u * WAVE + lane, s1 - 1)];
+        int cv[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) {
+            int c[6], om;
+            codes_of(M, (int)ix[u], c, om);
+            cv[u] = c[0];
+#pragma unroll
+            for (int l = 1; l < 6; ++l) if (l == ax) cv[u] = c[l];
+        }
+#pragma unroll
+        for (int u = 0; u < WB; ++u) {
+            const bool act = j0 + u * WAVE + lane < s1;
+            const bool right = cv[u] > thr;
+            const uint64_t br = ballot(act && right), bl = ballot(act && !right);
+            if (act) {
+                if (right) dst[start + len - 1 - (rb + __popcll(br & below))] = ix[u];
+                else dst[start + lb + __popcll(bl & below)] = ix[u];
+            }
+            lb += __popcll(bl);
+            rb += __popcll(br);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    int* const flag = &bs->vote[1][7];
+    if (tid == 0) {
+        const int last = atomicSub(&J.left, 1) == 1 ? 1 : 0;
+        if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every chunk's placements
+        *flag = last;
+    }
+    __syncthreads();
+    if (!*flag) return 0;
+    return wide_children(B, M, bs, nd, cur, J.qi, J.n1, J.d0, J.d1, kept);
 }
 
 // One output task of a cell above NMAX_NARROW (its slots, leaf starts and merged list are complete):
@@ -2651,13 +2880,19 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
         M.idx1 = B.idx1 + off;
         M.emit = B.emit + off;
         M.info = B.info + off;
-        if (tkind != TASK_NODE) {
+        if (!task_is_piece(tkind)) {
             // part of the output of a cell above NMAX_NARROW (not a piece of its partition)
             output_task(B, M, F, off, n, tkind, (int)wnode.start, (int)wnode.len, nmerged);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
             if (tid == 0) atomicSub(&ctr[C_PENDING], 1);
             continue;
+        }
+        if (tkind == TASK_WCOUNT) {
+            wide_count_task(B, M, F, bs, (int)wnode.start, (int)wnode.len);
+        } else if (tkind == TASK_WPLACE) {
+            m = wide_place_task(B, M, bs, (int)wnode.start, (int)wnode.len, cur ? M.nodes0 : M.nodes1);
+            cur ^= 1;
         }
         if (kind == 1) {
             FSums R;
@@ -2704,10 +2939,15 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
         }
         __syncthreads();
         if (wide) {
-            // a subset above NMAX_NARROW: split by the whole workgroup; its unfinished children of
-            // at least TASK_MIN particles become tasks, the smaller ones continue here
-            m = wide_split(B, M, F, bs, wnode, cur, qi, cur ? M.nodes0 : M.nodes1);
-            cur ^= 1;
+            // a subset above NMAX_NARROW: split by several workgroups (a job of chunk tasks), or by
+            // this whole workgroup when the job records are used up; unfinished children of at least
+            // TASK_MIN particles become tasks, the smaller ones continue here
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // its members and codes, device-wide
+            __syncthreads();
+            if (!start_wide_job(B, bs, wnode, cur, qi)) {
+                m = wide_split(B, M, F, bs, wnode, cur, qi, cur ? M.nodes0 : M.nodes1);
+                cur ^= 1;
+            }
         }
 
         // ---- Steps 2-6, level by level; large unfinished subsets become tasks ----
@@ -3231,6 +3471,8 @@ int fixed_lds_bytes(int which) {
 
 int64_t fixed_big_cell_bytes() { return (int64_t)sizeof(BigCell); }
 int64_t fixed_big_task_bytes() { return (int64_t)sizeof(BigTask); }
+int64_t fixed_wide_job_bytes() { return (int64_t)sizeof(WideJob); }
+int64_t fixed_wide_chunk_bytes() { return (int64_t)sizeof(WideChunk); }
 int fixed_task_min() { return TASK_MIN; }
 int64_t fixed_big_lists_bytes() { return (int64_t)(2 * BIG_NODES) * (int64_t)sizeof(Node<uint32_t>); }
 int64_t fixed_big_sched_bytes() { return (int64_t)BIG_NODES * 4; }
@@ -3315,6 +3557,10 @@ hipError_t fixed_cells_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<I
     G.ring_size = (int32_t)ws.ring_size;
     G.lists = (Node<uint32_t>*)ws.big_lists;
     G.sched = ws.big_sched;
+    G.jobs = (WideJob*)ws.big_jobs;
+    G.chunks = (WideChunk*)ws.big_chunks;
+    G.jobs_cap = ws.big_jobs ? ws.jobs_cap : 0;
+    G.chunks_cap = ws.big_chunks ? ws.chunks_cap : 0;
 
     // The three bins touch disjoint cells, queues and counters, so they may run concurrently: the
     // large-cell and 2048 bins go first on the side streams (their cells are the longest), the

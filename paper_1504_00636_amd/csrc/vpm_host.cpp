@@ -113,7 +113,7 @@ void free_ws(Workspace& ws) {
     if (ws.flags) hipFree(ws.flags);
     if (ws.scan_blocks) hipFree(ws.scan_blocks);
     void* bigs[] = {ws.big_rec, ws.big_pyz, ws.big_idx0, ws.big_idx1, ws.big_emit, ws.big_info, ws.big_cells,
-                    ws.big_tasks, ws.big_ready, ws.big_lists, ws.big_sched};
+                    ws.big_tasks, ws.big_ready, ws.big_lists, ws.big_sched, ws.big_jobs, ws.big_chunks};
     for (void* b : bigs) if (b) hipFree(b);
     if (ws.perm2) hipFree(ws.perm2);
     if (ws.stack) hipFree(ws.stack);
@@ -373,6 +373,13 @@ vpm_status vpm_reserve(vpm_ctx* ctx, int64_t max_particles, int64_t max_cells) {
     ws.big_wgs = ctx->grid_big;
     alloc(&ws.big_lists, (size_t)ws.big_wgs * (size_t)fixed_big_lists_bytes());
     alloc((void**)&ws.big_sched, (size_t)ws.big_wgs * (size_t)fixed_big_sched_bytes());
+    // subsets above 65,536 particles split by several workgroups: over one call, every level of such
+    // subsets holds at most np / 65,536 of them (disjoint), and there are at most 8 levels (cells of up
+    // to 2^24); a call that runs out falls back to one workgroup per subset
+    ws.jobs_cap = (int32_t)(2 * (np / 65536) + 256);
+    ws.chunks_cap = (int32_t)(9 * (np / 65536) + 256);
+    alloc(&ws.big_jobs, (size_t)ws.jobs_cap * (size_t)fixed_wide_job_bytes());
+    alloc(&ws.big_chunks, (size_t)ws.chunks_cap * (size_t)fixed_wide_chunk_bytes());
     alloc((void**)&ws.perm2, (size_t)np * 2 * 4);
     alloc((void**)&ws.stack, (size_t)np * 8);
     if (e == hipSuccess) e = hipMemset(ws.counters, 0, 4096);

@@ -60,6 +60,9 @@ struct Workspace {
     void* big_lists = nullptr;      // per workgroup of the large-cell kernel: node lists
     uint32_t* big_sched = nullptr;  // and a schedule table
     int big_wgs = 0;                // workgroups the slabs serve (the kernel's grid)
+    void* big_jobs = nullptr;       // subsets above 65,536 split by several workgroups: job records
+    void* big_chunks = nullptr;     // and their chunk records (none: one workgroup splits such a subset)
+    int32_t jobs_cap = 0, chunks_cap = 0;
     // scratch for the FP64 path: two permutation buffers and a node stack per particle slot
     int32_t* perm2 = nullptr;       // [2 * cap_particles]
     int64_t* stack = nullptr;       // [cap_particles]
@@ -177,6 +180,8 @@ const void* fixed_kernel_ptr(int which);   // for occupancy queries
 int fixed_block_threads(int which);
 int64_t fixed_big_cell_bytes();            // per-cell record of the large-cell kernel
 int64_t fixed_big_task_bytes();            // one task of its ring
+int64_t fixed_wide_job_bytes();            // a subset above 65,536 split by several workgroups
+int64_t fixed_wide_chunk_bytes();          // one chunk of it
 int fixed_task_min();                      // smallest subset handed to another workgroup
 int64_t fixed_big_lists_bytes();           // per workgroup of the large-cell kernel
 int64_t fixed_big_sched_bytes();
