@@ -72,3 +72,11 @@ def test_noalloc_rejects_sizes_past_its_limits():
         vpm.vpm_run_noalloc([a[:10] for a in arrs], cells, 10, vpm.make_params(**PARAMS), out,
                             torch.zeros(cells.numel(), dtype=torch.int64, device="cuda"), ot)
     assert ei.value.status == vpm.VPM_ERR_CAPACITY
+
+
+def test_noalloc_cell_above_2_16():
+    """A cell above 2^16 particles: vpm_run splits its top subsets over several workgroups (chunk
+    tasks), vpm_run_noalloc, which has no job records, with one workgroup each; both must give the
+    same bits."""
+    wl = population([200, 150000, 900], 33)
+    run_both(wl, vpm.VPM_MERGE_PAIR)
