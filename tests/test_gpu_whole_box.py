@@ -119,3 +119,22 @@ def test_wide_normalised_rule_and_photons(axis_rule):
     prm = dict(HEAVY, tol_p=0.03, axis_rule=axis_rule, mass=0.0)
     wl = W.from_cells([rows, ph], params=dict(prm), dtype=np.float32)
     full_check(wl, prm)
+
+
+def test_wide_cells_with_concurrent_bins():
+    """With the size bins on concurrent streams, idle workgroups of the large-cell kernel leave
+    instead of waiting for tasks: the chunk and output tasks of cells above 2^16 are then taken by
+    the workgroups that spawn them.  Same bits as the default configuration."""
+    c = ctx()
+    wl = cloud_cells([70000, 3000, 130000, 500, 5000], seed=28)
+    saved = c.get_tuning()
+    try:
+        c.set_tuning(vpm.make_tuning(concurrent_bins=1))
+        got, got_off, tot = gpu_run(wl, CLOUD)
+    finally:
+        c.set_tuning(saved)
+    ref, ref_off, ref_tot = gpu_run(wl, CLOUD)
+    assert tot == ref_tot
+    np.testing.assert_array_equal(got_off, ref_off)
+    for f in got:
+        np.testing.assert_array_equal(got[f], ref[f])
