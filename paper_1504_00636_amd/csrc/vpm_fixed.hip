@@ -2236,7 +2236,10 @@ constexpr int C_TASK_HEAD = 28, C_TASK_RESERVE = 29, C_PENDING = 30;   // counte
 // merged subsets nd.start, nd.start + nd.len, nd.start + 2 nd.len, ... of its list (TASK_MERGE).
 // TASK_WCOUNT and TASK_WPLACE are the two passes of one chunk of a subset above NMAX_NARROW split by
 // several workgroups (nd.start: the job, nd.len: the chunk).
-enum { TASK_NODE = 0, TASK_COPY = 1, TASK_MERGE = 2, TASK_WCOUNT = 3, TASK_WPLACE = 4 };
+// TASK_CFRAME and TASK_CENCODE are the root passes of a cell above NMAX_NARROW (its frame, then its
+// codes and exact root moments), one chunk each (nd.start: the job, nd.len: the chunk).
+enum { TASK_NODE = 0, TASK_COPY = 1, TASK_MERGE = 2, TASK_WCOUNT = 3, TASK_WPLACE = 4, TASK_CFRAME = 5,
+       TASK_CENCODE = 6 };
 VPM_DEV bool task_is_piece(int kind) { return kind != TASK_COPY && kind != TASK_MERGE; }
 struct BigTask { int32_t qi, cur; Node<uint32_t> nd; int32_t kind; };
 // A subset above NMAX_NARROW split by several workgroups: its slots fall into `nchunks` chunks of at
@@ -2246,7 +2249,7 @@ struct WideJob { Node<uint32_t> nd; int32_t cur, qi, nchunks, chunk0, left, n1, 
 // the counting pass) the exact moments of the subset's and V1's members in the chunk.
 struct WideChunk { int32_t cnt[8]; int32_t lb, pad; uint64_t P[19], L[19]; };
 constexpr int C_JOBS = 16, C_CHUNKS = 17;     // allocation counters of jobs and chunks, reset per call
-struct BigCell { Frame F; int64_t off; int32_t n, c, open, nmerged; };
+struct BigCell { Frame F; int64_t off; int32_t n, c, open, nmerged, bad, pad; };   // bad: passed through
 
 template <typename InT>
 struct BigArgs {
@@ -2542,7 +2545,8 @@ VPM_DEV WSums wsums_load(const uint64_t* q) {
 // threads call, after the subset's members are visible device-wide; false when the job and chunk
 // records are used up (the caller then splits the subset itself).
 template <typename InT>
-VPM_DEV bool start_wide_job(const BigArgs<InT>& B, BlockScratch<8>* bs, Node<uint32_t> nd, int cur, int qi) {
+VPM_DEV bool start_wide_job(const BigArgs<InT>& B, BlockScratch<8>* bs, Node<uint32_t> nd, int cur, int qi,
+                            int first_kind = TASK_WCOUNT) {
     int* const flag = &bs->vote[1][7];
     if (threadIdx.x == 0) {
         int ok = 0;
@@ -2555,7 +2559,7 @@ VPM_DEV bool start_wide_job(const BigArgs<InT>& B, BlockScratch<8>* bs, Node<uin
                 J.nd = nd; J.cur = cur; J.qi = qi; J.nchunks = K; J.chunk0 = c0; J.left = K;
                 Node<uint32_t> r;
                 r.start = (uint32_t)j; r.thr_axis = 0;
-                for (int k = 0; k < K; ++k) { r.len = (uint32_t)k; spawn_task(B, qi, cur, r, TASK_WCOUNT); }
+                for (int k = 0; k < K; ++k) { r.len = (uint32_t)k; spawn_task(B, qi, cur, r, first_kind); }
                 ok = 1;
             }
         }
@@ -2703,6 +2707,145 @@ VPM_DEV int wide_place_task(const BigArgs<InT>& B, const CellMem<uint32_t>& M, B
     return wide_children(B, M, bs, nd, cur, J.qi, J.n1, J.d0, J.d1, kept);
 }
 
+// The frame pass of chunk k of cell job j (all threads): the chunk's extreme values.  The workgroup
+// that finishes the last chunk forms the cell's frame (or, with a bad value, passes the cell through)
+// and starts the codes pass.
+template <typename InT>
+VPM_DEV void cell_frame_task(const BigArgs<InT>& B, BlockScratch<8>* bs, int j, int k) {
+    constexpr int NT = WAVE * 8;
+    const auto& A = B.A;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+    WideJob& J = B.jobs[j];
+    const int K = J.nchunks, n = J.nd.len, qi = J.qi;
+    BigCell& bc = B.cells[qi];
+    const int64_t off = bc.off;
+    const int c = bc.c;
+    const int span = (n + K - 1) / K;
+    const int a = min(n, k * span), b = min(n, a + span);
+    FrameAcc acc;
+    facc_init(acc);
+    facc_cell(acc, A.in, off + a, tid, b - a, NT);
+    const bool bad = ballot(acc.bad) != 0;
+#pragma unroll
+    for (int r = 0; r < 11; ++r) acc.v[r] = wave_max(acc.v[r]);
+    if (lane == 0) {
+        bs->bad[wv] = bad;
+        for (int r = 0; r < 11; ++r) bs->fmax[wv][r] = acc.v[r];
+    }
+    __syncthreads();
+    WideChunk& ck = B.chunks[J.chunk0 + k];
+    if (tid == 0) {
+        float v[11];
+        int anybad = 0;
+        for (int r = 0; r < 11; ++r) v[r] = bs->fmax[0][r];
+        for (int w = 0; w < 8; ++w) {
+            anybad |= bs->bad[w];
+            for (int r = 0; r < 11; ++r) v[r] = fmaxf(v[r], bs->fmax[w][r]);
+        }
+        for (int r = 0; r < 11; ++r) ck.P[r] = (uint64_t)__float_as_uint(v[r]);
+        ck.P[11] = (uint64_t)anybad;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    int* const flag = &bs->vote[1][7];
+    if (tid == 0) {
+        int out = 0;
+        if (atomicSub(&J.left, 1) == 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            float v[11];
+            int anybad = 0;
+            for (int r = 0; r < 11; ++r) v[r] = -INFINITY;
+            for (int q = 0; q < K; ++q) {
+                const WideChunk& cq = B.chunks[J.chunk0 + q];
+                for (int r = 0; r < 11; ++r) v[r] = fmaxf(v[r], __uint_as_float((uint32_t)cq.P[r]));
+                anybad |= (int)cq.P[11];
+            }
+            if (anybad) {
+                bc.bad = 1;
+                atomicOr(A.flags, FLAG_BAD_VALUE);
+                if (A.mode == 0) { A.out_count[c] = n; A.cell_mode[c] = CELL_UNTOUCHED; }
+                else A.n_subsets[c] = 0;
+                out = 2;
+            } else {
+                Frame F;
+                frame_from(v, cell_mass(A.P.mass, A.P.species, A.P.species_mass, c), F);
+                bc.F = F;
+                J.left = K;
+                Node<uint32_t> r;
+                r.start = (uint32_t)j; r.thr_axis = 0;
+                for (int q = 0; q < K; ++q) { r.len = (uint32_t)q; spawn_task(B, qi, 0, r, TASK_CENCODE); }
+                out = 1;
+            }
+        }
+        *flag = out;
+    }
+    __syncthreads();
+    if (*flag == 2 && A.mode == 1)                      // a passed-through cell: the identity partition
+        for (int i = tid; i < n; i += NT) { A.perm[off + i] = (int32_t)(off + i); A.subset_id[off + i] = -1; }
+}
+
+// The codes pass of chunk k of cell job j (all threads): the chunk's codes and its exact moments.
+// The workgroup that finishes the last chunk decides the root (the exact rule) and splits it (a job of
+// its own, or by itself when no records are left: then it returns the children it keeps in `kept`,
+// members in index buffer 1) or records the whole cell as one finished subset.
+template <typename InT>
+VPM_DEV int cell_encode_task(const BigArgs<InT>& B, const CellMem<uint32_t>& M, const Frame& F, BlockScratch<8>* bs,
+                             int j, int k, Node<uint32_t>* kept) {
+    constexpr int NT = WAVE * 8;
+    const auto& A = B.A;
+    const int tid = threadIdx.x, lane = lane_id();
+    WideJob& J = B.jobs[j];
+    const int K = J.nchunks, n = J.nd.len, qi = J.qi;
+    const int span = (n + K - 1) / K;
+    const int a = min(n, k * span), b = min(n, a + span);
+    FSums R;                                            // (the FP64 moments are not used here)
+    fsums_zero(R);
+    bool oob = false;
+    load_particles(A.in, B.cells[qi].off, a + tid, b, NT, [&](int i, const float* q, bool ok) {
+        if (ok) encode_particle(M, A.P, F, i, q, R, oob);
+    });
+    if (ballot(oob) != 0 && lane == 0) atomicOr(&M.sh->flags, FLAG_OUT_OF_CELL);
+    WSums W;
+    wsums_zero(W);
+    for (int i = a + tid; i < b; i += NT) {             // the codes this thread has just written
+        int cc[6], om;
+        codes_of(M, i, cc, om);
+        wsums_add(W, om, cc);
+    }
+    wsums_block_reduce<8>(W, (uint64_t*)M.sched);
+    WideChunk& ck = B.chunks[J.chunk0 + k];
+    if (tid == 0) wsums_store(ck.P, W);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    int* const flag = &bs->vote[1][7];
+    int* const dec = &bs->vote[1][6];
+    if (tid == 0) {
+        int last = 0;
+        if (atomicSub(&J.left, 1) == 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            WSums T;
+            wsums_zero(T);
+            for (int q = 0; q < K; ++q) wsums_acc(T, wsums_load(B.chunks[J.chunk0 + q].P));
+            *dec = pack_decision(decide_exact_wide(T, M.sh->dc, F));
+            last = 1;
+        }
+        *flag = last;
+    }
+    __syncthreads();
+    if (!*flag) return 0;
+    const Decision rd = unpack_decision(*dec);
+    __syncthreads();
+    if (rd.kind != D_SPLIT) {
+        const uint8_t base = INF_SET | (rd.kind == D_MERGED ? INF_MERGED : 0) | (uint8_t)(rd.jdir << INF_JSHIFT);
+        for (int i = tid; i < n; i += NT) M.info[i] = base | (i == 0 ? INF_HEAD : 0);
+        return 0;
+    }
+    Node<uint32_t> root;
+    root.start = 0; root.len = (uint32_t)n; root.thr_axis = (rd.thr << 8) | rd.axis;
+    if (start_wide_job(B, bs, root, 0, qi)) return 0;
+    return wide_split(B, M, F, bs, root, 0, qi, kept);
+}
+
 // One output task of a cell above NMAX_NARROW (its slots, leaf starts and merged list are complete):
 // TASK_COPY copies the unmerged particles of slots a .. a + cnt - 1 to their output slots; TASK_MERGE
 // merges the subsets a, a + cnt, a + 2 cnt, ... of the merged list (Step 7), one wavefront each.
@@ -2813,6 +2956,7 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
         bool wide = false;                     // the piece starts with a subset above NMAX_NARROW
         Node<IdxT> wnode;
         int tkind = TASK_NODE, nmerged = 0;
+        bool cell_job = false;                 // a new cell whose root passes went to chunk tasks
         int64_t off;
         Frame F;
         CellMem<IdxT> M;
@@ -2835,6 +2979,19 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
             c = qp[v];
             off = A.cell_off[c];
             n = (int)(A.cell_off[c + 1] - off);
+            if (n > NMAX_NARROW) {
+                // a cell above NMAX_NARROW: its frame and codes are chunk tasks of a job (when job
+                // records are left); this piece ends here
+                if (tid == 0) {
+                    BigCell& bc = B.cells[qi];
+                    bc.off = off; bc.n = n; bc.c = c; bc.open = 1; bc.bad = 0;
+                }
+                Node<IdxT> whole;
+                whole.start = 0; whole.len = (IdxT)n; whole.thr_axis = 0;
+                cell_job = start_wide_job(B, bs, whole, 0, qi, TASK_CFRAME);
+            }
+        }
+        if (kind == 1 && !cell_job) {
             const bool valid = cell_frame_block<WPB>(A.in, off, n, cell_mass(A.P.mass, A.P.species, A.P.species_mass, c),
                                                      F, bs);
             if (!valid) {
@@ -2851,9 +3008,9 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
             }
             if (tid == 0) {
                 BigCell& bc = B.cells[qi];
-                bc.F = F; bc.off = off; bc.n = n; bc.c = c; bc.open = 1;
+                bc.F = F; bc.off = off; bc.n = n; bc.c = c; bc.open = 1; bc.bad = 0;
             }
-        } else {
+        } else if (kind == 2) {
             // ---- a task: a subset of a cell started elsewhere ----
             const BigTask t = B.tasks[sh.qi];
             qi = __builtin_amdgcn_readfirstlane(t.qi);
@@ -2888,13 +3045,18 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
             if (tid == 0) atomicSub(&ctr[C_PENDING], 1);
             continue;
         }
-        if (tkind == TASK_WCOUNT) {
+        if (tkind == TASK_CFRAME) {
+            cell_frame_task(B, bs, (int)wnode.start, (int)wnode.len);
+        } else if (tkind == TASK_CENCODE) {
+            m = cell_encode_task(B, M, F, bs, (int)wnode.start, (int)wnode.len, M.nodes1);
+            if (m > 0) cur = 1;
+        } else if (tkind == TASK_WCOUNT) {
             wide_count_task(B, M, F, bs, (int)wnode.start, (int)wnode.len);
         } else if (tkind == TASK_WPLACE) {
             m = wide_place_task(B, M, bs, (int)wnode.start, (int)wnode.len, cur ? M.nodes0 : M.nodes1);
             cur ^= 1;
         }
-        if (kind == 1) {
+        if (kind == 1 && !cell_job) {
             FSums R;
             fsums_zero(R);
             bool oob = false;
@@ -2991,8 +3153,9 @@ __global__ __launch_bounds__(WAVE * 8, 2) void k_fixed_big(BigArgs<InT> B) {
         __syncthreads();
         if (tid == 0) {
             if (sh.flags) atomicOr(A.flags, sh.flags);
-            const int last = atomicSub(&B.cells[qi].open, 1) == 1 ? 1 : 0;
+            int last = atomicSub(&B.cells[qi].open, 1) == 1 ? 1 : 0;
             if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every other piece's writes
+            if (last && B.cells[qi].bad) last = 0;     // passed through: its output is the input
             sh.last = last;
         }
         __syncthreads();

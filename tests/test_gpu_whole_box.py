@@ -138,3 +138,25 @@ def test_wide_cells_with_concurrent_bins():
     np.testing.assert_array_equal(got_off, ref_off)
     for f in got:
         np.testing.assert_array_equal(got[f], ref[f])
+
+
+def test_wide_cell_with_a_bad_value_passes_through():
+    """A NaN in a 100,000-particle cell: the cell is flagged and copied unchanged (its identity
+    partition in vpm_partition), the other cells are merged as usual."""
+    c = ctx()
+    wl = cloud_cells([3000, 100000, 90000], seed=29)
+    lo = int(wl.cell_off[1])
+    wl.px[lo + 777] = np.nan
+    c.device_status(clear=True)
+    perm, sid, nsub = gpu_partition(wl, CLOUD)
+    assert c.device_status(clear=True) & vpm.VPM_FLAG_BAD_VALUE
+    hi = int(wl.cell_off[2])
+    assert nsub[1] == 0 and np.all(sid[lo:hi] == -1) and np.array_equal(perm[lo:hi], np.arange(lo, hi))
+    got, got_off, tot = gpu_run(wl, CLOUD)
+    c.device_status(clear=True)
+    o = int(got_off[1])
+    assert got_off[2] - got_off[1] == hi - lo
+    np.testing.assert_array_equal(got["w"][o:o + hi - lo], wl.w[lo:hi].astype(np.float32).astype(np.float64))
+    good = wl.cells([0, 2])
+    ref = oracle.run_workload(good, decide=oracle.FIXED, **oracle_params(CLOUD))
+    assert nsub[0] == ref.n_subsets[0] and nsub[2] == ref.n_subsets[1]
