@@ -58,6 +58,17 @@ def test_graph_replay_matches_eager(merge, concurrent):
         c.set_tuning(default)
 
 
+def test_graph_replay_with_cells_above_2_16():
+    """Whole-box cells inside a captured graph: their chunk and output tasks, and the job counters
+    that each event resets, replay like the rest."""
+    sizes1 = [300, 90000, 700, 5000]
+    sizes2 = [70000, 40, 20000, 66000]
+    wl1, wl2 = population(sizes1, 13), population(sizes2, 14)
+    cap = max(wl1.n, wl2.n) + 37
+    c = ctx(cap, len(sizes1))
+    _graph_replay(c, wl1, wl2, sizes1, cap, vpm.VPM_MERGE_PAIR)
+
+
 def _graph_replay(c, wl1, wl2, sizes1, cap, merge):
     refs = {1: eager(c, wl1, merge), 2: eager(c, wl2, merge)}
     # the eager result is the oracle's (so a replay that matches it matches the oracle)
