@@ -434,8 +434,9 @@ def extra_workload(ctx, vpm, name, wl32, wl64, prm, steps, fp64_steps, tune=True
 
 def whole_box(ctx, vpm, W, seed, steps=3, cpu=True):
     """Global merging: a whole simulation box passed as one cell (the method's first subset is the
-    box), in two populations: the counter-propagating blocks at 4,000 electrons per unit cell (4 M
-    particles in a 100 x 20 box) and a 64 x 64 patch of the two-stream population (2.1 M particles).
+    box), in three populations: the counter-propagating blocks at 4,000 and at 16,000 electrons per
+    unit cell (4 M and 16 M particles in a 100 x 20 box; the largest cell is 2^24 = 16.8 M) and a
+    64 x 64 patch of the two-stream population (2.1 M particles).
     Each is timed per merge event; the oracle is timed on the same box (its CPU baseline), and that
     run's partition is compared with the GPU's (bit-exact)."""
     import torch
@@ -446,8 +447,10 @@ def whole_box(ctx, vpm, W, seed, steps=3, cpu=True):
     saved = ctx.get_tuning()
     ctx.set_tuning(vpm.make_tuning())
     blocks = W.counter_blocks(per_cell=4000, seed=seed)
+    blocks16 = W.counter_blocks(per_cell=16000, seed=seed + 1)     # 16 M particles: near the largest cell
     ts = W.two_stream_grid(nx=64, ny=64, mean=512, seed=seed)
     cases = [("counter_blocks_4M", blocks, dict(blocks.params, cell_len=(100.0, 20.0, 1.0), tol_x=0.02)),
+             ("counter_blocks_16M", blocks16, dict(blocks16.params, cell_len=(100.0, 20.0, 1.0), tol_x=0.02)),
              ("two_stream_64x64", ts, dict(ts.params, cell_len=(64.0, 64.0, 1.0), tol_x=0.02))]
     for name, wl, prm in cases:
         box = W.Workload(name, *[getattr(wl, f).astype(np.float32) for f in W.FIELDS],
