@@ -766,6 +766,8 @@ def main():
     ap.add_argument("--valu-summary", metavar="PMC_DIR")
     ap.add_argument("--shower-only", action="store_true",
                     help="time only the shower population (every size bin) and print its record (profiling runs)")
+    ap.add_argument("--whole-box-only", action="store_true",
+                    help="time only the whole-box populations (each merged as one cell) and print their record")
     ap.add_argument("--bins-in-sequence", action="store_true",
                     help="with --shower-only --no-autotune: run the size bins one after another (per-bin times)")
     ap.add_argument("--graph", action="store_true",
@@ -788,6 +790,11 @@ def main():
 
     if args.copy_calib:
         copy_calibration()
+        return
+    if args.whole_box_only:
+        ctx = vpm.Context(0)
+        ctx.reserve(17_000_000, 4096)
+        print(json.dumps(whole_box(ctx, vpm, W, args.seed, steps=args.steps, cpu=not args.no_cpu)))
         return
     if args.shower_only:
         ctx = vpm.Context(0)
