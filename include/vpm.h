@@ -78,7 +78,7 @@ typedef enum { VPM_AXIS_RAW = 0, VPM_AXIS_NORMALISED = 1 } vpm_axis_rule;
 #define VPM_FLAG_CELL_TOO_LARGE 0x4u  /* a cell above the largest size: passed through (2^24 =
                                          16,777,216 particles for vpm_run, vpm_run_species and
                                          vpm_partition with fixed-point decisions; 65,536 for
-                                         the FP64 form and vpm_merge)                           */
+                                         the FP64 form, vpm_merge and vpm_blind)                */
 #define VPM_FLAG_BAD_OFFSETS    0x8u  /* cell_off decreasing, not starting at 0, or past n_particles;
                                          a cell whose own range is invalid is passed through, but
                                          cells whose ranges overlap make the whole output
@@ -189,7 +189,8 @@ vpm_status vpm_merge(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
  *   group     device int32[n_particles] (may be NULL): the cell-local output ordinal of each input
  *             particle (its own index in untouched cells)
  * p: n_min_cell, mass and dtype (VPM_F32 only) are used; tolerances, min_subset, merge_mode and
- * decide are not (p must still pass vpm_check_params).  Output and errors as vpm_run.           */
+ * decide are not (p must still pass vpm_check_params).  Output and errors as vpm_run; cells above
+ * 65,536 particles are flagged VPM_FLAG_CELL_TOO_LARGE and copied.                               */
 vpm_status vpm_blind(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, int64_t n_cells,
                      int64_t n_particles, const vpm_params *p, double alpha, uint64_t seed, vpm_soa *out,
                      int64_t *out_off, int64_t *out_total, int32_t *group, hipStream_t stream);
