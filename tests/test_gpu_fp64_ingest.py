@@ -91,3 +91,14 @@ def test_fp64_partition_merge_and_blind():
     assert torch.equal(a[4], b[4]) and torch.equal(a[6], b[6]) and torch.equal(a[7], b[7])
     for x, y in zip(a[3] + a[5], b[3] + b[5]):
         assert torch.equal(x.view(torch.int32), y.view(torch.int32))
+
+
+def test_fp64_input_cells_above_2_16():
+    """Whole-box cells from FP64 arrays: the frame and codes chunk tasks round as they load, so the
+    output equals that of the host-rounded FP32 population."""
+    wl = population([90000, 500, 140000], 53)
+    c = ctx(wl.n, wl.n_cells)
+    a = _run(c, wl, torch.float64)
+    b = _run(c, wl.astype(np.float32), torch.float32)
+    _same(a, b)
+    assert a[2] < wl.n
