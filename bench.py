@@ -200,8 +200,8 @@ def valu_from_profiles():
 
 
 # the size-bin kernels, in the order of their upper limits in the tuning (the last has none)
-BINS = [("fixed_cells_small", "bin_s_max"), ("fixed_cells_576", "bin_a_max"), ("fixed_cells_2048", "bin_b_max"),
-        ("fixed_cells_4352", "bin_c_max"), ("fixed_cells_big", None)]
+BINS = [("fixed_cells_small", "bin_s_max"), ("fixed_cells_576", "bin_a_max"), ("fixed_cells_1152", "bin_d_max"),
+        ("fixed_cells_2048", "bin_b_max"), ("fixed_cells_4352", "bin_c_max"), ("fixed_cells_big", None)]
 ORACLE_KEYS = ("tol_x", "tol_p", "n_min_cell", "min_subset", "cell_len", "mass")
 
 
@@ -209,7 +209,7 @@ def bin_of_cells(counts, tuning, n_min_cell):
     """The size bin of every cell as the library assigns it (-1: left untouched)."""
     lims = [tuning[k] for _, k in BINS[:-1]]
     b = np.searchsorted(np.asarray(lims), counts, side="left")      # first bin whose limit >= count
-    proc = (counts > n_min_cell) & (counts > 0) & (counts <= 65536)
+    proc = (counts > n_min_cell) & (counts > 0) & (counts <= (1 << 24))
     return np.where(proc, b, -1)
 
 

@@ -200,6 +200,7 @@ vpm_status vpm_blind(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
  *   in a batch with other small cells by one wavefront (up to 16 cells, 512 particles, in LDS)
  *                                                  if n <= bin_s_max  (bin_s_max <= 256; 0: none)
  *   by one wavefront, working set in LDS          if n <= bin_a_max  (bin_a_max <= 576)
+ *   two wavefronts, working set in LDS            if n <= bin_d_max  (bin_d_max <= 1152)
  *   four wavefronts, working set in LDS           if n <= bin_b_max  (bin_b_max <= 2048)
  *   eight wavefronts, working set in LDS          if n <= bin_c_max  (bin_c_max <= 4352)
  *   eight wavefronts, working set in global memory otherwise (n <= 2^24: a whole box may be one
@@ -207,8 +208,9 @@ vpm_status vpm_blind(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
  *     subset above 65,536 particles is split by one workgroup on exact integer moments and its
  *     unfinished children are handed to other workgroups);
  * a subset of len particles is handled by a group of about len / ppl lanes (ppl = 8, 16 or 32;
- * at most 64 lanes).  Limits must satisfy 1 <= bin_a_max <= bin_b_max <= bin_c_max.
- * concurrent_bins = 1 runs the four bins at once on the context's side streams (forked from and
+ * at most 64 lanes).  Limits must satisfy 1 <= bin_a_max <= bin_d_max <= bin_b_max <= bin_c_max
+ * (bin_d_max = bin_a_max: no two-wavefront bin).
+ * concurrent_bins = 1 runs the bins at once on the context's side streams (forked from and
  * joined back to the caller's stream), 0 runs them one after another on the caller's stream.
  * exact_decisions = 1 takes every Step 3-5 decision of the fixed-point path by the exact integer
  * rule (Sec. "Algorithm", Steps 3-5, on 128/256/320-bit moments recomputed from the codes) instead
@@ -223,12 +225,13 @@ typedef struct {
     int32_t concurrent_bins;
     int32_t bin_s_max;
     int32_t exact_decisions;
+    int32_t bin_d_max;
 } vpm_tuning;
 
 /* Host-only validation of a tuning block (no device needed). */
 vpm_status vpm_check_tuning(const vpm_tuning *t);
 
-/* The context's current tuning (initially ppl 16, limits 576 / 2048 / 4352, bins in sequence,
+/* The context's current tuning (initially ppl 16, limits 576 / 1152 / 2048 / 4352, bins in sequence,
  * small-cell batches for cells of up to 128 particles). */
 vpm_status vpm_get_tuning(vpm_ctx *ctx, vpm_tuning *t);
 vpm_status vpm_set_tuning(vpm_ctx *ctx, const vpm_tuning *t);

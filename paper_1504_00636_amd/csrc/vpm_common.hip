@@ -20,6 +20,7 @@ __global__ void k_reset(int32_t* counters) {
 __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_cells, int64_t n_particles,
                                              int32_t n_min_cell, int32_t* counters, int32_t* q_untouched,
                                              int32_t* q_a, int32_t* q_b, int32_t* q_c, int32_t* q_big, int32_t* q_s,
+                                             int32_t* q_d,
                                              int64_t* out_count,
                                              uint8_t* cell_mode, uint32_t* flags, BinLimits lim,
                                              const uint8_t* species, int n_species, int32_t* bq0,
@@ -45,6 +46,8 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
             cls = Q_S;
         } else if (n <= lim.a) {
             cls = Q_A;
+        } else if (n <= lim.d) {
+            cls = Q_D;
         } else if (n <= lim.b) {
             cls = Q_B;
         } else if (n <= lim.c) {
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* cell_off, int64_t n_
         s_base[threadIdx.x] = k ? atomicAdd(&counters[ci], k) : 0;
     }
     __syncthreads();
-    int32_t* const qs[Q_COUNT] = {q_untouched, q_a, q_b, q_c, q_big, q_s};
+    int32_t* const qs[Q_COUNT] = {q_untouched, q_a, q_b, q_c, q_big, q_s, q_d};
     int32_t* const bqs[BIGQ_CLASSES] = {bq0, bq1, bq2, bq3};
 #pragma unroll
     for (int q = 0; q < Q_COUNT; ++q)
@@ -260,7 +263,8 @@ hipError_t launch_bin(const Workspace& ws, const LaunchCfg& lc, const int64_t* c
     const int64_t blocks = (n_cells + 255) / 256;
     hipLaunchKernelGGL(k_bin, dim3((unsigned)blocks), dim3(256), 0, lc.stream, cell_off, n_cells, n_particles,
                        n_min_cell, ws.counters, ws.queue[Q_UNTOUCHED], ws.queue[Q_A], ws.queue[Q_B],
-                       ws.queue[Q_C], ws.queue[Q_BIG], ws.queue[Q_S], ws.out_count, ws.cell_mode, ws.flags, lim,
+                       ws.queue[Q_C], ws.queue[Q_BIG], ws.queue[Q_S], ws.queue[Q_D], ws.out_count, ws.cell_mode,
+                       ws.flags, lim,
                        species, n_species, ws.bigq[0], ws.bigq[1], ws.bigq[2], ws.bigq[3]);
     if (lc.post) lc.post(lc.prof, "bin", lc.stream);
     return hipGetLastError();

@@ -3618,7 +3618,7 @@ __global__ __launch_bounds__(WAVE) void k_fixed_blind(BlindArgs<InT> B) {
     }
 }
 
-constexpr int WPB_A = 1, WPB_B = 4, WPB_C = 8, WPB_BIG = 8;
+constexpr int WPB_A = 1, WPB_D = 2, WPB_B = 4, WPB_C = 8, WPB_BIG = 8;
 
 }  // namespace
 
@@ -3628,6 +3628,7 @@ int fixed_lds_bytes(int which) {
         case 0: return (int)(header_bytes<WPB_A>() + slice_bytes<uint16_t>(NMAX_A));
         case 1: return (int)(header_bytes<WPB_B>() + slice_bytes<uint16_t>(NMAX_B));
         case 2: return (int)(header_bytes<WPB_C>() + slice_bytes<uint16_t>(NMAX_C));
+        case 5: return (int)(header_bytes<WPB_D>() + slice_bytes<uint16_t>(NMAX_D));
         default: return (int)big_lds_bytes();
     }
 }
@@ -3646,12 +3647,13 @@ const void* fixed_kernel_ptr(int which) {
         case 0: return (const void*)k_fixed_cells<NMAX_A, uint16_t, true, WPB_A, float>;
         case 1: return (const void*)k_fixed_cells<NMAX_B, uint16_t, true, WPB_B, float>;
         case 2: return (const void*)k_fixed_cells<NMAX_C, uint16_t, true, WPB_C, float>;
+        case 5: return (const void*)k_fixed_cells<NMAX_D, uint16_t, true, WPB_D, float>;
         default: return (const void*)k_fixed_big<float>;
     }
 }
 
 int fixed_block_threads(int which) {
-    return WAVE * (which == 0 || which == 4 ? 1 : which == 1 ? WPB_B : which == 2 ? WPB_C : WPB_BIG);
+    return WAVE * (which == 0 || which == 4 ? 1 : which == 1 ? WPB_B : which == 2 ? WPB_C : which == 5 ? WPB_D : WPB_BIG);
 }
 
 namespace {
@@ -3677,7 +3679,7 @@ hipError_t fixed_merge_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<I
     G.perm = perm; G.subset_id = subset_id; G.n_subsets = n_subsets;
     G.starts = ws.perm2;
     G.marks = ws.perm2 + (ws.cap_particles + 1);   // the second of the two buffers
-    const int qs[5] = {Q_BIG, Q_C, Q_B, Q_S, Q_A};
+    const int qs[6] = {Q_BIG, Q_C, Q_B, Q_S, Q_D, Q_A};
     for (int q : qs) {
         A.queue = ws.queue[q];
         A.qlen_index = q;
@@ -3753,10 +3755,11 @@ hipError_t fixed_cells_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<I
         if (e != hipSuccess) return join_back(e);
     }
     struct Bin { int q; const char* name; hipStream_t s; };
-    const Bin bins[5] = {{Q_BIG, "fixed_cells_big", forked ? lc.side[0] : lc.stream},
+    const Bin bins[6] = {{Q_BIG, "fixed_cells_big", forked ? lc.side[0] : lc.stream},
                          {Q_C, "fixed_cells_4352", forked ? lc.side[1] : lc.stream},
                          {Q_B, "fixed_cells_2048", forked ? lc.side[2] : lc.stream},
                          {Q_S, "fixed_cells_small", lc.stream},
+                         {Q_D, "fixed_cells_1152", lc.stream},
                          {Q_A, "fixed_cells_576", lc.stream}};
     for (const Bin& b : bins) {
         A.queue = ws.queue[b.q];
@@ -3769,6 +3772,9 @@ hipError_t fixed_cells_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<I
         else if (b.q == Q_B)
             hipLaunchKernelGGL((k_fixed_cells<NMAX_B, uint16_t, true, WPB_B, InT>), dim3(lc.grid_b), dim3(WAVE * WPB_B),
                                fixed_lds_bytes(1), b.s, A);
+        else if (b.q == Q_D)
+            hipLaunchKernelGGL((k_fixed_cells<NMAX_D, uint16_t, true, WPB_D, InT>), dim3(lc.grid_d), dim3(WAVE * WPB_D),
+                               fixed_lds_bytes(5), b.s, A);
         else if (b.q == Q_S)
             hipLaunchKernelGGL(k_fixed_small<InT>, dim3(lc.grid_s), dim3(WAVE), fixed_lds_bytes(4), b.s, A);
         else if (b.q == Q_C)

@@ -376,7 +376,7 @@ hipError_t launch_fp64_cells(const Workspace& ws, const LaunchCfg& lc, const Soa
     A.stack = ws.stack;
     A.perm = perm; A.subset_id = subset_id; A.n_subsets = n_subsets;
     A.flags = ws.flags;
-    const int qs[5] = {Q_BIG, Q_C, Q_B, Q_S, Q_A};
+    const int qs[6] = {Q_BIG, Q_C, Q_B, Q_S, Q_D, Q_A};
     for (int q : qs) {
         A.queue = ws.queue[q];
         A.qlen_index = q;
@@ -411,7 +411,7 @@ hipError_t launch_fp64_merge(const Workspace& ws, const LaunchCfg& lc, const Soa
     A.perm = nullptr; A.subset_id = nullptr; A.n_subsets = nullptr;
     A.flags = ws.flags;
     G.perm = perm; G.subset_id = subset_id; G.n_subsets = n_subsets;
-    const int qs[5] = {Q_BIG, Q_C, Q_B, Q_S, Q_A};
+    const int qs[6] = {Q_BIG, Q_C, Q_B, Q_S, Q_D, Q_A};
     for (int q : qs) {
         A.queue = ws.queue[q];
         A.qlen_index = q;

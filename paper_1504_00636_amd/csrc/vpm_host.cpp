@@ -18,8 +18,8 @@ struct vpm_ctx {
     int device = 0;
     int cu_count = 0;
     Workspace ws;
-    int grid_a = 0, grid_b = 0, grid_c = 0, grid_big = 0, grid_s = 0, grid_fp64 = 0;
-    vpm_tuning tune = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128, 0};
+    int grid_a = 0, grid_b = 0, grid_c = 0, grid_big = 0, grid_s = 0, grid_fp64 = 0, grid_d = 0;
+    vpm_tuning tune = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128, 0, NMAX_D};
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     std::string last_error;
@@ -90,6 +90,7 @@ LaunchCfg make_cfg(vpm_ctx* c, hipStream_t s) {
     lc.grid_b = c->grid_b;
     lc.grid_c = c->grid_c;
     lc.grid_s = c->grid_s;
+    lc.grid_d = c->grid_d;
     lc.grid_big = std::min(c->grid_big, c->ws.big_wgs > 0 ? c->ws.big_wgs : c->grid_big);
     lc.grid_fp64 = c->grid_fp64;
     const bool fork = c->tune.concurrent_bins != 0;
@@ -146,7 +147,8 @@ int ilog2(int v) {
 // big: the largest cell processed (the fixed-point partition takes whole boxes; the FP64 form and
 // vpm_merge keep to NMAX_BIG)
 BinLimits bin_limits(const vpm_ctx* c, int32_t big) {
-    return BinLimits{c->tune.bin_a_max, c->tune.bin_b_max, c->tune.bin_c_max, c->tune.bin_s_max, big};
+    return BinLimits{c->tune.bin_a_max, c->tune.bin_b_max, c->tune.bin_c_max, c->tune.bin_s_max, big,
+                     c->tune.bin_d_max};
 }
 
 FixedParams fixed_params(const vpm_params* p, const vpm_tuning& t) {
@@ -291,8 +293,8 @@ vpm_status vpm_create(vpm_ctx** out, int device) {
     hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device);
     if (c->cu_count <= 0) c->cu_count = 256;
     // persistent grids: as many workgroups as fit on the chip at once
-    int* grids[5] = {&c->grid_a, &c->grid_b, &c->grid_c, &c->grid_big, &c->grid_s};
-    for (int b = 0; b < 5; ++b) {
+    int* grids[6] = {&c->grid_a, &c->grid_b, &c->grid_c, &c->grid_big, &c->grid_s, &c->grid_d};
+    for (int b = 0; b < 6; ++b) {
         int nb = 0;
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(b), fixed_block_threads(b), fixed_lds_bytes(b));
         *grids[b] = c->cu_count * (nb > 0 ? nb : 1);
@@ -501,6 +503,7 @@ vpm_status vpm_check_tuning(const vpm_tuning* t) {
     if (t->concurrent_bins != 0 && t->concurrent_bins != 1) return VPM_ERR_INVALID_ARG;
     if (t->bin_s_max < 0 || t->bin_s_max > SMALL_MAX) return VPM_ERR_INVALID_ARG;
     if (t->exact_decisions != 0 && t->exact_decisions != 1) return VPM_ERR_INVALID_ARG;
+    if (t->bin_d_max < t->bin_a_max || t->bin_d_max > NMAX_D || t->bin_d_max > t->bin_b_max) return VPM_ERR_INVALID_ARG;
     return VPM_OK;
 }
 
@@ -553,7 +556,7 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
         ms = bestms;
         return VPM_OK;
     };
-    vpm_tuning cur = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128, was_tuned.exact_decisions};
+    vpm_tuning cur = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128, was_tuned.exact_decisions, NMAX_D};
     float cur_ms = 0.f;
     st = time_cfg(cur, cur_ms);
     // coordinate search: each parameter in turn over its candidates, keeping the others; a second
@@ -565,13 +568,15 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
     const int cs[3] = {2560, 3456, NMAX_C};
     const int conc[2] = {0, 1};
     const int ss[5] = {0, 32, 64, 128, SMALL_MAX};
+    const int ds[3] = {0, 864, NMAX_D};            // 0: no two-wavefront bin (bin_d_max = bin_a_max)
     bool changed = true;
     for (int pass = 0; pass < 2 && changed && st == VPM_OK; ++pass) {
         changed = false;
-        const int order[6] = {4, 0, 1, 2, 3, 5};
-        for (int di = 0; di < 6 && st == VPM_OK; ++di) {
+        const int order[7] = {4, 0, 1, 6, 2, 3, 5};
+        for (int di = 0; di < 7 && st == VPM_OK; ++di) {
             const int dim = order[di];
-            const int* cand = dim == 0 ? ppls : dim == 1 ? as : dim == 2 ? bs : dim == 3 ? cs : dim == 4 ? conc : ss;
+            const int* cand = dim == 0 ? ppls : dim == 1 ? as : dim == 2 ? bs : dim == 3 ? cs : dim == 4 ? conc
+                            : dim == 5 ? ss : ds;
             const int nc = dim == 1 || dim == 5 ? 5 : dim == 4 ? 2 : 3;
             for (int k = 0; k < nc && st == VPM_OK; ++k) {
                 vpm_tuning t = cur;
@@ -580,10 +585,14 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
                 else if (dim == 2) t.bin_b_max = cand[k];
                 else if (dim == 3) t.bin_c_max = cand[k];
                 else if (dim == 4) t.concurrent_bins = cand[k];
-                else t.bin_s_max = cand[k];
+                else if (dim == 5) t.bin_s_max = cand[k];
+                else t.bin_d_max = cand[k] == 0 ? t.bin_a_max : cand[k];
+                // keep the two-wavefront bin's limit inside the others' when they move
+                if (dim != 6) t.bin_d_max = std::max(t.bin_a_max, std::min(t.bin_d_max, t.bin_b_max));
                 if (vpm_check_tuning(&t) != VPM_OK) continue;
                 if (t.ppl == cur.ppl && t.bin_a_max == cur.bin_a_max && t.bin_b_max == cur.bin_b_max &&
-                    t.bin_c_max == cur.bin_c_max && t.concurrent_bins == cur.concurrent_bins && t.bin_s_max == cur.bin_s_max)
+                    t.bin_c_max == cur.bin_c_max && t.concurrent_bins == cur.concurrent_bins &&
+                    t.bin_s_max == cur.bin_s_max && t.bin_d_max == cur.bin_d_max)
                     continue;
                 float ms = 0.f;
                 st = time_cfg(t, ms);

@@ -13,6 +13,7 @@ enum CellMode : uint8_t { CELL_PROCESSED = 0, CELL_UNTOUCHED = 1 };
 
 // Size bins of the fixed-point path.
 constexpr int NMAX_A = 576;     // 1 wavefront per cell, working set in LDS (8 cells per CU)
+constexpr int NMAX_D = 1152;    // 2 wavefronts per cell, working set in LDS (4 cells per CU)
 constexpr int NMAX_B = 2048;    // 4 wavefronts per cell, working set in LDS (2 cells per CU)
 constexpr int NMAX_C = 4352;    // 8 wavefronts per cell, working set in LDS (1 cell per CU)
 constexpr int NMAX_BIG = 65536; // 8 wavefronts per piece, several workgroups per cell, working set global
@@ -20,7 +21,7 @@ constexpr int NMAX_WIDE = 1 << 24;  // largest cell of the fixed-point vpm_run /
                                     // subsets above NMAX_BIG are split by one workgroup each, exactly)
 constexpr int NMAX_S = 512;     // batches of small cells: 1 wavefront, up to 512 particles in LDS
 constexpr int SMALL_MAX = 256;  // largest cell the small-cell bin may take
-enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_C = 3, Q_BIG = 4, Q_S = 5, Q_COUNT = 6 };
+enum Queue { Q_UNTOUCHED = 0, Q_A = 1, Q_B = 2, Q_C = 3, Q_BIG = 4, Q_S = 5, Q_D = 6, Q_COUNT = 7 };
 // The cells of Q_BIG are also listed by size class (k: up to 8192 << k particles), so that the
 // global-memory bin can claim its largest cells first; the lists' lengths are counters
 // [BIGQ_LEN0, BIGQ_LEN0 + 4).
@@ -114,11 +115,11 @@ __host__ __device__ inline double cell_mass(double mass, const uint8_t* species,
 
 // Routing thresholds of the size bins: cells of up to `s` particles go to the small-cell batches,
 // up to `a` to bin A, up to `b` to B, up to `c` to C, larger ones to the global-memory bin.
-struct BinLimits { int32_t a, b, c, s, big; };   // big: the largest cell processed
+struct BinLimits { int32_t a, b, c, s, big, d; };   // big: the largest cell processed; a <= d <= b
 
 struct LaunchCfg {
     hipStream_t stream;
-    int grid_a, grid_b, grid_c, grid_big, grid_s, grid_fp64;   // persistent grid sizes
+    int grid_a, grid_b, grid_c, grid_big, grid_s, grid_fp64, grid_d;   // persistent grid sizes
     // Optional fork/join for the size bins: bins run concurrently on two side streams (default
     // priority) that wait on `fork` (recorded on `stream`) and are joined back through `join`.
     hipStream_t side[3];

@@ -29,7 +29,7 @@ static __device__ __align__(256) uint8_t scratch[NA_SCRATCH_BYTES];
 constexpr int NA_MAX_DEVICES = 64;
 std::mutex g_mutex;
 uint8_t* g_ptr[NA_MAX_DEVICES] = {};        // device address of `scratch` per device (null: not yet)
-int g_grid[NA_MAX_DEVICES][5] = {};        // persistent grid sizes of the LDS bins per device
+int g_grid[NA_MAX_DEVICES][6] = {};        // persistent grid sizes of the LDS bins per device
 
 __global__ void k_na_clear(uint32_t* flags) {
     if (threadIdx.x == 0) *flags = 0;
@@ -74,7 +74,7 @@ size_t carve(uint8_t* base, Workspace& ws) {
 }
 
 // Set-up on the current device, once: the array's device address and the bins' grid sizes.
-vpm_status device_setup(int dev, uint8_t** ptr, int grid[5]) {
+vpm_status device_setup(int dev, uint8_t** ptr, int grid[6]) {
     std::lock_guard<std::mutex> lock(g_mutex);
     if (!g_ptr[dev]) {
         void* p = nullptr;
@@ -84,7 +84,7 @@ vpm_status device_setup(int dev, uint8_t** ptr, int grid[5]) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
-        for (int b = 0; b < 5; ++b) {
+        for (int b = 0; b < 6; ++b) {
             int nb = 0;
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fixed_kernel_ptr(b), fixed_block_threads(b),
                                                          fixed_lds_bytes(b));
@@ -93,7 +93,7 @@ vpm_status device_setup(int dev, uint8_t** ptr, int grid[5]) {
         g_ptr[dev] = (uint8_t*)p;
     }
     *ptr = g_ptr[dev];
-    for (int b = 0; b < 5; ++b) grid[b] = g_grid[dev][b];
+    for (int b = 0; b < 6; ++b) grid[b] = g_grid[dev][b];
     return VPM_OK;
 }
 
@@ -116,7 +116,7 @@ extern "C" vpm_status vpm_run_noalloc(const vpm_soa* in, const int64_t* cell_off
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NA_MAX_DEVICES) return VPM_ERR_NO_DEVICE;
     uint8_t* base = nullptr;
-    int grid[5];
+    int grid[6];
     st = device_setup(dev, &base, grid);
     if (st != VPM_OK) return st;
 
@@ -125,6 +125,7 @@ extern "C" vpm_status vpm_run_noalloc(const vpm_soa* in, const int64_t* cell_off
     LaunchCfg lc;
     lc.stream = stream;
     lc.grid_a = grid[0]; lc.grid_b = grid[1]; lc.grid_c = grid[2]; lc.grid_big = grid[3]; lc.grid_s = grid[4];
+    lc.grid_d = grid[5];
     lc.grid_fp64 = 0;
     for (int i = 0; i < 3; ++i) { lc.side[i] = nullptr; lc.join[i] = nullptr; }
     lc.fork = nullptr;                     // the bins run one after another on the caller's stream
@@ -150,7 +151,7 @@ extern "C" vpm_status vpm_run_noalloc(const vpm_soa* in, const int64_t* cell_off
     fp.mass = p->mass;
     fp.species = nullptr;
     for (int k = 0; k < VPM_MAX_SPECIES; ++k) fp.species_mass[k] = p->mass;
-    const BinLimits lim{NMAX_A, NMAX_B, NMAX_C, 128, NMAX_WIDE};
+    const BinLimits lim{NMAX_A, NMAX_B, NMAX_C, 128, NMAX_WIDE, NMAX_D};
 
     // the flags start at zero for every call (a kernel, not a memset: the call may be captured)
     hipLaunchKernelGGL(k_na_clear, dim3(1), dim3(64), 0, stream, ws.flags);

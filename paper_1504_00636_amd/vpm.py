@@ -44,18 +44,21 @@ class VpmParams(C.Structure):
 
 class VpmTuning(C.Structure):
     _fields_ = [("ppl", C.c_int32), ("bin_a_max", C.c_int32), ("bin_b_max", C.c_int32), ("bin_c_max", C.c_int32),
-                ("concurrent_bins", C.c_int32), ("bin_s_max", C.c_int32), ("exact_decisions", C.c_int32)]
+                ("concurrent_bins", C.c_int32), ("bin_s_max", C.c_int32), ("exact_decisions", C.c_int32),
+                ("bin_d_max", C.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 def make_tuning(ppl=16, bin_a_max=576, bin_b_max=2048, bin_c_max=4352, concurrent_bins=0, bin_s_max=128,
-                exact_decisions=0) -> VpmTuning:
+                exact_decisions=0, bin_d_max=None) -> VpmTuning:
+    """bin_d_max None: 1152 kept between bin_a_max and bin_b_max."""
     t = VpmTuning()
     t.ppl, t.bin_a_max, t.bin_b_max, t.bin_c_max = int(ppl), int(bin_a_max), int(bin_b_max), int(bin_c_max)
     t.concurrent_bins, t.bin_s_max = int(concurrent_bins), int(bin_s_max)
     t.exact_decisions = int(exact_decisions)
+    t.bin_d_max = max(int(bin_a_max), min(1152, int(bin_b_max))) if bin_d_max is None else int(bin_d_max)
     return t
 
 

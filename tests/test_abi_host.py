@@ -129,7 +129,10 @@ def test_binding_argument_counts_match_header():
     ((16, 576, 2048, 4352, 1), True), ((16, 576, 2048, 4352, 2), False), ((16, 576, 2048, 4352, -1), False),
     ((16, 576, 2048, 4352, 0, 0), True), ((16, 576, 2048, 4352, 0, 256), True), ((16, 576, 2048, 4352, 0, 257), False),
     ((16, 576, 2048, 4352, 0, -1), False), ((16, 576, 2048, 4352, 0, 128, 1), True),
-    ((16, 576, 2048, 4352, 0, 128, 2), False), ((16, 576, 2048, 4352, 0, 128, -1), False)])
+    ((16, 576, 2048, 4352, 0, 128, 2), False), ((16, 576, 2048, 4352, 0, 128, -1), False),
+    ((16, 576, 2048, 4352, 0, 128, 0, 576), True), ((16, 576, 2048, 4352, 0, 128, 0, 1152), True),
+    ((16, 576, 2048, 4352, 0, 128, 0, 575), False), ((16, 576, 2048, 4352, 0, 128, 0, 1153), False),
+    ((16, 300, 800, 4352, 0, 128, 0, 900), False), ((16, 300, 800, 4352, 0, 128, 0, 800), True)])
 def test_check_tuning(t, ok):
     st = vpm.vpm_check_tuning(vpm.make_tuning(*t))
     assert (st == vpm.VPM_OK) == ok, (t, st)

@@ -17,7 +17,8 @@ SIZES = [1, 2, 5, 17, 64, 200, 575, 577, 900, 2047, 2049, 3000, 4353, 6000, 300,
 TUNINGS = [(16, 576, 2048, 4352), (8, 64, 512, 1024, 1), (32, 320, 1024, 2560), (8, 1, 1, 1, 0, 0),
            (32, 576, 576, 576, 1), (16, 100, 2048, 2048), (16, 576, 2048, 4352, 1), (16, 576, 2048, 4352, 0, 0),
            (8, 576, 2048, 4352, 0, 256), (32, 576, 2048, 4352, 1, 17), (16, 576, 2048, 4352, 0, 128, 1),
-           (8, 320, 1024, 2560, 1, 64, 1)]
+           (8, 320, 1024, 2560, 1, 64, 1), (16, 576, 2048, 4352, 0, 128, 0, 576), (8, 200, 2048, 4352, 1, 64, 0, 700),
+           (32, 576, 1152, 1152, 0, 128, 0, 1152)]
 
 
 def _run(c, arrs, off, n, p):
