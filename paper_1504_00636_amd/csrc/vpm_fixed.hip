@@ -3728,7 +3728,7 @@ hipError_t fixed_cells_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<I
     G.chunks_cap = ws.big_chunks ? ws.chunks_cap : 0;
 
     // The three bins touch disjoint cells, queues and counters, so they may run concurrently: the
-    // large-cell and 2048 bins go first on the side streams (their cells are the longest), the
+    // large-cell and four-wavefront bins go first on the side streams (their cells are the longest), the
     // 576 bin fills the rest of the chip on the caller's stream, and the caller's stream then waits
     // for both side streams.
     bool forked = lc.fork != nullptr;
@@ -3757,7 +3757,7 @@ hipError_t fixed_cells_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<I
     struct Bin { int q; const char* name; hipStream_t s; };
     const Bin bins[6] = {{Q_BIG, "fixed_cells_big", forked ? lc.side[0] : lc.stream},
                          {Q_C, "fixed_cells_4352", forked ? lc.side[1] : lc.stream},
-                         {Q_B, "fixed_cells_2048", forked ? lc.side[2] : lc.stream},
+                         {Q_B, "fixed_cells_2176", forked ? lc.side[2] : lc.stream},
                          {Q_S, "fixed_cells_small", lc.stream},
                          {Q_D, "fixed_cells_1152", lc.stream},
                          {Q_A, "fixed_cells_576", lc.stream}};

@@ -51,7 +51,7 @@ class VpmTuning(C.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
-def make_tuning(ppl=16, bin_a_max=576, bin_b_max=2048, bin_c_max=4352, concurrent_bins=0, bin_s_max=128,
+def make_tuning(ppl=16, bin_a_max=576, bin_b_max=2176, bin_c_max=4352, concurrent_bins=0, bin_s_max=128,
                 exact_decisions=0, bin_d_max=None) -> VpmTuning:
     """bin_d_max None: 1152 kept between bin_a_max and bin_b_max."""
     t = VpmTuning()

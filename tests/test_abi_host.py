@@ -124,7 +124,7 @@ def test_binding_argument_counts_match_header():
 @pytest.mark.parametrize("t,ok", [
     ((16, 576, 2048, 4352), True), ((8, 1, 1, 1), True), ((32, 320, 1024, 2560), True),
     ((4, 576, 2048, 4352), False), ((12, 576, 2048, 4352), False), ((16, 0, 2048, 4352), False),
-    ((16, 577, 2048, 4352), False), ((16, 576, 575, 4352), False), ((16, 576, 2049, 4352), False),
+    ((16, 577, 2048, 4352), False), ((16, 576, 575, 4352), False), ((16, 576, 2177, 4352), False), ((16, 576, 2176, 4352), True),
     ((16, 576, 2048, 2047), False), ((16, 576, 2048, 4353), False),
     ((16, 576, 2048, 4352, 1), True), ((16, 576, 2048, 4352, 2), False), ((16, 576, 2048, 4352, -1), False),
     ((16, 576, 2048, 4352, 0, 0), True), ((16, 576, 2048, 4352, 0, 256), True), ((16, 576, 2048, 4352, 0, 257), False),
