@@ -200,8 +200,8 @@ def valu_from_profiles():
 
 
 # the size-bin kernels, in the order of their upper limits in the tuning (the last has none)
-BINS = [("fixed_cells_small", "bin_s_max"), ("fixed_cells_576", "bin_a_max"), ("fixed_cells_1152", "bin_d_max"),
-        ("fixed_cells_2176", "bin_b_max"), ("fixed_cells_4352", "bin_c_max"), ("fixed_cells_big", None)]
+BINS = [("fixed_cells_small", "bin_s_max"), ("fixed_cells_576", "bin_a_max"), ("fixed_cells_1144", "bin_d_max"),
+        ("fixed_cells_2288", "bin_b_max"), ("fixed_cells_4592", "bin_c_max"), ("fixed_cells_big", None)]
 ORACLE_KEYS = ("tol_x", "tol_p", "n_min_cell", "min_subset", "cell_len", "mass")
 
 

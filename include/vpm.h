@@ -200,9 +200,9 @@ vpm_status vpm_blind(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
  *   in a batch with other small cells by one wavefront (up to 16 cells, 512 particles, in LDS)
  *                                                  if n <= bin_s_max  (bin_s_max <= 256; 0: none)
  *   by one wavefront, working set in LDS          if n <= bin_a_max  (bin_a_max <= 576)
- *   two wavefronts, working set in LDS            if n <= bin_d_max  (bin_d_max <= 1152)
- *   four wavefronts, working set in LDS           if n <= bin_b_max  (bin_b_max <= 2176)
- *   eight wavefronts, working set in LDS          if n <= bin_c_max  (bin_c_max <= 4352)
+ *   two wavefronts, working set in LDS            if n <= bin_d_max  (bin_d_max <= 1144)
+ *   four wavefronts, working set in LDS           if n <= bin_b_max  (bin_b_max <= 2288)
+ *   eight wavefronts, working set in LDS          if n <= bin_c_max  (bin_c_max <= 4592)
  *   eight wavefronts, working set in global memory otherwise (n <= 2^24: a whole box may be one
  *     cell, the method's first subset (Sec. "Algorithm", the remark on merging globally); a
  *     subset above 65,536 particles is split by one workgroup on exact integer moments and its
@@ -231,7 +231,7 @@ typedef struct {
 /* Host-only validation of a tuning block (no device needed). */
 vpm_status vpm_check_tuning(const vpm_tuning *t);
 
-/* The context's current tuning (initially ppl 16, limits 576 / 1152 / 2176 / 4352, bins in sequence,
+/* The context's current tuning (initially ppl 16, limits 576 / 1144 / 2288 / 4592, bins in sequence,
  * small-cell batches for cells of up to 128 particles). */
 vpm_status vpm_get_tuning(vpm_ctx *ctx, vpm_tuning *t);
 vpm_status vpm_set_tuning(vpm_ctx *ctx, const vpm_tuning *t);

@@ -3620,6 +3620,14 @@ __global__ __launch_bounds__(WAVE) void k_fixed_blind(BlindArgs<InT> B) {
 
 constexpr int WPB_A = 1, WPB_D = 2, WPB_B = 4, WPB_C = 8, WPB_BIG = 8;
 
+// Each LDS bin's limit is the largest cell for which 8 / 4 / 2 / 1 cells still fit a CU's 160 KB of
+// LDS (the occupancy step the bin is sized for: two waves per SIMD at the cell kernels' VGPR count).
+constexpr size_t LDS_PER_CU = 160 * 1024;
+static_assert(header_bytes<WPB_A>() + slice_bytes<uint16_t>(NMAX_A) <= LDS_PER_CU / 8, "bin A: 8 cells per CU");
+static_assert(header_bytes<WPB_D>() + slice_bytes<uint16_t>(NMAX_D) <= LDS_PER_CU / 4, "bin D: 4 cells per CU");
+static_assert(header_bytes<WPB_B>() + slice_bytes<uint16_t>(NMAX_B) <= LDS_PER_CU / 2, "bin B: 2 cells per CU");
+static_assert(header_bytes<WPB_C>() + slice_bytes<uint16_t>(NMAX_C) <= LDS_PER_CU, "bin C: 1 cell per CU");
+
 }  // namespace
 
 int fixed_lds_bytes(int which) {
@@ -3756,10 +3764,10 @@ hipError_t fixed_cells_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<I
     }
     struct Bin { int q; const char* name; hipStream_t s; };
     const Bin bins[6] = {{Q_BIG, "fixed_cells_big", forked ? lc.side[0] : lc.stream},
-                         {Q_C, "fixed_cells_4352", forked ? lc.side[1] : lc.stream},
-                         {Q_B, "fixed_cells_2176", forked ? lc.side[2] : lc.stream},
+                         {Q_C, "fixed_cells_4592", forked ? lc.side[1] : lc.stream},
+                         {Q_B, "fixed_cells_2288", forked ? lc.side[2] : lc.stream},
                          {Q_S, "fixed_cells_small", lc.stream},
-                         {Q_D, "fixed_cells_1152", lc.stream},
+                         {Q_D, "fixed_cells_1144", lc.stream},
                          {Q_A, "fixed_cells_576", lc.stream}};
     for (const Bin& b : bins) {
         A.queue = ws.queue[b.q];

@@ -13,9 +13,9 @@ enum CellMode : uint8_t { CELL_PROCESSED = 0, CELL_UNTOUCHED = 1 };
 
 // Size bins of the fixed-point path.
 constexpr int NMAX_A = 576;     // 1 wavefront per cell, working set in LDS (8 cells per CU)
-constexpr int NMAX_D = 1152;    // 2 wavefronts per cell, working set in LDS (4 cells per CU)
-constexpr int NMAX_B = 2176;    // 4 wavefronts per cell, working set in LDS (2 cells per CU)
-constexpr int NMAX_C = 4352;    // 8 wavefronts per cell, working set in LDS (1 cell per CU)
+constexpr int NMAX_D = 1144;    // 2 wavefronts per cell, working set in LDS (4 cells per CU)
+constexpr int NMAX_B = 2288;    // 4 wavefronts per cell, working set in LDS (2 cells per CU)
+constexpr int NMAX_C = 4592;    // 8 wavefronts per cell, working set in LDS (1 cell per CU)
 constexpr int NMAX_BIG = 65536; // 8 wavefronts per piece, several workgroups per cell, working set global
 constexpr int NMAX_WIDE = 1 << 24;  // largest cell of the fixed-point vpm_run / vpm_partition (a whole box;
                                     // subsets above NMAX_BIG are split by one workgroup each, exactly)

@@ -131,7 +131,7 @@ extern "C" vpm_status vpm_run_noalloc(const vpm_soa* in, const int64_t* cell_off
     lc.fork = nullptr;                     // the bins run one after another on the caller's stream
     lc.pre = nullptr; lc.post = nullptr; lc.prof = nullptr;
 
-    // the default tuning of a context: 16 particles per lane, bins 576 / 1152 / 2176 / 4352, batches <= 128
+    // the default tuning of a context: 16 particles per lane, bins 576 / 1144 / 2288 / 4592, batches <= 128
     FixedParams fp;
     fp.that_x = (uint64_t)llrint(p->tol_x * 16777216.0);
     fp.that_p = (uint64_t)llrint(p->tol_p * 16777216.0);

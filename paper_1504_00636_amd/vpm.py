@@ -51,14 +51,14 @@ class VpmTuning(C.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
-def make_tuning(ppl=16, bin_a_max=576, bin_b_max=2176, bin_c_max=4352, concurrent_bins=0, bin_s_max=128,
+def make_tuning(ppl=16, bin_a_max=576, bin_b_max=2288, bin_c_max=4592, concurrent_bins=0, bin_s_max=128,
                 exact_decisions=0, bin_d_max=None) -> VpmTuning:
-    """bin_d_max None: 1152 kept between bin_a_max and bin_b_max."""
+    """bin_d_max None: 1144 kept between bin_a_max and bin_b_max."""
     t = VpmTuning()
     t.ppl, t.bin_a_max, t.bin_b_max, t.bin_c_max = int(ppl), int(bin_a_max), int(bin_b_max), int(bin_c_max)
     t.concurrent_bins, t.bin_s_max = int(concurrent_bins), int(bin_s_max)
     t.exact_decisions = int(exact_decisions)
-    t.bin_d_max = max(int(bin_a_max), min(1152, int(bin_b_max))) if bin_d_max is None else int(bin_d_max)
+    t.bin_d_max = max(int(bin_a_max), min(1144, int(bin_b_max))) if bin_d_max is None else int(bin_d_max)
     return t
 
 

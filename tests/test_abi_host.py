@@ -124,14 +124,14 @@ def test_binding_argument_counts_match_header():
 @pytest.mark.parametrize("t,ok", [
     ((16, 576, 2048, 4352), True), ((8, 1, 1, 1), True), ((32, 320, 1024, 2560), True),
     ((4, 576, 2048, 4352), False), ((12, 576, 2048, 4352), False), ((16, 0, 2048, 4352), False),
-    ((16, 577, 2048, 4352), False), ((16, 576, 575, 4352), False), ((16, 576, 2177, 4352), False), ((16, 576, 2176, 4352), True),
-    ((16, 576, 2048, 2047), False), ((16, 576, 2048, 4353), False),
+    ((16, 577, 2048, 4352), False), ((16, 576, 575, 4352), False), ((16, 576, 2289, 4352), False), ((16, 576, 2288, 4352), True),
+    ((16, 576, 2048, 2047), False), ((16, 576, 2048, 4593), False), ((16, 576, 2048, 4592), True),
     ((16, 576, 2048, 4352, 1), True), ((16, 576, 2048, 4352, 2), False), ((16, 576, 2048, 4352, -1), False),
     ((16, 576, 2048, 4352, 0, 0), True), ((16, 576, 2048, 4352, 0, 256), True), ((16, 576, 2048, 4352, 0, 257), False),
     ((16, 576, 2048, 4352, 0, -1), False), ((16, 576, 2048, 4352, 0, 128, 1), True),
     ((16, 576, 2048, 4352, 0, 128, 2), False), ((16, 576, 2048, 4352, 0, 128, -1), False),
-    ((16, 576, 2048, 4352, 0, 128, 0, 576), True), ((16, 576, 2048, 4352, 0, 128, 0, 1152), True),
-    ((16, 576, 2048, 4352, 0, 128, 0, 575), False), ((16, 576, 2048, 4352, 0, 128, 0, 1153), False),
+    ((16, 576, 2048, 4352, 0, 128, 0, 576), True), ((16, 576, 2048, 4352, 0, 128, 0, 1144), True),
+    ((16, 576, 2048, 4352, 0, 128, 0, 575), False), ((16, 576, 2048, 4352, 0, 128, 0, 1145), False),
     ((16, 300, 800, 4352, 0, 128, 0, 900), False), ((16, 300, 800, 4352, 0, 128, 0, 800), True)])
 def test_check_tuning(t, ok):
     st = vpm.vpm_check_tuning(vpm.make_tuning(*t))

@@ -56,11 +56,11 @@ def test_merging_cloud(merge):
 
 @pytest.mark.parametrize("merge", MERGES)
 def test_size_bins_and_ragged_tails(merge):
-    """Sizes around every lane-group size and size-bin boundary (576, 1152, 2176 and 4352 particles
+    """Sizes around every lane-group size and size-bin boundary (576, 1144, 2288 and 4592 particles
     in LDS with 1, 2, 4 and 8 wavefronts per cell, larger cells in global slabs)."""
     sizes = [1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 32, 33, 63, 64, 65, 255, 256, 257, 511, 512, 513,
-             575, 576, 577, 1023, 1024, 1025, 1151, 1152, 1153, 2047, 2048, 2049, 2176, 2177, 4095, 4096,
-             4097, 4351, 4352, 4353, 9001]
+             575, 576, 577, 1023, 1024, 1025, 1143, 1144, 1145, 2047, 2048, 2049, 2288, 2289, 4095, 4096,
+             4097, 4352, 4353, 4591, 4592, 4593, 9001]
     wl = cloud_cells(sizes, seed=2, spread=0.08)
     full_check(wl, dict(CLOUD, min_subset=3), merge)
 

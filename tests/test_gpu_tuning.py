@@ -13,12 +13,12 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 SIZES = [1, 2, 5, 17, 64, 200, 575, 577, 900, 2047, 2049, 3000, 4353, 6000, 300, 12, 128, 129, 255, 256, 257,
-         3, 4, 9, 33, 90, 110, 7, 40, 60]
+         3, 4, 9, 33, 90, 110, 7, 40, 60, 1140, 2280, 4590]
 TUNINGS = [(16, 576, 2048, 4352), (8, 64, 512, 1024, 1), (32, 320, 1024, 2560), (8, 1, 1, 1, 0, 0),
            (32, 576, 576, 576, 1), (16, 100, 2048, 2048), (16, 576, 2048, 4352, 1), (16, 576, 2048, 4352, 0, 0),
            (8, 576, 2048, 4352, 0, 256), (32, 576, 2048, 4352, 1, 17), (16, 576, 2048, 4352, 0, 128, 1),
            (8, 320, 1024, 2560, 1, 64, 1), (16, 576, 2048, 4352, 0, 128, 0, 576), (8, 200, 2048, 4352, 1, 64, 0, 700),
-           (32, 576, 1152, 1152, 0, 128, 0, 1152)]
+           (32, 576, 1144, 1144, 0, 128, 0, 1144), (16, 576, 2288, 4592, 1)]
 
 
 def _run(c, arrs, off, n, p):
