@@ -210,8 +210,11 @@ vpm_status vpm_blind(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, i
  * a subset of len particles is handled by a group of about len / ppl lanes (ppl = 8, 16 or 32;
  * at most 64 lanes).  Limits must satisfy 1 <= bin_a_max <= bin_d_max <= bin_b_max <= bin_c_max
  * (bin_d_max = bin_a_max: no two-wavefront bin).
- * concurrent_bins = 1 runs the bins at once on the context's side streams (forked from and
- * joined back to the caller's stream), 0 runs them one after another on the caller's stream.
+ * concurrent_bins = 1 runs the large-cell, eight- and four-wavefront bins on the context's side
+ * streams (forked from and joined back to the caller's stream) beside the others; 2 runs only the
+ * two-wavefront bin on a side stream, beside the others one after another on the caller's stream
+ * (for populations centred on the one-wavefront bin, whose few larger cells then overlap it); 0
+ * runs every bin one after another on the caller's stream.
  * exact_decisions = 1 takes every Step 3-5 decision of the fixed-point path by the exact integer
  * rule (Sec. "Algorithm", Steps 3-5, on 128/256/320-bit moments recomputed from the codes) instead
  * of first trying the certified FP64 evaluation: slower, and by construction the same result; it

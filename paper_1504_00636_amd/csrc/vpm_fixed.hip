@@ -3735,13 +3735,18 @@ hipError_t fixed_cells_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<I
     G.jobs_cap = ws.big_jobs ? ws.jobs_cap : 0;
     G.chunks_cap = ws.big_chunks ? ws.chunks_cap : 0;
 
-    // The three bins touch disjoint cells, queues and counters, so they may run concurrently: the
-    // large-cell and four-wavefront bins go first on the side streams (their cells are the longest), the
-    // 576 bin fills the rest of the chip on the caller's stream, and the caller's stream then waits
-    // for both side streams.
+    // The bins touch disjoint cells, queues and counters, so they may run concurrently.  Mode 1: the
+    // large-cell, eight- and four-wavefront bins go first on the side streams (their cells are the
+    // longest) and the others fill the rest of the chip on the caller's stream.  Mode 2: only the
+    // two-wavefront bin goes to a side stream, where its cells (few, in a population centred on the
+    // one-wavefront bin's sizes) overlap the one-wavefront bin instead of running alone before it.
+    // The caller's stream then waits for the side streams.
+    const int nside = lc.conc_mode == 2 ? 1 : 3;
     bool forked = lc.fork != nullptr;
-    for (int i = 0; i < 3; ++i) forked = forked && lc.side[i] && lc.join[i];
-    G.wait_idle = forked ? 0 : 1;                 // with the bins in sequence nothing else needs the CUs
+    for (int i = 0; i < nside; ++i) forked = forked && lc.side[i] && lc.join[i];
+    const bool big_side = forked && nside == 3, d_side = forked && nside == 1;
+    // idle workgroups of the large-cell kernel wait for tasks unless that kernel shares the chip
+    G.wait_idle = big_side ? 0 : 1;
     hipError_t e = hipSuccess;
     // The side streams that have waited on the fork are joined back to the caller's stream on
     // every return, also after a failure, so that a stream capture in progress stays well formed.
@@ -3756,18 +3761,18 @@ hipError_t fixed_cells_t(const Workspace& ws, const LaunchCfg& lc, const SoaIn<I
     };
     if (forked) {
         e = hipEventRecord(lc.fork, lc.stream);
-        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        for (int i = 0; i < nside && e == hipSuccess; ++i) {
             e = hipStreamWaitEvent(lc.side[i], lc.fork, 0);
             if (e == hipSuccess) waited = i + 1;
         }
         if (e != hipSuccess) return join_back(e);
     }
     struct Bin { int q; const char* name; hipStream_t s; };
-    const Bin bins[6] = {{Q_BIG, "fixed_cells_big", forked ? lc.side[0] : lc.stream},
-                         {Q_C, "fixed_cells_4592", forked ? lc.side[1] : lc.stream},
-                         {Q_B, "fixed_cells_2288", forked ? lc.side[2] : lc.stream},
+    const Bin bins[6] = {{Q_BIG, "fixed_cells_big", big_side ? lc.side[0] : lc.stream},
+                         {Q_C, "fixed_cells_4592", big_side ? lc.side[1] : lc.stream},
+                         {Q_B, "fixed_cells_2288", big_side ? lc.side[2] : lc.stream},
                          {Q_S, "fixed_cells_small", lc.stream},
-                         {Q_D, "fixed_cells_1144", lc.stream},
+                         {Q_D, "fixed_cells_1144", d_side ? lc.side[0] : lc.stream},
                          {Q_A, "fixed_cells_576", lc.stream}};
     for (const Bin& b : bins) {
         A.queue = ws.queue[b.q];

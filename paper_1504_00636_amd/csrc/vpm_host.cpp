@@ -96,6 +96,7 @@ LaunchCfg make_cfg(vpm_ctx* c, hipStream_t s) {
     const bool fork = c->tune.concurrent_bins != 0;
     for (int i = 0; i < 3; ++i) { lc.side[i] = fork ? c->side[i] : nullptr; lc.join[i] = fork ? c->join[i] : nullptr; }
     lc.fork = fork ? c->fork : nullptr;
+    lc.conc_mode = c->tune.concurrent_bins;
     lc.pre = c->profiling ? prof_pre : nullptr;
     lc.post = c->profiling ? prof_post : nullptr;
     lc.prof = c;
@@ -500,7 +501,7 @@ vpm_status vpm_check_tuning(const vpm_tuning* t) {
     if (t->bin_a_max < 1 || t->bin_a_max > NMAX_A) return VPM_ERR_INVALID_ARG;
     if (t->bin_b_max < t->bin_a_max || t->bin_b_max > NMAX_B) return VPM_ERR_INVALID_ARG;
     if (t->bin_c_max < t->bin_b_max || t->bin_c_max > NMAX_C) return VPM_ERR_INVALID_ARG;
-    if (t->concurrent_bins != 0 && t->concurrent_bins != 1) return VPM_ERR_INVALID_ARG;
+    if (t->concurrent_bins < 0 || t->concurrent_bins > 2) return VPM_ERR_INVALID_ARG;
     if (t->bin_s_max < 0 || t->bin_s_max > SMALL_MAX) return VPM_ERR_INVALID_ARG;
     if (t->exact_decisions != 0 && t->exact_decisions != 1) return VPM_ERR_INVALID_ARG;
     if (t->bin_d_max < t->bin_a_max || t->bin_d_max > NMAX_D || t->bin_d_max > t->bin_b_max) return VPM_ERR_INVALID_ARG;
@@ -567,7 +568,7 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
     const int as[5] = {320, 384, 448, 512, NMAX_A};
     const int bs[3] = {1024, 1536, NMAX_B};
     const int cs[3] = {2560, 3456, NMAX_C};
-    const int conc[2] = {0, 1};
+    const int conc[3] = {0, 1, 2};
     const int ss[5] = {0, 32, 64, 128, SMALL_MAX};
     const int ds[3] = {0, 864, NMAX_D};            // 0: no two-wavefront bin (bin_d_max = bin_a_max)
     bool changed = true;
@@ -578,7 +579,7 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
             const int dim = order[di];
             const int* cand = dim == 0 ? ppls : dim == 1 ? as : dim == 2 ? bs : dim == 3 ? cs : dim == 4 ? conc
                             : dim == 5 ? ss : ds;
-            const int nc = dim == 1 || dim == 5 ? 5 : dim == 4 ? 2 : 3;
+            const int nc = dim == 1 || dim == 5 ? 5 : 3;
             for (int k = 0; k < nc && st == VPM_OK; ++k) {
                 vpm_tuning t = cur;
                 if (dim == 0) t.ppl = cand[k];

@@ -120,10 +120,13 @@ struct BinLimits { int32_t a, b, c, s, big, d; };   // big: the largest cell pro
 struct LaunchCfg {
     hipStream_t stream;
     int grid_a, grid_b, grid_c, grid_big, grid_s, grid_fp64, grid_d;   // persistent grid sizes
-    // Optional fork/join for the size bins: bins run concurrently on two side streams (default
+    // Optional fork/join for the size bins: bins run concurrently on side streams (default
     // priority) that wait on `fork` (recorded on `stream`) and are joined back through `join`.
+    // conc_mode 1: the large-cell, eight- and four-wavefront bins on side[0..2]; 2: only the
+    // two-wavefront bin, on side[0] (the others one after another on `stream`).
     hipStream_t side[3];
     hipEvent_t fork, join[3];
+    int conc_mode;
     // profiling hooks (may be null)
     void (*pre)(void* prof, const char* name, hipStream_t s);
     void (*post)(void* prof, const char* name, hipStream_t s);

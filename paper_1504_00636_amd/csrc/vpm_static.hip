@@ -129,6 +129,7 @@ extern "C" vpm_status vpm_run_noalloc(const vpm_soa* in, const int64_t* cell_off
     lc.grid_fp64 = 0;
     for (int i = 0; i < 3; ++i) { lc.side[i] = nullptr; lc.join[i] = nullptr; }
     lc.fork = nullptr;                     // the bins run one after another on the caller's stream
+    lc.conc_mode = 0;
     lc.pre = nullptr; lc.post = nullptr; lc.prof = nullptr;
 
     // the default tuning of a context: 16 particles per lane, bins 576 / 1144 / 2288 / 4592, batches <= 128

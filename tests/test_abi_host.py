@@ -126,7 +126,7 @@ def test_binding_argument_counts_match_header():
     ((4, 576, 2048, 4352), False), ((12, 576, 2048, 4352), False), ((16, 0, 2048, 4352), False),
     ((16, 577, 2048, 4352), False), ((16, 576, 575, 4352), False), ((16, 576, 2289, 4352), False), ((16, 576, 2288, 4352), True),
     ((16, 576, 2048, 2047), False), ((16, 576, 2048, 4593), False), ((16, 576, 2048, 4592), True),
-    ((16, 576, 2048, 4352, 1), True), ((16, 576, 2048, 4352, 2), False), ((16, 576, 2048, 4352, -1), False),
+    ((16, 576, 2048, 4352, 1), True), ((16, 576, 2048, 4352, 2), True), ((16, 576, 2048, 4352, 3), False), ((16, 576, 2048, 4352, -1), False),
     ((16, 576, 2048, 4352, 0, 0), True), ((16, 576, 2048, 4352, 0, 256), True), ((16, 576, 2048, 4352, 0, 257), False),
     ((16, 576, 2048, 4352, 0, -1), False), ((16, 576, 2048, 4352, 0, 128, 1), True),
     ((16, 576, 2048, 4352, 0, 128, 2), False), ((16, 576, 2048, 4352, 0, 128, -1), False),

@@ -42,9 +42,9 @@ def load(wl, bufs, off_buf):
 
 
 @pytest.mark.parametrize("merge,concurrent", [(vpm.VPM_MERGE_PAIR, 0), (vpm.VPM_MERGE_CENTROID, 0),
-                                              (vpm.VPM_MERGE_PAIR, 1)])
+                                              (vpm.VPM_MERGE_PAIR, 1), (vpm.VPM_MERGE_PAIR, 2)])
 def test_graph_replay_matches_eager(merge, concurrent):
-    """concurrent = 1: the size bins run on forked side streams inside the captured graph."""
+    """concurrent = 1 or 2: size bins run on forked side streams inside the captured graph."""
     sizes1 = [300, 40, 3, 0, 700, 2100, 64, 5000, 17]
     sizes2 = [20, 600, 0, 1, 580, 900, 4400, 12, 64]          # same cell count, other sizes
     wl1, wl2 = population(sizes1, 11), population(sizes2, 12)

@@ -18,7 +18,8 @@ TUNINGS = [(16, 576, 2048, 4352), (8, 64, 512, 1024, 1), (32, 320, 1024, 2560), 
            (32, 576, 576, 576, 1), (16, 100, 2048, 2048), (16, 576, 2048, 4352, 1), (16, 576, 2048, 4352, 0, 0),
            (8, 576, 2048, 4352, 0, 256), (32, 576, 2048, 4352, 1, 17), (16, 576, 2048, 4352, 0, 128, 1),
            (8, 320, 1024, 2560, 1, 64, 1), (16, 576, 2048, 4352, 0, 128, 0, 576), (8, 200, 2048, 4352, 1, 64, 0, 700),
-           (32, 576, 1144, 1144, 0, 128, 0, 1144), (16, 576, 2288, 4592, 1)]
+           (32, 576, 1144, 1144, 0, 128, 0, 1144), (16, 576, 2288, 4592, 1), (16, 576, 2288, 4592, 2),
+           (8, 320, 1024, 2560, 2, 64, 0, 700)]
 
 
 def _run(c, arrs, off, n, p):
