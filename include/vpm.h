@@ -241,8 +241,9 @@ vpm_status vpm_set_tuning(vpm_ctx *ctx, const vpm_tuning *t);
 
 /* Choose the tuning for a population: runs vpm_run with candidate configurations on the given
  * data (coordinate search over ppl, the bin limits, concurrent_bins and bin_s_max), times each on `stream` with HIP
- * events (best of four runs), keeps the fastest in the context and returns it in *best (host, may
- * be NULL); the default tuning is kept unless the choice beats it by 1 % on the best of eight.  Leaves
+ * events (best of three samples of three back-to-back runs), keeps the fastest in the context and
+ * returns it in *best (host, may be NULL); the default tuning is kept unless the choice beats it
+ * by 1 % on the best of six samples.  Leaves
  * vpm_run's result of the chosen configuration in out / out_off / out_total.  Synchronises
  * `stream`; cannot be captured in a graph.  Arguments as vpm_run (FIXED decisions only).      */
 vpm_status vpm_autotune(vpm_ctx *ctx, const vpm_soa *in, const int64_t *cell_off, int64_t n_cells,

@@ -539,20 +539,26 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
         ctx->profiling = was_profiling;
         return hip_fail(ctx, hipGetLastError(), "vpm_autotune");
     }
-    // time one configuration: one untimed run, then the best of `reps` timed runs
+    // time one configuration: one untimed run, then the best of `reps` samples, each the mean of
+    // three back-to-back runs (the steady state a caller's loop of events sees; a lone event after
+    // a synchronisation runs 1-2 % slower and less repeatably)
     auto time_cfg = [&](const vpm_tuning& t, float& ms, int reps) -> vpm_status {
         ctx->tune = t;
+        constexpr int BATCH = 3;
         float bestms = 1e30f;
         for (int r = 0; r <= reps; ++r) {
+            const int runs = r == 0 ? 1 : BATCH;
             hipEventRecord(e0, stream);
-            vpm_status s = vpm_run(ctx, in, cell_off, n_cells, n_particles, p, out, out_off, out_total, stream);
-            if (s != VPM_OK) return s;
+            for (int k = 0; k < runs; ++k) {
+                vpm_status s = vpm_run(ctx, in, cell_off, n_cells, n_particles, p, out, out_off, out_total, stream);
+                if (s != VPM_OK) return s;
+            }
             hipEventRecord(e1, stream);
             hipError_t e = hipEventSynchronize(e1);
             if (e != hipSuccess) return hip_fail(ctx, e, "vpm_autotune");
             float m = 0.f;
             hipEventElapsedTime(&m, e0, e1);
-            if (r > 0 && m < bestms) bestms = m;
+            if (r > 0 && m / runs < bestms) bestms = m / runs;
         }
         ms = bestms;
         return VPM_OK;
@@ -560,7 +566,7 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
     const vpm_tuning dflt = {16, NMAX_A, NMAX_B, NMAX_C, 0, 128, was_tuned.exact_decisions, NMAX_D};
     vpm_tuning cur = dflt;
     float cur_ms = 0.f;
-    st = time_cfg(cur, cur_ms, 4);
+    st = time_cfg(cur, cur_ms, 3);
     // coordinate search: each parameter in turn over its candidates, keeping the others; a second
     // pass when the first changed something.  Concurrency goes first: it changes which bin limits
     // are best more than the limits change whether concurrency pays.
@@ -597,21 +603,21 @@ vpm_status vpm_autotune(vpm_ctx* ctx, const vpm_soa* in, const int64_t* cell_off
                     t.bin_s_max == cur.bin_s_max && t.bin_d_max == cur.bin_d_max)
                     continue;
                 float ms = 0.f;
-                st = time_cfg(t, ms, 4);
+                st = time_cfg(t, ms, 3);
                 if (st == VPM_OK && ms < cur_ms * 0.99f) { cur = t; cur_ms = ms; changed = true; }
             }
         }
     }
-    // a search step accepts a candidate on the best of four runs, so a run of lucky timings can
-    // leave it on a configuration no faster than the default: keep the choice only if it still
-    // wins by 1 % on the best of eight runs of each
+    // a search step accepts a candidate on the best of three samples, so a lucky timing can leave
+    // it on a configuration no faster than the default: keep the choice only if it still wins by
+    // 1 % on the best of six samples of each
     const bool moved = cur.ppl != dflt.ppl || cur.bin_a_max != dflt.bin_a_max || cur.bin_b_max != dflt.bin_b_max ||
                        cur.bin_c_max != dflt.bin_c_max || cur.concurrent_bins != dflt.concurrent_bins ||
                        cur.bin_s_max != dflt.bin_s_max || cur.bin_d_max != dflt.bin_d_max;
     if (st == VPM_OK && moved) {
         float ms_cur = 0.f, ms_dflt = 0.f;
-        st = time_cfg(cur, ms_cur, 8);
-        if (st == VPM_OK) st = time_cfg(dflt, ms_dflt, 8);
+        st = time_cfg(cur, ms_cur, 6);
+        if (st == VPM_OK) st = time_cfg(dflt, ms_dflt, 6);
         if (st == VPM_OK && !(ms_cur < ms_dflt * 0.99f)) cur = dflt;
     }
     hipEventDestroy(e0);
