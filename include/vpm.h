@@ -57,7 +57,7 @@ extern "C" {
 typedef enum {
     VPM_OK = 0,
     VPM_ERR_INVALID_ARG = -1,   /* null pointer, negative size, tolerance/length out of range */
-    VPM_ERR_UNSUPPORTED = -2,   /* a dtype/decide combination this build does not implement   */
+    VPM_ERR_UNSUPPORTED = -2,   /* a dtype/decide combination the library does not implement */
     VPM_ERR_CAPACITY = -3,      /* more particles or cells than vpm_reserve provided for       */
     VPM_ERR_HIP = -4,           /* a HIP runtime call failed (message: vpm_last_error)         */
     VPM_ERR_NO_DEVICE = -5      /* no usable GPU                                               */
