@@ -147,11 +147,36 @@ def test_repeatable_bit_identical():
         np.testing.assert_array_equal(a[f], b[f])
 
 
-def _sampled_check(wl, params, sample, merge=vpm.VPM_MERGE_PAIR):
-    """Run the whole population on the GPU (the benchmark's launch configuration) and compare the
-    sampled cells with the oracle run on those cells alone."""
-    perm, sid, nsub = gpu_partition(wl, params, merge=merge)
-    got, got_off, tot = gpu_run(wl, params, merge=merge)
+def _autotune_for(wl, params, merge):
+    """Set the context to the tuning vpm_autotune picks for this population, as the benchmark does
+    before it times an event; returns the tuning that was set before."""
+    import torch
+    from tests.gpu_common import ctx
+    c = ctx(max(wl.n, 1), max(wl.n_cells, 1))
+    saved = c.get_tuning()
+    arrs, off = vpm.upload(wl, dtype=torch.float32)
+    out = [torch.empty_like(a) for a in arrs]
+    oo = torch.empty(off.numel(), dtype=torch.int64, device="cuda")
+    ot = torch.empty(1, dtype=torch.int64, device="cuda")
+    best = c.autotune(arrs, off, wl.n, vpm.make_params(merge_mode=merge, **params), out, oo, ot)
+    assert vpm.vpm_check_tuning(best) == vpm.VPM_OK
+    return c, saved
+
+
+def _sampled_check(wl, params, sample, merge=vpm.VPM_MERGE_PAIR, autotuned=False):
+    """Run the whole population on the GPU and compare the sampled cells with the oracle run on
+    those cells alone.  autotuned: in the launch configuration the benchmark times (the tuning
+    vpm_autotune picks for the population), else the context's default."""
+    if autotuned:
+        c, saved = _autotune_for(wl, params, merge)
+        try:
+            perm, sid, nsub = gpu_partition(wl, params, merge=merge)
+            got, got_off, tot = gpu_run(wl, params, merge=merge)
+        finally:
+            c.set_tuning(saved)
+    else:
+        perm, sid, nsub = gpu_partition(wl, params, merge=merge)
+        got, got_off, tot = gpu_run(wl, params, merge=merge)
     sub = wl.cells(sample)
     ref = oracle.run_workload(sub, merge_mode=merge, **oracle_params(params))
     for k, c in enumerate(sample):
@@ -176,6 +201,14 @@ def test_two_stream_full_size_sampled():
     _sampled_check(wl, wl.params, sample)
 
 
+def test_two_stream_full_size_sampled_autotuned():
+    """The same population and sample in the launch configuration the benchmark times."""
+    wl = W.two_stream_grid(seed=0).astype(np.float32)
+    r = np.random.Generator(np.random.Philox(13))
+    sample = np.sort(r.choice(wl.n_cells, 300, replace=False))
+    _sampled_check(wl, wl.params, sample, autotuned=True)
+
+
 def test_two_stream_paper_tolerances_sampled():
     """Same population with the paper's two-stream tolerances (T_X 0.8, T_P 0.15, N_min 200): merges."""
     wl = W.two_stream_grid(nx=64, ny=64, seed=1).astype(np.float32)
@@ -197,7 +230,7 @@ def test_shower_full_size_sampled():
                                      r.choice(mid, 40, replace=False), r.choice(small, 200, replace=False),
                                      r.choice(tiny, 20, replace=False)]))
     sample = np.unique(sample)
-    _sampled_check(wl, wl.params, sample)
+    _sampled_check(wl, wl.params, sample, autotuned=True)
 
 
 def test_shower_with_merging_sampled():
