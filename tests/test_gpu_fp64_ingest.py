@@ -40,7 +40,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("merge", [vpm.VPM_MERGE_PAIR, vpm.VPM_MERGE_CENTROID])
-@pytest.mark.parametrize("concurrent", [0, 1])
+@pytest.mark.parametrize("concurrent", [0, 1, 2])
 def test_fp64_input_equals_host_rounded_fp32(merge, concurrent):
     wl = population([300, 40, 3, 0, 700, 2100, 64, 5000, 17, 9000, 130, 1, 577, 4400], 51)
     c = ctx(wl.n, wl.n_cells)
