@@ -586,8 +586,10 @@ struct CellShared {          // per-cell bookkeeping, in LDS
 
 // Subsets of a large cell handed to other workgroups (the large-cell kernel): those that a split
 // leaves unfinished with at least TASK_MIN particles.  A level collects them here and publishes
-// them as tasks once the level's writes are complete.
-constexpr int TASK_MIN = 2048;
+// them as tasks once the level's writes are complete.  Smaller pieces are finished faster where
+// they are than through a hand-off (measured over 2,048 to 32,768: 8,192 is best on whole boxes of
+// 2 to 4 million particles and on populations with cells of up to 32,768).
+constexpr int TASK_MIN = 8192;
 constexpr int SPAWN_MAX = 64;          // per level: spawned subsets are disjoint, each >= TASK_MIN
 template <typename IdxT>
 struct SpawnList { int n; Node<IdxT> node[SPAWN_MAX]; };

@@ -429,7 +429,7 @@ def test_merge_rejects_duplicated_member(decide):
 @pytest.mark.parametrize("concurrent", [0, 1, 2])
 def test_large_cells_across_workgroups(concurrent):
     """Cells above the LDS bins are split by several workgroups at once once no cell is left to claim
-    (subsets of >= 2,048 particles go to a device task queue).  Heavy-tailed momenta and lognormal
+    (subsets of >= 8,192 particles go to a device task queue).  Heavy-tailed momenta and lognormal
     weights make the splits lopsided, so tasks spawn tasks along chains.  The result must be the
     oracle's, with the bins in sequence (idle workgroups wait for tasks), concurrent (they leave) and
     with only the two-wavefront bin beside the others (they wait again)."""
